@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Benchmark: decoded shots/s of BP + LSD-0 on the [[144,12,12]] bivariate bicycle code.
+
+Workload: H_X of the BB code (l=12, m=6, A = x^3+y+y^2, B = y^3+x+x^2), 72 x 144, under
+code-capacity X noise at p = 0.05; 65,536 seeded shots per step; min-sum BP (alpha = 0.625,
+at most 50 iterations, early exit) then LSD-0 on the shots BP does not solve.  A step is one
+qlsd_decode call over a batch whose syndromes already sit in HBM.
+
+Prints one JSON line (see --help).  Besides shots/s it reports per-launch latency
+percentiles, the logical error rate of the GPU run next to the oracle's on the same shots,
+the BP kernel's roofline position (algorithmic bytes per launch / its measured duration,
+HIP events on the launch stream) and the CPU oracle's throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+METRIC = "decoded shots/s at matched LER, [[144,12,12]] p=0.05; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--shots", type=int, default=65536)
+    ap.add_argument("--p", type=float, default=0.05)
+    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--batches", type=int, default=4, help="distinct pre-generated batches cycled")
+    ap.add_argument("--seed", type=int, default=20240626)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "bp_traffic_bb144.json"),
+                    help="HBM bytes per BP launch measured with rocprofv3 counters, if present")
+    return ap.parse_args()
+
+
+def bp_algorithmic_bytes(m, n, E, iters):
+    """Per shot: syndrome in and correction out as bits, plus every float32 c->v message
+    and posterior written and read once per flooding iteration."""
+    return float(len(iters) * ((m + 7) // 8 + (n + 7) // 8) + iters.astype(np.float64).sum() * (8 * E + 8 * n))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); shots are independent, "
+              "so a multi-GPU run would be N independent copies of this launch.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, sample, logical_failures
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    code = bivariate_bicycle(p=args.p)
+    B = args.shots
+    batches = []
+    for k in range(args.batches):
+        e, S = sample(code, B, seed=args.seed + k)
+        batches.append((e, torch.from_numpy(S).to(dev)))
+    bcode = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, flags=binding.FLAG_STAGE_TIMING)
+    corr = torch.empty((B, code.n), dtype=torch.uint8, device=dev)
+    info = torch.empty((B, 12), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    # correctness + iteration counts of each batch (untimed)
+    iters_per_batch, ler_gpu, lsd_frac = [], [], []
+    for e, s in batches:
+        dec.decode_into(s, corr, info)
+        torch.cuda.synchronize()
+        inf = binding.parse_info(info)
+        iters_per_batch.append(inf["bp_iters"].astype(np.int64))
+        lsd_frac.append(float(((inf["status"] & binding.ST_LSD_RUN) != 0).mean()))
+        c = corr.cpu().numpy()
+        Sn = s.cpu().numpy()
+        if not (((c.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == Sn).all():
+            print("correction does not satisfy its syndrome", file=sys.stderr)
+            sys.exit(3)
+        ler_gpu.append(logical_failures(code, e, c))
+
+    for k in range(args.warmup):
+        dec.decode_into(batches[k % len(batches)][1], corr, None)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K steps; per-step events for latency, stage events for the roofline
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    bp_ms, lsd_ms = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        dec.decode_into(batches[k % len(batches)][1], corr, None)
+        ends[k].record(stream)
+        if k % 8 == 7 or k == args.steps - 1:
+            # stage times of this launch (waits for it; at most one in eight steps)
+            a, b = dec.stage_ms()
+            bp_ms.append(a)
+            lsd_ms.append(b)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    shots_per_s = args.steps * B / wall
+    ms_per_step = wall * 1e3 / args.steps
+
+    # BP kernel roofline: algorithmic bytes per launch over its measured average duration
+    E = code.nnz
+    bytes_per_launch = np.mean([bp_algorithmic_bytes(code.m, code.n, E, it) for it in iters_per_batch])
+    bp_avg_ms = float(np.mean(bp_ms))
+    achieved = bytes_per_launch / (bp_avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        if tj.get("kernel_source_hash") == _kernel_hash():
+            traffic = tj.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "bp_lds_kernel", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "avg_launch_ms": round(bp_avg_ms, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch,
+                "lsd_avg_launch_ms": round(float(np.mean(lsd_ms)), 4)}
+
+    # logical error rate of the GPU run vs the oracle on the same shots (batch 0)
+    e0, s0 = batches[0]
+    out = {"metric": METRIC, "value": round(shots_per_s, 1), "unit": "shots/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "bb144_codecap_p0.05_bp50_lsd0", "code": "[[144,12,12]] BB l=12 m=6",
+                      "H": "72x144", "p": args.p, "shots_per_step": B, "max_iter": args.max_iter,
+                      "ms_scaling": 0.625, "lsd_order": 0},
+           "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                          "p99": round(float(np.percentile(lat, 99)), 4), "per": "launch of 65536 shots"},
+           "ler": {"gpu": round(float(np.mean([f.mean() for f in ler_gpu])), 6)},
+           "bp_mean_iters": round(float(np.mean([it.mean() for it in iters_per_batch])), 3),
+           "lsd_fraction": round(float(np.mean(lsd_frac)), 4),
+           "roofline": roofline}
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], ler_ref = cpu_baseline(code, e0, s0.cpu().numpy(), args)
+        f_gpu = ler_gpu[0]
+        p = max(ler_ref.mean(), 1.0 / B)
+        out["ler"].update({"gpu_batch0": round(float(f_gpu.mean()), 6),
+                           "oracle_batch0": round(float(ler_ref.mean()), 6),
+                           "two_sigma": round(2 * float(np.sqrt(p * (1 - p) / B)), 6),
+                           "matched": bool(abs(f_gpu.mean() - ler_ref.mean()) <= 2 * np.sqrt(p * (1 - p) / B))})
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("qlsd_bp.hip", "qlsd_internal.h"):
+        with open(os.path.join(HERE, "paper_2406_18655_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(code, errors, S, args):
+    """The CPU oracle (float64 BP + LSD, OpenMP over shots) on batch 0, as it stands."""
+    import oracle
+    from paper_2406_18655_amd.workloads import logical_failures
+    oc = oracle.Code.from_dense(code.H)
+    lam = oracle.llr_from_priors(code.priors)
+    threads = min(16, os.cpu_count() or 1)
+    # one full pass over batch 0 gives the oracle's LER on the same shots
+    t0 = time.perf_counter()
+    corr, st, it, _ = oracle.decode_batch(oc, lam, S, args.max_iter, nthreads=threads)
+    dt = time.perf_counter() - t0
+    done, tot = S.shape[0], dt
+    while tot < args.cpu_seconds:
+        t0 = time.perf_counter()
+        oracle.decode_batch(oc, lam, S, args.max_iter, nthreads=threads)
+        tot += time.perf_counter() - t0
+        done += S.shape[0]
+    ler_ref = logical_failures(code, errors, corr)
+    base = {"value": round(done / tot, 1), "unit": "shots/s", "cores": threads, "kind": "oracle",
+            "sample": f"batch 0 ({S.shape[0]} shots) decoded {done // S.shape[0]}x, {tot:.1f} s"}
+    return base, ler_ref
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,123 @@
+/*
+ * qlsd.h -- C ABI of the MI355X BP + localized-statistics decoder (libqlsd.so).
+ *
+ * Problem (Hillmann et al., arXiv:2406.18655, Sec. 2.1): given a detector check
+ * matrix H in F_2^{m x n}, per-fault priors p_j and a batch of syndromes s, return
+ * corrections e_hat with H e_hat = s that are as likely (low weight) as the method
+ * finds.  The method: min-sum belief propagation (Sec. 4.3, parallel schedule,
+ * scaling 0.625), and, for shots where BP does not satisfy the syndrome, LSD on
+ * BP's posterior LLRs (Sec. 4.1 / Alg. 1 with the synchronous rounds of
+ * Appendix B / Alg. 2; on-the-fly elimination of Sec. 4.2), optionally followed
+ * by the order-mu local reprocessing of Appendix D.
+ *
+ * Conventions for every entry point:
+ *   - Every function returns a qlsd_status (0 = success, < 0 = error) and never
+ *     throws; qlsd_last_error() gives a thread-local message for the last error.
+ *   - "host" pointers are read during the call only and copied.  "device"
+ *     pointers are caller-owned HIP device memory that must stay valid until the
+ *     work on `stream` has completed.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Decode
+ *     calls are asynchronous: argument errors are returned synchronously, device
+ *     failures surface from qlsd_sync().
+ *   - Decode calls never allocate: a decoder's device workspace is sized once for
+ *     max_batch shots in qlsd_decoder_create().
+ *   - A decoder handle is not re-entrant: calls that overlap on one decoder race
+ *     on its workspace.  Distinct decoders may run concurrently on distinct streams.
+ *   - Layouts are row-major, one byte per bit: syndromes B x m (values 0/1),
+ *     corrections B x n (0/1), LLRs B x n float32.
+ */
+#ifndef QLSD_H
+#define QLSD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QLSD_OK = 0,
+    QLSD_E_INVALID = -1,     /* bad argument, shape or matrix (e.g. a BP row of weight < 2) */
+    QLSD_E_PRIOR = -2,       /* a prior outside (0, 1) */
+    QLSD_E_NOMEM = -3,       /* device or host allocation failed */
+    QLSD_E_DEVICE = -4,      /* a HIP call or kernel failed */
+    QLSD_E_BATCH = -5,       /* B < 0 or B > max_batch */
+    QLSD_E_UNSUPPORTED = -6  /* size beyond what the kernels support */
+} qlsd_status;
+
+typedef struct qlsd_code_s *qlsd_code;       /* immutable H on the device; library-owned */
+typedef struct qlsd_decoder_s *qlsd_decoder; /* params, priors and workspace; library-owned */
+
+/* Parameters (Sec. 4.3 and Appendix D). */
+typedef struct {
+    int32_t max_iter;   /* BP iterations, >= 1 (30 in the paper; 50/100 for larger graphs) */
+    float ms_scaling;   /* min-sum scaling factor alpha (0.625 in the paper) */
+    int32_t lsd_order;  /* mu: extra growth steps + local exhaustive OSD order (0 = LSD-0) */
+    int32_t osd_method; /* 0 = exhaustive (OSD-E); others rejected */
+    uint32_t flags;     /* QLSD_FLAG_* */
+} qlsd_params;
+
+#define QLSD_FLAG_NO_EARLY_EXIT 1u /* run all max_iter BP iterations for every shot */
+#define QLSD_FLAG_STAGE_TIMING 2u  /* record HIP events around each kernel of qlsd_decode */
+
+/* Per-shot status bits (qlsd_shot_info.status). */
+#define QLSD_ST_BP_CONVERGED 1u /* BP's hard decision satisfies s; no LSD was needed   */
+#define QLSD_ST_LSD_RUN 2u      /* LSD produced the correction                          */
+#define QLSD_ST_UNSAT 4u        /* some cluster could not be made valid (s not in image) */
+#define QLSD_ST_BAD_LLR 8u      /* NaN soft information; correction left at zero        */
+#define QLSD_ST_OVERFLOW 16u    /* clusters outgrew the kernel's capacity; correction zero */
+
+typedef struct {
+    uint8_t status;           /* QLSD_ST_* bits */
+    uint8_t reserved;
+    int16_t bp_iters;         /* BP iterations run */
+    int16_t n_clusters;       /* LSD: clusters at termination */
+    int16_t rounds;           /* LSD: growth rounds */
+    int32_t max_cluster_cols; /* LSD: largest cluster, in columns */
+} qlsd_shot_info;             /* 12 bytes */
+
+/* H as CSR (host): row_ptr[m+1], col_idx[nnz] with columns sorted and unique per row.
+ * 1 <= m, n; nnz = row_ptr[m].  Copies to the current HIP device. */
+qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, qlsd_code *out);
+
+/* priors: host double[n], each in (0, 1) (QLSD_E_PRIOR otherwise); the decoder uses
+ * lambda_j = ln((1-p_j)/p_j) rounded to float32.  Allocates all device workspace for
+ * up to max_batch shots.  The code must outlive the decoder. */
+qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const double *priors,
+                                int32_t max_batch, qlsd_decoder *out);
+
+/* BP then LSD (Sec. 2.3): syndromes device u8[B*m] -> corrections device u8[B*n];
+ * info device qlsd_shot_info[B] or NULL.  0 <= B <= max_batch. */
+qlsd_status qlsd_decode(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
+                        qlsd_shot_info *info, void *stream);
+
+/* BP only: llr_out device float[B*n] receives the posterior LLRs L_j of the last
+ * iteration run; hard_out device u8[B*n] (nullable) receives [L_j < 0]. */
+qlsd_status qlsd_bp(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, float *llr_out,
+                    uint8_t *hard_out, qlsd_shot_info *info, void *stream);
+
+/* LSD only (Alg. 1/2): soft information llr device float[B*n] (lower = more likely
+ * in error; ties broken by the smaller fault index) -> corrections device u8[B*n]. */
+qlsd_status qlsd_lsd(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
+                     uint8_t *corrections, qlsd_shot_info *info, void *stream);
+
+/* Device time (ms) of the BP kernel and of the LSD kernel in the decoder's last
+ * qlsd_decode call, from HIP events recorded on that call's stream around each kernel.
+ * Needs QLSD_FLAG_STAGE_TIMING in the decoder's params (QLSD_E_INVALID otherwise);
+ * waits for those events.  Either output pointer (host float) may be NULL. */
+qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms);
+
+/* Waits for the decoder's last work and reports a device failure, if any. */
+qlsd_status qlsd_sync(qlsd_decoder dec);
+
+/* Thread-local text of the last error ("" if none).  Never NULL. */
+const char *qlsd_last_error(void);
+
+void qlsd_decoder_destroy(qlsd_decoder dec);
+void qlsd_code_destroy(qlsd_code code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QLSD_H */

@@ -1,0 +1,211 @@
+"""Thin ctypes binding over libqlsd's C ABI (include/qlsd.h).
+
+Argument marshalling only: torch supplies device memory and the current stream;
+every decoding step runs in the HIP kernels.  Loading fails loudly when the
+library has not been built -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqlsd.so")
+
+QLSD_OK = 0
+ST_BP_CONVERGED, ST_LSD_RUN, ST_UNSAT, ST_BAD_LLR, ST_OVERFLOW = 1, 2, 4, 8, 16
+FLAG_NO_EARLY_EXIT = 1
+FLAG_STAGE_TIMING = 2
+
+# every symbol include/qlsd.h declares
+EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
+           "qlsd_decoder_stage_ms", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
+           "qlsd_code_destroy"]
+
+INFO_DTYPE = np.dtype([("status", np.uint8), ("reserved", np.uint8), ("bp_iters", np.int16),
+                       ("n_clusters", np.int16), ("rounds", np.int16), ("max_cluster_cols", np.int32)])
+assert INFO_DTYPE.itemsize == 12
+
+
+class QlsdParams(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("ms_scaling", ctypes.c_float),
+                ("lsd_order", ctypes.c_int32), ("osd_method", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class QlsdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"qlsd status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Loads libqlsd.so (built by paper_2406_18655_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built: run paper_2406_18655_amd/build.py (no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.qlsd_code_create.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(P)]
+        L.qlsd_decoder_create.argtypes = [P, ctypes.POINTER(QlsdParams), P, I32, ctypes.POINTER(P)]
+        L.qlsd_decode.argtypes = [P, P, I32, P, P, P]
+        L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
+        L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
+        L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
+        L.qlsd_sync.argtypes = [P]
+        L.qlsd_last_error.restype = ctypes.c_char_p
+        L.qlsd_decoder_destroy.argtypes = [P]
+        L.qlsd_code_destroy.argtypes = [P]
+        for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
+                   "qlsd_decoder_stage_ms", "qlsd_sync"):
+            getattr(L, fn).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st: int):
+    if st != QLSD_OK:
+        raise QlsdError(st, lib().qlsd_last_error().decode())
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a tensor whose memory is the dense row-major layout the ABI expects."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libqlsd must be contiguous (row-major)")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def csr_of(H: np.ndarray):
+    H = np.asarray(H, dtype=np.uint8)
+    rows, cols = np.nonzero(H)
+    row_ptr = np.zeros(H.shape[0] + 1, dtype=np.int32)
+    np.add.at(row_ptr, rows + 1, 1)
+    return np.cumsum(row_ptr).astype(np.int32), cols.astype(np.int32)
+
+
+class Code:
+    """qlsd_code: H uploaded once to the current HIP device."""
+
+    def __init__(self, m: int, n: int, row_ptr: np.ndarray, col_idx: np.ndarray):
+        self.m, self.n = int(m), int(n)
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+        ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+        h = ctypes.c_void_p()
+        _check(lib().qlsd_code_create(self.m, self.n, int(rp[-1]), rp.ctypes.data, ci.ctypes.data,
+                                      ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_dense(cls, H: np.ndarray) -> "Code":
+        rp, ci = csr_of(H)
+        return cls(H.shape[0], H.shape[1], rp, ci)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qlsd_code_destroy(self._h)
+            self._h = None
+
+
+class Decoder:
+    """qlsd_decoder: params + priors + device workspace for up to max_batch shots."""
+
+    def __init__(self, code: Code, priors: np.ndarray, max_batch: int, max_iter: int = 30,
+                 ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0):
+        self.code = code
+        self.max_batch = int(max_batch)
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        if pri.shape != (code.n,):
+            raise ValueError("priors must have shape (n,)")
+        self.params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags))
+        h = ctypes.c_void_p()
+        _check(lib().qlsd_decoder_create(code._h, ctypes.byref(self.params), pri.ctypes.data,
+                                         self.max_batch, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qlsd_decoder_destroy(self._h)
+            self._h = None
+
+    # -- raw entry points (device pointers, caller-owned outputs) --------------------
+    def decode_into(self, syndromes, corrections, info=None, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        _check(lib().qlsd_decode(self._h, _ptr(syndromes), B, _ptr(corrections), _ptr(info),
+                                 _stream() if stream is None else stream))
+
+    def bp_into(self, syndromes, llr_out, hard_out=None, info=None, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        _check(lib().qlsd_bp(self._h, _ptr(syndromes), B, _ptr(llr_out), _ptr(hard_out), _ptr(info),
+                             _stream() if stream is None else stream))
+
+    def lsd_into(self, syndromes, llr, corrections, info=None, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        _check(lib().qlsd_lsd(self._h, _ptr(syndromes), _ptr(llr), B, _ptr(corrections), _ptr(info),
+                              _stream() if stream is None else stream))
+
+    def sync(self):
+        _check(lib().qlsd_sync(self._h))
+
+    def stage_ms(self):
+        """(bp_ms, lsd_ms) of the last decode call (needs FLAG_STAGE_TIMING)."""
+        a, b = ctypes.c_float(), ctypes.c_float()
+        _check(lib().qlsd_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # -- torch conveniences ----------------------------------------------------------
+    def _prep(self, syndromes):
+        import torch
+        s = syndromes
+        if not s.is_cuda or s.dtype != torch.uint8 or s.dim() != 2 or s.shape[1] != self.code.m:
+            raise ValueError("syndromes must be a uint8 CUDA tensor [B, m]")
+        return s.contiguous()
+
+    def decode(self, syndromes, want_info: bool = False):
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.decode_into(s, corr, info)
+        return (corr, info) if want_info else corr
+
+    def bp(self, syndromes, want_info: bool = True):
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        llr = torch.empty((B, self.code.n), dtype=torch.float32, device=s.device)
+        hard = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.bp_into(s, llr, hard, info)
+        return llr, hard, info
+
+    def lsd(self, syndromes, llr, want_info: bool = True):
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        if llr.dtype != torch.float32 or tuple(llr.shape) != (B, self.code.n) or not llr.is_cuda:
+            raise ValueError("llr must be a float32 CUDA tensor [B, n]")
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.lsd_into(s, llr.contiguous(), corr, info)
+        return corr, info
+
+
+def parse_info(info) -> np.ndarray:
+    """uint8 tensor/array [B, 12] -> structured numpy array with INFO_DTYPE fields."""
+    a = info.cpu().numpy() if hasattr(info, "cpu") else np.asarray(info)
+    return np.ascontiguousarray(a).view(INFO_DTYPE).reshape(-1)

@@ -1,0 +1,349 @@
+// C ABI of libqlsd: argument checking, device set-up and launch sequencing.
+// Every step of the decode runs in the HIP kernels of qlsd_bp.hip and qlsd_lsd.hip.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "qlsd_internal.h"
+
+using namespace qlsd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+qlsd_status fail(qlsd_status st, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+#define HIP_OK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(QLSD_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+hipError_t dev_copy(T **dst, const T *src, size_t count) {
+    *dst = nullptr;
+    hipError_t e = hipMalloc((void **)dst, sizeof(T) * std::max<size_t>(count, 1));
+    if (e != hipSuccess) return e;
+    if (count) e = hipMemcpy(*dst, src, sizeof(T) * count, hipMemcpyHostToDevice);
+    return e;
+}
+
+constexpr size_t kBpLdsBudget = 80 * 1024;  // two BP workgroups per CU
+constexpr int kMaxSlots = 64;
+
+}  // namespace
+
+struct qlsd_code_s {
+    int device;
+    DevGraph g;
+    int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge;
+    int min_rw;
+};
+
+struct qlsd_decoder_s {
+    qlsd_code code;
+    qlsd_params params;
+    int max_batch;
+    float *d_lam;
+    int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter
+    int *d_list;         // max_batch
+    float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
+    int bp_slots, bp_grid;
+    int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds;
+    int num_cus;
+    hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
+    bool timing;
+};
+
+extern "C" {
+
+const char *qlsd_last_error(void) { return g_err; }
+
+qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, qlsd_code *out) {
+    g_err[0] = 0;
+    if (!out) return fail(QLSD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (m < 1 || n < 1 || !row_ptr || (nnz > 0 && !col_idx))
+        return fail(QLSD_E_INVALID, "bad shape m=%d n=%d or NULL arrays", m, n);
+    if (nnz < 0 || nnz > (1ll << 30) || row_ptr[0] != 0 || row_ptr[m] != nnz)
+        return fail(QLSD_E_INVALID, "row_ptr[0] must be 0 and row_ptr[m] == nnz");
+    int max_rw = 0, min_rw = 1 << 30;
+    for (int i = 0; i < m; i++) {
+        const int a = row_ptr[i], b = row_ptr[i + 1];
+        if (b < a) return fail(QLSD_E_INVALID, "row_ptr not monotone at row %d", i);
+        max_rw = std::max(max_rw, b - a);
+        min_rw = std::min(min_rw, b - a);
+        for (int e = a; e < b; e++) {
+            if (col_idx[e] < 0 || col_idx[e] >= n) return fail(QLSD_E_INVALID, "col_idx out of range at %d", e);
+            if (e > a && col_idx[e] <= col_idx[e - 1])
+                return fail(QLSD_E_INVALID, "columns of row %d not sorted/unique", i);
+        }
+    }
+    std::vector<int32_t> col_ptr(n + 1, 0), row_idx(nnz), col_edge(nnz), fill(n, 0);
+    for (int64_t e = 0; e < nnz; e++) col_ptr[col_idx[e] + 1]++;
+    int max_cw = 0;
+    for (int j = 0; j < n; j++) {
+        max_cw = std::max(max_cw, col_ptr[j + 1]);
+        col_ptr[j + 1] += col_ptr[j];
+    }
+    for (int i = 0; i < m; i++)
+        for (int e = row_ptr[i]; e < row_ptr[i + 1]; e++) {
+            const int j = col_idx[e];
+            const int k = col_ptr[j] + fill[j]++;
+            row_idx[k] = i;
+            col_edge[k] = e;
+        }
+    qlsd_code c = new (std::nothrow) qlsd_code_s();
+    if (!c) return fail(QLSD_E_NOMEM, "host allocation failed");
+    HIP_OK(hipGetDevice(&c->device));
+    hipError_t e1 = dev_copy(&c->d_row_ptr, row_ptr, (size_t)m + 1);
+    hipError_t e2 = dev_copy(&c->d_col_idx, col_idx, (size_t)nnz);
+    hipError_t e3 = dev_copy(&c->d_col_ptr, col_ptr.data(), (size_t)n + 1);
+    hipError_t e4 = dev_copy(&c->d_row_idx, row_idx.data(), (size_t)nnz);
+    hipError_t e5 = dev_copy(&c->d_col_edge, col_edge.data(), (size_t)nnz);
+    if (e1 || e2 || e3 || e4 || e5) {
+        qlsd_code_destroy(c);
+        return fail(QLSD_E_NOMEM, "device allocation/copy of H failed");
+    }
+    c->g.m = m;
+    c->g.n = n;
+    c->g.nnz = (int)nnz;
+    c->g.max_rw = max_rw;
+    c->g.max_cw = max_cw;
+    c->g.row_ptr = c->d_row_ptr;
+    c->g.col_idx = c->d_col_idx;
+    c->g.col_ptr = c->d_col_ptr;
+    c->g.row_idx = c->d_row_idx;
+    c->g.col_edge = c->d_col_edge;
+    c->min_rw = min_rw;
+    *out = c;
+    return QLSD_OK;
+}
+
+void qlsd_code_destroy(qlsd_code c) {
+    if (!c) return;
+    hipFree(c->d_row_ptr);
+    hipFree(c->d_col_idx);
+    hipFree(c->d_col_ptr);
+    hipFree(c->d_row_idx);
+    hipFree(c->d_col_edge);
+    delete c;
+}
+
+qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const double *priors,
+                                int32_t max_batch, qlsd_decoder *out) {
+    g_err[0] = 0;
+    if (!out) return fail(QLSD_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!code || !params || !priors) return fail(QLSD_E_INVALID, "NULL code/params/priors");
+    if (max_batch < 1) return fail(QLSD_E_BATCH, "max_batch must be >= 1");
+    if (params->max_iter < 1 || params->max_iter > 30000) return fail(QLSD_E_INVALID, "max_iter out of range");
+    if (!(params->ms_scaling > 0.f && params->ms_scaling <= 1.f)) return fail(QLSD_E_INVALID, "ms_scaling must be in (0,1]");
+    if (params->lsd_order != 0) return fail(QLSD_E_UNSUPPORTED, "lsd_order > 0 is not built yet");
+    if (params->osd_method != 0) return fail(QLSD_E_UNSUPPORTED, "only osd_method 0 (exhaustive)");
+    const DevGraph &g = code->g;
+    if (code->min_rw < 2) return fail(QLSD_E_INVALID, "BP needs every row weight >= 2");
+    if (g.max_rw > kMaxRowWeight || g.max_cw > kMaxColWeight)
+        return fail(QLSD_E_UNSUPPORTED, "row weight %d / column weight %d beyond %d / %d", g.max_rw, g.max_cw,
+                    kMaxRowWeight, kMaxColWeight);
+    std::vector<float> lam(g.n);
+    for (int j = 0; j < g.n; j++) {
+        const double p = priors[j];
+        if (!(p > 0.0 && p < 1.0)) return fail(QLSD_E_PRIOR, "prior %d = %g not in (0,1)", j, p);
+        lam[j] = (float)log((1.0 - p) / p);
+    }
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != code->device) return fail(QLSD_E_INVALID, "code lives on device %d, current is %d", code->device, dev);
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+
+    qlsd_decoder d = new (std::nothrow) qlsd_decoder_s();
+    if (!d) return fail(QLSD_E_NOMEM, "host allocation failed");
+    d->code = code;
+    d->params = *params;
+    d->max_batch = max_batch;
+    d->num_cus = prop.multiProcessorCount;
+
+    // BP: shot slots per workgroup under the LDS budget
+    int S = kMaxSlots;
+    while (S > 0 && bp_lds_bytes(g, S) > kBpLdsBudget) S--;
+    if (S < 8 || g.n >= 65535 || g.nnz >= 65535) {
+        delete d;
+        return fail(QLSD_E_UNSUPPORTED, "graph too large for LDS-resident BP (n=%d, nnz=%d)", g.n, g.nnz);
+    }
+    d->bp_slots = S;
+    d->bp_grid = 2 * d->num_cus;
+
+    // LSD: local-row capacity 64*W
+    int W = 1;
+    while (64 * W < g.m && W < 4) W *= 2;
+    d->lsd_W = W;
+    d->lsd_keys_in_lds = (size_t)g.n * 4 <= 16384;
+    d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0);
+    if ((size_t)d->lsd_wave_bytes * (kLsdThreads / 64) > 64 * 1024) {
+        delete d;
+        return fail(QLSD_E_UNSUPPORTED, "LSD workspace per wavefront too large");
+    }
+    d->lsd_grid = 8 * d->num_cus;
+    d->timing = (params->flags & QLSD_FLAG_STAGE_TIMING) != 0;
+    for (int k = 0; k < 3; k++) d->ev[k] = nullptr;
+    if (d->timing)
+        for (int k = 0; k < 3; k++)
+            if (hipEventCreate(&d->ev[k]) != hipSuccess) {
+                qlsd_decoder_destroy(d);
+                return fail(QLSD_E_DEVICE, "hipEventCreate failed");
+            }
+
+    hipError_t e1 = dev_copy(&d->d_lam, lam.data(), lam.size());
+    hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * 8);
+    hipError_t e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
+    hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
+    if (e1 || e2 || e3 || e4) {
+        qlsd_decoder_destroy(d);
+        return fail(QLSD_E_NOMEM, "device workspace allocation failed (max_batch=%d)", max_batch);
+    }
+    *out = d;
+    return QLSD_OK;
+}
+
+void qlsd_decoder_destroy(qlsd_decoder d) {
+    if (!d) return;
+    hipFree(d->d_lam);
+    hipFree(d->d_ctl);
+    hipFree(d->d_list);
+    hipFree(d->d_llr);
+    for (int k = 0; k < 3; k++)
+        if (d->ev[k]) hipEventDestroy(d->ev[k]);
+    delete d;
+}
+
+static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
+    BpArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = d->code->g;
+    a.lam = d->d_lam;
+    a.syn = syn;
+    a.B = B;
+    a.max_iter = d->params.max_iter;
+    a.alpha = d->params.ms_scaling;
+    a.early_exit = (d->params.flags & QLSD_FLAG_NO_EARLY_EXIT) ? 0 : 1;
+    a.S = d->bp_slots;
+    a.next_shot = d->d_ctl + 0;
+    a.lsd_count = d->d_ctl + 1;
+    return a;
+}
+
+static int bp_grid(qlsd_decoder d, int B) {
+    const int need = (B + d->bp_slots - 1) / d->bp_slots;
+    return std::max(1, std::min(d->bp_grid, need));
+}
+
+static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, uint8_t *corr,
+                        qlsd_shot_info *info) {
+    LsdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = d->code->g;
+    a.syn = syn;
+    a.llr = llr;
+    a.next_item = d->d_ctl + 2;
+    a.corr = corr;
+    a.info = info;
+    a.keys_in_lds = d->lsd_keys_in_lds;
+    a.wave_bytes = d->lsd_wave_bytes;
+    return a;
+}
+
+static qlsd_status check_call(qlsd_decoder d, const void *syn, int B, const void *out) {
+    g_err[0] = 0;
+    if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    if (B < 0 || B > d->max_batch) return fail(QLSD_E_BATCH, "B=%d outside [0, %d]", B, d->max_batch);
+    if (B > 0 && (!syn || !out)) return fail(QLSD_E_INVALID, "NULL syndromes or output");
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
+                        qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK || B == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
+    BpArgs a = bp_args(d, syndromes, B);
+    a.corr = corrections;
+    a.llr_lsd = d->d_llr;
+    a.lsd_list = d->d_list;
+    a.info = info;
+    HIP_OK(launch_bp(a, bp_grid(d, B), s));
+    if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
+    LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
+    l.list = d->d_list;
+    l.list_count = d->d_ctl + 1;
+    l.bp_ran = 1;
+    HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
+    if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_bp(qlsd_decoder d, const uint8_t *syndromes, int32_t B, float *llr_out, uint8_t *hard_out,
+                    qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, llr_out);
+    if (st != QLSD_OK || B == 0) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    BpArgs a = bp_args(d, syndromes, B);
+    a.corr = hard_out;
+    a.llr_out = llr_out;
+    a.info = info;
+    HIP_OK(launch_bp(a, bp_grid(d, B), s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr, int32_t B,
+                     uint8_t *corrections, qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK || B == 0) return st;
+    if (!llr) return fail(QLSD_E_INVALID, "llr is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    LsdArgs l = lsd_args(d, syndromes, llr, corrections, info);
+    l.count = B;
+    HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_decoder_stage_ms(qlsd_decoder d, float *bp_ms, float *lsd_ms) {
+    g_err[0] = 0;
+    if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    if (!d->timing) return fail(QLSD_E_INVALID, "decoder was created without QLSD_FLAG_STAGE_TIMING");
+    HIP_OK(hipEventSynchronize(d->ev[2]));
+    float a = 0.f, b = 0.f;
+    HIP_OK(hipEventElapsedTime(&a, d->ev[0], d->ev[1]));
+    HIP_OK(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
+    if (bp_ms) *bp_ms = a;
+    if (lsd_ms) *lsd_ms = b;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_sync(qlsd_decoder d) {
+    g_err[0] = 0;
+    if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    HIP_OK(hipDeviceSynchronize());
+    HIP_OK(hipGetLastError());
+    return QLSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,68 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/qlsd.h"
+
+namespace qlsd {
+
+// Device copy of H: CSR (checks -> faults) and CSC (faults -> checks); edge id = CSR position.
+struct DevGraph {
+    int m, n, nnz;
+    int max_rw, max_cw;
+    const int32_t *row_ptr, *col_idx;   // m+1, nnz
+    const int32_t *col_ptr, *row_idx;   // n+1, nnz
+    const int32_t *col_edge;            // nnz: CSR edge id of each CSC entry
+};
+
+// Arguments of the BP kernel (messages resident in LDS, persistent slots).
+struct BpArgs {
+    DevGraph g;
+    const float *lam;          // n, prior LLRs (float32)
+    const uint8_t *syn;        // B x m
+    int B;
+    int max_iter;
+    float alpha;
+    int early_exit;
+    int S;                     // shot slots per workgroup
+    int *next_shot;            // queue head (zeroed before launch)
+    uint8_t *corr;             // B x n: hard decision of the last iteration (nullable)
+    float *llr_out;            // B x n: posterior LLRs of every shot (nullable)
+    float *llr_lsd;            // B x n: posterior LLRs of shots that did not converge (nullable)
+    int *lsd_list;             // shots needing LSD (nullable)
+    int *lsd_count;            // length of lsd_list (zeroed before launch)
+    qlsd_shot_info *info;      // B (nullable)
+};
+
+// Arguments of the LSD kernel (one wavefront per shot).
+struct LsdArgs {
+    DevGraph g;
+    const uint8_t *syn;        // B x m
+    const float *llr;          // B x n soft information
+    const int *list;           // shots to decode (nullable: shots 0..count-1)
+    const int *list_count;     // device count when list != nullptr
+    int count;                 // count when list == nullptr
+    int *next_item;            // work counter (zeroed before launch)
+    uint8_t *corr;             // B x n
+    qlsd_shot_info *info;      // B (nullable)
+    int bp_ran;                // info: keep bp_iters written by BP
+    int keys_in_lds;
+    int wave_bytes;            // LDS bytes per wavefront
+};
+
+// LDS carve sizes (bytes) shared by host (launch config) and device.
+size_t bp_lds_bytes(const DevGraph &g, int S);
+size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds);
+
+hipError_t launch_zero(int *p, int count, hipStream_t st);
+hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);
+hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
+
+constexpr int kBpThreads = 256;
+constexpr int kLsdThreads = 256;   // 4 wavefronts, each decodes its own shots
+constexpr int kMaxRowWeight = 32;  // BP register arrays
+constexpr int kMaxColWeight = 16;
+
+}  // namespace qlsd

@@ -1,0 +1,485 @@
+// Localized statistics decoding (LSD-0) on the GPU: one wavefront per shot.
+//
+// What is computed (Hillmann et al., Sec. 4.1 / Alg. 1, Defs. 4.1-4.4, with the synchronous
+// rounds of Appendix B / Alg. 2):
+//   * one cluster per flipped detector;
+//   * per round, every invalid cluster C picks its candidate fault of lowest key (llr_j, j)
+//     among Lambda(C) = N(checks(C)) \ faults(C), all picks made on the round-start state;
+//   * the picked faults join their clusters; clusters that own, or in this round claim, a
+//     common detector of a picked fault merge (Def. 4.4);
+//   * the new columns are reduced on the fly (Sec. 4.2), in ascending key order, and a cluster
+//     is valid once its local syndrome lies in the image of its columns;
+//   * once every cluster is valid, each is solved on its pivot columns and the union is e_hat.
+//
+// MI355X mapping.  A shot's clusters own disjoint detector sets, so the elimination of all its
+// clusters can share one row space: detectors get compact "local rows" in the order they join a
+// cluster, and all reductions happen in a single Gauss-Jordan basis over those rows.  Columns of
+// different clusters never share a row, so this is exactly the block-diagonal form that the
+// paper's merge step (Sec. 4.2, block swap of zero rows) produces -- a merge costs nothing.
+// The basis is bit-sliced across the wavefront: lane l holds local rows l, l+64, ... and, for
+// each, the row's bits over the pivot rows (Mrow) and, for the column that created each pivot,
+// the pivots whose combination contains it (CT).  Reducing a new column, adding a pivot and
+// solving are then per-lane AND/XOR/popcount plus a few ballots -- no cross-lane reductions.
+// Union-find over local rows lives in LDS (lock-free CAS hooking of the larger root under the
+// smaller one); candidate selection is a per-row scan plus an LDS 64-bit atomic min per root.
+#include "qlsd_internal.h"
+
+namespace qlsd {
+
+namespace {
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t lo = __shfl_xor((int)(uint32_t)v, off, 64);
+        const uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), off, 64);
+        const uint64_t o = ((uint64_t)hi << 32) | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+// Order-preserving map of a float32 LLR to uint32 (-0 treated as +0).
+__device__ __forceinline__ uint32_t ordered_key(float x) {
+    uint32_t u = __float_as_uint(x);
+    if (u == 0x80000000u) u = 0u;
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int kFree = 0x7fffffff;
+constexpr uint8_t kValid = 0, kInvalid = 1, kFrozen = 2;
+
+struct LsdLds {
+    uint32_t *keys;    // n (when keys_in_lds)
+    uint64_t *sel;     // K: per-root best candidate key
+    uint64_t *lkey;    // K: selection list keys
+    int32_t *lroot;    // K: selection list roots
+    int32_t *colAt;    // K: column that created the pivot at this local row
+    int32_t *croot;    // K: union-find parent over local rows
+    int32_t *rowOf;    // K: detector of each local row
+    int32_t *loc;      // m: local row of each detector, -1 if unclustered
+    int32_t *claimer;  // m: smallest root claiming an unclustered detector this round
+    uint32_t *incol;   // ceil(n/32): fault already in a cluster
+    uint8_t *state;    // K: kValid / kInvalid / kFrozen (meaningful at roots)
+    int32_t *ctl;      // 4: [0] local row count
+};
+
+__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, size_t *offs) {
+    size_t off = 0;
+    offs[0] = off; off += keys_in_lds ? align8(sizeof(uint32_t) * n) : 0;
+    offs[1] = off; off += sizeof(uint64_t) * K;
+    offs[2] = off; off += sizeof(uint64_t) * K;
+    offs[3] = off; off += sizeof(int32_t) * K;
+    offs[4] = off; off += sizeof(int32_t) * K;
+    offs[5] = off; off += sizeof(int32_t) * K;
+    offs[6] = off; off += sizeof(int32_t) * K;
+    offs[7] = off; off += sizeof(int32_t) * m;
+    offs[8] = off; off += sizeof(int32_t) * m;
+    offs[9] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
+    offs[10] = off; off += align8(K);
+    offs[11] = off; off += sizeof(int32_t) * 4;
+    return align8(off);
+}
+
+__device__ __forceinline__ int find_root(volatile int32_t *par, int x) {
+    int p = par[x];
+    while (p != x) { x = p; p = par[x]; }
+    return x;
+}
+
+__device__ void unite(int32_t *par, int x, int y) {
+    volatile int32_t *vp = par;
+    for (;;) {
+        x = find_root(vp, x);
+        y = find_root(vp, y);
+        if (x == y) return;
+        if (x < y) { const int tmp = x; x = y; y = tmp; }
+        // hook the larger root under the smaller one
+        if (atomicCAS(&par[x], x, y) == x) return;
+    }
+}
+
+template <int W>
+struct Basis {
+    uint64_t Mrow[W][W];  // per lane row s: bits over pivot local rows (rows of the reduced pivot vectors)
+    uint64_t CT[W][W];    // per lane row s (if a pivot row): pivots whose combination uses its column
+    uint64_t piv[W];      // uniform: pivot local rows
+    uint64_t sp[W];       // uniform: reduced syndrome over local rows
+};
+
+template <int W>
+__device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t (&b)[W]) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++) c += __popcll(a[w] & b[w]);
+    return c & 1;
+}
+
+// Adds column g (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
+// it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
+template <int W>
+__device__ bool insert_column(Basis<W> &B, const LsdLds &S, const DevGraph &g, int col, int lane) {
+    const int c0 = g.col_ptr[col], c1 = g.col_ptr[col + 1];
+    uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
+    for (int u = c0; u < c1; u++) {
+        const int lr = S.loc[g.row_idx[u]];
+        if (lr >= 0 && lr < 64 * W && (lr & 63) == lane) bf |= 1u << (lr >> 6);
+    }
+    uint64_t a[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
+    uint32_t bpf = 0;
+#pragma unroll
+    for (int s = 0; s < W; s++) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_and<W>(B.Mrow[s], a)) << s;
+    uint64_t bp[W];
+    int rs = -1;
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        bp[s] = ballot((bpf >> s) & 1u);
+        if (rs < 0 && bp[s]) rs = s;
+    }
+    if (rs < 0) return false;
+    const int rl = __builtin_ctzll(bp[rs]);
+    uint64_t R[W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        uint64_t v = 0;
+#pragma unroll
+        for (int s = 0; s < W; s++)
+            if (s == rs) v = readlane64(B.Mrow[s][w], rl);
+        R[w] = v;
+    }
+    // rows in the reduced column's support: eliminate the new pivot row from the old pivots
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        if ((bpf >> s) & 1u) {
+#pragma unroll
+            for (int w = 0; w < W; w++) B.Mrow[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+        }
+    }
+    // combination tracking
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        const bool is_piv = (B.piv[s] >> lane) & 1ull;
+        if (is_piv && parity_and<W>(B.CT[s], a)) {
+#pragma unroll
+            for (int w = 0; w < W; w++) B.CT[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+        }
+        if (s == rs && lane == rl) {
+#pragma unroll
+            for (int w = 0; w < W; w++) B.CT[s][w] = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
+        }
+    }
+    B.piv[rs] |= 1ull << rl;
+    if (lane == 0) S.colAt[rs * 64 + rl] = col;
+    if ((B.sp[rs] >> rl) & 1ull) {
+#pragma unroll
+        for (int s = 0; s < W; s++) B.sp[s] ^= bp[s];
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
+
+template <int W>
+__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lane) {
+    constexpr int K = 64 * W;
+    const DevGraph &g = A.g;
+    const int m = g.m, n = g.n;
+    const float *llr = A.llr + (size_t)shot * n;
+    const uint8_t *syn = A.syn + (size_t)shot * m;
+    uint8_t *corr = A.corr + (size_t)shot * n;
+
+    bool nan = false;
+    for (int j = lane; j < n; j += 64) {
+        const float v = llr[j];
+        nan |= (v != v);
+        if (A.keys_in_lds) S.keys[j] = ordered_key(v);
+    }
+    for (int w = lane; w < (n + 31) / 32; w += 64) S.incol[w] = 0u;
+    for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
+    for (int j = lane; j < n; j += 64) corr[j] = 0;
+    __threadfence_block();  // the zero stores complete before any later scatter to this row
+    wave_sync();
+
+    uint8_t status = QLSD_ST_LSD_RUN;
+    int rounds = 0;
+    auto finish = [&](uint8_t st, int ncl, int maxc) {
+        if (A.info && lane == 0) {
+            qlsd_shot_info *inf = A.info + shot;
+            inf->status = st;
+            if (!A.bp_ran) inf->bp_iters = 0;
+            inf->n_clusters = (int16_t)ncl;
+            inf->rounds = (int16_t)rounds;
+            inf->max_cluster_cols = maxc;
+        }
+    };
+    if (ballot(nan)) { finish(QLSD_ST_LSD_RUN | QLSD_ST_BAD_LLR, 0, 0); return; }
+
+    // clusters: one per flipped detector, local rows in ascending detector order
+    int nrows = 0;
+    for (int i0 = 0; i0 < m; i0 += 64) {
+        const int i = i0 + lane;
+        const bool f = i < m && (syn[i] & 1);
+        const uint64_t bal = ballot(f);
+        if (f) {
+            const int idx = nrows + __popcll(bal & ((1ull << lane) - 1ull));
+            if (idx < K) {
+                S.loc[i] = idx;
+                S.rowOf[idx] = i;
+                S.croot[idx] = idx;
+                S.state[idx] = kInvalid;
+            }
+        }
+        nrows += __popcll(bal);
+    }
+    if (nrows == 0) { finish(QLSD_ST_LSD_RUN, 0, 0); return; }
+    if (nrows > K) { finish(QLSD_ST_LSD_RUN | QLSD_ST_OVERFLOW, 0, 0); return; }
+    const int nseed = nrows;
+    if (lane == 0) S.ctl[0] = nrows;
+
+    Basis<W> B;
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+#pragma unroll
+        for (int w = 0; w < W; w++) { B.Mrow[s][w] = 0; B.CT[s][w] = 0; }
+        B.piv[s] = 0;
+        const int lo = s * 64;
+        B.sp[s] = nseed >= lo + 64 ? ~0ull : (nseed > lo ? ((1ull << (nseed - lo)) - 1ull) : 0ull);
+    }
+    wave_sync();
+
+    for (;;) {
+        // (1) selection: per invalid root, the candidate of smallest key (round-start state)
+#pragma unroll
+        for (int s = 0; s < W; s++) S.sel[s * 64 + lane] = ~0ull;
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            if (r < nrows) {
+                const int c = S.croot[r];
+                if (S.state[c] == kInvalid) {
+                    const int d = S.rowOf[r];
+                    uint64_t best = ~0ull;
+                    for (int e = g.row_ptr[d]; e < g.row_ptr[d + 1]; e++) {
+                        const int j = g.col_idx[e];
+                        if (in_col(S.incol, j)) continue;
+                        const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
+                        const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)j;
+                        best = key < best ? key : best;
+                    }
+                    if (best != ~0ull) atomicMin((unsigned long long *)&S.sel[c], (unsigned long long)best);
+                }
+            }
+        }
+        wave_sync();
+        // (2) compact list of (root, key); an invalid root with no candidate is frozen (UNSAT)
+        int nsel = 0;
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            bool take = false;
+            uint64_t key = ~0ull;
+            if (r < nrows && S.croot[r] == r && S.state[r] == kInvalid) {
+                key = S.sel[r];
+                if (key == ~0ull) { S.state[r] = kFrozen; status |= QLSD_ST_UNSAT; }
+                else take = true;
+            }
+            const uint64_t bal = ballot(take);
+            if (take) {
+                const int p = nsel + __popcll(bal & ((1ull << lane) - 1ull));
+                S.lkey[p] = key;
+                S.lroot[p] = r;
+            }
+            nsel += __popcll(bal);
+        }
+        if (ballot(status & QLSD_ST_UNSAT)) status |= QLSD_ST_UNSAT;
+        wave_sync();
+        if (nsel == 0) break;
+
+        // (3) claims and unions (Def. 4.4): pairs (selection, detector of its fault)
+        const int cwm = g.max_cw;
+        const int npairs = nsel * cwm;
+        for (int id = lane; id < npairs; id += 64) {
+            const int p = id / cwm, u = id - p * cwm;
+            const int col = (int)(uint32_t)S.lkey[p];
+            const int c0 = g.col_ptr[col];
+            if (u < g.col_ptr[col + 1] - c0) {
+                const int d = g.row_idx[c0 + u];
+                if (S.loc[d] < 0) atomicMin(&S.claimer[d], S.lroot[p]);
+            }
+        }
+        wave_sync();
+        for (int id = lane; id < npairs; id += 64) {
+            const int p = id / cwm, u = id - p * cwm;
+            const int col = (int)(uint32_t)S.lkey[p];
+            const int c0 = g.col_ptr[col];
+            if (u < g.col_ptr[col + 1] - c0) {
+                const int d = g.row_idx[c0 + u];
+                const int c = S.lroot[p];
+                const int cl = S.claimer[d];
+                if (cl != kFree) {
+                    if (cl == c) {
+                        const int idx = atomicAdd(&S.ctl[0], 1);
+                        if (idx < K) {
+                            S.rowOf[idx] = d;
+                            S.croot[idx] = c;
+                            S.state[idx] = kValid;
+                            S.loc[d] = idx;
+                        }
+                    } else {
+                        unite(S.croot, c, cl);
+                    }
+                } else {
+                    unite(S.croot, c, S.croot[S.loc[d]]);
+                }
+            }
+        }
+        wave_sync();
+        const int nrows_new = S.ctl[0];
+        if (nrows_new > K) { finish(status | QLSD_ST_OVERFLOW, 0, 0); for (int j = lane; j < n; j += 64) corr[j] = 0; return; }
+        // flatten the forest; release this round's claims
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            if (r < nrows_new) S.croot[r] = find_root(S.croot, r);
+        }
+        for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
+        nrows = nrows_new;
+        wave_sync();
+
+        // (4) the round's distinct new columns, ascending key, each reduced on the fly
+        uint32_t done = 0;  // bit q: list entry lane + 64 q consumed
+        for (;;) {
+            uint64_t mine = ~0ull;
+            for (int q = 0; q * 64 + lane < nsel; q++)
+                if (!((done >> q) & 1u)) {
+                    const uint64_t k = S.lkey[q * 64 + lane];
+                    mine = k < mine ? k : mine;
+                }
+            const uint64_t kmin = wave_min_u64(mine);
+            if (kmin == ~0ull) break;
+            for (int q = 0; q * 64 + lane < nsel; q++)
+                if (S.lkey[q * 64 + lane] == kmin) done |= 1u << q;
+            const int col = (int)(uint32_t)kmin;
+            if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
+            insert_column<W>(B, S, g, col, lane);
+        }
+        wave_sync();
+
+        // (5) validity: a cluster is valid iff its reduced syndrome vanishes
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            if (r < nrows && S.croot[r] == r && S.state[r] != kFrozen) S.state[r] = kValid;
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            if (r < nrows && ((B.sp[s] >> lane) & 1ull)) {
+                const int c = S.croot[r];
+                if (S.state[c] != kFrozen) S.state[c] = kInvalid;
+            }
+        }
+        wave_sync();
+        rounds++;
+        bool any_invalid = false;
+#pragma unroll
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            any_invalid |= (r < nrows && S.croot[r] == r && S.state[r] == kInvalid);
+        }
+        if (!ballot(any_invalid)) break;
+    }
+
+    // solve: seed rows carry s = 1, claimed rows s = 0; frozen clusters contribute nothing
+    uint64_t as[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        const int r = s * 64 + lane;
+        const bool seed = r < nseed && S.state[S.croot[r]] != kFrozen;
+        as[s] = ballot(seed) & B.piv[s];
+    }
+    int ncl = 0;
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        const int r = s * 64 + lane;
+        const bool is_root = r < nrows && S.croot[r] == r;
+        ncl += __popcll(ballot(is_root));
+        const bool x = ((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as);
+        if (x) corr[S.colAt[r]] = 1;
+    }
+    // faults of frozen clusters stay zero: their pivot rows never enter `as`
+    finish(status, ncl, 0);
+}
+
+template <int W>
+__global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    constexpr int K = 64 * W;
+    unsigned char *base = smem + (size_t)wid * A.wave_bytes;
+    size_t offs[12];
+    lsd_layout(A.g.m, A.g.n, K, A.keys_in_lds != 0, offs);
+    LsdLds S;
+    S.keys = (uint32_t *)(base + offs[0]);
+    S.sel = (uint64_t *)(base + offs[1]);
+    S.lkey = (uint64_t *)(base + offs[2]);
+    S.lroot = (int32_t *)(base + offs[3]);
+    S.colAt = (int32_t *)(base + offs[4]);
+    S.croot = (int32_t *)(base + offs[5]);
+    S.rowOf = (int32_t *)(base + offs[6]);
+    S.loc = (int32_t *)(base + offs[7]);
+    S.claimer = (int32_t *)(base + offs[8]);
+    S.incol = (uint32_t *)(base + offs[9]);
+    S.state = (uint8_t *)(base + offs[10]);
+    S.ctl = (int32_t *)(base + offs[11]);
+
+    const int total = A.list ? *A.list_count : A.count;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(A.next_item, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= total) break;
+        const int shot = A.list ? A.list[item] : item;
+        decode_shot<W>(A, S, shot, lane);
+        wave_sync();
+    }
+}
+
+}  // namespace
+
+size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
+    size_t offs[12];
+    return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
+}
+
+hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st) {
+    const size_t lds = (size_t)a.wave_bytes * (kLsdThreads / 64);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(lsd_kernel<1>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
+        case 2: hipLaunchKernelGGL(lsd_kernel<2>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
+        case 4: hipLaunchKernelGGL(lsd_kernel<4>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace qlsd

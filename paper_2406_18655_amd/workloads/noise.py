@@ -39,13 +39,13 @@ def syndromes(code: CheckMatrix, errors: np.ndarray) -> np.ndarray:
     import scipy.sparse as sp
     Hs = sp.csr_matrix(code.H.astype(np.int32))
     s = (Hs @ errors.T.astype(np.int32)).T
-    return (np.asarray(s) & 1).astype(np.uint8)
+    return np.ascontiguousarray(np.asarray(s) & 1, dtype=np.uint8)
 
 
 def sample(code: CheckMatrix, shots: int, seed: int, start: int = 0):
     """(errors uint8 [shots,n], syndromes uint8 [shots,m])."""
     e = sample_errors(code.priors, shots, seed, start)
-    return e, syndromes(code, e)
+    return e, syndromes(code, e)  # both C-contiguous
 
 
 def logical_failures(code: CheckMatrix, errors: np.ndarray, corrections: np.ndarray) -> np.ndarray:

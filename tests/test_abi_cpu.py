@@ -1,0 +1,75 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol, and
+rejects malformed input on the host before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2406_18655_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    with open(os.path.join(ROOT, "include", "qlsd.h")) as f:
+        txt = f.read()
+    return sorted(set(re.findall(r"\b(qlsd_[a-z_]+)\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2406_18655_amd import build
+        build.build()
+    return binding.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    decl = _declared_symbols()
+    assert set(decl) == set(binding.EXPORTS)
+    for name in decl:
+        assert hasattr(lib, name), name
+
+
+def test_code_create_rejects_bad_csr(lib):
+    h = ctypes.c_void_p()
+    rp = np.array([0, 2, 4], dtype=np.int32)
+    bad_cols = np.array([1, 0, 0, 1], dtype=np.int32)  # row 0 not sorted
+    st = lib.qlsd_code_create(2, 2, 4, rp.ctypes.data, bad_cols.ctypes.data, ctypes.byref(h))
+    assert st == -1 and b"sorted" in lib.qlsd_last_error()
+    out_of_range = np.array([0, 5, 0, 1], dtype=np.int32)
+    st = lib.qlsd_code_create(2, 2, 4, rp.ctypes.data, out_of_range.ctypes.data, ctypes.byref(h))
+    assert st == -1
+    st = lib.qlsd_code_create(0, 2, 0, rp.ctypes.data, None, ctypes.byref(h))
+    assert st == -1
+    bad_ptr = np.array([0, 3, 4], dtype=np.int32)
+    st = lib.qlsd_code_create(2, 2, 3, bad_ptr.ctypes.data, bad_cols.ctypes.data, ctypes.byref(h))
+    assert st == -1
+
+
+def test_null_handles_are_rejected(lib):
+    assert lib.qlsd_decode(None, None, 0, None, None, None) == -1
+    assert lib.qlsd_sync(None) == -1
+    assert lib.qlsd_last_error() != b""
+    lib.qlsd_decoder_destroy(None)
+    lib.qlsd_code_destroy(None)
+
+
+def test_info_layout_matches_header():
+    assert binding.INFO_DTYPE.itemsize == 12
+    assert ctypes.sizeof(binding.QlsdParams) == 20
+
+
+def test_binding_rejects_strided_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(ValueError):
+        binding._ptr(torch.zeros((4, 3), dtype=torch.uint8).t())
+    assert binding._ptr(torch.zeros((4, 3), dtype=torch.uint8)) is not None
+
+
+def test_generated_syndromes_are_row_major():
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, sample
+    e, s = sample(bivariate_bicycle(), 64, seed=1)
+    assert e.flags["C_CONTIGUOUS"] and s.flags["C_CONTIGUOUS"]
