@@ -40,7 +40,7 @@ hipError_t dev_copy(T **dst, const T *src, size_t count) {
     return e;
 }
 
-constexpr size_t kBpLdsBudget = 80 * 1024;  // two BP workgroups per CU
+constexpr size_t kBpLdsBudget = 40 * 1024;  // four BP workgroups per CU
 constexpr int kMaxSlots = 64;
 
 }  // namespace
@@ -58,10 +58,11 @@ struct qlsd_decoder_s {
     int max_batch;
     float *d_lam;
     int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter
-    int *d_list;         // max_batch
+    uint8_t *d_flag;     // max_batch: shot goes from BP to LSD
+    int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
     int bp_slots, bp_grid;
-    int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds;
+    int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds, lsd_graph_in_lds;
     int num_cus;
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
     bool timing;
@@ -94,9 +95,10 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     }
     std::vector<int32_t> col_ptr(n + 1, 0), row_idx(nnz), col_edge(nnz), fill(n, 0);
     for (int64_t e = 0; e < nnz; e++) col_ptr[col_idx[e] + 1]++;
-    int max_cw = 0;
+    int max_cw = 0, min_cw = 1 << 30;
     for (int j = 0; j < n; j++) {
         max_cw = std::max(max_cw, col_ptr[j + 1]);
+        min_cw = std::min(min_cw, col_ptr[j + 1]);
         col_ptr[j + 1] += col_ptr[j];
     }
     for (int i = 0; i < m; i++)
@@ -123,6 +125,8 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     c->g.nnz = (int)nnz;
     c->g.max_rw = max_rw;
     c->g.max_cw = max_cw;
+    c->g.min_rw = min_rw;
+    c->g.min_cw = min_cw;
     c->g.row_ptr = c->d_row_ptr;
     c->g.col_idx = c->d_col_idx;
     c->g.col_ptr = c->d_col_ptr;
@@ -178,23 +182,30 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     d->max_batch = max_batch;
     d->num_cus = prop.multiProcessorCount;
 
-    // BP: shot slots per workgroup under the LDS budget
-    int S = kMaxSlots;
-    while (S > 0 && bp_lds_bytes(g, S) > kBpLdsBudget) S--;
-    if (S < 8 || g.n >= 65535 || g.nnz >= 65535) {
+    // BP: shot slots per workgroup.  Prefer 4 workgroups per CU (40 KB of LDS each) with at
+    // least 12 slots; larger graphs take 2 (80 KB) or 1 (160 KB) workgroup per CU.
+    int S = 0, wg_per_cu = 4;
+    for (wg_per_cu = 4; wg_per_cu >= 1; wg_per_cu /= 2) {
+        const size_t budget = kBpLdsBudget * (4 / wg_per_cu) - (wg_per_cu == 1 ? 1024 : 0);
+        S = kMaxSlots;
+        while (S > 0 && bp_lds_bytes(g, S) > budget) S--;
+        if (S >= 12 || (wg_per_cu == 1 && S >= 4)) break;
+    }
+    if (S < 4 || g.n >= 65535 || g.nnz >= 65535) {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "graph too large for LDS-resident BP (n=%d, nnz=%d)", g.n, g.nnz);
     }
     d->bp_slots = S;
-    d->bp_grid = 2 * d->num_cus;
+    d->bp_grid = std::max(1, wg_per_cu) * d->num_cus;
 
     // LSD: local-row capacity 64*W
     int W = 1;
     while (64 * W < g.m && W < 4) W *= 2;
     d->lsd_W = W;
     d->lsd_keys_in_lds = (size_t)g.n * 4 <= 16384;
+    d->lsd_graph_in_lds = (2 * (size_t)g.nnz + g.m + g.n + 2) * 2 <= 24576 && g.n < 65536 && g.m < 65536;
     d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0);
-    if ((size_t)d->lsd_wave_bytes * (kLsdThreads / 64) > 64 * 1024) {
+    if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0) > 64 * 1024) {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "LSD workspace per wavefront too large");
     }
@@ -210,7 +221,8 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
 
     hipError_t e1 = dev_copy(&d->d_lam, lam.data(), lam.size());
     hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * 8);
-    hipError_t e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
+    hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
+    if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
     hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
     if (e1 || e2 || e3 || e4) {
         qlsd_decoder_destroy(d);
@@ -224,6 +236,7 @@ void qlsd_decoder_destroy(qlsd_decoder d) {
     if (!d) return;
     hipFree(d->d_lam);
     hipFree(d->d_ctl);
+    hipFree(d->d_flag);
     hipFree(d->d_list);
     hipFree(d->d_llr);
     for (int k = 0; k < 3; k++)
@@ -243,7 +256,6 @@ static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
     a.early_exit = (d->params.flags & QLSD_FLAG_NO_EARLY_EXIT) ? 0 : 1;
     a.S = d->bp_slots;
     a.next_shot = d->d_ctl + 0;
-    a.lsd_count = d->d_ctl + 1;
     return a;
 }
 
@@ -263,6 +275,7 @@ static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, ui
     a.corr = corr;
     a.info = info;
     a.keys_in_lds = d->lsd_keys_in_lds;
+    a.graph_in_lds = d->lsd_graph_in_lds;
     a.wave_bytes = d->lsd_wave_bytes;
     return a;
 }
@@ -281,14 +294,15 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     if (st != QLSD_OK || B == 0) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_OK(launch_zero(d->d_ctl, 8, s));
-    if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
     BpArgs a = bp_args(d, syndromes, B);
+    if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
     a.corr = corrections;
     a.llr_lsd = d->d_llr;
-    a.lsd_list = d->d_list;
+    a.lsd_flag = d->d_flag;
     a.info = info;
     HIP_OK(launch_bp(a, bp_grid(d, B), s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
+    HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
     l.list_count = d->d_ctl + 1;

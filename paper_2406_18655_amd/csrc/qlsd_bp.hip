@@ -24,43 +24,56 @@ constexpr float kClamp = 18446744073709551616.0f;  // 2^64
 __device__ __forceinline__ float clampf(float x) { return __builtin_amdgcn_fmed3f(x, -kClamp, kClamp); }
 
 struct BpLds {
+    int SE, SN, PW;  // message and posterior strides per slot (odd: consecutive slots hit distinct
+                     // banks); 32-bit words per slot of the syndrome / parity bit vectors
+    int C;           // shots per queue chunk
     float *msg, *Lv, *lam;
-    int *sshot, *siter, *sbad, *act, *ctl, *retk, *newk;
-    uint16_t *rp, *ci, *cp, *ce;
-    uint8_t *syn;
+    uint32_t *synw, *parw;
+    int *sshot, *siter, *act, *actm, *actl, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
+    uint16_t *rp, *ci, *cp, *ce, *ri;
+    uint8_t *stg;    // 2 chunk buffers of C syndromes (raw bytes)
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline int odd_stride(int x) { return x | 1; }
+
+constexpr int kSlotArrays = 12;  // int arrays of S entries in the slot-state block
+constexpr int kCtl = 16;         // control words
 
 __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S) {
     BpLds L;
+    L.SE = odd_stride(E);
+    L.SN = odd_stride(n);
+    L.PW = (m + 31) / 32;
+    L.C = S;
     size_t off = 0;
-    L.msg = (float *)(base + off); off += sizeof(float) * (size_t)E * S;
-    L.Lv = (float *)(base + off); off += sizeof(float) * (size_t)n * S;
+    L.msg = (float *)(base + off); off += sizeof(float) * (size_t)L.SE * S;
+    L.Lv = (float *)(base + off); off += sizeof(float) * (size_t)L.SN * S;
     L.lam = (float *)(base + off); off += sizeof(float) * n;
-    L.sshot = (int *)(base + off); off += sizeof(int) * S;
-    L.siter = (int *)(base + off); off += sizeof(int) * S;
-    L.sbad = (int *)(base + off); off += sizeof(int) * S;
-    L.act = (int *)(base + off); off += sizeof(int) * S;
-    L.retk = (int *)(base + off); off += sizeof(int) * S;
-    L.newk = (int *)(base + off); off += sizeof(int) * S;
-    L.ctl = (int *)(base + off); off += sizeof(int) * 8;
+    L.synw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
+    L.parw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
+    int *ip = (int *)(base + off);
+    L.sshot = ip; L.siter = ip + S; L.act = ip + 2 * S; L.actm = ip + 3 * S; L.actl = ip + 4 * S;
+    L.newk = ip + 5 * S; L.newq = ip + 6 * S; L.rk = ip + 7 * S; L.rshot = ip + 8 * S; L.rit = ip + 9 * S;
+    L.rconv = ip + 10 * S; L.ctl = ip + 11 * S;
+    off += sizeof(int) * ((size_t)(kSlotArrays - 1) * S + kCtl);
     L.rp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (m + 1);
     L.ci = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
     L.cp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (n + 1);
     L.ce = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
-    L.syn = (uint8_t *)(base + off);
+    L.ri = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
+    L.stg = (uint8_t *)(base + off);
     return L;
 }
 
 // Walks the flattened (row, active-slot) item space of one phase: item = row * A + a.
 struct ItemWalk {
     int row, a, qd, rm, A;
-    __device__ ItemWalk(int t, int NT, int A_) : A(A_) {
+    __device__ ItemWalk(int t, int step, int A_) : A(A_) {
         row = t / A;
         a = t - row * A;
-        qd = NT / A;
-        rm = NT - qd * A;
+        qd = step / A;
+        rm = step - qd * A;
     }
     __device__ __forceinline__ void next() {
         a += rm;
@@ -69,60 +82,284 @@ struct ItemWalk {
     }
 };
 
-template <int MAXRW, int MAXCW>
+// Fault (variable-node) update of fault j in one active slot: posterior, exclusive sums, and
+// the hard decision's contribution to every check's parity.  REG: every column has exactly CW
+// edges (no predication).
+template <int CW, bool REG>
+struct FaultItem {
+    float r[CW];
+    int eid[CW];
+    int c0, cw, j, slot;
+    __device__ __forceinline__ void load(const BpLds &L, int j_, int slot_) {
+        j = j_;
+        slot = slot_;
+        c0 = REG ? j * CW : L.cp[j];
+        cw = REG ? CW : L.cp[j + 1] - c0;
+        const bool fresh = L.siter[L.act[slot]] == 0;
+        const float *mk = L.msg + L.actm[slot];
+#pragma unroll
+        for (int u = 0; u < CW; u++) {
+            if (REG || u < cw) {
+                eid[u] = L.ce[c0 + u];
+                r[u] = fresh ? 0.f : mk[eid[u]];
+            } else {
+                eid[u] = 0;
+                r[u] = 0.f;
+            }
+        }
+    }
+    __device__ __forceinline__ void store(const BpLds &L, bool count_parity) const {
+        float *mk = L.msg + L.actm[slot];
+        const float lam = L.lam[j];
+        float pre[CW + 1];
+        pre[0] = lam;
+#pragma unroll
+        for (int u = 0; u < CW; u++) pre[u + 1] = pre[u] + r[u];
+        float suf = 0.f;
+#pragma unroll
+        for (int u = CW - 1; u >= 0; u--) {
+            if (REG || u < cw) {
+                mk[eid[u]] = clampf(pre[u] + suf);
+                suf += r[u];
+            }
+        }
+        const float Lt = clampf(pre[CW]);  // padding entries add exact zeros
+        L.Lv[L.actl[slot] + j] = Lt;
+        if (count_parity && Lt < 0.f) {
+            uint32_t *pw = L.parw + (size_t)L.act[slot] * L.PW;
+#pragma unroll
+            for (int u = 0; u < CW; u++) {
+                if (REG || u < cw) {
+                    const int i = L.ri[c0 + u];
+                    atomicXor(pw + (i >> 5), 1u << (i & 31));
+                }
+            }
+        }
+    }
+};
+
+// Check update of check i in one active slot (min-sum with the syndrome sign).  REG: every
+// row has exactly RW edges.
+template <int RW, bool REG>
+struct CheckItem {
+    float q[RW];
+    int e0, rw, slot;
+    uint32_t sb;
+    __device__ __forceinline__ void load(const BpLds &L, int i, int slot_) {
+        slot = slot_;
+        e0 = REG ? i * RW : L.rp[i];
+        rw = REG ? RW : L.rp[i + 1] - e0;
+        const float *mk = L.msg + L.actm[slot] + e0;
+        sb = (L.synw[(size_t)L.act[slot] * L.PW + (i >> 5)] >> (i & 31)) & 1u;
+#pragma unroll
+        for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? mk[u] : INFINITY;
+    }
+    __device__ __forceinline__ void store(const BpLds &L, float alpha) const {
+        uint32_t sg = sb << 31;
+        float mn1 = INFINITY, mn2 = INFINITY;
+#pragma unroll
+        for (int u = 0; u < RW; u++) {
+            sg ^= __float_as_uint(q[u]);
+            const float a = fabsf(q[u]);
+            mn2 = __builtin_amdgcn_fmed3f(mn1, mn2, a);
+            mn1 = fminf(mn1, a);
+        }
+        const float m1 = alpha * mn1, m2 = alpha * mn2;
+        float *mk = L.msg + L.actm[slot] + e0;
+#pragma unroll
+        for (int u = 0; u < RW; u++) {
+            if (REG || u < rw) {
+                const float mag = (fabsf(q[u]) == mn1) ? m2 : m1;
+                const uint32_t sgn = (sg ^ __float_as_uint(q[u])) & 0x80000000u;
+                mk[u] = __uint_as_float(__float_as_uint(mag) | sgn);
+            }
+        }
+    }
+};
+
+// Control words (L.ctl): [0] retired, [1] fresh, [2] active this iteration; [3] current
+// staging buffer, [4] cursor into it; [5] request pending; [6] load scheduled (base, -1 none),
+// [7] its count, [8] its buffer; [9] queue exhausted; [10 + 2b] base of staging buffer b
+// (-1 free, -2 drained this iteration, free from the next), [11 + 2b] its shot count.
+template <int MAXRW, int MAXCW, bool REG>
 __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = threadIdx.x, NT = blockDim.x;
+    const int lane = t & 63, wave = t >> 6;
     const int m = args.g.m, n = args.g.n, E = args.g.nnz, S = args.S;
     BpLds L = carve_bp(smem, m, n, E, S);
+    const int C = L.C;
 
     for (int x = t; x <= m; x += NT) L.rp[x] = (uint16_t)args.g.row_ptr[x];
     for (int x = t; x < E; x += NT) L.ci[x] = (uint16_t)args.g.col_idx[x];
     for (int x = t; x <= n; x += NT) L.cp[x] = (uint16_t)args.g.col_ptr[x];
     for (int x = t; x < E; x += NT) L.ce[x] = (uint16_t)args.g.col_edge[x];
+    for (int x = t; x < E; x += NT) L.ri[x] = (uint16_t)args.g.row_idx[x];
     for (int x = t; x < n; x += NT) L.lam[x] = args.lam[x];
-    for (int k = t; k < S; k += NT) { L.sshot[k] = -1; L.siter[k] = 0; L.sbad[k] = 0; }
+    for (int k = t; k < S; k += NT) { L.sshot[k] = -1; L.siter[k] = 0; }
+    for (int x = t; x < S * L.PW; x += NT) { L.parw[x] = 0u; L.synw[x] = 0u; }
+    // first chunk: fetched synchronously into staging buffer 0
+    if (t == 0) {
+        const int b0 = atomicAdd(args.next_shot, C);
+        const int c0 = max(0, min(C, args.B - b0));
+        L.ctl[3] = 0;
+        L.ctl[4] = 0;
+        L.ctl[5] = 0;
+        L.ctl[6] = -1;
+        L.ctl[9] = b0 + C >= args.B;
+        L.ctl[10] = c0 > 0 ? b0 : -1;
+        L.ctl[11] = c0;
+        L.ctl[12] = -1;
+        L.ctl[13] = 0;
+    }
+    __syncthreads();
+    if (L.ctl[10] >= 0) {
+        const int b0 = L.ctl[10], c0 = L.ctl[11];
+        for (int x = t; x < c0 * m; x += NT) L.stg[x] = args.syn[(size_t)b0 * m + x];
+    }
     __syncthreads();
 
     const float alpha = args.alpha;
     const int T = args.max_iter;
+    const int PW = L.PW;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int req = 0;  // wavefront 0, lane 0: result of the queue request issued one iteration earlier
 
     for (;;) {
-        // ---- slot management: retire converged / exhausted shots, collect slots to refill
-        if (t == 0) { L.ctl[0] = 0; L.ctl[1] = 0; }
-        __syncthreads();
-        if (t < S) {
-            const int k = t;
-            bool need = L.sshot[k] < 0;
-            if (!need) {
-                const int it = L.siter[k];
-                const bool conv = it >= 1 && !L.sbad[k];
-                if ((args.early_exit && conv) || it >= T) {
-                    L.retk[atomicAdd(&L.ctl[0], 1)] = k;
-                    need = true;
-                } else {
-                    L.sbad[k] = 0;
+        // ---- slot management (wavefront 0, one lane per slot): test convergence (parity of the
+        // last hard decision against the syndrome), retire converged or exhausted shots, give
+        // free slots the next staged shots, list the active slots, keep the queue pipeline full.
+        if (wave == 0) {
+            const bool valid = lane < S;
+            int shot = valid ? L.sshot[lane] : -1;
+            int it = valid ? L.siter[lane] : 0;
+            const bool active = shot >= 0;
+            bool sat = active;
+            if (active) {
+                for (int w = 0; w < PW; w++) {
+                    sat &= L.parw[lane * PW + w] == L.synw[lane * PW + w];
+                    L.parw[lane * PW + w] = 0u;
                 }
             }
-            if (need) L.newk[atomicAdd(&L.ctl[1], 1)] = k;
+            const bool conv = active && it >= 1 && sat;
+            const bool retire = active && ((args.early_exit && conv) || it >= T);
+            const bool need = valid && (!active || retire);
+            const uint64_t rmask = __ballot(retire);
+            if (retire) {
+                const int p = __popcll(rmask & lt);
+                L.rk[p] = lane;
+                L.rshot[p] = shot;
+                L.rit[p] = it;
+                L.rconv[p] = conv ? 1 : 0;
+            }
+            // staged shots: the rest of the current buffer, then the other buffer if loaded
+            const int cur = L.ctl[3], cursor = L.ctl[4];
+            const int cbase = L.ctl[10 + 2 * cur], ccount = L.ctl[11 + 2 * cur];
+            const int obase = L.ctl[10 + 2 * (1 - cur)], ocount = L.ctl[11 + 2 * (1 - cur)];
+            const int avail0 = cbase >= 0 ? ccount - cursor : 0;
+            const int avail1 = obase >= 0 ? ocount : 0;
+            const uint64_t nmask = __ballot(need);
+            const int r = __popcll(nmask & lt);
+            bool fresh = false;
+            if (need) {
+                if (r < avail0) {
+                    shot = cbase + cursor + r;
+                    fresh = true;
+                    L.newq[r] = cur * C + cursor + r;
+                } else if (r - avail0 < avail1) {
+                    shot = obase + (r - avail0);
+                    fresh = true;
+                    L.newq[r] = (1 - cur) * C + (r - avail0);
+                } else {
+                    shot = -1;
+                }
+                it = 0;
+            } else if (active) {
+                it = it + 1;
+            }
+            if (valid) { L.sshot[lane] = shot; L.siter[lane] = it; }
+            const uint64_t fmask = __ballot(fresh);
+            const int nfresh = __popcll(fmask);
+            if (fresh) L.newk[r] = lane;  // fresh lanes are exactly the first nfresh needing ones
+            const bool on = valid && shot >= 0;
+            const uint64_t amask = __ballot(on);
+            if (on) {
+                const int a = __popcll(amask & lt);
+                L.act[a] = lane;
+                L.actm[a] = lane * L.SE;
+                L.actl[a] = lane * L.SN;
+            }
+            if (lane == 0) {
+                L.ctl[0] = (int)__popcll(rmask);
+                L.ctl[1] = nfresh;
+                L.ctl[2] = (int)__popcll(amask);
+                // buffers drained last iteration are free now
+                for (int bb = 0; bb < 2; bb++)
+                    if (L.ctl[10 + 2 * bb] == -2) L.ctl[10 + 2 * bb] = -1;
+                // advance the cursor; a buffer drained now stays readable for this iteration
+                int ncur = cur, ncursor = cursor;
+                if (nfresh < avail0) {
+                    ncursor = cursor + nfresh;
+                } else if (cbase >= 0) {
+                    L.ctl[10 + 2 * cur] = -2;
+                    L.ctl[11 + 2 * cur] = 0;
+                    if (obase >= 0) {
+                        ncur = 1 - cur;
+                        ncursor = nfresh - avail0;
+                        if (ncursor >= ocount) {
+                            L.ctl[10 + 2 * ncur] = -2;
+                            L.ctl[11 + 2 * ncur] = 0;
+                            ncursor = 0;
+                        }
+                    } else {
+                        ncursor = 0;
+                    }
+                }
+                L.ctl[3] = ncur;
+                L.ctl[4] = ncursor;
+                // a request issued one iteration ago has landed: stage that chunk now
+                L.ctl[6] = -1;
+                if (L.ctl[5]) {
+                    L.ctl[5] = 0;
+                    const int cnt = max(0, min(C, args.B - req));
+                    if (req + C >= args.B) L.ctl[9] = 1;
+                    if (cnt > 0) {
+                        // a free buffer exists: requests are only issued when one is free
+                        const int dst = L.ctl[10 + 2 * ncur] == -1 ? ncur : 1 - ncur;
+                        L.ctl[10 + 2 * dst] = req;
+                        L.ctl[11 + 2 * dst] = cnt;
+                        if (dst == ncur) L.ctl[4] = 0;
+                        L.ctl[6] = req;
+                        L.ctl[7] = cnt;
+                        L.ctl[8] = dst;
+                    }
+                }
+                // keep one request in flight while a buffer is free and shots remain
+                const bool free_buf = L.ctl[10] == -1 || L.ctl[12] == -1;
+                if (!L.ctl[9] && !L.ctl[5] && free_buf) {
+                    req = atomicAdd(args.next_shot, C);
+                    L.ctl[5] = 1;
+                }
+            }
         }
         __syncthreads();
-        if (t == 0) {
-            const int want = L.ctl[1];
-            L.ctl[2] = want ? atomicAdd(args.next_shot, want) : 0;
-        }
-        __syncthreads();
-        const int nret = L.ctl[0], nnew = L.ctl[1], base = L.ctl[2];
+        const int nret = L.ctl[0], nfresh = L.ctl[1], A = L.ctl[2];
+        const int ldb = L.ctl[6], ldc = L.ctl[7], ldbuf = L.ctl[8];
+        const bool pending = L.ctl[5] != 0;
 
-        // ---- outputs of retired shots (coalesced rows)
+        // ---- outputs of retired shots (coalesced rows), staging of the next chunk, and the
+        // syndromes of fresh shots (from staging, packed into bit words by wavefront ballots)
+        if (ldb >= 0) {
+            uint8_t *dst = L.stg + (size_t)ldbuf * C * m;
+            const uint8_t *src = args.syn + (size_t)ldb * m;
+            for (int x = t; x < ldc * m; x += NT) dst[x] = src[x];
+        }
         for (int r = 0; r < nret; r++) {
-            const int k = L.retk[r];
-            const int shot = L.sshot[k];
-            const int it = L.siter[k];
-            const bool conv = it >= 1 && !L.sbad[k];
+            const int k = L.rk[r], shot = L.rshot[r];
+            const bool conv = L.rconv[r] != 0;
             const size_t row = (size_t)shot * n;
             for (int j = t; j < n; j += NT) {
-                const float Lj = L.Lv[j * S + k];
+                const float Lj = L.Lv[k * L.SN + j];
                 if (args.corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
                 if (args.llr_out) args.llr_out[row + j] = Lj;
                 if (!conv && args.llr_lsd) args.llr_lsd[row + j] = Lj;
@@ -132,114 +369,57 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
                     qlsd_shot_info inf;
                     inf.status = conv ? QLSD_ST_BP_CONVERGED : 0;
                     inf.reserved = 0;
-                    inf.bp_iters = (int16_t)it;
+                    inf.bp_iters = (int16_t)L.rit[r];
                     inf.n_clusters = 0;
                     inf.rounds = 0;
                     inf.max_cluster_cols = 0;
                     args.info[shot] = inf;
                 }
-                if (!conv && args.lsd_list) args.lsd_list[atomicAdd(args.lsd_count, 1)] = shot;
+                if (args.lsd_flag) args.lsd_flag[shot] = conv ? 0 : 1;
             }
         }
-        __syncthreads();
-
-        // ---- refill: syndrome in, c->v messages zero (the next fault phase then sets q = lambda)
-        for (int r = 0; r < nnew; r++) {
-            const int k = L.newk[r];
-            const int shot = base + r;
-            const bool valid = shot < args.B;
-            if (t == 0) { L.sshot[k] = valid ? shot : -1; L.siter[k] = -1; L.sbad[k] = 0; }
-            if (valid) {
-                const uint8_t *s = args.syn + (size_t)shot * m;
-                for (int i = t; i < m; i += NT) L.syn[i * S + k] = s[i] & 1;
-                for (int e = t; e < E; e += NT) L.msg[e * S + k] = 0.f;
+        for (int f = wave; f < nfresh; f += NT / 64) {
+            const int k = L.newk[f];
+            const uint8_t *sq = L.stg + (size_t)L.newq[f] * m;
+            for (int i0 = 0; i0 < m; i0 += 64) {
+                const int i = i0 + lane;
+                const uint64_t bits = __ballot(i < m && (sq[i] & 1));
+                if (lane == 0) {
+                    L.synw[k * PW + (i0 >> 5)] = (uint32_t)bits;
+                    if ((i0 >> 5) + 1 < PW) L.synw[k * PW + (i0 >> 5) + 1] = (uint32_t)(bits >> 32);
+                }
             }
         }
+        if (A == 0 && !pending && ldb < 0) break;
         __syncthreads();
-        if (t == 0) {
-            int na = 0;
-            for (int k = 0; k < S; k++)
-                if (L.sshot[k] >= 0) L.act[na++] = k;
-            L.ctl[3] = na;
-        }
-        __syncthreads();
-        const int A = L.ctl[3];
-        if (A == 0) break;
 
-        // ---- fault (variable-node) phase: L = lambda + sum r, q = exclusive sums
+        // ---- fault phase (fresh slots start from q = lambda, i.e. zero incoming messages);
+        // two items per thread in flight: both loads before both stores
         {
-            ItemWalk w(t, NT, A);
-            for (int idx = t; idx < n * A; idx += NT, w.next()) {
-                const int j = w.row, k = L.act[w.a];
-                const int c0 = L.cp[j], cw = L.cp[j + 1] - c0;
-                float r[MAXCW];
-                int eid[MAXCW];
-#pragma unroll
-                for (int u = 0; u < MAXCW; u++) {
-                    if (u < cw) {
-                        eid[u] = L.ce[c0 + u];
-                        r[u] = L.msg[eid[u] * S + k];
-                    }
-                }
-                const float lam = L.lam[j];
-                float pre[MAXCW + 1];
-                pre[0] = lam;
-#pragma unroll
-                for (int u = 0; u < MAXCW; u++) pre[u + 1] = (u < cw) ? pre[u] + r[u] : pre[u];
-                float suf = 0.f;
-#pragma unroll
-                for (int u = MAXCW - 1; u >= 0; u--) {
-                    if (u < cw) {
-                        const float q = (u + 1 < cw) ? pre[u] + suf : pre[u];
-                        L.msg[eid[u] * S + k] = clampf(q);
-                        suf = (u + 1 < cw) ? r[u] + suf : r[u];
-                    }
-                }
-                float Lt = lam;
-#pragma unroll
-                for (int u = 0; u < MAXCW; u++)
-                    if (u < cw) Lt = pre[u + 1];
-                L.Lv[j * S + k] = clampf(Lt);
+            const int total = n * A;
+            ItemWalk w0(t, 2 * NT, A > 0 ? A : 1), w1(t + NT, 2 * NT, A > 0 ? A : 1);
+            for (int idx = t; idx < total; idx += 2 * NT, w0.next(), w1.next()) {
+                const bool hb = idx + NT < total;
+                FaultItem<MAXCW, REG> a, b;
+                a.load(L, w0.row, w0.a);
+                b.load(L, hb ? w1.row : w0.row, hb ? w1.a : w0.a);
+                a.store(L, true);
+                b.store(L, hb);
             }
         }
         __syncthreads();
-        if (t < A) L.siter[L.act[t]] += 1;
-        __syncthreads();
 
-        // ---- check phase: min-sum messages; syndrome test of the current hard decision
+        // ---- check phase: min-sum messages
         {
-            ItemWalk w(t, NT, A);
-            for (int idx = t; idx < m * A; idx += NT, w.next()) {
-                const int i = w.row, k = L.act[w.a];
-                const int e0 = L.rp[i], rw = L.rp[i + 1] - e0;
-                const bool test = L.siter[k] >= 1;
-                const uint32_t sb = L.syn[i * S + k];
-                uint32_t sg = sb << 31;
-                uint32_t hp = 0;
-                float mn1 = INFINITY, mn2 = INFINITY;
-                float q[MAXRW];
-#pragma unroll
-                for (int u = 0; u < MAXRW; u++) {
-                    if (u < rw) {
-                        const int e = e0 + u;
-                        q[u] = L.msg[e * S + k];
-                        sg ^= __float_as_uint(q[u]);
-                        const float a = fabsf(q[u]);
-                        mn2 = __builtin_amdgcn_fmed3f(mn1, mn2, a);
-                        mn1 = fminf(mn1, a);
-                        if (test) hp ^= L.Lv[L.ci[e] * S + k] < 0.f ? 1u : 0u;
-                    }
-                }
-                if (test && hp != sb) L.sbad[k] = 1;
-                const float m1 = alpha * mn1, m2 = alpha * mn2;
-#pragma unroll
-                for (int u = 0; u < MAXRW; u++) {
-                    if (u < rw) {
-                        const float mag = (fabsf(q[u]) == mn1) ? m2 : m1;
-                        const uint32_t sgn = (sg ^ __float_as_uint(q[u])) & 0x80000000u;
-                        L.msg[(e0 + u) * S + k] = __uint_as_float(__float_as_uint(mag) | sgn);
-                    }
-                }
+            const int total = m * A;
+            ItemWalk w0(t, 2 * NT, A > 0 ? A : 1), w1(t + NT, 2 * NT, A > 0 ? A : 1);
+            for (int idx = t; idx < total; idx += 2 * NT, w0.next(), w1.next()) {
+                const bool hb = idx + NT < total;
+                CheckItem<MAXRW, REG> a, b;
+                a.load(L, w0.row, w0.a);
+                b.load(L, hb ? w1.row : w0.row, hb ? w1.a : w0.a);
+                a.store(L, alpha);
+                b.store(L, alpha);  // a duplicate of item a when hb is false: same values, same places
             }
         }
         __syncthreads();
@@ -249,28 +429,33 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
 }  // namespace
 
 size_t bp_lds_bytes(const DevGraph &g, int S) {
+    const size_t PW = ((size_t)g.m + 31) / 32;
     size_t b = 0;
-    b += sizeof(float) * ((size_t)g.nnz * S + (size_t)g.n * S + g.n);
-    b += sizeof(int) * (6 * (size_t)S + 8);
-    b += sizeof(uint16_t) * ((size_t)g.m + 1 + g.nnz + g.n + 1 + g.nnz);
-    b += (size_t)g.m * S;
+    b += sizeof(float) * ((size_t)odd_stride(g.nnz) * S + (size_t)odd_stride(g.n) * S + g.n);
+    b += sizeof(uint32_t) * 2 * PW * S;
+    b += sizeof(int) * ((size_t)(kSlotArrays - 1) * S + kCtl);
+    b += sizeof(uint16_t) * ((size_t)g.m + 1 + g.nnz + g.n + 1 + 2 * (size_t)g.nnz);
+    b += (size_t)2 * S * g.m;  // two staging buffers of S syndromes
     return align16(b);
 }
 
-template <int RW, int CW>
+template <int RW, int CW, bool REG>
 static hipError_t launch_bp_t(const BpArgs &a, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW>,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW, REG>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_lds_kernel<RW, CW>), dim3(grid), dim3(kBpThreads), lds, st, a);
+    hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG>), dim3(grid), dim3(kBpThreads), lds, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
     const size_t lds = bp_lds_bytes(a.g, a.S);
-    if (a.g.max_rw <= 8 && a.g.max_cw <= 4) return launch_bp_t<8, 4>(a, grid, lds, st);
-    if (a.g.max_rw <= 16 && a.g.max_cw <= 8) return launch_bp_t<16, 8>(a, grid, lds, st);
-    return launch_bp_t<kMaxRowWeight, kMaxColWeight>(a, grid, lds, st);
+    const DevGraph &g = a.g;
+    const bool regular = g.min_rw == g.max_rw && g.min_cw == g.max_cw;
+    if (regular && g.max_rw == 6 && g.max_cw == 3) return launch_bp_t<6, 3, true>(a, grid, lds, st);
+    if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false>(a, grid, lds, st);
+    if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false>(a, grid, lds, st);
+    return launch_bp_t<kMaxRowWeight, kMaxColWeight, false>(a, grid, lds, st);
 }
 
 namespace {
@@ -278,7 +463,10 @@ __global__ void zero_kernel(int *p, int count) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0;
 }
+
 }  // namespace
+
+
 
 hipError_t launch_zero(int *p, int count, hipStream_t st) {
     hipLaunchKernelGGL(zero_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, count);

@@ -12,6 +12,7 @@ namespace qlsd {
 struct DevGraph {
     int m, n, nnz;
     int max_rw, max_cw;
+    int min_rw, min_cw;
     const int32_t *row_ptr, *col_idx;   // m+1, nnz
     const int32_t *col_ptr, *row_idx;   // n+1, nnz
     const int32_t *col_edge;            // nnz: CSR edge id of each CSC entry
@@ -31,8 +32,7 @@ struct BpArgs {
     uint8_t *corr;             // B x n: hard decision of the last iteration (nullable)
     float *llr_out;            // B x n: posterior LLRs of every shot (nullable)
     float *llr_lsd;            // B x n: posterior LLRs of shots that did not converge (nullable)
-    int *lsd_list;             // shots needing LSD (nullable)
-    int *lsd_count;            // length of lsd_list (zeroed before launch)
+    uint8_t *lsd_flag;         // B: 1 iff the shot did not converge and goes to LSD (nullable)
     qlsd_shot_info *info;      // B (nullable)
 };
 
@@ -49,16 +49,19 @@ struct LsdArgs {
     qlsd_shot_info *info;      // B (nullable)
     int bp_ran;                // info: keep bp_iters written by BP
     int keys_in_lds;
+    int graph_in_lds;          // H staged as u16 CSR/CSC in LDS once per workgroup
     int wave_bytes;            // LDS bytes per wavefront
 };
 
 // LDS carve sizes (bytes) shared by host (launch config) and device.
 size_t bp_lds_bytes(const DevGraph &g, int S);
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds);
+size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds);
 
 hipError_t launch_zero(int *p, int count, hipStream_t st);
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
+hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
 constexpr int kBpThreads = 256;
 constexpr int kLsdThreads = 256;   // 4 wavefronts, each decodes its own shots

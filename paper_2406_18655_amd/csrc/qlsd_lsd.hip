@@ -22,6 +22,8 @@
 // solving are then per-lane AND/XOR/popcount plus a few ballots -- no cross-lane reductions.
 // Union-find over local rows lives in LDS (lock-free CAS hooking of the larger root under the
 // smaller one); candidate selection is a per-row scan plus an LDS 64-bit atomic min per root.
+#include <type_traits>
+
 #include "qlsd_internal.h"
 
 namespace qlsd {
@@ -58,6 +60,19 @@ __device__ __forceinline__ uint32_t ordered_key(float x) {
     if (u == 0x80000000u) u = 0u;
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
+
+// Read-only view of H used by the LSD kernel: u16 copies in LDS (small codes) or the int32
+// arrays in global memory.
+template <bool InLds>
+struct GView {
+    using T = typename std::conditional<InLds, uint16_t, int32_t>::type;
+    const T *rp, *ci, *cp, *ri;
+    int max_cw;
+    __device__ __forceinline__ int row_ptr(int i) const { return rp[i]; }
+    __device__ __forceinline__ int col_idx(int e) const { return ci[e]; }
+    __device__ __forceinline__ int col_ptr(int j) const { return cp[j]; }
+    __device__ __forceinline__ int row_idx(int e) const { return ri[e]; }
+};
 
 constexpr int kFree = 0x7fffffff;
 constexpr uint8_t kValid = 0, kInvalid = 1, kFrozen = 2;
@@ -96,6 +111,10 @@ __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_l
     return align8(off);
 }
 
+__host__ __device__ inline size_t lsd_graph_bytes(int m, int n, int nnz) {
+    return align8(sizeof(uint16_t) * ((size_t)m + 1 + nnz + n + 1 + nnz));
+}
+
 __device__ __forceinline__ int find_root(volatile int32_t *par, int x) {
     int p = par[x];
     while (p != x) { x = p; p = par[x]; }
@@ -132,12 +151,12 @@ __device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t
 
 // Adds column g (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
-template <int W>
-__device__ bool insert_column(Basis<W> &B, const LsdLds &S, const DevGraph &g, int col, int lane) {
-    const int c0 = g.col_ptr[col], c1 = g.col_ptr[col + 1];
+template <int W, class G>
+__device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col, int lane) {
+    const int c0 = g.col_ptr(col), c1 = g.col_ptr(col + 1);
     uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
     for (int u = c0; u < c1; u++) {
-        const int lr = S.loc[g.row_idx[u]];
+        const int lr = S.loc[g.row_idx(u)];
         if (lr >= 0 && lr < 64 * W && (lr & 63) == lane) bf |= 1u << (lr >> 6);
     }
     uint64_t a[W];
@@ -196,11 +215,10 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, const DevGraph &g, i
 
 __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
 
-template <int W>
-__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lane) {
+template <int W, class G>
+__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane) {
     constexpr int K = 64 * W;
-    const DevGraph &g = A.g;
-    const int m = g.m, n = g.n;
+    const int m = A.g.m, n = A.g.n;
     const float *llr = A.llr + (size_t)shot * n;
     const uint8_t *syn = A.syn + (size_t)shot * m;
     uint8_t *corr = A.corr + (size_t)shot * n;
@@ -277,8 +295,9 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lan
                 if (S.state[c] == kInvalid) {
                     const int d = S.rowOf[r];
                     uint64_t best = ~0ull;
-                    for (int e = g.row_ptr[d]; e < g.row_ptr[d + 1]; e++) {
-                        const int j = g.col_idx[e];
+                    const int e1 = g.row_ptr(d + 1);
+                    for (int e = g.row_ptr(d); e < e1; e++) {
+                        const int j = g.col_idx(e);
                         if (in_col(S.incol, j)) continue;
                         const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
                         const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)j;
@@ -319,9 +338,9 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lan
         for (int id = lane; id < npairs; id += 64) {
             const int p = id / cwm, u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr[col];
-            if (u < g.col_ptr[col + 1] - c0) {
-                const int d = g.row_idx[c0 + u];
+            const int c0 = g.col_ptr(col);
+            if (u < g.col_ptr(col + 1) - c0) {
+                const int d = g.row_idx(c0 + u);
                 if (S.loc[d] < 0) atomicMin(&S.claimer[d], S.lroot[p]);
             }
         }
@@ -329,9 +348,9 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lan
         for (int id = lane; id < npairs; id += 64) {
             const int p = id / cwm, u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr[col];
-            if (u < g.col_ptr[col + 1] - c0) {
-                const int d = g.row_idx[c0 + u];
+            const int c0 = g.col_ptr(col);
+            if (u < g.col_ptr(col + 1) - c0) {
+                const int d = g.row_idx(c0 + u);
                 const int c = S.lroot[p];
                 const int cl = S.claimer[d];
                 if (cl != kFree) {
@@ -430,14 +449,31 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, int shot, int lan
     finish(status, ncl, 0);
 }
 
-template <int W>
+template <int W, bool GL>
 __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int K = 64 * W;
-    unsigned char *base = smem + (size_t)wid * A.wave_bytes;
+    const int m = A.g.m, n = A.g.n, E = A.g.nnz;
+    GView<GL> g;
+    g.max_cw = A.g.max_cw;
+    size_t gbytes = 0;
+    if constexpr (GL) {
+        uint16_t *t16 = (uint16_t *)smem;
+        uint16_t *rp = t16, *ci = rp + (m + 1), *cp = ci + E, *ri = cp + (n + 1);
+        for (int x = threadIdx.x; x <= m; x += blockDim.x) rp[x] = (uint16_t)A.g.row_ptr[x];
+        for (int x = threadIdx.x; x < E; x += blockDim.x) ci[x] = (uint16_t)A.g.col_idx[x];
+        for (int x = threadIdx.x; x <= n; x += blockDim.x) cp[x] = (uint16_t)A.g.col_ptr[x];
+        for (int x = threadIdx.x; x < E; x += blockDim.x) ri[x] = (uint16_t)A.g.row_idx[x];
+        g.rp = rp; g.ci = ci; g.cp = cp; g.ri = ri;
+        gbytes = lsd_graph_bytes(m, n, E);
+        __syncthreads();
+    } else {
+        g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
+    }
+    unsigned char *base = smem + gbytes + (size_t)wid * A.wave_bytes;
     size_t offs[12];
-    lsd_layout(A.g.m, A.g.n, K, A.keys_in_lds != 0, offs);
+    lsd_layout(m, n, K, A.keys_in_lds != 0, offs);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
     S.sel = (uint64_t *)(base + offs[1]);
@@ -459,27 +495,65 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
         const int shot = A.list ? A.list[item] : item;
-        decode_shot<W>(A, S, shot, lane);
+        decode_shot<W>(A, S, g, shot, lane);
         wave_sync();
     }
 }
 
+template <int W>
+hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
+    const size_t lds = (a.graph_in_lds ? lsd_graph_bytes(a.g.m, a.g.n, a.g.nnz) : 0) +
+                       (size_t)a.wave_bytes * (kLsdThreads / 64);
+    if (a.graph_in_lds) {
+        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((lsd_kernel<W, true>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((lsd_kernel<W, false>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+// Shots flagged by BP -> a dense list (one 64-shot ballot and one atomic per wavefront).
+__global__ void compact_kernel(const uint8_t *flag, int B, int *list, int *count) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool f = b < B && flag[b];
+    const uint64_t bal = __ballot(f);
+    int base = 0;
+    if (lane == 0 && bal) base = atomicAdd(count, (int)__popcll(bal));
+    base = __shfl(base, 0, 64);
+    if (f) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+}
+
 }  // namespace
+
+hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st) {
+    hipLaunchKernelGGL(compact_kernel, dim3((B + 255) / 256), dim3(256), 0, st, flag, B, list, count);
+    return hipGetLastError();
+}
 
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
     size_t offs[12];
     return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
 }
 
+size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds) {
+    return (graph_in_lds ? lsd_graph_bytes(g.m, g.n, g.nnz) : 0) +
+           lsd_wave_bytes(g, W, keys_in_lds) * (kLsdThreads / 64);
+}
+
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st) {
-    const size_t lds = (size_t)a.wave_bytes * (kLsdThreads / 64);
     switch (W) {
-        case 1: hipLaunchKernelGGL(lsd_kernel<1>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
-        case 2: hipLaunchKernelGGL(lsd_kernel<2>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
-        case 4: hipLaunchKernelGGL(lsd_kernel<4>, dim3(grid), dim3(kLsdThreads), lds, st, a); break;
+        case 1: return launch_lsd_w<1>(a, grid, st);
+        case 2: return launch_lsd_w<2>(a, grid, st);
+        case 4: return launch_lsd_w<4>(a, grid, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace qlsd

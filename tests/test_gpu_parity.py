@@ -246,3 +246,4 @@ def test_edge_cases(oracle_mod):
     with pytest.raises(binding.QlsdError) as ex:
         binding.Decoder(bc, bad, 16)
     assert ex.value.status == -2
+
