@@ -120,11 +120,13 @@ def bp(code: Code, lam: np.ndarray, s: np.ndarray, max_iter: int, alpha: float =
 
 def lsd(code: Code, s: np.ndarray, llr: np.ndarray, mu: int = 0, omega: np.ndarray | None = None,
         force_merge: bool = False):
-    """One shot of LSD-mu on soft information llr -> (corr uint8[n], status, stats[4])."""
+    """One shot of LSD-mu on soft information llr -> (corr uint8[n], status, stats[6]):
+    stats = clusters, largest cluster's columns, rounds, clustered columns, clustered checks,
+    largest cluster's checks."""
     s = np.ascontiguousarray(s, dtype=np.uint8)
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     corr = np.empty(code.n, dtype=np.uint8)
-    stats = np.zeros(4, dtype=np.int32)
+    stats = np.zeros(6, dtype=np.int32)
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.int64)
     st = lib().oracle_lsd(code._h, _p(s), _p(llr), int(mu), None if om is None else _p(om),
                           int(force_merge), _p(corr), _p(stats))

@@ -472,8 +472,9 @@ static int lsd_round(const ocode *c, cluster_t *cl, int ncl, int *owner, int *in
 
 /*
  * LSD (order mu) on soft information llr.  corr (n bytes) receives e_hat.
- * stats (nullable, 4 ints): final cluster count, largest cluster column count,
- * growth rounds, total clustered columns.  Returns status bits.
+ * stats (nullable, 6 ints): final cluster count, largest cluster column count,
+ * growth rounds, total clustered columns, total clustered checks, largest cluster
+ * check count.  Returns status bits.
  * force_merge != 0 puts every check into one cluster that may grow by any column:
  * the result is then global OSD-0.
  */
@@ -482,7 +483,7 @@ int oracle_lsd(const void *code, const uint8_t *s, const double *llr, int mu, co
     const ocode *c = (const ocode *)code;
     uint32_t status = 0;
     memset(corr, 0, c->n);
-    if (stats) memset(stats, 0, sizeof(int32_t) * 4);
+    if (stats) memset(stats, 0, sizeof(int32_t) * 6);
     for (int j = 0; j < c->n; j++)
         if (isnan(llr[j])) return (int)ST_BAD_LLR;
 
@@ -536,16 +537,21 @@ int oracle_lsd(const void *code, const uint8_t *s, const double *llr, int mu, co
             rounds++;
         }
         /* step 6: local solutions, united into one correction */
-        int nalive = 0, maxc = 0, tot = 0;
+        int nalive = 0, maxc = 0, tot = 0, totr = 0, maxr = 0;
         for (int a = 0; a < ncl; a++) {
             if (!cl[a].alive) continue;
             nalive++;
             tot += cl[a].ncols;
+            totr += cl[a].nrows;
             if (cl[a].ncols > maxc) maxc = cl[a].ncols;
+            if (cl[a].nrows > maxr) maxr = cl[a].nrows;
             if (cl[a].frozen) continue;
             cluster_solve(c, &cl[a], s, llr, force_merge ? 0 : mu, omega, rowpos, corr);
         }
-        if (stats) { stats[0] = nalive; stats[1] = maxc; stats[2] = rounds; stats[3] = tot; }
+        if (stats) {
+            stats[0] = nalive; stats[1] = maxc; stats[2] = rounds; stats[3] = tot;
+            stats[4] = totr; stats[5] = maxr;
+        }
         free(sel); free(dsu);
     }
 done:

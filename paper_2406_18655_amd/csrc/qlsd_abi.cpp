@@ -42,6 +42,7 @@ hipError_t dev_copy(T **dst, const T *src, size_t count) {
 
 constexpr size_t kBpLdsBudget = 40 * 1024;  // four BP workgroups per CU
 constexpr int kMaxSlots = 64;
+constexpr size_t kLdsPerCu = 160 * 1024;
 
 }  // namespace
 
@@ -57,11 +58,13 @@ struct qlsd_decoder_s {
     qlsd_params params;
     int max_batch;
     float *d_lam;
+    int64_t *d_omega;
     int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter
     uint8_t *d_flag;     // max_batch: shot goes from BP to LSD
     int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
     int bp_slots, bp_grid;
+    bool bp_graph;       // one workgroup per shot (large graphs) instead of S slots per workgroup
     int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds, lsd_graph_in_lds;
     int num_cus;
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
@@ -156,7 +159,8 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     if (max_batch < 1) return fail(QLSD_E_BATCH, "max_batch must be >= 1");
     if (params->max_iter < 1 || params->max_iter > 30000) return fail(QLSD_E_INVALID, "max_iter out of range");
     if (!(params->ms_scaling > 0.f && params->ms_scaling <= 1.f)) return fail(QLSD_E_INVALID, "ms_scaling must be in (0,1]");
-    if (params->lsd_order != 0) return fail(QLSD_E_UNSUPPORTED, "lsd_order > 0 is not built yet");
+    if (params->lsd_order < 0 || params->lsd_order > 12)
+        return fail(QLSD_E_UNSUPPORTED, "lsd_order must be in [0, 12]");
     if (params->osd_method != 0) return fail(QLSD_E_UNSUPPORTED, "only osd_method 0 (exhaustive)");
     const DevGraph &g = code->g;
     if (code->min_rw < 2) return fail(QLSD_E_INVALID, "BP needs every row weight >= 2");
@@ -164,10 +168,13 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         return fail(QLSD_E_UNSUPPORTED, "row weight %d / column weight %d beyond %d / %d", g.max_rw, g.max_cw,
                     kMaxRowWeight, kMaxColWeight);
     std::vector<float> lam(g.n);
+    std::vector<int64_t> omega(g.n);
     for (int j = 0; j < g.n; j++) {
         const double p = priors[j];
         if (!(p > 0.0 && p < 1.0)) return fail(QLSD_E_PRIOR, "prior %d = %g not in (0,1)", j, p);
-        lam[j] = (float)log((1.0 - p) / p);
+        const double l = log((1.0 - p) / p);
+        lam[j] = (float)l;
+        omega[j] = (int64_t)llround(ldexp(l, 20));  // integer weight of the order-mu search
     }
     int dev = 0;
     HIP_OK(hipGetDevice(&dev));
@@ -191,21 +198,29 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         while (S > 0 && bp_lds_bytes(g, S) > budget) S--;
         if (S >= 12 || (wg_per_cu == 1 && S >= 4)) break;
     }
-    if (S < 4 || g.n >= 65535 || g.nnz >= 65535) {
+    if (S >= 4 && g.n < 65535 && g.nnz < 65535) {
+        d->bp_graph = false;
+        d->bp_slots = S;
+        d->bp_grid = std::max(1, wg_per_cu) * d->num_cus;
+    } else if (bp_graph_lds_bytes(g) <= kLdsPerCu - 1024) {
+        // one workgroup per shot with the shot's messages in LDS
+        d->bp_graph = true;
+        d->bp_slots = 1;
+        d->bp_grid = d->num_cus;
+    } else {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "graph too large for LDS-resident BP (n=%d, nnz=%d)", g.n, g.nnz);
     }
-    d->bp_slots = S;
-    d->bp_grid = std::max(1, wg_per_cu) * d->num_cus;
 
     // LSD: local-row capacity 64*W
     int W = 1;
     while (64 * W < g.m && W < 4) W *= 2;
+    if (params->lsd_order > 0) W = 4;  // extra growth steps: room for 256 clustered checks
     d->lsd_W = W;
     d->lsd_keys_in_lds = (size_t)g.n * 4 <= 16384;
     d->lsd_graph_in_lds = (2 * (size_t)g.nnz + g.m + g.n + 2) * 2 <= 24576 && g.n < 65536 && g.m < 65536;
     d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0);
-    if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0) > 64 * 1024) {
+    if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0) > kLdsPerCu - 1024) {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "LSD workspace per wavefront too large");
     }
@@ -220,6 +235,7 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
             }
 
     hipError_t e1 = dev_copy(&d->d_lam, lam.data(), lam.size());
+    if (e1 == hipSuccess) e1 = dev_copy(&d->d_omega, omega.data(), omega.size());
     hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * 8);
     hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
     if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
@@ -235,6 +251,7 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
 void qlsd_decoder_destroy(qlsd_decoder d) {
     if (!d) return;
     hipFree(d->d_lam);
+    hipFree(d->d_omega);
     hipFree(d->d_ctl);
     hipFree(d->d_flag);
     hipFree(d->d_list);
@@ -264,6 +281,10 @@ static int bp_grid(qlsd_decoder d, int B) {
     return std::max(1, std::min(d->bp_grid, need));
 }
 
+static hipError_t run_bp(qlsd_decoder d, const BpArgs &a, int B, hipStream_t s) {
+    return d->bp_graph ? launch_bp_graph(a, bp_grid(d, B), s) : launch_bp(a, bp_grid(d, B), s);
+}
+
 static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, uint8_t *corr,
                         qlsd_shot_info *info) {
     LsdArgs a;
@@ -276,6 +297,8 @@ static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, ui
     a.info = info;
     a.keys_in_lds = d->lsd_keys_in_lds;
     a.graph_in_lds = d->lsd_graph_in_lds;
+    a.mu = d->params.lsd_order;
+    a.omega = d->d_omega;
     a.wave_bytes = d->lsd_wave_bytes;
     return a;
 }
@@ -300,7 +323,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     a.llr_lsd = d->d_llr;
     a.lsd_flag = d->d_flag;
     a.info = info;
-    HIP_OK(launch_bp(a, bp_grid(d, B), s));
+    HIP_OK(run_bp(d, a, B, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
     HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
@@ -322,7 +345,7 @@ qlsd_status qlsd_bp(qlsd_decoder d, const uint8_t *syndromes, int32_t B, float *
     a.corr = hard_out;
     a.llr_out = llr_out;
     a.info = info;
-    HIP_OK(launch_bp(a, bp_grid(d, B), s));
+    HIP_OK(run_bp(d, a, B, s));
     return QLSD_OK;
 }
 

@@ -426,6 +426,151 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
     }
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Large graphs (e.g. a 936 x 8800 detector error model): one workgroup per shot.  The shot's
+// messages (one float per edge) and posteriors live in LDS; H is read from global memory
+// (it is shared by every workgroup and stays in L2).  Threads run over faults in the fault
+// phase and over checks in the check phase; the syndrome test is the same XOR-parity scheme.
+// ------------------------------------------------------------------------------------------
+template <int MAXRW, int MAXCW>
+__global__ __launch_bounds__(kBpGraphThreads) void bp_graph_kernel(BpArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = threadIdx.x, NT = blockDim.x;
+    const int m = args.g.m, n = args.g.n, E = args.g.nnz;
+    const int PW = (m + 31) / 32;
+    float *msg = (float *)smem;
+    float *Lv = msg + E;
+    uint32_t *synw = (uint32_t *)(Lv + n);
+    uint32_t *parw = synw + PW;
+    int *ctl = (int *)(parw + PW);
+    const int32_t *row_ptr = args.g.row_ptr, *col_ptr = args.g.col_ptr;
+    const int32_t *col_edge = args.g.col_edge, *row_idx = args.g.row_idx;
+    const float alpha = args.alpha;
+    const int T = args.max_iter;
+    const int lane = t & 63, wave = t >> 6;
+
+    for (;;) {
+        if (t == 0) ctl[0] = atomicAdd(args.next_shot, 1);
+        __syncthreads();
+        const int shot = ctl[0];
+        if (shot >= args.B) break;
+        const uint8_t *syn = args.syn + (size_t)shot * m;
+        for (int i0 = wave * 64; i0 < m; i0 += NT) {
+            const int i = i0 + lane;
+            const uint64_t bits = __ballot(i < m && (syn[i] & 1));
+            if (lane == 0) {
+                synw[i0 >> 5] = (uint32_t)bits;
+                if ((i0 >> 5) + 1 < PW) synw[(i0 >> 5) + 1] = (uint32_t)(bits >> 32);
+            }
+        }
+        for (int w = t; w < PW; w += NT) parw[w] = 0u;
+        for (int e = t; e < E; e += NT) msg[e] = 0.f;  // r = 0: the first fault phase sets q = lambda
+        __syncthreads();
+        int it = 0;
+        bool conv = false;
+        for (;;) {
+            // fault phase
+            for (int j = t; j < n; j += NT) {
+                const int c0 = col_ptr[j], cw = col_ptr[j + 1] - c0;
+                float r[MAXCW];
+                int eid[MAXCW];
+#pragma unroll
+                for (int u = 0; u < MAXCW; u++) {
+                    eid[u] = u < cw ? col_edge[c0 + u] : 0;
+                    r[u] = u < cw ? msg[eid[u]] : 0.f;
+                }
+                const float lam = args.lam[j];
+                float pre[MAXCW + 1];
+                pre[0] = lam;
+#pragma unroll
+                for (int u = 0; u < MAXCW; u++) pre[u + 1] = pre[u] + r[u];
+                float suf = 0.f;
+#pragma unroll
+                for (int u = MAXCW - 1; u >= 0; u--) {
+                    if (u < cw) {
+                        msg[eid[u]] = clampf(pre[u] + suf);
+                        suf += r[u];
+                    }
+                }
+                const float Lt = clampf(pre[MAXCW]);
+                Lv[j] = Lt;
+                if (Lt < 0.f) {
+                    for (int u = 0; u < cw; u++) {
+                        const int i = row_idx[c0 + u];
+                        atomicXor(parw + (i >> 5), 1u << (i & 31));
+                    }
+                }
+            }
+            __syncthreads();
+            // syndrome test of the hard decision after iteration it (it >= 1)
+            if (wave == 0) {
+                bool ok = true;
+                for (int w = lane; w < PW; w += 64) {
+                    ok &= parw[w] == synw[w];
+                    parw[w] = 0u;
+                }
+                const bool all = __ballot(!ok) == 0;
+                if (lane == 0) ctl[1] = all ? 1 : 0;
+            }
+            __syncthreads();
+            const bool sat = ctl[1] != 0;
+            conv = it >= 1 && sat;
+            if ((args.early_exit && conv) || it >= T) break;
+            it++;
+            // check phase
+            for (int i = t; i < m; i += NT) {
+                const int e0 = row_ptr[i], rw = row_ptr[i + 1] - e0;
+                const uint32_t sb = (synw[i >> 5] >> (i & 31)) & 1u;
+                float q[MAXRW];
+#pragma unroll
+                for (int u = 0; u < MAXRW; u++) q[u] = u < rw ? msg[e0 + u] : INFINITY;
+                uint32_t sg = sb << 31;
+                float mn1 = INFINITY, mn2 = INFINITY;
+#pragma unroll
+                for (int u = 0; u < MAXRW; u++) {
+                    sg ^= __float_as_uint(q[u]);
+                    const float a = fabsf(q[u]);
+                    mn2 = __builtin_amdgcn_fmed3f(mn1, mn2, a);
+                    mn1 = fminf(mn1, a);
+                }
+                const float m1 = alpha * mn1, m2 = alpha * mn2;
+#pragma unroll
+                for (int u = 0; u < MAXRW; u++) {
+                    if (u < rw) {
+                        const float mag = (fabsf(q[u]) == mn1) ? m2 : m1;
+                        const uint32_t sgn = (sg ^ __float_as_uint(q[u])) & 0x80000000u;
+                        msg[e0 + u] = __uint_as_float(__float_as_uint(mag) | sgn);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // outputs
+        const size_t row = (size_t)shot * n;
+        for (int j = t; j < n; j += NT) {
+            const float Lj = Lv[j];
+            if (args.corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
+            if (args.llr_out) args.llr_out[row + j] = Lj;
+            if (!conv && args.llr_lsd) args.llr_lsd[row + j] = Lj;
+        }
+        if (t == 0) {
+            if (args.info) {
+                qlsd_shot_info inf;
+                inf.status = conv ? QLSD_ST_BP_CONVERGED : 0;
+                inf.reserved = 0;
+                inf.bp_iters = (int16_t)it;
+                inf.n_clusters = 0;
+                inf.rounds = 0;
+                inf.max_cluster_cols = 0;
+                args.info[shot] = inf;
+            }
+            if (args.lsd_flag) args.lsd_flag[shot] = conv ? 0 : 1;
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 size_t bp_lds_bytes(const DevGraph &g, int S) {
@@ -446,6 +591,27 @@ static hipError_t launch_bp_t(const BpArgs &a, int grid, size_t lds, hipStream_t
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG>), dim3(grid), dim3(kBpThreads), lds, st, a);
     return hipGetLastError();
+}
+
+size_t bp_graph_lds_bytes(const DevGraph &g) {
+    const size_t PW = ((size_t)g.m + 31) / 32;
+    return align16(sizeof(float) * ((size_t)g.nnz + g.n) + sizeof(uint32_t) * 2 * PW + sizeof(int) * 4);
+}
+
+template <int RW, int CW>
+static hipError_t launch_bp_graph_t(const BpArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)bp_graph_kernel<RW, CW>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bp_graph_kernel<RW, CW>), dim3(grid), dim3(kBpGraphThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
+    const size_t lds = bp_graph_lds_bytes(a.g);
+    if (a.g.max_rw <= 8 && a.g.max_cw <= 4) return launch_bp_graph_t<8, 4>(a, grid, lds, st);
+    if (a.g.max_rw <= 16 && a.g.max_cw <= 8) return launch_bp_graph_t<16, 8>(a, grid, lds, st);
+    return launch_bp_graph_t<kMaxRowWeight, kMaxColWeight>(a, grid, lds, st);
 }
 
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {

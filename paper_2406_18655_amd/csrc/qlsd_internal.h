@@ -50,20 +50,25 @@ struct LsdArgs {
     int bp_ran;                // info: keep bp_iters written by BP
     int keys_in_lds;
     int graph_in_lds;          // H staged as u16 CSR/CSC in LDS once per workgroup
+    int mu;                    // LSD order (0 = LSD-0)
+    const int64_t *omega;      // n: integer fault weights for the order-mu search (mu > 0)
     int wave_bytes;            // LDS bytes per wavefront
 };
 
 // LDS carve sizes (bytes) shared by host (launch config) and device.
 size_t bp_lds_bytes(const DevGraph &g, int S);
+size_t bp_graph_lds_bytes(const DevGraph &g);
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds);
 size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds);
 
 hipError_t launch_zero(int *p, int count, hipStream_t st);
-hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);
+hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);        // S slots per workgroup
+hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st);  // one workgroup per shot
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
 constexpr int kBpThreads = 256;
+constexpr int kBpGraphThreads = 1024;
 constexpr int kLsdThreads = 256;   // 4 wavefronts, each decodes its own shots
 constexpr int kMaxRowWeight = 32;  // BP register arrays
 constexpr int kMaxColWeight = 16;

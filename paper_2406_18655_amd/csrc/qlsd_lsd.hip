@@ -75,6 +75,7 @@ struct GView {
 };
 
 constexpr int kFree = 0x7fffffff;
+constexpr int kMaxMu = 12;  // largest supported order mu (2^mu patterns per cluster)
 constexpr uint8_t kValid = 0, kInvalid = 1, kFrozen = 2;
 
 struct LsdLds {
@@ -90,6 +91,11 @@ struct LsdLds {
     uint32_t *incol;   // ceil(n/32): fault already in a cluster
     uint8_t *state;    // K: kValid / kInvalid / kFrozen (meaningful at roots)
     int32_t *ctl;      // 4: [0] local row count
+    int32_t *colNP;    // K: clustered columns that were dependent when added (LSD-mu)
+    int64_t *wq;       // K: integer weight of the column that created each pivot (LSD-mu)
+    uint64_t *zk;      // kMaxMu * W: solution change of each reprocessed column (LSD-mu)
+    int32_t *tsel;     // kMaxMu: reprocessed columns of the current cluster (LSD-mu)
+    int64_t *tw;       // kMaxMu: their weights
 };
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
@@ -108,6 +114,11 @@ __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_l
     offs[9] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
     offs[10] = off; off += align8(K);
     offs[11] = off; off += sizeof(int32_t) * 4;
+    offs[12] = off; off += sizeof(int32_t) * K;
+    offs[13] = off; off += sizeof(int64_t) * K;
+    offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);
+    offs[15] = off; off += sizeof(int32_t) * kMaxMu;
+    offs[16] = off; off += sizeof(int64_t) * kMaxMu;
     return align8(off);
 }
 
@@ -215,6 +226,129 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col,
 
 __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
 
+
+// Local exhaustive reprocessing of order w (Appendix D) for every cluster that is not frozen.
+// T = the cluster's dependent columns in ascending key, T_w its first w = min(mu, |T|).  Every
+// pattern t over T_w fixes x_T = t and the pivot part x_P = x0 + sum_{k in t} z_k, where z_k is
+// the pivot combination of column T_k (every T_k lies in the span of the pivots).  The cost is
+// the integer weight of the set columns; the strictly smallest cost wins, the smaller t on ties.
+// Patterns are spread over the lanes.
+template <int W, class G>
+__device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const Basis<W> &B,
+                               const uint64_t (&x0)[W], int nrows, int npc, const float *llr,
+                               uint8_t *corr, int lane) {
+    constexpr int K = 64 * W;
+    const int mu = A.mu < kMaxMu ? A.mu : kMaxMu;
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        const int r = s * 64 + lane;
+        if ((B.piv[s] >> lane) & 1ull) S.wq[r] = A.omega[S.colAt[r]];
+    }
+    uint64_t roots[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        const int r = s * 64 + lane;
+        roots[s] = ballot(r < nrows && S.croot[r] == r && S.state[r] != kFrozen);
+    }
+    wave_sync();
+    const int nnp = npc < K ? npc : K;
+    for (int s0 = 0; s0 < W; s0++) {
+        while (roots[s0]) {
+            const int c = s0 * 64 + __builtin_ctzll(roots[s0]);
+            roots[s0] &= roots[s0] - 1;
+            uint64_t inC[W];
+#pragma unroll
+            for (int s = 0; s < W; s++) {
+                const int r = s * 64 + lane;
+                inC[s] = ballot(r < nrows && S.croot[r] == c);
+            }
+            // T_w: the cluster's dependent columns of smallest key
+            uint32_t chosen = 0;  // bit u: entry lane + 64 u taken
+            int w = 0;
+            for (; w < mu; w++) {
+                uint64_t mine = ~0ull;
+                for (int u = 0; u * 64 + lane < nnp; u++) {
+                    if ((chosen >> u) & 1u) continue;
+                    const int col = S.colNP[u * 64 + lane];
+                    const int rr = S.loc[g.row_idx(g.col_ptr(col))];
+                    if (S.croot[rr] != c) continue;
+                    const uint32_t kj = A.keys_in_lds ? S.keys[col] : ordered_key(llr[col]);
+                    const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)col;
+                    mine = key < mine ? key : mine;
+                }
+                const uint64_t kmin = wave_min_u64(mine);
+                if (kmin == ~0ull) break;
+                const int col = (int)(uint32_t)kmin;
+                for (int u = 0; u * 64 + lane < nnp; u++)
+                    if (S.colNP[u * 64 + lane] == col) chosen |= 1u << u;
+                // z_w: pivot rows of this cluster whose combination reproduces column col
+                uint32_t bf = 0;
+                for (int e = g.col_ptr(col); e < g.col_ptr(col + 1); e++) {
+                    const int lr = S.loc[g.row_idx(e)];
+                    if (lr >= 0 && lr < K && (lr & 63) == lane) bf |= 1u << (lr >> 6);
+                }
+                uint64_t a[W];
+#pragma unroll
+                for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
+#pragma unroll
+                for (int s = 0; s < W; s++) {
+                    const uint64_t z = ballot(((B.piv[s] & inC[s]) >> lane) & 1ull && parity_and<W>(B.CT[s], a));
+                    if (lane == 0) S.zk[w * W + s] = z;
+                }
+                if (lane == 0) {
+                    S.tsel[w] = col;
+                    S.tw[w] = A.omega[col];
+                }
+            }
+            wave_sync();
+            // search the 2^w patterns
+            uint64_t xc[W];
+#pragma unroll
+            for (int s = 0; s < W; s++) xc[s] = x0[s] & inC[s];
+            const int npat = 1 << w;
+            uint64_t best = ~0ull;
+            for (int pt = lane; pt < npat; pt += 64) {
+                uint64_t x[W];
+                int64_t cost = 0;
+#pragma unroll
+                for (int s = 0; s < W; s++) x[s] = xc[s];
+                for (int k = 0; k < w; k++) {
+                    if ((pt >> k) & 1) {
+                        cost += S.tw[k];
+#pragma unroll
+                        for (int s = 0; s < W; s++) x[s] ^= S.zk[k * W + s];
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < W; s++) {
+                    uint64_t v = x[s];
+                    while (v) {
+                        cost += S.wq[s * 64 + __builtin_ctzll(v)];
+                        v &= v - 1;
+                    }
+                }
+                const uint64_t key = ((uint64_t)(cost + (1ll << 50)) << 12) | (uint64_t)pt;
+                best = key < best ? key : best;
+            }
+            const int tb = (int)(wave_min_u64(best) & 4095ull);
+            uint64_t x[W];
+#pragma unroll
+            for (int s = 0; s < W; s++) x[s] = xc[s];
+            for (int k = 0; k < w; k++) {
+                if ((tb >> k) & 1) {
+#pragma unroll
+                    for (int s = 0; s < W; s++) x[s] ^= S.zk[k * W + s];
+                    if (lane == 0) corr[S.tsel[k]] = 1;
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < W; s++)
+                if ((x[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
+            wave_sync();
+        }
+    }
+}
+
 template <int W, class G>
 __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane) {
     constexpr int K = 64 * W;
@@ -282,8 +416,13 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     }
     wave_sync();
 
+    // LSD-0 rounds grow the invalid clusters until none is left; LSD-mu then runs mu more
+    // rounds in which every cluster that is not frozen grows (Appendix D).
+    bool grow_all = false;
+    int mu_left = 0;
+    int npc = 0;  // dependent columns recorded in colNP
     for (;;) {
-        // (1) selection: per invalid root, the candidate of smallest key (round-start state)
+        // (1) selection: per growing root, the candidate of smallest key (round-start state)
 #pragma unroll
         for (int s = 0; s < W; s++) S.sel[s * 64 + lane] = ~0ull;
         wave_sync();
@@ -292,7 +431,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const int r = s * 64 + lane;
             if (r < nrows) {
                 const int c = S.croot[r];
-                if (S.state[c] == kInvalid) {
+                if (grow_all ? S.state[c] != kFrozen : S.state[c] == kInvalid) {
                     const int d = S.rowOf[r];
                     uint64_t best = ~0ull;
                     const int e1 = g.row_ptr(d + 1);
@@ -315,10 +454,10 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const int r = s * 64 + lane;
             bool take = false;
             uint64_t key = ~0ull;
-            if (r < nrows && S.croot[r] == r && S.state[r] == kInvalid) {
+            if (r < nrows && S.croot[r] == r && (grow_all ? S.state[r] != kFrozen : S.state[r] == kInvalid)) {
                 key = S.sel[r];
-                if (key == ~0ull) { S.state[r] = kFrozen; status |= QLSD_ST_UNSAT; }
-                else take = true;
+                if (key != ~0ull) take = true;
+                else if (S.state[r] == kInvalid) { S.state[r] = kFrozen; status |= QLSD_ST_UNSAT; }
             }
             const uint64_t bal = ballot(take);
             if (take) {
@@ -330,7 +469,14 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         if (ballot(status & QLSD_ST_UNSAT)) status |= QLSD_ST_UNSAT;
         wave_sync();
-        if (nsel == 0) break;
+        if (nsel == 0) {
+            if (!grow_all && A.mu > 0) {  // every invalid cluster is frozen; valid ones may still grow
+                grow_all = true;
+                mu_left = A.mu;
+                continue;
+            }
+            break;
+        }
 
         // (3) claims and unions (Def. 4.4): pairs (selection, detector of its fault)
         const int cwm = g.max_cw;
@@ -398,7 +544,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 if (S.lkey[q * 64 + lane] == kmin) done |= 1u << q;
             const int col = (int)(uint32_t)kmin;
             if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
-            insert_column<W>(B, S, g, col, lane);
+            const bool pivot = insert_column<W>(B, S, g, col, lane);
+            if (!pivot && A.mu > 0) {
+                if (lane == 0 && npc < K) S.colNP[npc] = col;
+                npc++;
+            }
         }
         wave_sync();
 
@@ -419,13 +569,26 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         wave_sync();
         rounds++;
+        if (grow_all) {
+            if (--mu_left == 0) break;
+            continue;
+        }
         bool any_invalid = false;
 #pragma unroll
         for (int s = 0; s < W; s++) {
             const int r = s * 64 + lane;
             any_invalid |= (r < nrows && S.croot[r] == r && S.state[r] == kInvalid);
         }
-        if (!ballot(any_invalid)) break;
+        if (!ballot(any_invalid)) {
+            if (A.mu <= 0) break;
+            grow_all = true;
+            mu_left = A.mu;
+        }
+    }
+    if (npc > K) {
+        finish(status | QLSD_ST_OVERFLOW, 0, 0);
+        for (int j = lane; j < n; j += 64) corr[j] = 0;
+        return;
     }
 
     // solve: seed rows carry s = 1, claimed rows s = 0; frozen clusters contribute nothing
@@ -437,15 +600,23 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         as[s] = ballot(seed) & B.piv[s];
     }
     int ncl = 0;
+    uint64_t x0[W];  // LSD-0 solution: pivot rows whose column is set
 #pragma unroll
     for (int s = 0; s < W; s++) {
         const int r = s * 64 + lane;
         const bool is_root = r < nrows && S.croot[r] == r;
         ncl += __popcll(ballot(is_root));
-        const bool x = ((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as);
-        if (x) corr[S.colAt[r]] = 1;
+        x0[s] = ballot(((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as));
     }
-    // faults of frozen clusters stay zero: their pivot rows never enter `as`
+    if (A.mu <= 0) {
+#pragma unroll
+        for (int s = 0; s < W; s++)
+            if ((x0[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
+        // faults of frozen clusters stay zero: their pivot rows never enter `as`
+        finish(status, ncl, 0);
+        return;
+    }
+    osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, corr, lane);
     finish(status, ncl, 0);
 }
 
@@ -472,7 +643,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
     }
     unsigned char *base = smem + gbytes + (size_t)wid * A.wave_bytes;
-    size_t offs[12];
+    size_t offs[17];
     lsd_layout(m, n, K, A.keys_in_lds != 0, offs);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
@@ -487,6 +658,11 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
     S.incol = (uint32_t *)(base + offs[9]);
     S.state = (uint8_t *)(base + offs[10]);
     S.ctl = (int32_t *)(base + offs[11]);
+    S.colNP = (int32_t *)(base + offs[12]);
+    S.wq = (int64_t *)(base + offs[13]);
+    S.zk = (uint64_t *)(base + offs[14]);
+    S.tsel = (int32_t *)(base + offs[15]);
+    S.tw = (int64_t *)(base + offs[16]);
 
     const int total = A.list ? *A.list_count : A.count;
     for (;;) {
@@ -538,7 +714,7 @@ hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hip
 }
 
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
-    size_t offs[12];
+    size_t offs[17];
     return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
 }
 

@@ -1,0 +1,105 @@
+"""GPU parity on the synthetic circuit-level-shaped detector error model (936 x 8800,
+log-uniform priors): one-workgroup-per-shot BP and LSD of order mu (Appendix D)."""
+import numpy as np
+import pytest
+
+from paper_2406_18655_amd import binding
+from paper_2406_18655_amd.workloads import synthetic_dem, bivariate_bicycle, sample
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+@pytest.fixture(scope="module")
+def dem():
+    return synthetic_dem()
+
+
+def _dec(code, T, B, mu=0, flags=0):
+    bc = binding.Code.from_dense(code.H)
+    return bc, binding.Decoder(bc, code.priors, B, max_iter=T, lsd_order=mu, flags=flags)
+
+
+@pytest.mark.parametrize("T", [3, 40])
+def test_dem_bp_posteriors(oracle_mod, dem, T):
+    print(f"case dem_bp T={T}", flush=True)
+    e, S = sample(dem, 12, seed=5)
+    _, dec = _dec(dem, T, 12, flags=binding.FLAG_NO_EARLY_EXIT)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    L32 = llr.cpu().numpy().astype(np.float64)
+    oc = oracle_mod.Code.from_dense(dem.H)
+    lam = oracle_mod.llr_from_priors(dem.priors)
+    floor = np.abs(lam).min()
+    for b in range(12):
+        conv, it, L64, h64 = oracle_mod.bp(oc, lam, S[b], T, early_exit=False)
+        err = np.abs(L32[b] - L64) / np.maximum(np.abs(L64), floor)
+        assert err.max() <= 1e-4, (b, float(err.max()))
+
+
+@pytest.mark.parametrize("mu", [0, 10])
+def test_dem_lsd_mu_bit_exact(oracle_mod, dem, mu):
+    print(f"case dem_lsd mu={mu}", flush=True)
+    e, S = sample(dem, 600, seed=8)
+    _, dec = _dec(dem, 100, 600, mu=mu)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    inf = binding.parse_info(info)
+    idx = np.nonzero((inf["status"] & 1) == 0)[0][:60]
+    assert len(idx) >= 30
+    L = llr.cpu().numpy()[idx]
+    corr, linfo = dec.lsd(torch.from_numpy(S[idx]).cuda(), torch.from_numpy(L).cuda())
+    torch.cuda.synchronize()
+    corr = corr.cpu().numpy()
+    li = binding.parse_info(linfo)
+    oc = oracle_mod.Code.from_dense(dem.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(dem.priors))
+    for k, b in enumerate(idx):
+        want, st, stats = oracle_mod.lsd(oc, S[b], L[k].astype(np.float64), mu=mu, omega=om)
+        assert not (li["status"][k] & binding.ST_OVERFLOW), k
+        assert (corr[k] == want).all(), (k, mu)
+        assert li["rounds"][k] == stats[2] and li["n_clusters"][k] == stats[0], k
+
+
+def test_dem_decode_word_error_within_2sigma(oracle_mod, dem):
+    print("case dem_decode", flush=True)
+    B = 3000
+    e, S = sample(dem, B, seed=77)
+    _, dec = _dec(dem, 100, B, mu=10)
+    corr, info = dec.decode(torch.from_numpy(S).cuda(), want_info=True)
+    torch.cuda.synchronize()
+    corr = corr.cpu().numpy()
+    assert (((corr.astype(np.int64) @ dem.H.T.astype(np.int64)) % 2) == S).all()
+    oc = oracle_mod.Code.from_dense(dem.H)
+    lam = oracle_mod.llr_from_priors(dem.priors)
+    om = oracle_mod.omega_from_llr(lam)
+    ocorr, ost, oit, _ = oracle_mod.decode_batch(oc, lam, S, 100, mu=10, omega=om)
+    f_gpu = (corr != e).any(1)
+    f_ref = (ocorr != e).any(1)
+    p = max(f_ref.mean(), 1.0 / B)
+    two_sigma = 2 * np.sqrt(p * (1 - p) / B)
+    print(f"word error gpu={f_gpu.mean():.4f} oracle={f_ref.mean():.4f} 2sigma={two_sigma:.4f}")
+    assert abs(f_gpu.mean() - f_ref.mean()) <= two_sigma
+
+
+def test_bb_lsd_mu_bit_exact(oracle_mod):
+    code = bivariate_bicycle(p=0.06)
+    e, S = sample(code, 400, seed=19)
+    _, dec = _dec(code, 30, 400, mu=4)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    L = llr.cpu().numpy()
+    corr, li = dec.lsd(torch.from_numpy(S).cuda(), llr)
+    torch.cuda.synchronize()
+    corr = corr.cpu().numpy()
+    oc = oracle_mod.Code.from_dense(code.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(code.priors))
+    for b in range(400):
+        want, st, stats = oracle_mod.lsd(oc, S[b], L[b].astype(np.float64), mu=4, omega=om)
+        assert (corr[b] == want).all(), b
