@@ -40,6 +40,10 @@ def parse():
     ap.add_argument("--seed", type=int, default=20240626)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="streaming mode: Poisson arrivals over a mix of codes; one JSON line per rate")
+    ap.add_argument("--serve-rates", default="1e5,1e6,1e7")
+    ap.add_argument("--serve-requests", type=int, default=200000)
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "bp_traffic_bb144.json"),
                     help="HBM bytes per BP launch measured with rocprofv3 counters, if present")
     return ap.parse_args()
@@ -193,5 +197,62 @@ def cpu_baseline(code, errors, S, args):
     return base, ler_ref
 
 
+def serve_main(args):
+    """Continuous-batching service over HGP(3,4) n=16/24/32, the BB code and the synthetic DEM
+    (uniform mix), Poisson arrivals at each rate; latency = completion - arrival per request."""
+    import torch
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, random_34_hgp, synthetic_dem, sample
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    mix = [("hgp34_n16", random_34_hgp(16, p=0.03), 30, 0, 4096),
+           ("hgp34_n24", random_34_hgp(24, p=0.03), 30, 0, 2048),
+           ("hgp34_n32", random_34_hgp(32, p=0.03), 30, 0, 1024),
+           ("bb144", bivariate_bicycle(p=0.05), 50, 0, 4096),
+           ("dem936x8800", synthetic_dem(), 100, 10, 512)]
+    per_code = args.serve_requests // len(mix)
+    pools = []
+    for k, (name, code, T, mu, bs) in enumerate(mix):
+        e, S = sample(code, per_code, seed=args.seed + 100 + k)
+        pools.append(S)
+    for rate in [float(x) for x in args.serve_rates.split(",")]:
+        rng = np.random.default_rng(args.seed)
+        srv = binding.Server(64 << 30)
+        outs, cids = [], []
+        for k, (name, code, T, mu, bs) in enumerate(mix):
+            cid, lanes = srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=bs, max_lanes=3,
+                                      max_iter=T, lsd_order=mu)
+            arr = np.cumsum(rng.exponential(1e6 / (rate / len(mix)), size=per_code))
+            out = np.zeros((per_code, code.n), dtype=np.uint8)
+            srv.submit_many(cid, pools[k], out, np.arange(per_code, dtype=np.uint64), arr)
+            outs.append(out)
+            cids.append(cid)
+        total = per_code * len(mix)
+        srv.start()
+        srv.wait(total, timeout_s=600)
+        comp = srv.completions()
+        srv.close()
+        lat = comp["done_us"] - comp["arrival_us"]
+        span_s = (comp["done_us"].max() - comp["arrival_us"].min()) * 1e-6
+        codes = {}
+        for k, (name, *_r) in enumerate(mix):
+            sel = comp["code_id"] == cids[k]
+            codes[name] = {"p50_us": round(float(np.percentile(lat[sel], 50)), 1),
+                           "p99_us": round(float(np.percentile(lat[sel], 99)), 1),
+                           "mean_batch": round(float(comp["batch_size"][sel].mean()), 1)}
+        print(json.dumps({"metric": "streaming decode latency over a mixed-code Poisson load",
+                          "offered_shots_per_s": rate, "requests": int(total),
+                          "throughput_shots_per_s": round(total / span_s, 1),
+                          "p50_us": round(float(np.percentile(lat, 50)), 1),
+                          "p99_us": round(float(np.percentile(lat, 99)), 1),
+                          "per_code": codes, "ordering": "plain BP+LSD",
+                          "latency_includes": "host staging, PCIe copies, scheduler polling"}), flush=True)
+
+
 if __name__ == "__main__":
-    main()
+    _a = parse()
+    if _a.serve:
+        serve_main(_a)
+    else:
+        main()

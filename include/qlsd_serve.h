@@ -1,0 +1,86 @@
+/*
+ * qlsd_serve.h -- continuous-batching decode service over several codes (part of libqlsd.so).
+ *
+ * A server owns, per registered code, a few "lanes": each lane is a decoder (qlsd_decoder with
+ * max_batch = batch_shots), its own HIP stream, pinned host staging and device buffers for one
+ * batch.  Lanes are the unit of admission: a code gets as many lanes as fit in the server's
+ * device-memory budget (at least one, else registration fails with QLSD_E_NOMEM).  A scheduler
+ * thread forms a batch for a lane as soon as the lane is free, from whatever requests of that
+ * code have arrived (FIFO, up to batch_shots) -- requests that arrive while other batches run
+ * wait in host memory and are admitted as lanes free up; nothing is dropped.  Batches of
+ * different codes (and of different lanes of one code) overlap on the device.  Every decode is
+ * the BP + LSD of qlsd_decode (include/qlsd.h), so a request's correction does not depend on
+ * which other requests shared its batch.
+ *
+ * Arrival times make open-loop load tests possible without a host thread per request: a
+ * submitted request becomes visible to the scheduler only once the server clock (microseconds
+ * since qlsd_server_start) reaches its arrival time.  Latency = completion - arrival.
+ *
+ * Host buffers passed to qlsd_server_submit* are caller-owned and must stay valid until the
+ * request's completion has been reported.  Functions return qlsd_status; qlsd_last_error()
+ * describes failures.  A server handle may be used from one caller thread at a time (the
+ * scheduler thread is internal).
+ */
+#ifndef QLSD_SERVE_H
+#define QLSD_SERVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qlsd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qlsd_server_s *qlsd_server;
+
+typedef struct {
+    uint64_t tag;        /* caller's request id */
+    int32_t code_id;     /* as returned by qlsd_server_add_code */
+    uint8_t status;      /* QLSD_ST_* bits of the shot */
+    uint8_t reserved[3];
+    double arrival_us;   /* server clock */
+    double done_us;      /* server clock when the scheduler saw the batch finish */
+    int32_t batch_size;  /* shots in the batch that carried this request */
+    int32_t reserved2;
+} qlsd_completion;       /* 40 bytes */
+
+/* device_budget_bytes: device memory the lanes of all codes may use (decoder workspace plus
+ * one batch of buffers per lane). */
+qlsd_status qlsd_server_create(size_t device_budget_bytes, qlsd_server *out);
+
+/* Registers a code with decoder parameters and priors (host, n doubles).  Creates up to
+ * max_lanes lanes, each decoding batches of at most batch_shots shots, as far as the budget
+ * allows.  *code_id receives the code's id; *lanes_out (nullable) the lanes created. */
+qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_params *params,
+                                 const double *priors, int32_t batch_shots, int32_t max_lanes,
+                                 int32_t *code_id, int32_t *lanes_out);
+
+/* Queues count requests of one code: syndromes host u8[count*m], corrections_out host
+ * u8[count*n] (written on completion), tags[count], arrival_us[count] (server clock; NULL =
+ * all arrive immediately).  Arrival times of one code must be non-decreasing. */
+qlsd_status qlsd_server_submit_many(qlsd_server s, int32_t code_id, int32_t count,
+                                    const uint8_t *syndromes, uint8_t *corrections_out,
+                                    const uint64_t *tags, const double *arrival_us);
+
+/* Starts the scheduler thread; the server clock starts at 0 here. */
+qlsd_status qlsd_server_start(qlsd_server s);
+
+/* Blocks until at least `count` requests have completed in total, or timeout_s elapses
+ * (QLSD_E_DEVICE then, with a message).  Device failures are reported here too. */
+qlsd_status qlsd_server_wait(qlsd_server s, int64_t count, double timeout_s);
+
+/* Moves up to max completion records (oldest first) into out; *n_out receives how many. */
+qlsd_status qlsd_server_completions(qlsd_server s, qlsd_completion *out, int32_t max, int32_t *n_out);
+
+/* Current server clock in microseconds (0 before start). */
+double qlsd_server_now_us(qlsd_server s);
+
+/* Stops the scheduler after the in-flight batches finish and frees every lane. */
+void qlsd_server_destroy(qlsd_server s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QLSD_SERVE_H */

@@ -209,3 +209,100 @@ def parse_info(info) -> np.ndarray:
     """uint8 tensor/array [B, 12] -> structured numpy array with INFO_DTYPE fields."""
     a = info.cpu().numpy() if hasattr(info, "cpu") else np.asarray(info)
     return np.ascontiguousarray(a).view(INFO_DTYPE).reshape(-1)
+
+
+# --------------------------------------------------------------------------- serving
+SERVE_EXPORTS = ["qlsd_server_create", "qlsd_server_add_code", "qlsd_server_submit_many",
+                 "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions",
+                 "qlsd_server_now_us", "qlsd_server_destroy"]
+
+COMPLETION_DTYPE = np.dtype([("tag", np.uint64), ("code_id", np.int32), ("status", np.uint8),
+                             ("r0", np.uint8, 3), ("arrival_us", np.float64), ("done_us", np.float64),
+                             ("batch_size", np.int32), ("r1", np.int32)])
+assert COMPLETION_DTYPE.itemsize == 40
+
+
+def _serve_lib():
+    L = lib()
+    if not getattr(L, "_serve_ready", False):
+        P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        L.qlsd_server_create.argtypes = [ctypes.c_size_t, ctypes.POINTER(P)]
+        L.qlsd_server_add_code.argtypes = [P, P, ctypes.POINTER(QlsdParams), P, I32, I32,
+                                           ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.qlsd_server_submit_many.argtypes = [P, I32, I32, P, P, P, P]
+        L.qlsd_server_start.argtypes = [P]
+        L.qlsd_server_wait.argtypes = [P, I64, D]
+        L.qlsd_server_completions.argtypes = [P, P, I32, ctypes.POINTER(I32)]
+        L.qlsd_server_now_us.argtypes = [P]
+        L.qlsd_server_now_us.restype = D
+        L.qlsd_server_destroy.argtypes = [P]
+        for fn in ("qlsd_server_create", "qlsd_server_add_code", "qlsd_server_submit_many",
+                   "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions"):
+            getattr(L, fn).restype = ctypes.c_int
+        L._serve_ready = True
+    return L
+
+
+class Server:
+    """Continuous-batching decode service over several codes (include/qlsd_serve.h).
+
+    Requests are numpy host arrays; the server keeps references until it is closed."""
+
+    def __init__(self, device_budget_bytes: int):
+        L = _serve_lib()
+        h = ctypes.c_void_p()
+        _check(L.qlsd_server_create(int(device_budget_bytes), ctypes.byref(h)))
+        self._h = h
+        self._keep = []
+        self.codes = {}
+
+    def add_code(self, code: "Code", priors: np.ndarray, batch_shots: int, max_lanes: int = 2,
+                 max_iter: int = 30, ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0):
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags))
+        cid, lanes = ctypes.c_int32(), ctypes.c_int32()
+        _check(_serve_lib().qlsd_server_add_code(self._h, code._h, ctypes.byref(params), pri.ctypes.data,
+                                                 int(batch_shots), int(max_lanes), ctypes.byref(cid),
+                                                 ctypes.byref(lanes)))
+        self.codes[cid.value] = (code.m, code.n)
+        self._keep.append(code)
+        return cid.value, lanes.value
+
+    def submit_many(self, code_id: int, syndromes: np.ndarray, outputs: np.ndarray, tags: np.ndarray,
+                    arrival_us: Optional[np.ndarray] = None):
+        m, n = self.codes[code_id]
+        S = np.ascontiguousarray(syndromes, dtype=np.uint8)
+        if S.ndim != 2 or S.shape[1] != m or outputs.shape != (S.shape[0], n) or outputs.dtype != np.uint8 \
+                or not outputs.flags["C_CONTIGUOUS"]:
+            raise ValueError("syndromes [N, m] and contiguous uint8 outputs [N, n] expected")
+        tg = np.ascontiguousarray(tags, dtype=np.uint64)
+        ar = None if arrival_us is None else np.ascontiguousarray(arrival_us, dtype=np.float64)
+        self._keep += [S, outputs, tg, ar]
+        _check(_serve_lib().qlsd_server_submit_many(self._h, int(code_id), S.shape[0], S.ctypes.data,
+                                                    outputs.ctypes.data, tg.ctypes.data,
+                                                    None if ar is None else ar.ctypes.data))
+
+    def start(self):
+        _check(_serve_lib().qlsd_server_start(self._h))
+
+    def wait(self, count: int, timeout_s: float = 120.0):
+        _check(_serve_lib().qlsd_server_wait(self._h, int(count), float(timeout_s)))
+
+    def completions(self, max_records: int = 1 << 22) -> np.ndarray:
+        out = np.empty(max_records, dtype=COMPLETION_DTYPE)
+        k = ctypes.c_int32()
+        _check(_serve_lib().qlsd_server_completions(self._h, out.ctypes.data, int(max_records), ctypes.byref(k)))
+        return out[:k.value].copy()
+
+    def now_us(self) -> float:
+        return float(_serve_lib().qlsd_server_now_us(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _serve_lib().qlsd_server_destroy(self._h)
+            self._h = None
+        self._keep = []
+
+    def __del__(self):
+        if _lib is not None:
+            self.close()

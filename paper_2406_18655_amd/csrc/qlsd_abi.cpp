@@ -71,6 +71,21 @@ struct qlsd_decoder_s {
     bool timing;
 };
 
+namespace qlsd {
+void set_last_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+int code_rows(qlsd_code c) { return c->g.m; }
+int code_cols(qlsd_code c) { return c->g.n; }
+size_t decoder_device_bytes(qlsd_decoder d) {
+    const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
+    return n * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float));
+}
+}  // namespace qlsd
+
 extern "C" {
 
 const char *qlsd_last_error(void) { return g_err; }

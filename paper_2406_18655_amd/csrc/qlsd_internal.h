@@ -67,6 +67,12 @@ hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st);  // one w
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
+// Host helpers shared by the ABI files.
+void set_last_error(const char *fmt, ...);
+int code_rows(qlsd_code c);
+int code_cols(qlsd_code c);
+size_t decoder_device_bytes(qlsd_decoder d);  // workspace allocated by qlsd_decoder_create
+
 constexpr int kBpThreads = 256;
 constexpr int kBpGraphThreads = 1024;
 constexpr int kLsdThreads = 256;   // 4 wavefronts, each decodes its own shots

@@ -1,0 +1,288 @@
+// Continuous-batching decode service (include/qlsd_serve.h): lanes of decoders on their own
+// streams, a scheduler thread that forms batches from arrived requests whenever a lane is free,
+// and per-request latency bookkeeping.  All decoding runs through qlsd_decode.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/qlsd_serve.h"
+#include "qlsd_internal.h"
+
+namespace {
+
+struct Request {
+    const uint8_t *syn;
+    uint8_t *out;
+    uint64_t tag;
+    double arrival_us;
+};
+
+struct Lane {
+    qlsd_decoder dec = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    uint8_t *d_syn = nullptr, *d_corr = nullptr, *d_info = nullptr;
+    uint8_t *h_syn = nullptr, *h_corr = nullptr, *h_info = nullptr;
+    bool busy = false;
+    std::vector<Request> batch;
+};
+
+struct Code {
+    int m = 0, n = 0, batch_shots = 0;
+    std::vector<Lane> lanes;
+    std::deque<Request> pending;  // arrival order
+};
+
+}  // namespace
+
+struct qlsd_server_s {
+    size_t budget = 0, used = 0;
+    std::vector<Code *> codes;
+    std::mutex mu;                      // pending queues and completions
+    std::condition_variable cv;
+    std::vector<qlsd_completion> done;  // not yet drained by the caller
+    int64_t completed = 0;
+    std::atomic<bool> stop{false}, started{false};
+    std::thread worker;
+    std::chrono::steady_clock::time_point epoch;
+    char error[256] = "";
+};
+
+namespace {
+
+double now_us(const qlsd_server_s *s) {
+    if (!s->started.load()) return 0.0;
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - s->epoch).count();
+}
+
+void free_lane(Lane &l) {
+    if (l.stream) hipStreamSynchronize(l.stream);
+    if (l.dec) qlsd_decoder_destroy(l.dec);
+    if (l.done) hipEventDestroy(l.done);
+    if (l.stream) hipStreamDestroy(l.stream);
+    hipFree(l.d_syn);
+    hipFree(l.d_corr);
+    hipFree(l.d_info);
+    hipHostFree(l.h_syn);
+    hipHostFree(l.h_corr);
+    hipHostFree(l.h_info);
+    l = Lane();
+}
+
+// Launches one batch on a free lane from the requests of code c that have arrived.
+bool launch_batch(qlsd_server_s *s, Code &c, Lane &l, double t) {
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        while (!c.pending.empty() && (int)l.batch.size() < c.batch_shots && c.pending.front().arrival_us <= t) {
+            l.batch.push_back(c.pending.front());
+            c.pending.pop_front();
+        }
+    }
+    const int B = (int)l.batch.size();
+    if (B == 0) return false;
+    for (int b = 0; b < B; b++) memcpy(l.h_syn + (size_t)b * c.m, l.batch[b].syn, c.m);
+    hipMemcpyAsync(l.d_syn, l.h_syn, (size_t)B * c.m, hipMemcpyHostToDevice, l.stream);
+    qlsd_status st = qlsd_decode(l.dec, l.d_syn, B, l.d_corr, (qlsd_shot_info *)l.d_info, l.stream);
+    if (st != QLSD_OK) snprintf(s->error, sizeof(s->error), "decode failed: %s", qlsd_last_error());
+    hipMemcpyAsync(l.h_corr, l.d_corr, (size_t)B * c.n, hipMemcpyDeviceToHost, l.stream);
+    hipMemcpyAsync(l.h_info, l.d_info, (size_t)B * sizeof(qlsd_shot_info), hipMemcpyDeviceToHost, l.stream);
+    hipEventRecord(l.done, l.stream);
+    l.busy = true;
+    return true;
+}
+
+void finish_batch(qlsd_server_s *s, int code_id, Code &c, Lane &l) {
+    const double t = now_us(s);
+    const int B = (int)l.batch.size();
+    std::vector<qlsd_completion> recs(B);
+    for (int b = 0; b < B; b++) {
+        memcpy(l.batch[b].out, l.h_corr + (size_t)b * c.n, c.n);
+        qlsd_completion &r = recs[b];
+        memset(&r, 0, sizeof(r));
+        r.tag = l.batch[b].tag;
+        r.code_id = code_id;
+        r.status = ((const qlsd_shot_info *)l.h_info)[b].status;
+        r.arrival_us = l.batch[b].arrival_us;
+        r.done_us = t;
+        r.batch_size = B;
+    }
+    l.batch.clear();
+    l.busy = false;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->done.insert(s->done.end(), recs.begin(), recs.end());
+        s->completed += B;
+    }
+    s->cv.notify_all();
+}
+
+void scheduler(qlsd_server_s *s) {
+    while (true) {
+        bool progress = false, any_busy = false;
+        const double t = now_us(s);
+        for (size_t ci = 0; ci < s->codes.size(); ci++) {
+            Code &c = *s->codes[ci];
+            for (Lane &l : c.lanes) {
+                if (l.busy) {
+                    const hipError_t q = hipEventQuery(l.done);
+                    if (q == hipSuccess) {
+                        finish_batch(s, (int)ci, c, l);
+                        progress = true;
+                    } else if (q != hipErrorNotReady) {
+                        snprintf(s->error, sizeof(s->error), "device failure: %s", hipGetErrorString(q));
+                        s->stop = true;
+                        s->cv.notify_all();
+                        return;
+                    }
+                }
+                if (!l.busy && launch_batch(s, c, l, t)) progress = true;
+                any_busy |= l.busy;
+            }
+        }
+        if (s->stop.load() && !any_busy) return;
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(any_busy ? 5 : 20));
+    }
+}
+
+qlsd_status serr(qlsd_server_s *s, qlsd_status st, const char *msg) {
+    if (s) snprintf(s->error, sizeof(s->error), "%s", msg);
+    qlsd::set_last_error("%s", msg);
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+qlsd_status qlsd_server_create(size_t device_budget_bytes, qlsd_server *out) {
+    if (!out) return serr(nullptr, QLSD_E_INVALID, "out is NULL");
+    qlsd_server s = new (std::nothrow) qlsd_server_s();
+    if (!s) return serr(nullptr, QLSD_E_NOMEM, "host allocation failed");
+    s->budget = device_budget_bytes;
+    *out = s;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_params *params, const double *priors,
+                                 int32_t batch_shots, int32_t max_lanes, int32_t *code_id, int32_t *lanes_out) {
+    if (!s || !code || !params || !priors || !code_id) return serr(s, QLSD_E_INVALID, "NULL argument");
+    if (s->started.load()) return serr(s, QLSD_E_INVALID, "codes must be added before qlsd_server_start");
+    if (batch_shots < 1 || max_lanes < 1) return serr(s, QLSD_E_BATCH, "batch_shots and max_lanes must be >= 1");
+    Code *c = new (std::nothrow) Code();
+    if (!c) return serr(s, QLSD_E_NOMEM, "host allocation failed");
+    c->m = qlsd::code_rows(code);
+    c->n = qlsd::code_cols(code);
+    c->batch_shots = batch_shots;
+    for (int k = 0; k < max_lanes; k++) {
+        Lane l;
+        qlsd_status st = qlsd_decoder_create(code, params, priors, batch_shots, &l.dec);
+        if (st != QLSD_OK) {
+            if (k == 0) { delete c; return st; }
+            break;
+        }
+        const size_t bufs = (size_t)batch_shots * (c->m + c->n + sizeof(qlsd_shot_info));
+        const size_t need = qlsd::decoder_device_bytes(l.dec) + bufs;
+        if (s->used + need > s->budget) {
+            qlsd_decoder_destroy(l.dec);
+            if (k == 0) {
+                delete c;
+                return serr(s, QLSD_E_NOMEM, "device budget too small for one lane of this code");
+            }
+            break;
+        }
+        bool ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess &&
+                  hipMalloc((void **)&l.d_syn, (size_t)batch_shots * c->m) == hipSuccess &&
+                  hipMalloc((void **)&l.d_corr, (size_t)batch_shots * c->n) == hipSuccess &&
+                  hipMalloc((void **)&l.d_info, (size_t)batch_shots * sizeof(qlsd_shot_info)) == hipSuccess &&
+                  hipHostMalloc((void **)&l.h_syn, (size_t)batch_shots * c->m, 0) == hipSuccess &&
+                  hipHostMalloc((void **)&l.h_corr, (size_t)batch_shots * c->n, 0) == hipSuccess &&
+                  hipHostMalloc((void **)&l.h_info, (size_t)batch_shots * sizeof(qlsd_shot_info), 0) == hipSuccess;
+        if (!ok) {
+            free_lane(l);
+            if (k == 0) { delete c; return serr(s, QLSD_E_NOMEM, "lane allocation failed"); }
+            break;
+        }
+        l.batch.reserve(batch_shots);
+        s->used += need;
+        c->lanes.push_back(std::move(l));
+    }
+    *code_id = (int32_t)s->codes.size();
+    if (lanes_out) *lanes_out = (int32_t)c->lanes.size();
+    s->codes.push_back(c);
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_submit_many(qlsd_server s, int32_t code_id, int32_t count, const uint8_t *syndromes,
+                                    uint8_t *corrections_out, const uint64_t *tags, const double *arrival_us) {
+    if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
+    if (count < 0 || (count > 0 && (!syndromes || !corrections_out || !tags)))
+        return serr(s, QLSD_E_INVALID, "bad request arrays");
+    Code &c = *s->codes[code_id];
+    std::lock_guard<std::mutex> g(s->mu);
+    double last = c.pending.empty() ? -1e300 : c.pending.back().arrival_us;
+    for (int32_t k = 0; k < count; k++) {
+        const double a = arrival_us ? arrival_us[k] : 0.0;
+        if (a < last) return serr(s, QLSD_E_INVALID, "arrival times of a code must be non-decreasing");
+        last = a;
+        c.pending.push_back(Request{syndromes + (size_t)k * c.m, corrections_out + (size_t)k * c.n, tags[k], a});
+    }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_start(qlsd_server s) {
+    if (!s) return serr(s, QLSD_E_INVALID, "server is NULL");
+    if (s->started.load()) return serr(s, QLSD_E_INVALID, "already started");
+    s->epoch = std::chrono::steady_clock::now();
+    s->started = true;
+    s->worker = std::thread(scheduler, s);
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_wait(qlsd_server s, int64_t count, double timeout_s) {
+    if (!s) return serr(s, QLSD_E_INVALID, "server is NULL");
+    std::unique_lock<std::mutex> g(s->mu);
+    const bool ok = s->cv.wait_for(g, std::chrono::duration<double>(timeout_s),
+                                   [&] { return s->completed >= count || s->error[0] != 0; });
+    if (s->error[0]) {
+        qlsd::set_last_error("%s", s->error);
+        return QLSD_E_DEVICE;
+    }
+    if (!ok) return serr(s, QLSD_E_DEVICE, "timed out waiting for completions");
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_completions(qlsd_server s, qlsd_completion *out, int32_t max, int32_t *n_out) {
+    if (!s || !n_out || (max > 0 && !out)) return serr(s, QLSD_E_INVALID, "bad arguments");
+    std::lock_guard<std::mutex> g(s->mu);
+    const int32_t k = (int32_t)std::min<size_t>((size_t)std::max(max, 0), s->done.size());
+    std::copy(s->done.begin(), s->done.begin() + k, out);
+    s->done.erase(s->done.begin(), s->done.begin() + k);
+    *n_out = k;
+    return QLSD_OK;
+}
+
+double qlsd_server_now_us(qlsd_server s) { return s ? now_us(s) : 0.0; }
+
+void qlsd_server_destroy(qlsd_server s) {
+    if (!s) return;
+    s->stop = true;
+    if (s->worker.joinable()) s->worker.join();
+    for (Code *c : s->codes) {
+        for (Lane &l : c->lanes) free_lane(l);
+        delete c;
+    }
+    delete s;
+}
+
+}  // extern "C"

@@ -12,8 +12,8 @@ from paper_2406_18655_amd import binding
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared_symbols():
-    with open(os.path.join(ROOT, "include", "qlsd.h")) as f:
+def _declared_symbols(header="qlsd.h"):
+    with open(os.path.join(ROOT, "include", header)) as f:
         txt = f.read()
     return sorted(set(re.findall(r"\b(qlsd_[a-z_]+)\(", txt)))
 
@@ -29,7 +29,9 @@ def lib():
 def test_every_declared_symbol_is_exported(lib):
     decl = _declared_symbols()
     assert set(decl) == set(binding.EXPORTS)
-    for name in decl:
+    serve = [x for x in _declared_symbols("qlsd_serve.h") if x.startswith("qlsd_server")]
+    assert set(serve) == set(binding.SERVE_EXPORTS)
+    for name in decl + serve:
         assert hasattr(lib, name), name
 
 
@@ -60,6 +62,20 @@ def test_null_handles_are_rejected(lib):
 def test_info_layout_matches_header():
     assert binding.INFO_DTYPE.itemsize == 12
     assert ctypes.sizeof(binding.QlsdParams) == 20
+    assert binding.COMPLETION_DTYPE.itemsize == 40
+
+
+def test_server_host_side_validation(lib):
+    L = binding._serve_lib()
+    h = ctypes.c_void_p()
+    assert L.qlsd_server_create(1 << 20, ctypes.byref(h)) == 0
+    cid, lanes = ctypes.c_int32(), ctypes.c_int32()
+    params = binding.QlsdParams(30, 0.625, 0, 0, 0)
+    # no code handle: refused before any device work
+    assert L.qlsd_server_add_code(h, None, ctypes.byref(params), None, 16, 1, ctypes.byref(cid),
+                                  ctypes.byref(lanes)) == -1
+    assert L.qlsd_server_submit_many(h, 0, 1, None, None, None, None) == -1
+    L.qlsd_server_destroy(h)
 
 
 def test_binding_rejects_strided_tensors():

@@ -1,0 +1,105 @@
+"""Serving: continuous batching over a mix of codes.  Each request's correction must be the
+same alone and in the mix (BP and LSD have no cross-shot reductions), every correction
+satisfies its syndrome, and a small device budget defers requests instead of dropping them."""
+import numpy as np
+import pytest
+
+from paper_2406_18655_amd import binding
+from paper_2406_18655_amd.workloads import (bivariate_bicycle, surface_hgp, random_34_hgp, synthetic_dem,
+                                            sample)
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+def _mix():
+    return [(bivariate_bicycle(p=0.05), 50, 0, 1500, 4096), (random_34_hgp(16, p=0.03), 30, 0, 1000, 2048),
+            (surface_hgp(5, p=0.05), 30, 0, 800, 1024), (synthetic_dem(), 100, 10, 200, 256)]
+
+
+def _alone(code, T, mu, S):
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, S.shape[0], max_iter=T, lsd_order=mu)
+    out = dec.decode(torch.from_numpy(S).cuda()).cpu().numpy()
+    return out
+
+
+def _run(budget, rate_per_s, max_lanes=2, seed=0):
+    rng = np.random.default_rng(seed)
+    srv = binding.Server(budget)
+    jobs = []
+    for k, (code, T, mu, N, bs) in enumerate(_mix()):
+        bc = binding.Code.from_dense(code.H)
+        cid, lanes = srv.add_code(bc, code.priors, batch_shots=bs, max_lanes=max_lanes, max_iter=T, lsd_order=mu)
+        e, S = sample(code, N, seed=500 + k)
+        # Poisson arrivals of this code's share of the aggregate rate
+        gaps = rng.exponential(1e6 / (rate_per_s / 4), size=N)
+        arr = np.cumsum(gaps)
+        out = np.zeros((N, code.n), dtype=np.uint8)
+        srv.submit_many(cid, S, out, np.arange(N, dtype=np.uint64) + (k << 32), arr)
+        jobs.append((code, T, mu, S, out, lanes))
+    total = sum(j[3].shape[0] for j in jobs)
+    srv.start()
+    srv.wait(total, timeout_s=120)
+    comp = srv.completions()
+    srv.close()
+    return jobs, comp, total
+
+
+def test_mix_equals_alone():
+    jobs, comp, total = _run(budget=8 << 30, rate_per_s=2e5)
+    assert len(comp) == total
+    assert (comp["done_us"] >= comp["arrival_us"]).all()
+    assert comp["batch_size"].max() > 1  # requests really were batched together
+    for code, T, mu, S, out, lanes in jobs:
+        assert lanes == 2
+        assert (((out.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == S).all()
+        np.testing.assert_array_equal(out, _alone(code, T, mu, S))
+    lat = comp["done_us"] - comp["arrival_us"]
+    print(f"latency p50={np.percentile(lat, 50):.0f}us p99={np.percentile(lat, 99):.0f}us")
+
+
+def test_one_lane_per_code_defers_not_drops():
+    # arrivals far faster than one lane per code can serve: requests wait, none is lost
+    jobs, comp, total = _run(budget=8 << 30, rate_per_s=1e7, max_lanes=1)
+    assert len(comp) == total
+    for code, T, mu, S, out, lanes in jobs:
+        assert lanes == 1
+        np.testing.assert_array_equal(out, _alone(code, T, mu, S))
+
+
+def _lane_bytes(code, bs):
+    m, n = code.m, code.n
+    return n * 12 + 32 + bs * (1 + 4 + 4 * n) + bs * (m + n + 12)
+
+
+def test_budget_limits_lanes():
+    code = bivariate_bicycle(p=0.05)
+    srv = binding.Server(int(2.5 * _lane_bytes(code, 4096)))
+    cid, lanes = srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=4096, max_lanes=4,
+                              max_iter=50)
+    assert lanes == 2
+    e, S = sample(code, 3000, seed=3)
+    out = np.zeros((3000, code.n), dtype=np.uint8)
+    srv.submit_many(cid, S, out, np.arange(3000, dtype=np.uint64))
+    srv.start()
+    srv.wait(3000, timeout_s=60)
+    assert len(srv.completions()) == 3000
+    srv.close()
+    np.testing.assert_array_equal(out, _alone(code, 50, 0, S))
+
+
+def test_budget_too_small_is_refused():
+    srv = binding.Server(1 << 10)
+    code = bivariate_bicycle()
+    with pytest.raises(binding.QlsdError) as ex:
+        srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=4096)
+    assert ex.value.status == -3
+    srv.close()
