@@ -306,3 +306,82 @@ class Server:
     def __del__(self):
         if _lib is not None:
             self.close()
+
+
+# ------------------------------------------------------------------ learned refinement
+NET_PARAMS = 9537
+NET_EXPORTS = ["qlsd_net_create", "qlsd_net_set_params", "qlsd_net_get_params", "qlsd_net_forward",
+               "qlsd_net_gradient", "qlsd_net_train_step", "qlsd_decoder_set_net", "qlsd_net_destroy"]
+
+
+def _net_lib():
+    L = lib()
+    if not getattr(L, "_net_ready", False):
+        P, I32, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+        L.qlsd_net_create.argtypes = [P, P, P, ctypes.POINTER(P)]
+        L.qlsd_net_set_params.argtypes = [P, P]
+        L.qlsd_net_get_params.argtypes = [P, P]
+        L.qlsd_net_forward.argtypes = [P, P, P, I32, P, P]
+        L.qlsd_net_gradient.argtypes = [P, P, P, P, I32, P, P, P]
+        L.qlsd_net_train_step.argtypes = [P, P, P, P, I32, F, P]
+        L.qlsd_decoder_set_net.argtypes = [P, P]
+        L.qlsd_net_destroy.argtypes = [P]
+        for fn in NET_EXPORTS[:-1]:
+            getattr(L, fn).restype = ctypes.c_int
+        L._net_ready = True
+    return L
+
+
+class Net:
+    """Learned LLR refinement (include/qlsd_net.h) for one code; parameters live on the device."""
+
+    def __init__(self, code: "Code", priors: np.ndarray, params: np.ndarray):
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        th = np.ascontiguousarray(params, dtype=np.float32)
+        if th.shape != (NET_PARAMS,):
+            raise ValueError(f"params must have shape ({NET_PARAMS},)")
+        h = ctypes.c_void_p()
+        _check(_net_lib().qlsd_net_create(code._h, pri.ctypes.data, th.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        self.code = code
+
+    def set_params(self, params: np.ndarray):
+        th = np.ascontiguousarray(params, dtype=np.float32)
+        _check(_net_lib().qlsd_net_set_params(self._h, th.ctypes.data))
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(NET_PARAMS, dtype=np.float32)
+        _check(_net_lib().qlsd_net_get_params(self._h, out.ctypes.data))
+        return out
+
+    def forward(self, syndromes, llr):
+        import torch
+        out = torch.empty_like(llr)
+        _check(_net_lib().qlsd_net_forward(self._h, _ptr(syndromes), _ptr(llr), llr.shape[0], _ptr(out), _stream()))
+        return out
+
+    def gradient(self, syndromes, llr, errors):
+        import torch
+        g = torch.empty(NET_PARAMS, dtype=torch.float32, device=llr.device)
+        loss = torch.empty(1, dtype=torch.float32, device=llr.device)
+        _check(_net_lib().qlsd_net_gradient(self._h, _ptr(syndromes), _ptr(llr), _ptr(errors), llr.shape[0],
+                                            _ptr(g), _ptr(loss), _stream()))
+        return g, loss
+
+    def train_step(self, syndromes, llr, errors, lr: float):
+        _check(_net_lib().qlsd_net_train_step(self._h, _ptr(syndromes), _ptr(llr), _ptr(errors), llr.shape[0],
+                                              float(lr), _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _net_lib().qlsd_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
+def attach_net(decoder: "Decoder", net: Optional[Net]):
+    """decoder.decode then runs BP, the refinement on the shots BP did not solve, and LSD."""
+    _check(_net_lib().qlsd_decoder_set_net(decoder._h, None if net is None else net._h))
+    decoder._net = net

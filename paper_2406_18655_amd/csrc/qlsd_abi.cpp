@@ -9,6 +9,7 @@
 #include <new>
 #include <vector>
 
+#include "../../include/qlsd_net.h"
 #include "qlsd_internal.h"
 
 using namespace qlsd;
@@ -69,6 +70,7 @@ struct qlsd_decoder_s {
     int num_cus;
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
     bool timing;
+    qlsd_net net;       // optional refinement between BP and LSD
 };
 
 namespace qlsd {
@@ -79,6 +81,7 @@ void set_last_error(const char *fmt, ...) {
     va_end(ap);
 }
 int code_rows(qlsd_code c) { return c->g.m; }
+DevGraph code_graph(qlsd_code c) { return c->g; }
 int code_cols(qlsd_code c) { return c->g.n; }
 size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
@@ -341,6 +344,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     HIP_OK(run_bp(d, a, B, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
     HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
+    if (d->net) HIP_OK(net_refine_listed(d->net, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
     l.list_count = d->d_ctl + 1;
@@ -387,6 +391,13 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder d, float *bp_ms, float *lsd_ms) {
     HIP_OK(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
     if (bp_ms) *bp_ms = a;
     if (lsd_ms) *lsd_ms = b;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_decoder_set_net(qlsd_decoder d, qlsd_net net) {
+    g_err[0] = 0;
+    if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    d->net = net;
     return QLSD_OK;
 }
 

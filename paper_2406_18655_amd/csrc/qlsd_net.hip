@@ -1,0 +1,612 @@
+// Learned reliability refinement between BP and LSD (include/qlsd_net.h): a 3-layer
+// message-passing network over the Tanner graph, hidden width 32.  Dense products run on
+// bf16 MFMA (v_mfma_f32_16x16x16bf16_1k, float32 accumulate); neighbour means in float32.
+// One workgroup (4 wavefronts) per shot at a time; node features of the shot stay in LDS.
+// Training keeps the weight-gradient tiles of the nine 32x32 matrices in registers across all
+// shots a workgroup processes and adds them to the global gradient once per workgroup.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "../../include/qlsd_net.h"
+#include "qlsd_internal.h"
+
+namespace qlsd {
+namespace {
+
+constexpr int HID = 32;
+constexpr int NL = 3;
+constexpr int NPAR = QLSD_NET_PARAMS;
+constexpr int kNetThreads = 256;
+// parameter offsets (floats)
+constexpr int P_W0 = 0, P_B0 = 64, P_LAYER = 96, P_LSTRIDE = 3136;
+constexpr int P_A = 0, P_a = 1024, P_B = 1056, P_C = 2080, P_b = 3104;
+constexpr int P_W = 96 + 3 * 3136, P_BO = P_W + 32;
+// small float vectors kept in LDS: W0, b0, a1..3, b1..3, w, bo
+constexpr int SV_W0 = 0, SV_B0 = 64, SV_A = 96, SV_BL = 192, SV_W = 288, SV_BO = 320, SV_N = 321;
+
+typedef short short4v __attribute__((ext_vector_type(4)));
+typedef float float4v __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__host__ __device__ inline int pad16(int x) { return (x + 15) & ~15; }
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+struct NetArgs {
+    DevGraph g;
+    const float *lam;       // n
+    const float *theta;     // NPAR
+    const uint8_t *syn;     // B x m
+    const float *llr;       // B x n
+    const uint8_t *err;     // B x n (training)
+    float *llr_out;         // B x n (inference)
+    const int *list;        // shots to process (nullable: 0..count-1)
+    const int *list_count;  // device count when list != nullptr
+    int count;
+    float *grad;            // NPAR (training, accumulated)
+    float *loss;            // 1 (training, accumulated)
+    float inv_total;        // 1 / (shots * n) (training)
+    int train;
+};
+
+struct NetLds {
+    int n, m, E, NP, MP;
+    uint16_t *wbf;               // 9 x 1024 bf16: [layer][A,B,C][out][in]
+    float *sv;                   // small vectors
+    float *svg;                  // their gradient accumulators (training)
+    uint16_t *rp, *ci, *cp, *ri;
+    float *lam, *Lsh;            // n, n
+    uint16_t *Hb[NL + 1];        // NP x 32
+    uint16_t *Cb[NL + 1];        // MP x 32 (index 1..3)
+    uint16_t *AGG;               // max(NP,MP) x 32
+    uint16_t *DUV;               // max(NP,MP) x 32 (training)
+    float *DH, *DT, *DC;         // NP x 32, max x 32, MP x 32 (training)
+    float *misc;                 // [0] loss accumulator
+};
+
+__host__ __device__ inline size_t net_layout(int n, int m, int E, bool train, size_t *o) {
+    const int NP = pad16(n), MP = pad16(m), XP = NP > MP ? NP : MP;
+    size_t off = 0;
+    o[0] = off; off += al16(sizeof(uint16_t) * 9 * 1024);
+    o[1] = off; off += al16(sizeof(float) * SV_N);
+    o[2] = off; off += train ? al16(sizeof(float) * SV_N) : 0;
+    o[3] = off; off += al16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + E));
+    o[4] = off; off += al16(sizeof(float) * 2 * (size_t)n);
+    o[5] = off; off += al16(sizeof(uint16_t) * ((NL + 1) * (size_t)NP * HID + NL * (size_t)MP * HID));
+    o[6] = off; off += al16(sizeof(uint16_t) * (size_t)XP * HID);
+    o[7] = off; off += train ? al16(sizeof(uint16_t) * (size_t)XP * HID) : 0;
+    o[8] = off; off += train ? al16(sizeof(float) * ((size_t)NP + XP + MP) * HID) : 0;
+    o[9] = off; off += al16(sizeof(float) * 4);
+    return off;
+}
+
+__device__ NetLds carve_net(unsigned char *base, int n, int m, int E, bool train) {
+    size_t o[10];
+    net_layout(n, m, E, train, o);
+    NetLds L;
+    L.n = n; L.m = m; L.E = E; L.NP = pad16(n); L.MP = pad16(m);
+    const int XP = L.NP > L.MP ? L.NP : L.MP;
+    L.wbf = (uint16_t *)(base + o[0]);
+    L.sv = (float *)(base + o[1]);
+    L.svg = (float *)(base + o[2]);
+    L.rp = (uint16_t *)(base + o[3]);
+    L.ci = L.rp + (m + 1);
+    L.cp = L.ci + E;
+    L.ri = L.cp + (n + 1);
+    L.lam = (float *)(base + o[4]);
+    L.Lsh = L.lam + n;
+    uint16_t *a = (uint16_t *)(base + o[5]);
+    for (int l = 0; l <= NL; l++) { L.Hb[l] = a; a += (size_t)L.NP * HID; }
+    L.Cb[0] = nullptr;
+    for (int l = 1; l <= NL; l++) { L.Cb[l] = a; a += (size_t)L.MP * HID; }
+    L.AGG = (uint16_t *)(base + o[6]);
+    L.DUV = (uint16_t *)(base + o[7]);
+    L.DH = (float *)(base + o[8]);
+    L.DT = L.DH + (size_t)L.NP * HID;
+    L.DC = L.DT + (size_t)XP * HID;
+    L.misc = (float *)(base + o[9]);
+    return L;
+}
+
+// One 16x16 output tile: acc += A[16 x K] * B[K x 16], operands bf16 in LDS addressed by
+// strides (element (r,k) of A at A[r*ars + k*aks], element (k,c) of B at B[k*bks + c*bns]).
+// Lane layout of v_mfma_f32_16x16x16bf16_1k: lane l supplies A row (l & 15), k = 4(l >> 4)..+3,
+// B column (l & 15), same k; it receives D rows 4(l >> 4)..+3 of column (l & 15).
+__device__ __forceinline__ float4v mma16(const uint16_t *A, int ars, int aks, const uint16_t *B, int bks, int bns,
+                                         int K, float4v acc, int lane) {
+    const int r = lane & 15, kq = (lane >> 4) * 4;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        short4v a, b;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            a[t] = (short)A[r * ars + (k0 + kq + t) * aks];
+            b[t] = (short)B[(k0 + kq + t) * bks + r * bns];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ const uint16_t *Wmat(const NetLds &L, int layer, int which) {  // which: 0 A, 1 B, 2 C
+    return L.wbf + ((size_t)(layer - 1) * 3 + which) * 1024;
+}
+
+// Mean over the neighbours: dst[node][f] = (1/deg) sum src[nb][f]; rows >= count zero-filled.
+__device__ void mean_checks(const NetLds &L, const uint16_t *Hsrc, uint16_t *dst) {  // per check over its faults
+    for (int it = threadIdx.x; it < L.MP * HID; it += kNetThreads) {
+        const int i = it >> 5, f = it & 31;
+        float s = 0.f;
+        if (i < L.m) {
+            const int e0 = L.rp[i], e1 = L.rp[i + 1];
+            for (int e = e0; e < e1; e++) s += bf2f(Hsrc[L.ci[e] * HID + f]);
+            s /= (float)(e1 - e0);
+        }
+        dst[it] = f2bf(s);
+    }
+}
+__device__ void mean_faults(const NetLds &L, const uint16_t *Csrc, uint16_t *dst) {  // per fault over its checks
+    for (int it = threadIdx.x; it < L.NP * HID; it += kNetThreads) {
+        const int j = it >> 5, f = it & 31;
+        float s = 0.f;
+        if (j < L.n) {
+            const int c0 = L.cp[j], c1 = L.cp[j + 1];
+            for (int c = c0; c < c1; c++) s += bf2f(Csrc[L.ri[c] * HID + f]);
+            if (c1 > c0) s /= (float)(c1 - c0);
+        }
+        dst[it] = f2bf(s);
+    }
+}
+
+// Forward pass of one shot; Hb[0..3], Cb[1..3] hold the activations afterwards.
+__device__ void forward_shot(const NetLds &L, const uint8_t *syn, int lane, int wave) {
+    // input layer
+    for (int it = threadIdx.x; it < L.NP * HID; it += kNetThreads) {
+        const int j = it >> 5, f = it & 31;
+        float h = 0.f;
+        if (j < L.n) {
+            const float x0 = tanhf(L.Lsh[j] * 0.125f), x1 = L.lam[j] * 0.125f;
+            h = fmaxf(L.sv[SV_W0 + f * 2] * x0 + L.sv[SV_W0 + f * 2 + 1] * x1 + L.sv[SV_B0 + f], 0.f);
+        }
+        L.Hb[0][it] = f2bf(h);
+    }
+    __syncthreads();
+    for (int l = 1; l <= NL; l++) {
+        mean_checks(L, L.Hb[l - 1], L.AGG);
+        __syncthreads();
+        // c = relu(A m + sigma a)
+        for (int tile = wave; tile < (L.MP / 16) * 2; tile += 4) {
+            const int rt = tile >> 1, ct = tile & 1;
+            float4v acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mma16(L.AGG + rt * 16 * HID, HID, 1, Wmat(L, l, 0) + ct * 16 * HID, 1, HID, HID, acc, lane);
+            const int col = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int row = rt * 16 + (lane >> 4) * 4 + t;
+                float v = 0.f;
+                if (row < L.m) {
+                    const float sg = (syn[row] & 1) ? -1.f : 1.f;
+                    v = fmaxf(acc[t] + sg * L.sv[SV_A + (l - 1) * HID + col], 0.f);
+                }
+                L.Cb[l][row * HID + col] = f2bf(v);
+            }
+        }
+        __syncthreads();
+        mean_faults(L, L.Cb[l], L.AGG);
+        __syncthreads();
+        // h = relu(B h + C g + b)
+        for (int tile = wave; tile < (L.NP / 16) * 2; tile += 4) {
+            const int rt = tile >> 1, ct = tile & 1;
+            float4v acc = {0.f, 0.f, 0.f, 0.f};
+            acc = mma16(L.Hb[l - 1] + rt * 16 * HID, HID, 1, Wmat(L, l, 1) + ct * 16 * HID, 1, HID, HID, acc, lane);
+            acc = mma16(L.AGG + rt * 16 * HID, HID, 1, Wmat(L, l, 2) + ct * 16 * HID, 1, HID, HID, acc, lane);
+            const int col = ct * 16 + (lane & 15);
+#pragma unroll
+            for (int t = 0; t < 4; t++) {
+                const int row = rt * 16 + (lane >> 4) * 4 + t;
+                const float v = row < L.n ? fmaxf(acc[t] + L.sv[SV_BL + (l - 1) * HID + col], 0.f) : 0.f;
+                L.Hb[l][row * HID + col] = f2bf(v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__device__ __forceinline__ float delta_of(const NetLds &L, int j) {
+    float d = L.sv[SV_BO];
+    const uint16_t *h = L.Hb[NL] + j * HID;
+#pragma unroll
+    for (int f = 0; f < HID; f++) d += L.sv[SV_W + f] * bf2f(h[f]);
+    return d;
+}
+
+__global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    const int n = A.g.n, m = A.g.m, E = A.g.nnz;
+    const bool train = A.train != 0;
+    NetLds L = carve_net(smem, n, m, E, train);
+
+    // weights: 32x32 matrices as bf16, vectors as float
+    for (int x = t; x < 9 * 1024; x += kNetThreads) {
+        const int mat = x >> 10, layer = mat / 3, which = mat % 3;
+        const int off = P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C) + (x & 1023);
+        L.wbf[x] = f2bf(A.theta[off]);
+    }
+    for (int x = t; x < SV_N; x += kNetThreads) {
+        float v;
+        if (x < SV_B0) v = A.theta[P_W0 + x];
+        else if (x < SV_A) v = A.theta[P_B0 + (x - SV_B0)];
+        else if (x < SV_BL) { const int l = (x - SV_A) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_a + ((x - SV_A) & 31)]; }
+        else if (x < SV_W) { const int l = (x - SV_BL) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_b + ((x - SV_BL) & 31)]; }
+        else if (x < SV_BO) v = A.theta[P_W + (x - SV_W)];
+        else v = A.theta[P_BO];
+        L.sv[x] = v;
+        if (train) L.svg[x] = 0.f;
+    }
+    for (int x = t; x <= m; x += kNetThreads) L.rp[x] = (uint16_t)A.g.row_ptr[x];
+    for (int x = t; x < E; x += kNetThreads) L.ci[x] = (uint16_t)A.g.col_idx[x];
+    for (int x = t; x <= n; x += kNetThreads) L.cp[x] = (uint16_t)A.g.col_ptr[x];
+    for (int x = t; x < E; x += kNetThreads) L.ri[x] = (uint16_t)A.g.row_idx[x];
+    for (int x = t; x < n; x += kNetThreads) L.lam[x] = A.lam[x];
+    if (t == 0) L.misc[0] = 0.f;
+    __syncthreads();
+
+    // weight-gradient tiles kept in registers: wavefront w owns tile (w >> 1, w & 1) of each
+    // of the nine matrices [layer][A,B,C]
+    float4v gacc[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) gacc[q] = (float4v){0.f, 0.f, 0.f, 0.f};
+    const int trow = (wave >> 1) * 16, tcol = (wave & 1) * 16;
+
+    const int total = A.list ? *A.list_count : A.count;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int shot = A.list ? A.list[item] : item;
+        const uint8_t *syn = A.syn + (size_t)shot * m;
+        const float *llr = A.llr + (size_t)shot * n;
+        for (int j = t; j < n; j += kNetThreads) L.Lsh[j] = llr[j];
+        __syncthreads();
+        forward_shot(L, syn, lane, wave);
+
+        if (!train) {
+            for (int j = t; j < n; j += kNetThreads) A.llr_out[(size_t)shot * n + j] = L.Lsh[j] + delta_of(L, j);
+            __syncthreads();
+            continue;
+        }
+
+        // ---- loss and output layer
+        const uint8_t *err = A.err + (size_t)shot * n;
+        for (int it = t; it < L.NP * HID; it += kNetThreads) L.DH[it] = 0.f;
+        __syncthreads();
+        for (int j = t; j < n; j += kNetThreads) {
+            const float Lp = L.Lsh[j] + delta_of(L, j);
+            const float e = (float)(err[j] & 1);
+            // softplus(-L') + e L'
+            const float lossj = fmaxf(-Lp, 0.f) + log1pf(expf(-fabsf(Lp))) + e * Lp;
+            atomicAdd(&L.misc[0], lossj * A.inv_total);
+            const float dD = (e - 1.f / (1.f + expf(Lp))) * A.inv_total;
+            atomicAdd(&L.svg[SV_BO], dD);
+            const uint16_t *h = L.Hb[NL] + j * HID;
+            for (int f = 0; f < HID; f++) {
+                atomicAdd(&L.svg[SV_W + f], dD * bf2f(h[f]));
+                L.DH[j * HID + f] = dD * L.sv[SV_W + f];
+            }
+        }
+        __syncthreads();
+        for (int l = NL; l >= 1; l--) {
+            // du = dh * [h_l > 0]; db_l; g_l recomputed into AGG
+            for (int it = t; it < L.NP * HID; it += kNetThreads) {
+                const float du = bf2f(L.Hb[l][it]) > 0.f ? L.DH[it] : 0.f;
+                L.DUV[it] = f2bf(du);
+                if (du != 0.f) atomicAdd(&L.svg[SV_BL + (l - 1) * HID + (it & 31)], du);
+            }
+            mean_faults(L, L.Cb[l], L.AGG);
+            __syncthreads();
+            // dB += du^T h_{l-1}, dC += du^T g  (K = faults)
+            gacc[(l - 1) * 3 + 1] = mma16(L.DUV + trow, 1, HID, L.Hb[l - 1] + tcol, HID, 1, L.NP,
+                                          gacc[(l - 1) * 3 + 1], lane);
+            gacc[(l - 1) * 3 + 2] = mma16(L.DUV + trow, 1, HID, L.AGG + tcol, HID, 1, L.NP, gacc[(l - 1) * 3 + 2], lane);
+            // dg = du C -> DT, dh_{l-1} = du B -> DH
+            for (int tile = wave; tile < (L.NP / 16) * 4; tile += 4) {
+                const int rt = tile >> 2, which = (tile >> 1) & 1, ct = tile & 1;
+                float4v acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mma16(L.DUV + rt * 16 * HID, HID, 1, Wmat(L, l, which == 0 ? 2 : 1) + ct * 16, HID, 1, HID, acc,
+                            lane);
+                float *dst = which == 0 ? L.DT : L.DH;
+                const int col = ct * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; q++) dst[(rt * 16 + (lane >> 4) * 4 + q) * HID + col] = acc[q];
+            }
+            __syncthreads();
+            // dc_i = sum_{j in N(i)} dg_j / deg_j
+            for (int it = t; it < L.MP * HID; it += kNetThreads) {
+                const int i = it >> 5, f = it & 31;
+                float s = 0.f;
+                if (i < m) {
+                    for (int e = L.rp[i]; e < L.rp[i + 1]; e++) {
+                        const int j = L.ci[e];
+                        s += L.DT[j * HID + f] / (float)(L.cp[j + 1] - L.cp[j]);
+                    }
+                }
+                L.DC[it] = s;
+            }
+            __syncthreads();
+            // dv = dc * [c > 0]; da; m_l recomputed into AGG
+            for (int it = t; it < L.MP * HID; it += kNetThreads) {
+                const int i = it >> 5;
+                const float dv = bf2f(L.Cb[l][it]) > 0.f ? L.DC[it] : 0.f;
+                L.DUV[it] = f2bf(dv);
+                if (dv != 0.f) atomicAdd(&L.svg[SV_A + (l - 1) * HID + (it & 31)], (syn[i] & 1) ? -dv : dv);
+            }
+            mean_checks(L, L.Hb[l - 1], L.AGG);
+            __syncthreads();
+            // dA += dv^T m (K = checks); dm = dv A -> DT
+            gacc[(l - 1) * 3 + 0] = mma16(L.DUV + trow, 1, HID, L.AGG + tcol, HID, 1, L.MP, gacc[(l - 1) * 3 + 0], lane);
+            for (int tile = wave; tile < (L.MP / 16) * 2; tile += 4) {
+                const int rt = tile >> 1, ct = tile & 1;
+                float4v acc = {0.f, 0.f, 0.f, 0.f};
+                acc = mma16(L.DUV + rt * 16 * HID, HID, 1, Wmat(L, l, 0) + ct * 16, HID, 1, HID, acc, lane);
+                const int col = ct * 16 + (lane & 15);
+#pragma unroll
+                for (int q = 0; q < 4; q++) L.DT[(rt * 16 + (lane >> 4) * 4 + q) * HID + col] = acc[q];
+            }
+            __syncthreads();
+            // dh_{l-1} += sum_{i in N(j)} dm_i / deg_i
+            for (int it = t; it < L.NP * HID; it += kNetThreads) {
+                const int j = it >> 5, f = it & 31;
+                if (j < n) {
+                    float s = 0.f;
+                    for (int c = L.cp[j]; c < L.cp[j + 1]; c++) {
+                        const int i = L.ri[c];
+                        s += L.DT[i * HID + f] / (float)(L.rp[i + 1] - L.rp[i]);
+                    }
+                    L.DH[it] += s;
+                }
+            }
+            __syncthreads();
+        }
+        // input layer
+        for (int it = t; it < n * HID; it += kNetThreads) {
+            const int j = it >> 5, f = it & 31;
+            if (bf2f(L.Hb[0][it]) > 0.f) {
+                const float du = L.DH[it];
+                const float x0 = tanhf(L.Lsh[j] * 0.125f), x1 = L.lam[j] * 0.125f;
+                atomicAdd(&L.svg[SV_W0 + f * 2], du * x0);
+                atomicAdd(&L.svg[SV_W0 + f * 2 + 1], du * x1);
+                atomicAdd(&L.svg[SV_B0 + f], du);
+            }
+        }
+        __syncthreads();
+    }
+    if (!train) return;
+    // flush: matrix tiles (acc rows = out feature, cols = in feature), vectors, loss
+#pragma unroll
+    for (int q = 0; q < 9; q++) {
+        const int layer = q / 3, which = q % 3;
+        const int base = P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
+        const int col = tcol + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = trow + (lane >> 4) * 4 + r;
+            atomicAdd(&A.grad[base + row * HID + col], gacc[q][r]);
+        }
+    }
+    __syncthreads();
+    for (int x = t; x < SV_N; x += kNetThreads) {
+        int off;
+        if (x < SV_B0) off = P_W0 + x;
+        else if (x < SV_A) off = P_B0 + (x - SV_B0);
+        else if (x < SV_BL) off = P_LAYER + ((x - SV_A) >> 5) * P_LSTRIDE + P_a + ((x - SV_A) & 31);
+        else if (x < SV_W) off = P_LAYER + ((x - SV_BL) >> 5) * P_LSTRIDE + P_b + ((x - SV_BL) & 31);
+        else if (x < SV_BO) off = P_W + (x - SV_W);
+        else off = P_BO;
+        atomicAdd(&A.grad[off], L.svg[x]);
+    }
+    if (t == 0) atomicAdd(A.loss, L.misc[0]);
+}
+
+__global__ void zero_f32(float *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+__global__ void adam_kernel(float *theta, const float *grad, float *m1, float *m2, int n, float lr, float b1t, float b2t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float a = 0.9f * m1[i] + 0.1f * g;
+    const float b = 0.999f * m2[i] + 0.001f * g * g;
+    m1[i] = a;
+    m2[i] = b;
+    theta[i] -= lr * (a / (1.f - b1t)) / (sqrtf(b / (1.f - b2t)) + 1e-8f);
+}
+
+}  // namespace
+
+size_t net_lds_bytes(const DevGraph &g, bool train) {
+    size_t o[10];
+    return net_layout(g.n, g.m, g.nnz, train, o);
+}
+
+static hipError_t launch_net(const NetArgs &a, int grid, hipStream_t st) {
+    const size_t lds = net_lds_bytes(a.g, a.train != 0);
+    hipError_t e = hipFuncSetAttribute((const void *)net_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(net_kernel, dim3(grid), dim3(kNetThreads), lds, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace qlsd
+
+using namespace qlsd;
+
+struct qlsd_net_s {
+    qlsd_code code;
+    DevGraph g;
+    float *d_lam = nullptr, *d_theta = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_grad = nullptr, *d_loss = nullptr;
+    int step = 0;
+    int num_cus = 0;
+    int infer_wg_per_cu = 1;
+};
+
+extern "C" {
+
+qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *params, qlsd_net *out) {
+    if (!out || !code || !priors || !params) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
+    *out = nullptr;
+    const DevGraph g = code_graph(code);
+    if (g.n >= 65535 || g.nnz >= 65535 || net_lds_bytes(g, true) > 159 * 1024) {
+        set_last_error("graph too large for the LDS-resident refinement network");
+        return QLSD_E_UNSUPPORTED;
+    }
+    std::vector<float> lam(g.n);
+    for (int j = 0; j < g.n; j++) {
+        if (!(priors[j] > 0.0 && priors[j] < 1.0)) { set_last_error("prior %d not in (0,1)", j); return QLSD_E_PRIOR; }
+        lam[j] = (float)log((1.0 - priors[j]) / priors[j]);
+    }
+    qlsd_net net = new (std::nothrow) qlsd_net_s();
+    if (!net) { set_last_error("host allocation failed"); return QLSD_E_NOMEM; }
+    net->code = code;
+    net->g = g;
+    bool ok = hipMalloc((void **)&net->d_lam, sizeof(float) * g.n) == hipSuccess &&
+              hipMalloc((void **)&net->d_theta, sizeof(float) * NPAR) == hipSuccess &&
+              hipMalloc((void **)&net->d_m1, sizeof(float) * NPAR) == hipSuccess &&
+              hipMalloc((void **)&net->d_m2, sizeof(float) * NPAR) == hipSuccess &&
+              hipMalloc((void **)&net->d_grad, sizeof(float) * NPAR) == hipSuccess &&
+              hipMalloc((void **)&net->d_loss, sizeof(float) * 4) == hipSuccess &&
+              hipMemcpy(net->d_lam, lam.data(), sizeof(float) * g.n, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(net->d_theta, params, sizeof(float) * NPAR, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(net->d_m1, 0, sizeof(float) * NPAR) == hipSuccess &&
+              hipMemset(net->d_m2, 0, sizeof(float) * NPAR) == hipSuccess;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    ok = ok && hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess;
+    if (!ok) {
+        qlsd_net_destroy(net);
+        set_last_error("device allocation failed");
+        return QLSD_E_NOMEM;
+    }
+    net->num_cus = prop.multiProcessorCount;
+    net->infer_wg_per_cu = std::max<int>(1, std::min<int>(8, (int)((160 * 1024) / (net_lds_bytes(g, false) + 1024))));
+    *out = net;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_net_set_params(qlsd_net net, const float *params) {
+    if (!net || !params) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
+    if (hipMemcpy(net->d_theta, params, sizeof(float) * NPAR, hipMemcpyHostToDevice) != hipSuccess) {
+        set_last_error("hipMemcpy failed");
+        return QLSD_E_DEVICE;
+    }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_net_get_params(qlsd_net net, float *params) {
+    if (!net || !params) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(params, net->d_theta, sizeof(float) * NPAR, hipMemcpyDeviceToHost) != hipSuccess) {
+        set_last_error("hipMemcpy failed");
+        return QLSD_E_DEVICE;
+    }
+    return QLSD_OK;
+}
+
+static NetArgs net_args(qlsd_net net) {
+    NetArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = net->g;
+    a.lam = net->d_lam;
+    a.theta = net->d_theta;
+    return a;
+}
+
+qlsd_status qlsd_net_forward(qlsd_net net, const uint8_t *syndromes, const float *llr, int32_t B, float *llr_out,
+                             void *stream) {
+    if (!net || B < 0 || (B > 0 && (!syndromes || !llr || !llr_out))) { set_last_error("bad arguments"); return QLSD_E_INVALID; }
+    if (B == 0) return QLSD_OK;
+    NetArgs a = net_args(net);
+    a.syn = syndromes;
+    a.llr = llr;
+    a.llr_out = llr_out;
+    a.count = B;
+    const int grid = std::min(B, net->num_cus * net->infer_wg_per_cu);
+    if (launch_net(a, grid, (hipStream_t)stream) != hipSuccess) { set_last_error("net launch failed"); return QLSD_E_DEVICE; }
+    return QLSD_OK;
+}
+
+static qlsd_status grad_impl(qlsd_net net, const uint8_t *syn, const float *llr, const uint8_t *err, int32_t B,
+                             float *grad, float *loss, hipStream_t st) {
+    hipLaunchKernelGGL(zero_f32, dim3((NPAR + 255) / 256), dim3(256), 0, st, grad, NPAR);
+    hipLaunchKernelGGL(zero_f32, dim3(1), dim3(64), 0, st, loss, 1);
+    NetArgs a = net_args(net);
+    a.syn = syn;
+    a.llr = llr;
+    a.err = err;
+    a.count = B;
+    a.grad = grad;
+    a.loss = loss;
+    a.inv_total = 1.f / ((float)B * (float)net->g.n);
+    a.train = 1;
+    const int grid = std::min(B, net->num_cus);
+    if (launch_net(a, grid, st) != hipSuccess) { set_last_error("net launch failed"); return QLSD_E_DEVICE; }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_net_gradient(qlsd_net net, const uint8_t *syndromes, const float *llr, const uint8_t *errors,
+                              int32_t B, float *grad, float *loss, void *stream) {
+    if (!net || B < 1 || !syndromes || !llr || !errors || !grad || !loss) { set_last_error("bad arguments"); return QLSD_E_INVALID; }
+    return grad_impl(net, syndromes, llr, errors, B, grad, loss, (hipStream_t)stream);
+}
+
+qlsd_status qlsd_net_train_step(qlsd_net net, const uint8_t *syndromes, const float *llr, const uint8_t *errors,
+                                int32_t B, float lr, void *stream) {
+    if (!net || B < 1 || !syndromes || !llr || !errors) { set_last_error("bad arguments"); return QLSD_E_INVALID; }
+    hipStream_t st = (hipStream_t)stream;
+    qlsd_status s = grad_impl(net, syndromes, llr, errors, B, net->d_grad, net->d_loss, st);
+    if (s != QLSD_OK) return s;
+    net->step++;
+    const float b1t = powf(0.9f, (float)net->step), b2t = powf(0.999f, (float)net->step);
+    hipLaunchKernelGGL(adam_kernel, dim3((NPAR + 255) / 256), dim3(256), 0, st, net->d_theta, net->d_grad, net->d_m1,
+                       net->d_m2, NPAR, lr, b1t, b2t);
+    if (hipGetLastError() != hipSuccess) { set_last_error("adam launch failed"); return QLSD_E_DEVICE; }
+    return QLSD_OK;
+}
+
+void qlsd_net_destroy(qlsd_net net) {
+    if (!net) return;
+    hipFree(net->d_lam);
+    hipFree(net->d_theta);
+    hipFree(net->d_m1);
+    hipFree(net->d_m2);
+    hipFree(net->d_grad);
+    hipFree(net->d_loss);
+    delete net;
+}
+
+}  // extern "C"
+
+namespace qlsd {
+// Refinement of the LLRs of the listed shots, in place (decode path).
+hipError_t net_refine_listed(qlsd_net_s *net, const uint8_t *syn, float *llr, const int *list, const int *list_count,
+                             int max_count, hipStream_t st) {
+    NetArgs a = net_args(net);
+    a.syn = syn;
+    a.llr = llr;
+    a.llr_out = llr;
+    a.list = list;
+    a.list_count = list_count;
+    a.count = max_count;
+    const int grid = std::max(1, std::min(max_count, net->num_cus * net->infer_wg_per_cu));
+    return launch_net(a, grid, st);
+}
+const float *net_loss_ptr(qlsd_net net) { return net->d_loss; }
+}  // namespace qlsd

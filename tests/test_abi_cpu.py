@@ -31,7 +31,9 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(decl) == set(binding.EXPORTS)
     serve = [x for x in _declared_symbols("qlsd_serve.h") if x.startswith("qlsd_server")]
     assert set(serve) == set(binding.SERVE_EXPORTS)
-    for name in decl + serve:
+    net = [x for x in _declared_symbols("qlsd_net.h") if x.startswith(("qlsd_net", "qlsd_decoder_set_net"))]
+    assert set(net) == set(binding.NET_EXPORTS)
+    for name in decl + serve + net:
         assert hasattr(lib, name), name
 
 
@@ -63,6 +65,10 @@ def test_info_layout_matches_header():
     assert binding.INFO_DTYPE.itemsize == 12
     assert ctypes.sizeof(binding.QlsdParams) == 20
     assert binding.COMPLETION_DTYPE.itemsize == 40
+    import oracle.learned as ol
+    with open(os.path.join(ROOT, "include", "qlsd_net.h")) as f:
+        assert f"#define QLSD_NET_PARAMS {ol.N_PARAMS}" in f.read()
+    assert binding.NET_PARAMS == ol.N_PARAMS
 
 
 def test_server_host_side_validation(lib):

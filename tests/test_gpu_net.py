@@ -1,0 +1,112 @@
+"""GPU parity of the learned refinement: bf16-MFMA forward and backward against the float64
+oracle (oracle/learned.py), identity at zero output weights, and training on the GPU."""
+import numpy as np
+import pytest
+
+import oracle.learned as ol
+from paper_2406_18655_amd import binding
+from paper_2406_18655_amd.workloads import bivariate_bicycle, sample
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    binding.lib()
+
+
+def _bp_failures(code, shots, seed, T=30):
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, shots, max_iter=T)
+    e, S = sample(code, shots, seed=seed)
+    s = torch.from_numpy(S).cuda()
+    llr, hard, info = dec.bp(s)
+    torch.cuda.synchronize()
+    inf = binding.parse_info(info)
+    idx = np.nonzero((inf["status"] & 1) == 0)[0]
+    return bc, e[idx], S[idx], llr.cpu().numpy()[idx]
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed)
+    th = ol.init_params(seed=seed, zero_output=False)
+    return (th + rng.normal(size=th.shape) * 0.05).astype(np.float32)
+
+
+def test_forward_matches_oracle():
+    code = bivariate_bicycle(p=0.06)
+    bc, e, S, L = _bp_failures(code, 2000, seed=4)
+    S, L = S[:64], L[:64]
+    th = _theta(7)
+    net = binding.Net(bc, code.priors, th)
+    out = net.forward(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda())
+    torch.cuda.synchronize()
+    d_gpu = out.cpu().numpy().astype(np.float64) - L.astype(np.float64)
+    lam = np.log((1 - code.priors) / code.priors).astype(np.float32).astype(np.float64)
+    worst = 0.0
+    for b in range(len(S)):
+        d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
+        rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
+        worst = max(worst, rel)
+        assert rel <= 2e-2, (b, rel)
+    print(f"worst relative L2 error of Delta: {worst:.2e}")
+
+
+def test_gradient_matches_oracle():
+    code = bivariate_bicycle(p=0.06)
+    bc, e, S, L = _bp_failures(code, 2000, seed=5)
+    S, L, e = S[:32], L[:32], e[:32]
+    th = _theta(8)
+    net = binding.Net(bc, code.priors, th)
+    g, loss = net.gradient(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda(), torch.from_numpy(e).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    lam = np.log((1 - code.priors) / code.priors).astype(np.float32).astype(np.float64)
+    l_ref, g_ref = ol.batch_loss_and_grad(th.astype(np.float64), code.H, [x.astype(np.float64) for x in L], lam, S, e)
+    assert abs(float(loss.item()) - l_ref) <= 1e-3 * max(1.0, abs(l_ref))
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
+    print(f"gradient relative L2 error {rel:.2e}, cosine {cos:.6f}")
+    assert rel <= 5e-2 and cos >= 0.998
+    # every parameter block is right, not only the dominant ones
+    off = 0
+    for name, shp in ol.PARAM_LAYOUT:
+        k = int(np.prod(shp))
+        gr, gg = g_ref[off:off + k], g[off:off + k]
+        if np.linalg.norm(gr) > 1e-6:
+            assert np.linalg.norm(gg - gr) / np.linalg.norm(gr) <= 0.1, name
+        off += k
+
+
+def test_zero_output_net_decodes_like_plain():
+    code = bivariate_bicycle(p=0.05)
+    bc = binding.Code.from_dense(code.H)
+    e, S = sample(code, 20000, seed=6)
+    s = torch.from_numpy(S).cuda()
+    plain = binding.Decoder(bc, code.priors, 20000, max_iter=50)
+    c0 = plain.decode(s).cpu().numpy()
+    learned = binding.Decoder(bc, code.priors, 20000, max_iter=50)
+    net = binding.Net(bc, code.priors, ol.init_params(seed=2, zero_output=True).astype(np.float32))
+    binding.attach_net(learned, net)
+    c1 = learned.decode(s).cpu().numpy()
+    assert (c0 == c1).all()
+
+
+def test_training_reduces_loss():
+    code = bivariate_bicycle(p=0.05)
+    bc, e, S, L = _bp_failures(code, 40000, seed=9)
+    th = ol.init_params(seed=0, zero_output=True).astype(np.float32)
+    net = binding.Net(bc, code.priors, th)
+    Sd, Ld, Ed = (torch.from_numpy(x).cuda() for x in (S, L, e))
+    _, l0 = net.gradient(Sd[:2048], Ld[:2048], Ed[:2048])
+    B = 512
+    for step in range(150):
+        k = (step * B) % (len(S) - B)
+        net.train_step(Sd[k:k + B], Ld[k:k + B], Ed[k:k + B], 2e-3)
+    _, l1 = net.gradient(Sd[:2048], Ld[:2048], Ed[:2048])
+    torch.cuda.synchronize()
+    print(f"loss {l0.item():.4f} -> {l1.item():.4f}")
+    assert l1.item() < l0.item()
