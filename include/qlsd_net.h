@@ -39,6 +39,9 @@ typedef struct qlsd_net_s *qlsd_net;
 /* priors: host double[n] (as for qlsd_decoder_create); params: host float[QLSD_NET_PARAMS]. */
 qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *params, qlsd_net *out);
 qlsd_status qlsd_net_set_params(qlsd_net net, const float *params);  /* host float[QLSD_NET_PARAMS]; synchronous */
+/* Replaces the priors (host double[n], each in (0,1)) that qlsd_net_forward, _gradient and
+ * _train_step feed the network, e.g. to train one net over several noise strengths; synchronous. */
+qlsd_status qlsd_net_set_priors(qlsd_net net, const double *priors);
 qlsd_status qlsd_net_get_params(qlsd_net net, float *params);        /* host float[QLSD_NET_PARAMS]; synchronous */
 
 /* llr_out = L + Delta for B shots: syndromes device u8[B*m], llr device float[B*n]
@@ -57,7 +60,9 @@ qlsd_status qlsd_net_train_step(qlsd_net net, const uint8_t *syndromes, const fl
                                 int32_t B, float lr, void *stream);
 
 /* Attach (or, with NULL, detach) a net to a decoder of the same code: qlsd_decode then runs
- * BP, the refinement on the shots BP did not solve, and LSD on the refined LLRs. */
+ * BP, the refinement on the shots BP did not solve, and LSD on the refined LLRs.  The attached
+ * net reads the decoder's priors (not its own), so one net may serve decoders of different
+ * noise strengths.  The net must outlive the attachment. */
 qlsd_status qlsd_decoder_set_net(qlsd_decoder dec, qlsd_net net);
 
 void qlsd_net_destroy(qlsd_net net);

@@ -310,7 +310,7 @@ class Server:
 
 # ------------------------------------------------------------------ learned refinement
 NET_PARAMS = 9537
-NET_EXPORTS = ["qlsd_net_create", "qlsd_net_set_params", "qlsd_net_get_params", "qlsd_net_forward",
+NET_EXPORTS = ["qlsd_net_create", "qlsd_net_set_params", "qlsd_net_set_priors", "qlsd_net_get_params", "qlsd_net_forward",
                "qlsd_net_gradient", "qlsd_net_train_step", "qlsd_decoder_set_net", "qlsd_net_destroy"]
 
 
@@ -320,6 +320,7 @@ def _net_lib():
         P, I32, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
         L.qlsd_net_create.argtypes = [P, P, P, ctypes.POINTER(P)]
         L.qlsd_net_set_params.argtypes = [P, P]
+        L.qlsd_net_set_priors.argtypes = [P, P]
         L.qlsd_net_get_params.argtypes = [P, P]
         L.qlsd_net_forward.argtypes = [P, P, P, I32, P, P]
         L.qlsd_net_gradient.argtypes = [P, P, P, P, I32, P, P, P]
@@ -348,6 +349,12 @@ class Net:
     def set_params(self, params: np.ndarray):
         th = np.ascontiguousarray(params, dtype=np.float32)
         _check(_net_lib().qlsd_net_set_params(self._h, th.ctypes.data))
+
+    def set_priors(self, priors: np.ndarray):
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        if pri.shape != (self.code.n,):
+            raise ValueError(f"priors must have shape ({self.code.n},)")
+        _check(_net_lib().qlsd_net_set_priors(self._h, pri.ctypes.data))
 
     def get_params(self) -> np.ndarray:
         out = np.empty(NET_PARAMS, dtype=np.float32)

@@ -344,7 +344,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     HIP_OK(run_bp(d, a, B, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
     HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
-    if (d->net) HIP_OK(net_refine_listed(d->net, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, s));
+    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
     l.list_count = d->d_ctl + 1;

@@ -314,6 +314,16 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
                     } else {
                         ncursor = 0;
                     }
+                } else if (obase >= 0) {
+                    // the current buffer holds nothing (drained or free): every fresh shot came
+                    // from the other buffer, which becomes the current one
+                    ncur = 1 - cur;
+                    ncursor = nfresh;
+                    if (ncursor >= ocount) {
+                        L.ctl[10 + 2 * ncur] = -2;
+                        L.ctl[11 + 2 * ncur] = 0;
+                        ncursor = 0;
+                    }
                 }
                 L.ctl[3] = ncur;
                 L.ctl[4] = ncursor;

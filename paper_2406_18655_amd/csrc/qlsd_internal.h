@@ -74,8 +74,8 @@ int code_cols(qlsd_code c);
 size_t decoder_device_bytes(qlsd_decoder d);  // workspace allocated by qlsd_decoder_create
 DevGraph code_graph(qlsd_code c);
 size_t net_lds_bytes(const DevGraph &g, bool train);
-hipError_t net_refine_listed(struct qlsd_net_s *net, const uint8_t *syn, float *llr, const int *list,
-                             const int *list_count, int max_count, hipStream_t st);
+hipError_t net_refine_listed(struct qlsd_net_s *net, const float *lam, const uint8_t *syn, float *llr,
+                             const int *list, const int *list_count, int max_count, hipStream_t st);
 
 constexpr int kBpThreads = 256;
 constexpr int kBpGraphThreads = 1024;

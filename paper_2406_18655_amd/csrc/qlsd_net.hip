@@ -31,11 +31,13 @@ constexpr int SV_W0 = 0, SV_B0 = 64, SV_A = 96, SV_BL = 192, SV_W = 288, SV_BO =
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// float -> bf16, round to nearest even (gfx950 converts in hardware: v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    const float2v v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2v));
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -149,7 +151,7 @@ __device__ void mean_checks(const NetLds &L, const uint16_t *Hsrc, uint16_t *dst
         if (i < L.m) {
             const int e0 = L.rp[i], e1 = L.rp[i + 1];
             for (int e = e0; e < e1; e++) s += bf2f(Hsrc[L.ci[e] * HID + f]);
-            s /= (float)(e1 - e0);
+            if (e1 > e0) s *= 1.0f / (float)(e1 - e0);
         }
         dst[it] = f2bf(s);
     }
@@ -161,7 +163,7 @@ __device__ void mean_faults(const NetLds &L, const uint16_t *Csrc, uint16_t *dst
         if (j < L.n) {
             const int c0 = L.cp[j], c1 = L.cp[j + 1];
             for (int c = c0; c < c1; c++) s += bf2f(Csrc[L.ri[c] * HID + f]);
-            if (c1 > c0) s /= (float)(c1 - c0);
+            if (c1 > c0) s *= 1.0f / (float)(c1 - c0);
         }
         dst[it] = f2bf(s);
     }
@@ -414,6 +416,241 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
     if (t == 0) atomicAdd(A.loss, L.misc[0]);
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Inference: one wavefront per shot, no workgroup barriers.  The A/B/C weight fragments of all
+// three layers sit in registers (9 matrices x 2 k-steps x 2 output tiles of 4 bf16 per lane).
+// Products are formed transposed, D = W X^T, so that after an MFMA a lane holds 4 consecutive
+// output features of one node -- the same fragment the next product reads -- and results
+// leave as packed 8-byte words.  The neighbour means enter by linearity,
+//     A m_i = (1/deg_i) sum_{j in N(i)} A h_j,     C g_j = (1/deg_j) sum_{i in N(j)} C c_i,
+// so each neighbour's bf16 feature words feed the MFMA directly (no unpacking or vector sums)
+// and the 1/deg scaling is applied to the float32 accumulator.  Neighbour lists are padded to
+// the maximum degree with a zero sentinel row.  Compared with forward_shot (the training
+// forward) the means are not rounded to bf16 before the product; everything else matches.
+// ------------------------------------------------------------------------------------------
+constexpr int kInferWaves = 5;
+
+__host__ __device__ inline size_t infer_shared_bytes(int n, int m, int dr, int dc) {
+    return al16(sizeof(float) * SV_N) + al16(sizeof(uint16_t) * ((size_t)pad16(m) * dr + (size_t)pad16(n) * dc)) +
+           al16(sizeof(float) * ((size_t)pad16(m) + pad16(n) + n));
+}
+__host__ __device__ inline size_t infer_wave_bytes(int n, int m) {
+    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID) + al16(sizeof(float) * (size_t)m);
+}
+
+// Feature rows are 64 B (32 bf16 = 8 chunks of 4).  Chunk c of node v is stored at chunk
+// position c ^ ((v >> 1) & 7) of its row: a half-wavefront reads one chunk pair of 16 nodes,
+// and the swizzle spreads those reads over all LDS banks (conflict-free for consecutive nodes).
+__device__ __forceinline__ int frag_off(int row_off, int c) {  // row_off = 64 * node
+    return row_off + ((c ^ ((row_off >> 7) & 7)) << 3);
+}
+__device__ __forceinline__ short4v lds_frag(const unsigned char *base, int row_off, int c) {
+    return *(const short4v *)(base + frag_off(row_off, c));
+}
+// Whole-row access: chunks (2q, 2q+1) stay an aligned 16-byte pair, possibly swapped.
+__device__ __forceinline__ int pair_off(int node, int q2, bool &swap) {
+    const int p = (2 * q2) ^ ((node >> 1) & 7);
+    swap = (p & 1) != 0;
+    return node * 64 + ((p & ~1) << 3);
+}
+
+template <int DR, int DC>
+__global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    const int n = A.g.n, m = A.g.m, NP = pad16(n), MP = pad16(m);
+    const int dr = DR ? DR : A.g.max_rw, dc = DC ? DC : A.g.max_cw;
+    float *sv = (float *)smem;
+    uint16_t *nbc = (uint16_t *)(smem + al16(sizeof(float) * SV_N));  // [MP][dr] byte offsets into H
+    uint16_t *nbf = nbc + (size_t)MP * dr;                             // [NP][dc] byte offsets into C
+    float *rdc = (float *)((unsigned char *)nbc + al16(sizeof(uint16_t) * ((size_t)MP * dr + (size_t)NP * dc)));
+    float *rdf = rdc + MP, *lam = rdf + NP;
+    unsigned char *wbase = smem + infer_shared_bytes(n, m, dr, dc) + (size_t)wave * infer_wave_bytes(n, m);
+    uint16_t *H = (uint16_t *)wbase;                 // (NP + 1) x 32, row NP is zero
+    uint16_t *Cf = H + (size_t)(NP + 1) * HID;       // (MP + 1) x 32, row MP is zero
+    float *sg = (float *)(wbase + al16(sizeof(uint16_t) * ((size_t)NP + 1 + MP + 1) * HID));  // +-1 per check
+    unsigned char *Hb = (unsigned char *)H, *Cb = (unsigned char *)Cf;
+
+    for (int x = t; x < SV_N; x += blockDim.x) {
+        float v;
+        if (x < SV_B0) v = A.theta[P_W0 + x];
+        else if (x < SV_A) v = A.theta[P_B0 + (x - SV_B0)];
+        else if (x < SV_BL) { const int l = (x - SV_A) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_a + ((x - SV_A) & 31)]; }
+        else if (x < SV_W) { const int l = (x - SV_BL) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_b + ((x - SV_BL) & 31)]; }
+        else if (x < SV_BO) v = A.theta[P_W + (x - SV_W)];
+        else v = A.theta[P_BO];
+        sv[x] = v;
+    }
+    for (int x = t; x < MP * dr; x += blockDim.x) {
+        const int i = x / dr, k = x - i * dr;
+        int off = NP * HID * 2;
+        if (i < m) {
+            const int e0 = A.g.row_ptr[i], e1 = A.g.row_ptr[i + 1];
+            if (e0 + k < e1) off = A.g.col_idx[e0 + k] * HID * 2;
+        }
+        nbc[x] = (uint16_t)off;
+    }
+    for (int x = t; x < NP * dc; x += blockDim.x) {
+        const int j = x / dc, k = x - j * dc;
+        int off = MP * HID * 2;
+        if (j < n) {
+            const int c0 = A.g.col_ptr[j], c1 = A.g.col_ptr[j + 1];
+            if (c0 + k < c1) off = A.g.row_idx[c0 + k] * HID * 2;
+        }
+        nbf[x] = (uint16_t)off;
+    }
+    for (int x = t; x < MP; x += blockDim.x) {
+        const int d = x < m ? A.g.row_ptr[x + 1] - A.g.row_ptr[x] : 0;
+        rdc[x] = d > 0 ? 1.0f / (float)d : 0.f;
+    }
+    for (int x = t; x < NP; x += blockDim.x) {
+        const int d = x < n ? A.g.col_ptr[x + 1] - A.g.col_ptr[x] : 0;
+        rdf[x] = d > 0 ? 1.0f / (float)d : 0.f;
+        if (x < n) lam[x] = A.lam[x];
+    }
+    // sentinel rows (never written again)
+    if (lane < 16) {
+        ((uint32_t *)(H + (size_t)NP * HID))[lane] = 0u;
+        ((uint32_t *)(Cf + (size_t)MP * HID))[lane] = 0u;
+    }
+    __syncthreads();
+
+    // A-operand fragments: wf[mat][ks][ot] = W[ot*16 + (lane&15)][ks*16 + 4(lane>>4) .. +3]
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    short4v wf[9][2][2];
+#pragma unroll
+    for (int mat = 0; mat < 9; mat++) {
+        const int layer = mat / 3, which = mat % 3;
+        const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+            for (int ot = 0; ot < 2; ot++) {
+                const float *w = W + (ot * 16 + r16) * HID + ks * 16 + kq;
+                const uint32_t lo = pack_bf16x2(w[0], w[1]), hi = pack_bf16x2(w[2], w[3]);
+                wf[mat][ks][ot] = __builtin_bit_cast(short4v, make_uint2(lo, hi));
+            }
+    }
+
+    const int total = A.list ? *A.list_count : A.count;
+    for (int item = blockIdx.x * kInferWaves + wave; item < total; item += gridDim.x * kInferWaves) {
+        const int shot = A.list ? A.list[item] : item;
+        const uint8_t *syn = A.syn + (size_t)shot * m;
+        const float *llr = A.llr + (size_t)shot * n;
+        for (int i = lane; i < m; i += 64) sg[i] = (syn[i] & 1) ? -1.f : 1.f;
+        // input layer: lane j computes tanh once and writes its fault's 32 features (4 x 16 B)
+        for (int j = lane; j < NP; j += 64) {
+            float x0 = 0.f, x1 = 0.f;
+            if (j < n) { x0 = tanhf(llr[j] * 0.125f); x1 = lam[j] * 0.125f; }
+#pragma unroll
+            for (int f8 = 0; f8 < HID; f8 += 8) {
+                uint32_t w[4];
+#pragma unroll
+                for (int h2 = 0; h2 < 4; h2++) {
+                    const int f = f8 + 2 * h2;
+                    float v0 = 0.f, v1 = 0.f;
+                    if (j < n) {
+                        v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
+                        v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
+                    }
+                    w[h2] = pack_bf16x2(v0, v1);
+                }
+                bool sw;
+                const int o = pair_off(j, f8 >> 3, sw);
+                *(uint4 *)(Hb + o) = sw ? make_uint4(w[2], w[3], w[0], w[1]) : make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            // checks: c_i = relu((1/deg_i) sum_j A h_j + sigma_i a)
+            for (int rt = 0; rt < MP / 16; rt++) {
+                const int i = rt * 16 + r16;
+                float4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                const uint16_t *nb = nbc + i * dr;
+#pragma unroll
+                for (int k = 0; k < (DR ? DR : dr); k++) {
+                    const int off = nb[k];
+                    const short4v x0 = lds_frag(Hb, off, kq >> 2), x1 = lds_frag(Hb, off, 4 + (kq >> 2));
+#pragma unroll
+                    for (int ot = 0; ot < 2; ot++) {
+                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][0][ot], x0, acc[ot], 0, 0, 0);
+                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][1][ot], x1, acc[ot], 0, 0, 0);
+                    }
+                }
+                const float rd = rdc[i], sgn = i < m ? sg[i] : 0.f;
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    const float4v av = *(const float4v *)(sv + SV_A + l * HID + ot * 16 + kq);
+                    float v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc[ot][q] + sgn * av[q], 0.f);
+                    *(uint2 *)(Cb + frag_off(i * 64, ot * 4 + (kq >> 2))) =
+                        make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b)   (in place: a lane reads and
+            // writes only its own node's words)
+            for (int rt = 0; rt < NP / 16; rt++) {
+                const int j = rt * 16 + r16;
+                const short4v h0 = lds_frag(Hb, j * 64, kq >> 2), h1 = lds_frag(Hb, j * 64, 4 + (kq >> 2));
+                float4v as[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                float4v an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][0][ot], h0, as[ot], 0, 0, 0);
+                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][1][ot], h1, as[ot], 0, 0, 0);
+                }
+                const uint16_t *nb = nbf + j * dc;
+#pragma unroll
+                for (int k = 0; k < (DC ? DC : dc); k++) {
+                    const int off = nb[k];
+                    const short4v y0 = lds_frag(Cb, off, kq >> 2), y1 = lds_frag(Cb, off, 4 + (kq >> 2));
+#pragma unroll
+                    for (int ot = 0; ot < 2; ot++) {
+                        an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][0][ot], y0, an[ot], 0, 0, 0);
+                        an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][1][ot], y1, an[ot], 0, 0, 0);
+                    }
+                }
+                const float rd = rdf[j];
+                const bool live = j < n;
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    const float4v bv = *(const float4v *)(sv + SV_BL + l * HID + ot * 16 + kq);
+                    float v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = live ? fmaxf(as[ot][q] + rd * an[ot][q] + bv[q], 0.f) : 0.f;
+                    *(uint2 *)(Hb + frag_off(j * 64, ot * 4 + (kq >> 2))) =
+                        make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int j = lane; j < n; j += 64) {
+            float d = sv[SV_BO];
+#pragma unroll
+            for (int f8 = 0; f8 < 4; f8++) {
+                bool sw;
+                const uint4 v = *(const uint4 *)(Hb + pair_off(j, f8, sw));
+                const uint32_t w[4] = {sw ? v.z : v.x, sw ? v.w : v.y, sw ? v.x : v.z, sw ? v.y : v.w};
+#pragma unroll
+                for (int h2 = 0; h2 < 4; h2++) {
+                    d += sv[SV_W + f8 * 8 + 2 * h2] * __uint_as_float(w[h2] << 16);
+                    d += sv[SV_W + f8 * 8 + 2 * h2 + 1] * __uint_as_float(w[h2] & 0xffff0000u);
+                }
+            }
+            A.llr_out[(size_t)shot * n + j] = llr[j] + d;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
 __global__ void zero_f32(float *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -445,6 +682,29 @@ static hipError_t launch_net(const NetArgs &a, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 
+static size_t infer_lds_bytes(const DevGraph &g) {
+    return infer_shared_bytes(g.n, g.m, g.max_rw, g.max_cw) + kInferWaves * infer_wave_bytes(g.n, g.m);
+}
+
+// Inference launch: grid sized for the device, one wavefront per shot; the neighbour loops are
+// unrolled for codes of maximum row / column weight 6 / 3 (the bivariate bicycle codes), and run
+// to the code's maximum weights otherwise.
+template <int UR, int UF>
+static hipError_t launch_infer_t(const NetArgs &a, int max_items, int num_cus, hipStream_t st) {
+    const size_t lds = infer_lds_bytes(a.g);
+    hipError_t e = hipFuncSetAttribute((const void *)net_infer_kernel<UR, UF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
+    const int grid = std::max(1, std::min((max_items + kInferWaves - 1) / kInferWaves, num_cus * per_cu));
+    hipLaunchKernelGGL((net_infer_kernel<UR, UF>), dim3(grid), dim3(64 * kInferWaves), lds, st, a);
+    return hipGetLastError();
+}
+static hipError_t launch_infer(const NetArgs &a, int max_items, int num_cus, hipStream_t st) {
+    if (a.g.max_rw == 6 && a.g.max_cw == 3) return launch_infer_t<6, 3>(a, max_items, num_cus, st);
+    return launch_infer_t<0, 0>(a, max_items, num_cus, st);
+}
+
 }  // namespace qlsd
 
 using namespace qlsd;
@@ -455,7 +715,6 @@ struct qlsd_net_s {
     float *d_lam = nullptr, *d_theta = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_grad = nullptr, *d_loss = nullptr;
     int step = 0;
     int num_cus = 0;
-    int infer_wg_per_cu = 1;
 };
 
 extern "C" {
@@ -464,7 +723,9 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
     if (!out || !code || !priors || !params) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
     *out = nullptr;
     const DevGraph g = code_graph(code);
-    if (g.n >= 65535 || g.nnz >= 65535 || net_lds_bytes(g, true) > 159 * 1024) {
+    // u16 tables: CSR entries, and byte offsets of feature rows (64 B each) in inference
+    if (g.n >= 65535 || g.nnz >= 65535 || pad16(g.n) + 1 > 1023 || pad16(g.m) + 1 > 1023 ||
+        net_lds_bytes(g, true) > 159 * 1024 || infer_lds_bytes(g) > 159 * 1024) {
         set_last_error("graph too large for the LDS-resident refinement network");
         return QLSD_E_UNSUPPORTED;
     }
@@ -496,8 +757,21 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
         return QLSD_E_NOMEM;
     }
     net->num_cus = prop.multiProcessorCount;
-    net->infer_wg_per_cu = std::max<int>(1, std::min<int>(8, (int)((160 * 1024) / (net_lds_bytes(g, false) + 1024))));
     *out = net;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_net_set_priors(qlsd_net net, const double *priors) {
+    if (!net || !priors) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
+    std::vector<float> lam(net->g.n);
+    for (int j = 0; j < net->g.n; j++) {
+        if (!(priors[j] > 0.0 && priors[j] < 1.0)) { set_last_error("prior %d not in (0,1)", j); return QLSD_E_PRIOR; }
+        lam[j] = (float)log((1.0 - priors[j]) / priors[j]);
+    }
+    if (hipMemcpy(net->d_lam, lam.data(), sizeof(float) * net->g.n, hipMemcpyHostToDevice) != hipSuccess) {
+        set_last_error("hipMemcpy failed");
+        return QLSD_E_DEVICE;
+    }
     return QLSD_OK;
 }
 
@@ -538,8 +812,10 @@ qlsd_status qlsd_net_forward(qlsd_net net, const uint8_t *syndromes, const float
     a.llr = llr;
     a.llr_out = llr_out;
     a.count = B;
-    const int grid = std::min(B, net->num_cus * net->infer_wg_per_cu);
-    if (launch_net(a, grid, (hipStream_t)stream) != hipSuccess) { set_last_error("net launch failed"); return QLSD_E_DEVICE; }
+    if (launch_infer(a, B, net->num_cus, (hipStream_t)stream) != hipSuccess) {
+        set_last_error("net launch failed");
+        return QLSD_E_DEVICE;
+    }
     return QLSD_OK;
 }
 
@@ -596,17 +872,17 @@ void qlsd_net_destroy(qlsd_net net) {
 
 namespace qlsd {
 // Refinement of the LLRs of the listed shots, in place (decode path).
-hipError_t net_refine_listed(qlsd_net_s *net, const uint8_t *syn, float *llr, const int *list, const int *list_count,
-                             int max_count, hipStream_t st) {
+hipError_t net_refine_listed(qlsd_net_s *net, const float *lam, const uint8_t *syn, float *llr, const int *list,
+                             const int *list_count, int max_count, hipStream_t st) {
     NetArgs a = net_args(net);
+    a.lam = lam;  // the decoder's prior LLRs, so one net serves decoders of any noise strength
     a.syn = syn;
     a.llr = llr;
     a.llr_out = llr;
     a.list = list;
     a.list_count = list_count;
     a.count = max_count;
-    const int grid = std::max(1, std::min(max_count, net->num_cus * net->infer_wg_per_cu));
-    return launch_net(a, grid, st);
+    return launch_infer(a, max_count, net->num_cus, st);
 }
 const float *net_loss_ptr(qlsd_net net) { return net->d_loss; }
 }  // namespace qlsd

@@ -5,7 +5,7 @@ import pytest
 
 import oracle.learned as ol
 from paper_2406_18655_amd import binding
-from paper_2406_18655_amd.workloads import bivariate_bicycle, sample
+from paper_2406_18655_amd.workloads import bivariate_bicycle, surface_hgp, sample
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -110,3 +110,67 @@ def test_training_reduces_loss():
     torch.cuda.synchronize()
     print(f"loss {l0.item():.4f} -> {l1.item():.4f}")
     assert l1.item() < l0.item()
+
+
+def test_forward_matches_oracle_irregular_code():
+    """The distance-5 surface code (row weights 2..4, column weights 1..2): the kernel instance
+    that walks neighbour lists of the code's own maximum weights, padded with a zero row."""
+    code = surface_hgp(5, 0.1)
+    bc, e, S, L = _bp_failures(code, 4000, seed=12)
+    S, L = S[:64], L[:64]
+    th = _theta(9)
+    net = binding.Net(bc, code.priors, th)
+    out = net.forward(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda())
+    torch.cuda.synchronize()
+    d_gpu = out.cpu().numpy().astype(np.float64) - L.astype(np.float64)
+    lam = np.log((1 - code.priors) / code.priors).astype(np.float32).astype(np.float64)
+    for b in range(len(S)):
+        d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
+        rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
+        assert rel <= 2e-2, (b, rel)
+
+
+def test_set_priors_equals_fresh_net():
+    code_a, code_b = bivariate_bicycle(p=0.03), bivariate_bicycle(p=0.06)
+    bc, e, S, L = _bp_failures(code_b, 2000, seed=13)
+    th = _theta(10)
+    s, l = torch.from_numpy(S[:256]).cuda(), torch.from_numpy(L[:256]).cuda()
+    moved = binding.Net(bc, code_a.priors, th)
+    moved.set_priors(code_b.priors)
+    fresh = binding.Net(bc, code_b.priors, th)
+    assert torch.equal(moved.forward(s, l), fresh.forward(s, l))
+
+
+def test_trained_net_gain():
+    """What the trained refinement buys on held-out shots of [[144,12,12]] at p = 0.05 (weights
+    trained by paper_2406_18655_amd.train_ordering on other seeds): BP with 10 iterations, the
+    net and LSD against plain BP+LSD with 50 and with 10 iterations, paired on the same shots
+    (McNemar: shots one decoder gets right and the other wrong)."""
+    import os
+    from paper_2406_18655_amd.workloads import logical_failures
+    w = os.path.join(os.path.dirname(binding.__file__), "weights", "bb144_p0.05_T10.npy")
+    code = bivariate_bicycle(p=0.05)
+    bc = binding.Code.from_dense(code.H)
+    net = binding.Net(bc, code.priors, np.load(w))
+    B = 65536
+    decs = {"plain50": binding.Decoder(bc, code.priors, B, max_iter=50),
+            "plain10": binding.Decoder(bc, code.priors, B, max_iter=10),
+            "learned10": binding.Decoder(bc, code.priors, B, max_iter=10)}
+    binding.attach_net(decs["learned10"], net)
+    fails = {k: [] for k in decs}
+    for rep in range(2):
+        e, S = sample(code, B, seed=900_000 + rep)
+        s = torch.from_numpy(S).cuda()
+        for k, d in decs.items():
+            c = d.decode(s).cpu().numpy()
+            assert (((c.astype(np.int64) @ code.H.T.astype(np.int64)) & 1) == S).all(), k
+            fails[k].append(logical_failures(code, e, c))
+    f = {k: np.concatenate(v) for k, v in fails.items()}
+    ler = {k: float(v.mean()) for k, v in f.items()}
+    print("LER", ler)
+    for base in ("plain50", "plain10"):
+        b = int(np.sum(f[base] & ~f["learned10"]))  # learned fixes
+        c = int(np.sum(~f[base] & f["learned10"]))  # learned breaks
+        z = (b - c) / np.sqrt(max(b + c, 1))
+        print(f"vs {base}: fixes {b}, breaks {c}, z = {z:.1f}")
+        assert z > 3.0, (base, b, c)

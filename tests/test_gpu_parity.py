@@ -81,6 +81,37 @@ def test_bp_posteriors_fixed_iterations(oracle_mod, which, T, shots):
     print(f"worst relative error {worst:.3e}")
 
 
+@pytest.mark.parametrize("T", [1, 3, 5])
+def test_bp_short_budget_full_batch(oracle_mod, T):
+    """A full 65,536-shot batch with a tiny iteration budget: slots retire almost in lockstep,
+    so staging chunks drain in the same iteration as the next chunk lands (the queue hand-over
+    between the two staging buffers).  Every shot must come back once, with the oracle's
+    posteriors on a sample."""
+    code = bivariate_bicycle(p=0.05)
+    B = 65536
+    print(f"case bp_short_budget T={T} shots={B}", flush=True)
+    e, S = sample(code, B, seed=300 + T)
+    _, dec = make(code, T, B)
+    llr, hard, info = dec.bp(syn_dev(S))
+    torch.cuda.synchronize()
+    inf = binding.parse_info(info)
+    assert ((inf["bp_iters"] >= 1) & (inf["bp_iters"] <= T)).all()
+    L32 = llr.cpu().numpy().astype(np.float64)
+    oc = ocode(oracle_mod, code)
+    lam = oracle_mod.llr_from_priors(code.priors)
+    floor = np.abs(lam).min()
+    rng = np.random.default_rng(T)
+    picks = np.concatenate([rng.choice(B, 200, replace=False), [0, B - 1]])
+    same = 0
+    for b in picks:
+        conv, it, L64, h64 = oracle_mod.bp(oc, lam, S[b], T)
+        if bool(inf["status"][b] & 1) == conv and inf["bp_iters"][b] == it:
+            same += 1
+            err = np.abs(L32[b] - L64) / np.maximum(np.abs(L64), floor)
+            assert err.max() <= 1e-4, (b, float(err.max()))
+    assert same >= 0.99 * len(picks), same
+
+
 def test_bp_early_exit_matches_oracle(oracle_mod):
     code = bivariate_bicycle(p=0.05)
     e, S = sample(code, 2000, seed=7)
