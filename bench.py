@@ -40,9 +40,14 @@ def parse():
     ap.add_argument("--seed", type=int, default=20240626)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-ordering leg")
+    ap.add_argument("--learned-iter", type=int, default=10, help="BP iterations of the learned form")
     ap.add_argument("--serve", action="store_true",
                     help="streaming mode: Poisson arrivals over a mix of codes; one JSON line per rate")
     ap.add_argument("--serve-rates", default="1e5,1e6,1e7")
+    ap.add_argument("--serve-ordering", default="plain,learned",
+                    help="plain: BP+LSD for every code; learned: the [[144,12,12]] lanes run BP 10 + "
+                         "the trained refinement + LSD")
     ap.add_argument("--serve-requests", type=int, default=200000)
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "bp_traffic_bb144.json"),
                     help="HBM bytes per BP launch measured with rocprofv3 counters, if present")
@@ -154,6 +159,9 @@ def main():
            "lsd_fraction": round(float(np.mean(lsd_frac)), 4),
            "roofline": roofline}
 
+    if not args.no_learned:
+        out["learned"] = learned_leg(code, bcode, batches, args, out["ler"]["gpu"], shots_per_s)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"], ler_ref = cpu_baseline(code, e0, s0.cpu().numpy(), args)
         f_gpu = ler_gpu[0]
@@ -163,6 +171,53 @@ def main():
                            "two_sigma": round(2 * float(np.sqrt(p * (1 - p) / B)), 6),
                            "matched": bool(abs(f_gpu.mean() - ler_ref.mean()) <= 2 * np.sqrt(p * (1 - p) / B))})
     print(json.dumps(out), flush=True)
+
+
+def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
+    """The learned form on the same batches: BP with fewer iterations, the trained refinement of
+    the shots BP leaves unsolved, then LSD; timed like the headline (K steps, inputs in HBM)."""
+    import torch
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import logical_failures
+    wdir = os.path.join(HERE, "paper_2406_18655_amd", "weights")
+    wname = f"bb144_p{args.p:g}_T{args.learned_iter}.npy"
+    if not os.path.exists(os.path.join(wdir, wname)):
+        wname = f"bb144_mix_T{args.learned_iter}.npy"
+    B = args.shots
+    net = binding.Net(bcode, code.priors, np.load(os.path.join(wdir, wname)))
+    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter)
+    binding.attach_net(dec, net)
+    corr = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+    fails = []
+    for e, s in batches:
+        dec.decode_into(s, corr, None)
+        c = corr.cpu().numpy()
+        if not (((c.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == s.cpu().numpy()).all():
+            print("learned: correction does not satisfy its syndrome", file=sys.stderr)
+            sys.exit(3)
+        fails.append(logical_failures(code, e, c))
+    for k in range(args.warmup):
+        dec.decode_into(batches[k % len(batches)][1], corr, None)
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        dec.decode_into(batches[k % len(batches)][1], corr, None)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    f = np.concatenate(fails)
+    return {"weights": wname, "bp_max_iter": args.learned_iter, "value": round(args.steps * B / wall, 1),
+            "unit": "shots/s", "ms_per_step": round(wall * 1e3 / args.steps, 4),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
+                           "p99": round(float(np.percentile(lat, 99)), 4)},
+            "ler": round(float(f.mean()), 6), "ler_plain": ler_plain,
+            "speedup_vs_plain": round(args.steps * B / wall / plain_shots_per_s, 3),
+            "shots_scored": int(f.size)}
 
 
 def _kernel_hash():
@@ -216,13 +271,18 @@ def serve_main(args):
     for k, (name, code, T, mu, bs) in enumerate(mix):
         e, S = sample(code, per_code, seed=args.seed + 100 + k)
         pools.append(S)
-    for rate in [float(x) for x in args.serve_rates.split(",")]:
+    weights = os.path.join(HERE, "paper_2406_18655_amd", "weights", "bb144_mix_T10.npy")
+    for ordering, rate in [(o, float(x)) for o in args.serve_ordering.split(",") for x in args.serve_rates.split(",")]:
         rng = np.random.default_rng(args.seed)
         srv = binding.Server(64 << 30)
         outs, cids = [], []
         for k, (name, code, T, mu, bs) in enumerate(mix):
-            cid, lanes = srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=bs, max_lanes=3,
-                                      max_iter=T, lsd_order=mu)
+            bc = binding.Code.from_dense(code.H)
+            learned = ordering == "learned" and name == "bb144"
+            cid, lanes = srv.add_code(bc, code.priors, batch_shots=bs, max_lanes=3,
+                                      max_iter=10 if learned else T, lsd_order=mu)
+            if learned:
+                srv.set_net(cid, binding.Net(bc, code.priors, np.load(weights)))
             arr = np.cumsum(rng.exponential(1e6 / (rate / len(mix)), size=per_code))
             out = np.zeros((per_code, code.n), dtype=np.uint8)
             srv.submit_many(cid, pools[k], out, np.arange(per_code, dtype=np.uint64), arr)
@@ -246,7 +306,9 @@ def serve_main(args):
                           "throughput_shots_per_s": round(total / span_s, 1),
                           "p50_us": round(float(np.percentile(lat, 50)), 1),
                           "p99_us": round(float(np.percentile(lat, 99)), 1),
-                          "per_code": codes, "ordering": "plain BP+LSD",
+                          "per_code": codes,
+                          "ordering": "plain BP+LSD" if ordering == "plain" else
+                                      "[[144,12,12]]: BP 10 + learned refinement + LSD; others plain",
                           "latency_includes": "host staging, PCIe copies, scheduler polling"}), flush=True)
 
 

@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include "qlsd.h"
+#include "qlsd_net.h"
 
 #ifdef __cplusplus
 extern "C" {
@@ -56,6 +57,11 @@ qlsd_status qlsd_server_create(size_t device_budget_bytes, qlsd_server *out);
 qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_params *params,
                                  const double *priors, int32_t batch_shots, int32_t max_lanes,
                                  int32_t *code_id, int32_t *lanes_out);
+
+/* Attaches a learned LLR refinement (include/qlsd_net.h, built for the same code) to every lane
+ * of code_id, or detaches it with net = NULL; only before qlsd_server_start.  The net is shared
+ * read-only by the lanes and must outlive the server. */
+qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net);
 
 /* Queues count requests of one code: syndromes host u8[count*m], corrections_out host
  * u8[count*n] (written on completion), tags[count], arrival_us[count] (server clock; NULL =

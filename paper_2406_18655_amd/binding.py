@@ -212,7 +212,7 @@ def parse_info(info) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------- serving
-SERVE_EXPORTS = ["qlsd_server_create", "qlsd_server_add_code", "qlsd_server_submit_many",
+SERVE_EXPORTS = ["qlsd_server_create", "qlsd_server_add_code", "qlsd_server_set_net", "qlsd_server_submit_many",
                  "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions",
                  "qlsd_server_now_us", "qlsd_server_destroy"]
 
@@ -230,13 +230,14 @@ def _serve_lib():
         L.qlsd_server_add_code.argtypes = [P, P, ctypes.POINTER(QlsdParams), P, I32, I32,
                                            ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.qlsd_server_submit_many.argtypes = [P, I32, I32, P, P, P, P]
+        L.qlsd_server_set_net.argtypes = [P, I32, P]
         L.qlsd_server_start.argtypes = [P]
         L.qlsd_server_wait.argtypes = [P, I64, D]
         L.qlsd_server_completions.argtypes = [P, P, I32, ctypes.POINTER(I32)]
         L.qlsd_server_now_us.argtypes = [P]
         L.qlsd_server_now_us.restype = D
         L.qlsd_server_destroy.argtypes = [P]
-        for fn in ("qlsd_server_create", "qlsd_server_add_code", "qlsd_server_submit_many",
+        for fn in ("qlsd_server_create", "qlsd_server_add_code", "qlsd_server_set_net", "qlsd_server_submit_many",
                    "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions"):
             getattr(L, fn).restype = ctypes.c_int
         L._serve_ready = True
@@ -267,6 +268,13 @@ class Server:
         self.codes[cid.value] = (code.m, code.n)
         self._keep.append(code)
         return cid.value, lanes.value
+
+    def set_net(self, code_id: int, net: Optional["Net"]):
+        """Attach a learned refinement to every lane of code_id (before start); the server keeps
+        a reference so the net outlives it."""
+        _net_lib()
+        _check(_serve_lib().qlsd_server_set_net(self._h, int(code_id), None if net is None else net._h))
+        self._keep.append(net)
 
     def submit_many(self, code_id: int, syndromes: np.ndarray, outputs: np.ndarray, tags: np.ndarray,
                     arrival_us: Optional[np.ndarray] = None):

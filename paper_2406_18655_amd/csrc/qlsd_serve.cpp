@@ -223,6 +223,16 @@ qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_param
     return QLSD_OK;
 }
 
+qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net) {
+    if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
+    if (s->started.load()) return serr(s, QLSD_E_INVALID, "nets must be attached before qlsd_server_start");
+    for (Lane &l : s->codes[code_id]->lanes) {
+        const qlsd_status st = qlsd_decoder_set_net(l.dec, net);
+        if (st != QLSD_OK) return st;
+    }
+    return QLSD_OK;
+}
+
 qlsd_status qlsd_server_submit_many(qlsd_server s, int32_t code_id, int32_t count, const uint8_t *syndromes,
                                     uint8_t *corrections_out, const uint64_t *tags, const double *arrival_us) {
     if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");

@@ -103,3 +103,33 @@ def test_budget_too_small_is_refused():
         srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=4096)
     assert ex.value.status == -3
     srv.close()
+
+
+def test_learned_lanes_equal_learned_alone():
+    """Lanes of the bivariate bicycle code carry the trained refinement (BP 10 iterations, net,
+    LSD) while a plain code shares the device: every correction equals that decoder run alone."""
+    import os
+    w = os.path.join(os.path.dirname(binding.__file__), "weights", "bb144_mix_T10.npy")
+    bb, sc = bivariate_bicycle(p=0.04), surface_hgp(5, p=0.05)
+    rng = np.random.default_rng(4)
+    srv = binding.Server(8 << 30)
+    bcb, bcs = binding.Code.from_dense(bb.H), binding.Code.from_dense(sc.H)
+    net = binding.Net(bcb, bb.priors, np.load(w))
+    cid_b, _ = srv.add_code(bcb, bb.priors, batch_shots=2048, max_lanes=2, max_iter=10)
+    srv.set_net(cid_b, net)
+    cid_s, _ = srv.add_code(bcs, sc.priors, batch_shots=1024, max_lanes=2, max_iter=30)
+    e_b, S_b = sample(bb, 3000, seed=71)
+    e_s, S_s = sample(sc, 1000, seed=72)
+    out_b = np.zeros((3000, bb.n), dtype=np.uint8)
+    out_s = np.zeros((1000, sc.n), dtype=np.uint8)
+    srv.submit_many(cid_b, S_b, out_b, np.arange(3000, dtype=np.uint64), np.cumsum(rng.exponential(5.0, 3000)))
+    srv.submit_many(cid_s, S_s, out_s, np.arange(1000, dtype=np.uint64), np.cumsum(rng.exponential(15.0, 1000)))
+    srv.start()
+    srv.wait(4000, timeout_s=120)
+    comp = srv.completions()
+    srv.close()
+    assert len(comp) == 4000 and comp["batch_size"].max() > 1
+    alone = binding.Decoder(bcb, bb.priors, 3000, max_iter=10)
+    binding.attach_net(alone, net)
+    np.testing.assert_array_equal(out_b, alone.decode(torch.from_numpy(S_b).cuda()).cpu().numpy())
+    np.testing.assert_array_equal(out_s, _alone(sc, 30, 0, S_s))
