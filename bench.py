@@ -49,6 +49,9 @@ def parse():
                     help="plain: BP+LSD for every code; learned: the [[144,12,12]] lanes run BP 10 + "
                          "the trained refinement + LSD")
     ap.add_argument("--serve-requests", type=int, default=200000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (three launches), the "
+                         "reference for scaling HBM byte counters")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "bp_traffic_bb144.json"),
                     help="HBM bytes per BP launch measured with rocprofv3 counters, if present")
     return ap.parse_args()
@@ -312,9 +315,23 @@ def serve_main(args):
                           "latency_includes": "host staging, PCIe copies, scheduler polling"}), flush=True)
 
 
+def copy_calibration(nbytes):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the factor that turns
+    the decoder kernels' counter readings into bytes."""
+    import torch
+    x = torch.randint(0, 255, (nbytes,), dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3, "equal": bool(torch.equal(x, y))}), flush=True)
+
+
 if __name__ == "__main__":
     _a = parse()
-    if _a.serve:
+    if _a.copy_calibration:
+        copy_calibration(_a.copy_calibration)
+    elif _a.serve:
         serve_main(_a)
     else:
         main()

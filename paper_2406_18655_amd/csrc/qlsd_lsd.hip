@@ -184,7 +184,13 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col,
         if (rs < 0 && bp[s]) rs = s;
     }
     if (rs < 0) return false;
-    const int rl = __builtin_ctzll(bp[rs]);
+    // rs is wave-uniform but not a compile-time index: select by unrolled compare so that the
+    // basis stays in registers (a runtime array index would put it in scratch memory)
+    uint64_t bprs = 0;
+#pragma unroll
+    for (int s = 0; s < W; s++)
+        if (s == rs) bprs = bp[s];
+    const int rl = __builtin_ctzll(bprs);
     uint64_t R[W];
 #pragma unroll
     for (int w = 0; w < W; w++) {
@@ -215,9 +221,15 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col,
             for (int w = 0; w < W; w++) B.CT[s][w] = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
-    B.piv[rs] |= 1ull << rl;
+    bool sp_hit = false;
+#pragma unroll
+    for (int s = 0; s < W; s++)
+        if (s == rs) {
+            B.piv[s] |= 1ull << rl;
+            sp_hit = (B.sp[s] >> rl) & 1ull;
+        }
     if (lane == 0) S.colAt[rs * 64 + rl] = col;
-    if ((B.sp[rs] >> rl) & 1ull) {
+    if (sp_hit) {
 #pragma unroll
         for (int s = 0; s < W; s++) B.sp[s] ^= bp[s];
     }
@@ -252,6 +264,7 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
     }
     wave_sync();
     const int nnp = npc < K ? npc : K;
+#pragma unroll
     for (int s0 = 0; s0 < W; s0++) {
         while (roots[s0]) {
             const int c = s0 * 64 + __builtin_ctzll(roots[s0]);
