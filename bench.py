@@ -33,9 +33,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--shots", type=int, default=65536)
+    ap.add_argument("--workload", choices=["bb144", "dem"], default="bb144",
+                    help="bb144: [[144,12,12]] code capacity p=0.05, BP 50 + LSD-0, 65,536 shots (headline); "
+                         "dem: synthetic 936 x 8800 detector error model, BP 100 + LSD-10, 16,384 shots")
+    ap.add_argument("--shots", type=int, default=None)
     ap.add_argument("--p", type=float, default=0.05)
-    ap.add_argument("--max-iter", type=int, default=50)
+    ap.add_argument("--max-iter", type=int, default=None)
+    ap.add_argument("--lsd-order", type=int, default=None)
     ap.add_argument("--batches", type=int, default=4, help="distinct pre-generated batches cycled")
     ap.add_argument("--seed", type=int, default=20240626)
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
@@ -65,26 +69,35 @@ def bp_algorithmic_bytes(m, n, E, iters):
 
 def main():
     args = parse()
+    dem = args.workload == "dem"
+    args.shots = args.shots or (16384 if dem else 65536)
+    args.max_iter = args.max_iter or (100 if dem else 50)
+    args.lsd_order = args.lsd_order if args.lsd_order is not None else (10 if dem else 0)
+    if dem:
+        args.no_learned = True  # the refinement net is built for LDS-resident graphs
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); shots are independent, "
               "so a multi-GPU run would be N independent copies of this launch.", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2406_18655_amd import binding
-    from paper_2406_18655_amd.workloads import bivariate_bicycle, sample, logical_failures
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, synthetic_dem, sample, logical_failures, syndromes
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
-    code = bivariate_bicycle(p=args.p)
+    code = synthetic_dem() if dem else bivariate_bicycle(p=args.p)
     B = args.shots
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    log(f"workload {args.workload}: sampling {args.batches} batches of {args.shots} shots")
     batches = []
     for k in range(args.batches):
         e, S = sample(code, B, seed=args.seed + k)
         batches.append((e, torch.from_numpy(S).to(dev)))
     bcode = binding.Code.from_dense(code.H)
-    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, flags=binding.FLAG_STAGE_TIMING)
+    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=args.lsd_order,
+                          flags=binding.FLAG_STAGE_TIMING)
     corr = torch.empty((B, code.n), dtype=torch.uint8, device=dev)
     info = torch.empty((B, 12), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
@@ -99,11 +112,12 @@ def main():
         lsd_frac.append(float(((inf["status"] & binding.ST_LSD_RUN) != 0).mean()))
         c = corr.cpu().numpy()
         Sn = s.cpu().numpy()
-        if not (((c.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == Sn).all():
+        if not (syndromes(code, c) == Sn).all():
             print("correction does not satisfy its syndrome", file=sys.stderr)
             sys.exit(3)
         ler_gpu.append(logical_failures(code, e, c))
 
+    log("correctness pass done; warmup and timed steps")
     for k in range(args.warmup):
         dec.decode_into(batches[k % len(batches)][1], corr, None)
     torch.cuda.synchronize()
@@ -135,12 +149,12 @@ def main():
     bp_avg_ms = float(np.mean(bp_ms))
     achieved = bytes_per_launch / (bp_avg_ms * 1e-3) / 1e9
     traffic = None
-    if os.path.exists(args.traffic_json):
+    if not dem and os.path.exists(args.traffic_json):
         with open(args.traffic_json) as f:
             tj = json.load(f)
         if tj.get("kernel_source_hash") == _kernel_hash():
             traffic = tj.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "bp_lds_kernel", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": "bp_graph_kernel" if dem else "bp_lds_kernel", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_ms": round(bp_avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
@@ -148,31 +162,43 @@ def main():
 
     # logical error rate of the GPU run vs the oracle on the same shots (batch 0)
     e0, s0 = batches[0]
-    out = {"metric": METRIC, "value": round(shots_per_s, 1), "unit": "shots/s", "n_gpus": 1,
+    if dem:
+        cfg = {"workload": "dem936x8800_bp100_lsd10", "code": "synthetic detector error model, 12 rounds",
+               "H": f"{code.m}x{code.n}", "nnz": int(code.nnz), "priors": "log-uniform [1e-4, 1e-2]",
+               "shots_per_step": B, "max_iter": args.max_iter, "ms_scaling": 0.625, "lsd_order": args.lsd_order}
+        metric = "decoded shots/s, synthetic DEM 936x8800 (BP 100 + LSD-10); p50/p99 latency"
+    else:
+        cfg = {"workload": "bb144_codecap_p0.05_bp50_lsd0", "code": "[[144,12,12]] BB l=12 m=6",
+               "H": "72x144", "p": args.p, "shots_per_step": B, "max_iter": args.max_iter,
+               "ms_scaling": 0.625, "lsd_order": 0}
+        metric = METRIC
+    out = {"metric": metric, "value": round(shots_per_s, 1), "unit": "shots/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "bb144_codecap_p0.05_bp50_lsd0", "code": "[[144,12,12]] BB l=12 m=6",
-                      "H": "72x144", "p": args.p, "shots_per_step": B, "max_iter": args.max_iter,
-                      "ms_scaling": 0.625, "lsd_order": 0},
+           "config": cfg,
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                          "p99": round(float(np.percentile(lat, 99)), 4), "per": "launch of 65536 shots"},
+                          "p99": round(float(np.percentile(lat, 99)), 4), "per": f"launch of {B} shots"},
            "ler": {"gpu": round(float(np.mean([f.mean() for f in ler_gpu])), 6)},
            "bp_mean_iters": round(float(np.mean([it.mean() for it in iters_per_batch])), 3),
            "lsd_fraction": round(float(np.mean(lsd_frac)), 4),
            "roofline": roofline}
 
+    log(f"timed {args.steps} steps: {shots_per_s:.4g} shots/s")
     if not args.no_learned:
+        log("learned leg")
         out["learned"] = learned_leg(code, bcode, batches, args, out["ler"]["gpu"], shots_per_s)
 
     if not args.no_cpu_baseline:
+        log(f"cpu baseline (about {args.cpu_seconds:.0f} s)")
         out["cpu_baseline"], ler_ref = cpu_baseline(code, e0, s0.cpu().numpy(), args)
-        f_gpu = ler_gpu[0]
-        p = max(ler_ref.mean(), 1.0 / B)
+        f_gpu = ler_gpu[0][:ler_ref.size]
+        Bs = ler_ref.size
+        p = max(ler_ref.mean(), 1.0 / Bs)
         out["ler"].update({"gpu_batch0": round(float(f_gpu.mean()), 6),
                            "oracle_batch0": round(float(ler_ref.mean()), 6),
-                           "two_sigma": round(2 * float(np.sqrt(p * (1 - p) / B)), 6),
-                           "matched": bool(abs(f_gpu.mean() - ler_ref.mean()) <= 2 * np.sqrt(p * (1 - p) / B))})
+                           "two_sigma": round(2 * float(np.sqrt(p * (1 - p) / Bs)), 6),
+                           "matched": bool(abs(f_gpu.mean() - ler_ref.mean()) <= 2 * np.sqrt(p * (1 - p) / Bs))})
     print(json.dumps(out), flush=True)
 
 
@@ -181,7 +207,7 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     the shots BP leaves unsolved, then LSD; timed like the headline (K steps, inputs in HBM)."""
     import torch
     from paper_2406_18655_amd import binding
-    from paper_2406_18655_amd.workloads import logical_failures
+    from paper_2406_18655_amd.workloads import logical_failures, syndromes
     wdir = os.path.join(HERE, "paper_2406_18655_amd", "weights")
     wname = f"bb144_p{args.p:g}_T{args.learned_iter}.npy"
     if not os.path.exists(os.path.join(wdir, wname)):
@@ -195,7 +221,7 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     for e, s in batches:
         dec.decode_into(s, corr, None)
         c = corr.cpu().numpy()
-        if not (((c.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == s.cpu().numpy()).all():
+        if not (syndromes(code, c) == s.cpu().numpy()).all():
             print("learned: correction does not satisfy its syndrome", file=sys.stderr)
             sys.exit(3)
         fails.append(logical_failures(code, e, c))
@@ -239,19 +265,23 @@ def cpu_baseline(code, errors, S, args):
     oc = oracle.Code.from_dense(code.H)
     lam = oracle.llr_from_priors(code.priors)
     threads = min(16, os.cpu_count() or 1)
-    # one full pass over batch 0 gives the oracle's LER on the same shots
+    mu = args.lsd_order
+    omega = oracle.omega_from_llr(lam) if mu > 0 else None
+    if args.workload == "dem":  # the float64 oracle takes ~ms per DEM shot: a bounded sample
+        S, errors = S[:2048], errors[:2048]
+    # one full pass over the sample gives the oracle's LER on the same shots
     t0 = time.perf_counter()
-    corr, st, it, _ = oracle.decode_batch(oc, lam, S, args.max_iter, nthreads=threads)
+    corr, st, it, _ = oracle.decode_batch(oc, lam, S, args.max_iter, mu=mu, omega=omega, nthreads=threads)
     dt = time.perf_counter() - t0
     done, tot = S.shape[0], dt
     while tot < args.cpu_seconds:
         t0 = time.perf_counter()
-        oracle.decode_batch(oc, lam, S, args.max_iter, nthreads=threads)
+        oracle.decode_batch(oc, lam, S, args.max_iter, mu=mu, omega=omega, nthreads=threads)
         tot += time.perf_counter() - t0
         done += S.shape[0]
     ler_ref = logical_failures(code, errors, corr)
     base = {"value": round(done / tot, 1), "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": f"batch 0 ({S.shape[0]} shots) decoded {done // S.shape[0]}x, {tot:.1f} s"}
+            "sample": f"first {S.shape[0]} shots of batch 0 decoded {done // S.shape[0]}x, {tot:.1f} s"}
     return base, ler_ref
 
 

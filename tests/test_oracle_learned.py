@@ -48,3 +48,26 @@ def test_param_count_and_layout():
     assert ol.N_PARAMS == 9537
     p = ol.unpack(np.arange(ol.N_PARAMS, dtype=np.float64))
     assert p["W0"][0, 0] == 0 and p["A1"][0, 0] == 96 and p["bo"][0] == ol.N_PARAMS - 1
+
+
+def test_forward_hand_computed_example():
+    """Hand-worked forward pass on the length-3 repetition code (checks {0,1} and {1,2}) with
+    weights that route one feature: h0 = relu(tanh(L/8)) in feature 0; layer 1 has A = B = C = I,
+    a = -0.1 on feature 0 (syndrome sign enters as -1 for a flipped check); layers 2-3 pass h
+    through (B = I, A = C = 0); the output reads feature 0.  With tanh(L/8) = (0.5, 0.25, 0.75)
+    and s = (1, 0):
+        m = (0.375, 0.5)             (check means of h0)
+        c = (0.375 + 0.1, 0.5 - 0.1) = (0.475, 0.4)
+        g = (0.475, (0.475 + 0.4)/2, 0.4) = (0.475, 0.4375, 0.4)
+        h1 = h0 + g = (0.975, 0.6875, 1.15)  = Delta."""
+    H = np.array([[1, 1, 0], [0, 1, 1]], dtype=np.uint8)
+    p = {name: np.zeros(shp) for name, shp in ol.PARAM_LAYOUT}
+    p["W0"][0, 0] = 1.0
+    eye = np.eye(ol.HID)
+    p["A1"], p["B1"], p["C1"] = eye, eye, eye
+    p["a1"][0] = -0.1
+    p["B2"], p["B3"] = eye, eye
+    p["w"][0] = 1.0
+    L = 8.0 * np.arctanh(np.array([0.5, 0.25, 0.75]))
+    delta = ol.forward(ol.pack(p), H, L, np.full(3, 3.0), np.array([1, 0], dtype=np.uint8))
+    np.testing.assert_allclose(delta, [0.975, 0.6875, 1.15], rtol=0, atol=1e-12)
