@@ -45,7 +45,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-ordering leg")
-    ap.add_argument("--learned-iter", type=int, default=10, help="BP iterations of the learned form")
+    ap.add_argument("--learned-iter", type=int, default=None,
+                    help="BP iterations of the learned form (default 10 for bb144, 30 for dem)")
     ap.add_argument("--serve", action="store_true",
                     help="streaming mode: Poisson arrivals over a mix of codes; one JSON line per rate")
     ap.add_argument("--serve-rates", default="1e5,1e6,1e7")
@@ -73,8 +74,7 @@ def main():
     args.shots = args.shots or (16384 if dem else 65536)
     args.max_iter = args.max_iter or (100 if dem else 50)
     args.lsd_order = args.lsd_order if args.lsd_order is not None else (10 if dem else 0)
-    if dem:
-        args.no_learned = True  # the refinement net is built for LDS-resident graphs
+    args.learned_iter = args.learned_iter or (30 if dem else 10)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); shots are independent, "
               "so a multi-GPU run would be N independent copies of this launch.", file=sys.stderr)
@@ -209,12 +209,15 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     from paper_2406_18655_amd import binding
     from paper_2406_18655_amd.workloads import logical_failures, syndromes
     wdir = os.path.join(HERE, "paper_2406_18655_amd", "weights")
-    wname = f"bb144_p{args.p:g}_T{args.learned_iter}.npy"
-    if not os.path.exists(os.path.join(wdir, wname)):
-        wname = f"bb144_mix_T{args.learned_iter}.npy"
+    if args.workload == "dem":
+        wname = f"dem_T{args.learned_iter}.npy"
+    else:
+        wname = f"bb144_p{args.p:g}_T{args.learned_iter}.npy"
+        if not os.path.exists(os.path.join(wdir, wname)):
+            wname = f"bb144_mix_T{args.learned_iter}.npy"
     B = args.shots
     net = binding.Net(bcode, code.priors, np.load(os.path.join(wdir, wname)))
-    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter)
+    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
     binding.attach_net(dec, net)
     corr = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
     fails = []

@@ -17,8 +17,14 @@
  * products run on bf16 MFMA with float32 accumulation; sums over neighbours in float32.
  * With w = 0 and b_out = 0 the refinement is the identity, so decoding equals plain BP+LSD.
  *
- * Shapes: supported for graphs with (n + m) <= 512 nodes after padding to multiples of 16 (all
- * the LDS-resident codes; the 8800-fault detector model is not supported).
+ * Shapes: n and nnz below 65535 whose u16 CSR/CSC tables fit in LDS next to the weights (up to
+ * about 60k edges, e.g. the 936 x 8800 detector error model).  Small graphs keep all activations
+ * in LDS (inference: one wavefront per shot).  On larger ones training keeps activations in a
+ * device workspace the net allocates at its first gradient call (one slice per compute unit,
+ * about 6 MB each for the detector model), and inference runs one workgroup per shot over a
+ * feature workspace (about 0.6 MB per compute unit for the detector model): the net's own for
+ * qlsd_net_forward, the decoder's for decoding (allocated by qlsd_decoder_set_net).  Calls that
+ * use the net's own workspaces (forward, gradient, train_step) must not overlap in time.
  * All device pointers are caller-owned; calls are asynchronous on `stream` unless stated.
  */
 #ifndef QLSD_NET_H
@@ -59,7 +65,9 @@ qlsd_status qlsd_net_gradient(qlsd_net net, const uint8_t *syndromes, const floa
 qlsd_status qlsd_net_train_step(qlsd_net net, const uint8_t *syndromes, const float *llr, const uint8_t *errors,
                                 int32_t B, float lr, void *stream);
 
-/* Attach (or, with NULL, detach) a net to a decoder of the same code: qlsd_decode then runs
+/* Attach (or, with NULL, detach) a net to a decoder of the same code (QLSD_E_INVALID if the
+ * net was built for a matrix of another shape; on large graphs it allocates the decoder's
+ * feature workspace, QLSD_E_NOMEM if that fails): qlsd_decode then runs
  * BP, the refinement on the shots BP did not solve, and LSD on the refined LLRs.  The attached
  * net reads the decoder's priors (not its own), so one net may serve decoders of different
  * noise strengths.  The net must outlive the attachment. */

@@ -60,7 +60,8 @@ qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_param
 
 /* Attaches a learned LLR refinement (include/qlsd_net.h, built for the same code) to every lane
  * of code_id, or detaches it with net = NULL; only before qlsd_server_start.  The net is shared
- * read-only by the lanes and must outlive the server. */
+ * read-only by the lanes and must outlive the server.  On large graphs each lane's decoder gets a
+ * feature workspace, charged to the device budget (QLSD_E_NOMEM if it does not fit). */
 qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net);
 
 /* Queues count requests of one code: syndromes host u8[count*m], corrections_out host

@@ -71,6 +71,8 @@ struct qlsd_decoder_s {
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
     bool timing;
     qlsd_net net;       // optional refinement between BP and LSD
+    unsigned char *d_netws;  // feature workspace of the refinement on large graphs (else nullptr)
+    size_t netws_bytes;
 };
 
 namespace qlsd {
@@ -85,7 +87,8 @@ DevGraph code_graph(qlsd_code c) { return c->g; }
 int code_cols(qlsd_code c) { return c->g.n; }
 size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
-    return n * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float));
+    return n * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
+           d->netws_bytes;
 }
 }  // namespace qlsd
 
@@ -274,6 +277,7 @@ void qlsd_decoder_destroy(qlsd_decoder d) {
     hipFree(d->d_flag);
     hipFree(d->d_list);
     hipFree(d->d_llr);
+    hipFree(d->d_netws);
     for (int k = 0; k < 3; k++)
         if (d->ev[k]) hipEventDestroy(d->ev[k]);
     delete d;
@@ -344,7 +348,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     HIP_OK(run_bp(d, a, B, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
     HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
-    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, s));
+    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, d->d_netws, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
     l.list_count = d->d_ctl + 1;
@@ -397,6 +401,31 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder d, float *bp_ms, float *lsd_ms) {
 qlsd_status qlsd_decoder_set_net(qlsd_decoder d, qlsd_net net) {
     g_err[0] = 0;
     if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    if (net) {
+        int m = 0, n = 0;
+        net_graph_dims(net, &m, &n);
+        if (m != d->code->g.m || n != d->code->g.n)
+            return fail(QLSD_E_INVALID, "net built for a %dx%d code, the decoder's is %dx%d", m, n, d->code->g.m, d->code->g.n);
+    }
+    // large graphs: the decoder gets its own feature workspace, so decoders sharing one net may
+    // run concurrently on different streams
+    const size_t need = net ? net_infer_workspace_bytes(net) : 0;
+    if (need != d->netws_bytes) {
+        if (d->d_netws) {
+            hipDeviceSynchronize();
+            hipFree(d->d_netws);
+        }
+        d->d_netws = nullptr;
+        d->netws_bytes = 0;
+        if (need) {
+            if (hipMalloc((void **)&d->d_netws, need) != hipSuccess) {
+                d->d_netws = nullptr;
+                d->net = nullptr;
+                return fail(QLSD_E_NOMEM, "device allocation of the refinement workspace failed");
+            }
+            d->netws_bytes = need;
+        }
+    }
     d->net = net;
     return QLSD_OK;
 }

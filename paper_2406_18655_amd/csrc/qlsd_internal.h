@@ -74,8 +74,11 @@ int code_cols(qlsd_code c);
 size_t decoder_device_bytes(qlsd_decoder d);  // workspace allocated by qlsd_decoder_create
 DevGraph code_graph(qlsd_code c);
 size_t net_lds_bytes(const DevGraph &g, bool train);
+void net_graph_dims(const struct qlsd_net_s *net, int *m, int *n);
+size_t net_infer_workspace_bytes(const struct qlsd_net_s *net);  // 0 for LDS-resident inference
 hipError_t net_refine_listed(struct qlsd_net_s *net, const float *lam, const uint8_t *syn, float *llr,
-                             const int *list, const int *list_count, int max_count, hipStream_t st);
+                             const int *list, const int *list_count, int max_count, unsigned char *ws,
+                             hipStream_t st);
 
 constexpr int kBpThreads = 256;
 constexpr int kBpGraphThreads = 1024;

@@ -59,6 +59,12 @@ struct NetArgs {
     float *loss;            // 1 (training, accumulated)
     float inv_total;        // 1 / (shots * n) (training)
     int train;
+    unsigned char *act;     // activation workspace, one slice per workgroup (nullptr: in LDS)
+    size_t act_stride;      // bytes per slice
+    const uint32_t *nbc;    // large-graph inference: [MP][max_rw] byte offsets of fault rows (padded)
+    const uint32_t *nbf;    // [NP][max_cw] byte offsets of check rows (padded)
+    const float *rdc;       // [MP] 1 / check degree (0 on padding)
+    const float *rdf;       // [NP] 1 / fault degree
 };
 
 struct NetLds {
@@ -76,25 +82,36 @@ struct NetLds {
     float *misc;                 // [0] loss accumulator
 };
 
-__host__ __device__ inline size_t net_layout(int n, int m, int E, bool train, size_t *o) {
-    const int NP = pad16(n), MP = pad16(m), XP = NP > MP ? NP : MP;
+// Per-workgroup storage.  The shared part (bf16 weights, small vectors and their gradient
+// accumulators, u16 CSR/CSC tables, the loss accumulator) always sits in LDS.  The activation
+// part (the shot's BP posteriors, features of every layer, aggregation and backward buffers)
+// sits in LDS after it when both fit, else in a workgroup-private slice of a device workspace
+// (large graphs such as the 936 x 8800 detector error model); the kernels address both the same way.
+__host__ __device__ inline size_t net_shared_layout(int n, int m, int E, bool train, size_t *o) {
     size_t off = 0;
     o[0] = off; off += al16(sizeof(uint16_t) * 9 * 1024);
     o[1] = off; off += al16(sizeof(float) * SV_N);
     o[2] = off; off += train ? al16(sizeof(float) * SV_N) : 0;
     o[3] = off; off += al16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + E));
-    o[4] = off; off += al16(sizeof(float) * 2 * (size_t)n);
-    o[5] = off; off += al16(sizeof(uint16_t) * ((NL + 1) * (size_t)NP * HID + NL * (size_t)MP * HID));
-    o[6] = off; off += al16(sizeof(uint16_t) * (size_t)XP * HID);
-    o[7] = off; off += train ? al16(sizeof(uint16_t) * (size_t)XP * HID) : 0;
-    o[8] = off; off += train ? al16(sizeof(float) * ((size_t)NP + XP + MP) * HID) : 0;
-    o[9] = off; off += al16(sizeof(float) * 4);
+    o[4] = off; off += al16(sizeof(float) * 4);
+    return off;
+}
+__host__ __device__ inline size_t net_act_layout(int n, int m, bool train, size_t *o) {
+    const int NP = pad16(n), MP = pad16(m), XP = NP > MP ? NP : MP;
+    size_t off = 0;
+    o[0] = off; off += al16(sizeof(float) * (size_t)n);
+    o[1] = off; off += al16(sizeof(uint16_t) * ((NL + 1) * (size_t)NP * HID + NL * (size_t)MP * HID));
+    o[2] = off; off += al16(sizeof(uint16_t) * (size_t)XP * HID);
+    o[3] = off; off += train ? al16(sizeof(uint16_t) * (size_t)XP * HID) : 0;
+    o[4] = off; off += train ? al16(sizeof(float) * ((size_t)NP + XP + MP) * HID) : 0;
     return off;
 }
 
-__device__ NetLds carve_net(unsigned char *base, int n, int m, int E, bool train) {
-    size_t o[10];
-    net_layout(n, m, E, train, o);
+__device__ NetLds carve_net(unsigned char *base, unsigned char *act, int n, int m, int E, bool train,
+                            const float *lam) {
+    size_t o[5], a5[5];
+    net_shared_layout(n, m, E, train, o);
+    net_act_layout(n, m, train, a5);
     NetLds L;
     L.n = n; L.m = m; L.E = E; L.NP = pad16(n); L.MP = pad16(m);
     const int XP = L.NP > L.MP ? L.NP : L.MP;
@@ -105,18 +122,18 @@ __device__ NetLds carve_net(unsigned char *base, int n, int m, int E, bool train
     L.ci = L.rp + (m + 1);
     L.cp = L.ci + E;
     L.ri = L.cp + (n + 1);
-    L.lam = (float *)(base + o[4]);
-    L.Lsh = L.lam + n;
-    uint16_t *a = (uint16_t *)(base + o[5]);
+    L.misc = (float *)(base + o[4]);
+    L.lam = (float *)lam;
+    L.Lsh = (float *)(act + a5[0]);
+    uint16_t *a = (uint16_t *)(act + a5[1]);
     for (int l = 0; l <= NL; l++) { L.Hb[l] = a; a += (size_t)L.NP * HID; }
     L.Cb[0] = nullptr;
     for (int l = 1; l <= NL; l++) { L.Cb[l] = a; a += (size_t)L.MP * HID; }
-    L.AGG = (uint16_t *)(base + o[6]);
-    L.DUV = (uint16_t *)(base + o[7]);
-    L.DH = (float *)(base + o[8]);
+    L.AGG = (uint16_t *)(act + a5[2]);
+    L.DUV = (uint16_t *)(act + a5[3]);
+    L.DH = (float *)(act + a5[4]);
     L.DT = L.DH + (size_t)L.NP * HID;
     L.DC = L.DT + (size_t)XP * HID;
-    L.misc = (float *)(base + o[9]);
     return L;
 }
 
@@ -236,7 +253,10 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int n = A.g.n, m = A.g.m, E = A.g.nnz;
     const bool train = A.train != 0;
-    NetLds L = carve_net(smem, n, m, E, train);
+    size_t so[5];
+    const size_t shared_bytes = net_shared_layout(n, m, E, train, so);
+    unsigned char *act = A.act ? A.act + (size_t)blockIdx.x * A.act_stride : smem + shared_bytes;
+    NetLds L = carve_net(smem, act, n, m, E, train, A.lam);
 
     // weights: 32x32 matrices as bf16, vectors as float
     for (int x = t; x < 9 * 1024; x += kNetThreads) {
@@ -259,7 +279,6 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
     for (int x = t; x < E; x += kNetThreads) L.ci[x] = (uint16_t)A.g.col_idx[x];
     for (int x = t; x <= n; x += kNetThreads) L.cp[x] = (uint16_t)A.g.col_ptr[x];
     for (int x = t; x < E; x += kNetThreads) L.ri[x] = (uint16_t)A.g.row_idx[x];
-    for (int x = t; x < n; x += kNetThreads) L.lam[x] = A.lam[x];
     if (t == 0) L.misc[0] = 0.f;
     __syncthreads();
 
@@ -651,6 +670,212 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
     }
 }
 
+
+// ------------------------------------------------------------------------------------------
+// Large-graph inference (graphs whose features do not fit in LDS, e.g. the 936 x 8800 detector
+// error model): one workgroup per shot, its 8 wavefronts splitting the 16-node tiles of each
+// phase, features in a workgroup-private slice of the device workspace (sized to stay in the
+// last-level cache across the grid).  The arithmetic is that of net_infer_kernel: transposed
+// products with weight fragments in registers, neighbour means by linearity on the float32
+// accumulator, padded neighbour lists with a zero sentinel row (u32 byte offsets built once per
+// net by big_tables_kernel).  Neighbour loads are issued in groups of kGather before their MFMAs.
+// ------------------------------------------------------------------------------------------
+constexpr int kBigWaves = 8;
+constexpr int kGather = 6;
+
+__global__ void big_tables_kernel(DevGraph g, uint32_t *nbc, uint32_t *nbf, float *rdc, float *rdf) {
+    const int NP = pad16(g.n), MP = pad16(g.m), dr = g.max_rw, dc = g.max_cw;
+    const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t x = tid; x < (size_t)MP * dr; x += stride) {
+        const int i = (int)(x / dr), k = (int)(x % dr);
+        uint32_t off = (uint32_t)NP * 64u;
+        if (i < g.m && g.row_ptr[i] + k < g.row_ptr[i + 1]) off = (uint32_t)g.col_idx[g.row_ptr[i] + k] * 64u;
+        nbc[x] = off;
+    }
+    for (size_t x = tid; x < (size_t)NP * dc; x += stride) {
+        const int j = (int)(x / dc), k = (int)(x % dc);
+        uint32_t off = (uint32_t)MP * 64u;
+        if (j < g.n && g.col_ptr[j] + k < g.col_ptr[j + 1]) off = (uint32_t)g.row_idx[g.col_ptr[j] + k] * 64u;
+        nbf[x] = off;
+    }
+    for (size_t x = tid; x < (size_t)MP; x += stride) {
+        const int d = x < (size_t)g.m ? g.row_ptr[x + 1] - g.row_ptr[x] : 0;
+        rdc[x] = d > 0 ? 1.0f / (float)d : 0.f;
+    }
+    for (size_t x = tid; x < (size_t)NP; x += stride) {
+        const int d = x < (size_t)g.n ? g.col_ptr[x + 1] - g.col_ptr[x] : 0;
+        rdf[x] = d > 0 ? 1.0f / (float)d : 0.f;
+    }
+}
+
+__host__ __device__ inline size_t big_slice_bytes(int n, int m) {
+    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID);
+}
+
+__device__ __forceinline__ short4v gfrag(const unsigned char *base, uint32_t off) {
+    return *(const short4v *)(base + off);
+}
+
+__global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A) {
+    __shared__ float sv[SV_N];
+    extern __shared__ __align__(16) unsigned char smem[];  // sg: m floats
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    const int n = A.g.n, m = A.g.m, NP = pad16(n), MP = pad16(m), dr = A.g.max_rw, dc = A.g.max_cw;
+    float *sg = (float *)smem;
+    unsigned char *Hb = A.act + (size_t)blockIdx.x * A.act_stride;
+    unsigned char *Cb = Hb + (size_t)(NP + 1) * 64;
+    const uint16_t *H16 = (const uint16_t *)Hb;
+
+    for (int x = t; x < SV_N; x += blockDim.x) {
+        float v;
+        if (x < SV_B0) v = A.theta[P_W0 + x];
+        else if (x < SV_A) v = A.theta[P_B0 + (x - SV_B0)];
+        else if (x < SV_BL) { const int l = (x - SV_A) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_a + ((x - SV_A) & 31)]; }
+        else if (x < SV_W) { const int l = (x - SV_BL) >> 5; v = A.theta[P_LAYER + l * P_LSTRIDE + P_b + ((x - SV_BL) & 31)]; }
+        else if (x < SV_BO) v = A.theta[P_W + (x - SV_W)];
+        else v = A.theta[P_BO];
+        sv[x] = v;
+    }
+    if (t < 16) {  // sentinel rows (never written again)
+        ((uint32_t *)(Hb + (size_t)NP * 64))[t] = 0u;
+        ((uint32_t *)(Cb + (size_t)MP * 64))[t] = 0u;
+    }
+    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    short4v wf[9][2][2];
+#pragma unroll
+    for (int mat = 0; mat < 9; mat++) {
+        const int layer = mat / 3, which = mat % 3;
+        const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
+#pragma unroll
+        for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+            for (int ot = 0; ot < 2; ot++) {
+                const float *w = W + (ot * 16 + r16) * HID + ks * 16 + kq;
+                wf[mat][ks][ot] = __builtin_bit_cast(short4v, make_uint2(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3])));
+            }
+    }
+    __syncthreads();
+
+    const int total = A.list ? *A.list_count : A.count;
+    for (int item = blockIdx.x; item < total; item += gridDim.x) {
+        const int shot = A.list ? A.list[item] : item;
+        const uint8_t *syn = A.syn + (size_t)shot * m;
+        const float *llr = A.llr + (size_t)shot * n;
+        for (int i = t; i < m; i += blockDim.x) sg[i] = (syn[i] & 1) ? -1.f : 1.f;
+        // input layer: thread j writes its fault's 32 features (4 x 16 B)
+        for (int j = t; j < NP; j += blockDim.x) {
+            float x0 = 0.f, x1 = 0.f;
+            if (j < n) { x0 = tanhf(llr[j] * 0.125f); x1 = A.lam[j] * 0.125f; }
+#pragma unroll
+            for (int f8 = 0; f8 < HID; f8 += 8) {
+                uint32_t w[4];
+#pragma unroll
+                for (int h2 = 0; h2 < 4; h2++) {
+                    const int f = f8 + 2 * h2;
+                    float v0 = 0.f, v1 = 0.f;
+                    if (j < n) {
+                        v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
+                        v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
+                    }
+                    w[h2] = pack_bf16x2(v0, v1);
+                }
+                *(uint4 *)(Hb + (size_t)j * 64 + f8 * 2) = make_uint4(w[0], w[1], w[2], w[3]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < NL; l++) {
+            // checks: c_i = relu((1/deg_i) sum_j A h_j + sigma_i a)
+            for (int rt = wave; rt < MP / 16; rt += kBigWaves) {
+                const int i = rt * 16 + r16;
+                float4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                const uint32_t *nb = A.nbc + (size_t)i * dr;
+                for (int k0 = 0; k0 < dr; k0 += kGather) {
+                    short4v x0[kGather], x1[kGather];
+#pragma unroll
+                    for (int k = 0; k < kGather; k++) {
+                        const uint32_t off = k0 + k < dr ? nb[k0 + k] : (uint32_t)NP * 64u;
+                        x0[k] = gfrag(Hb, off + kq * 2);
+                        x1[k] = gfrag(Hb, off + 32 + kq * 2);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kGather; k++)
+#pragma unroll
+                        for (int ot = 0; ot < 2; ot++) {
+                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][0][ot], x0[k], acc[ot], 0, 0, 0);
+                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][1][ot], x1[k], acc[ot], 0, 0, 0);
+                        }
+                }
+                const float rd = A.rdc[i], sgn = i < m ? sg[i] : 0.f;
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    float v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc[ot][q] + sgn * sv[SV_A + l * HID + ot * 16 + kq + q], 0.f);
+                    *(uint2 *)(Cb + (size_t)i * 64 + ot * 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                }
+            }
+            __syncthreads();
+            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b), in place (own rows only)
+            for (int rt = wave; rt < NP / 16; rt += kBigWaves) {
+                const int j = rt * 16 + r16;
+                const short4v h0 = gfrag(Hb, (uint32_t)j * 64u + kq * 2), h1 = gfrag(Hb, (uint32_t)j * 64u + 32 + kq * 2);
+                float4v as[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                float4v an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                const uint32_t *nb = A.nbf + (size_t)j * dc;
+                for (int k0 = 0; k0 < dc; k0 += kGather) {
+                    short4v y0[kGather], y1[kGather];
+#pragma unroll
+                    for (int k = 0; k < kGather; k++) {
+                        const uint32_t off = k0 + k < dc ? nb[k0 + k] : (uint32_t)MP * 64u;
+                        y0[k] = gfrag(Cb, off + kq * 2);
+                        y1[k] = gfrag(Cb, off + 32 + kq * 2);
+                    }
+#pragma unroll
+                    for (int k = 0; k < kGather; k++)
+#pragma unroll
+                        for (int ot = 0; ot < 2; ot++) {
+                            an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][0][ot], y0[k], an[ot], 0, 0, 0);
+                            an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][1][ot], y1[k], an[ot], 0, 0, 0);
+                        }
+                }
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][0][ot], h0, as[ot], 0, 0, 0);
+                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][1][ot], h1, as[ot], 0, 0, 0);
+                }
+                const float rd = A.rdf[j];
+                const bool live = j < n;
+#pragma unroll
+                for (int ot = 0; ot < 2; ot++) {
+                    float v[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)
+                        v[q] = live ? fmaxf(as[ot][q] + rd * an[ot][q] + sv[SV_BL + l * HID + ot * 16 + kq + q], 0.f) : 0.f;
+                    *(uint2 *)(Hb + (size_t)j * 64 + ot * 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                }
+            }
+            __syncthreads();
+        }
+        for (int j = t; j < n; j += blockDim.x) {
+            float d = sv[SV_BO];
+            const uint4 *h = (const uint4 *)(H16 + (size_t)j * HID);
+#pragma unroll
+            for (int f8 = 0; f8 < 4; f8++) {
+                const uint4 v = h[f8];
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int h2 = 0; h2 < 4; h2++) {
+                    d += sv[SV_W + f8 * 8 + 2 * h2] * __uint_as_float(w[h2] << 16);
+                    d += sv[SV_W + f8 * 8 + 2 * h2 + 1] * __uint_as_float(w[h2] & 0xffff0000u);
+                }
+            }
+            A.llr_out[(size_t)shot * n + j] = llr[j] + d;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void zero_f32(float *p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
@@ -669,18 +894,15 @@ __global__ void adam_kernel(float *theta, const float *grad, float *m1, float *m
 
 }  // namespace
 
-size_t net_lds_bytes(const DevGraph &g, bool train) {
-    size_t o[10];
-    return net_layout(g.n, g.m, g.nnz, train, o);
+static size_t net_shared_bytes(const DevGraph &g, bool train) {
+    size_t o[5];
+    return net_shared_layout(g.n, g.m, g.nnz, train, o);
 }
-
-static hipError_t launch_net(const NetArgs &a, int grid, hipStream_t st) {
-    const size_t lds = net_lds_bytes(a.g, a.train != 0);
-    hipError_t e = hipFuncSetAttribute((const void *)net_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(net_kernel, dim3(grid), dim3(kNetThreads), lds, st, a);
-    return hipGetLastError();
+static size_t net_act_bytes(const DevGraph &g, bool train) {
+    size_t o[5];
+    return net_act_layout(g.n, g.m, train, o);
 }
+size_t net_lds_bytes(const DevGraph &g, bool train) { return net_shared_bytes(g, train) + net_act_bytes(g, train); }
 
 static size_t infer_lds_bytes(const DevGraph &g) {
     return infer_shared_bytes(g.n, g.m, g.max_rw, g.max_cw) + kInferWaves * infer_wave_bytes(g.n, g.m);
@@ -715,7 +937,71 @@ struct qlsd_net_s {
     float *d_lam = nullptr, *d_theta = nullptr, *d_m1 = nullptr, *d_m2 = nullptr, *d_grad = nullptr, *d_loss = nullptr;
     int step = 0;
     int num_cus = 0;
+    bool wave_infer = false;          // inference by net_infer_kernel (LDS-resident, wave per shot)
+    unsigned char *d_act = nullptr;   // training activations when they do not fit in LDS (lazy)
+    size_t act_stride = 0;
+    int act_slices = 0;
+    // large-graph inference (net_infer_big_kernel): neighbour tables, and the net's own feature
+    // workspace for qlsd_net_forward (decoders bring their own, see qlsd_decoder_set_net)
+    uint32_t *d_nbc = nullptr, *d_nbf = nullptr;
+    float *d_rdc = nullptr, *d_rdf = nullptr;
+    unsigned char *d_iws = nullptr;
 };
+
+namespace qlsd {
+// Training, gradient and (for graphs the wave kernel cannot hold) inference launch of net_kernel:
+// one workgroup per shot at a time; activations in LDS or in the net's workspace slices.
+static hipError_t launch_net(qlsd_net_s *net, NetArgs a, int grid, hipStream_t st) {
+    const bool train = a.train != 0;
+    size_t lds = net_shared_bytes(a.g, train);
+    if (net->act_stride && !net->d_act &&
+        hipMalloc((void **)&net->d_act, net->act_stride * net->act_slices) != hipSuccess) {
+        net->d_act = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    if (net->d_act) {
+        a.act = net->d_act;
+        a.act_stride = net->act_stride;
+        grid = std::min(grid, net->act_slices);
+    } else {
+        lds += net_act_bytes(a.g, train);
+    }
+    hipError_t e = hipFuncSetAttribute((const void *)net_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(net_kernel, dim3(std::max(grid, 1)), dim3(kNetThreads), lds, st, a);
+    return hipGetLastError();
+}
+// Slices of the large-graph inference workspace: one per compute unit, so the grid's features
+// (about 0.6 MB per slice for the detector error model) stay in the last-level cache.
+static int big_slices(const qlsd_net_s *net) { return net->num_cus; }
+size_t net_infer_workspace_bytes(const qlsd_net_s *net) {
+    return net->wave_infer ? 0 : big_slice_bytes(net->g.n, net->g.m) * (size_t)big_slices(net);
+}
+static hipError_t launch_infer_big(const qlsd_net_s *net, NetArgs a, unsigned char *ws, int max_items, hipStream_t st) {
+    a.act = ws;
+    a.act_stride = big_slice_bytes(a.g.n, a.g.m);
+    a.nbc = net->d_nbc;
+    a.nbf = net->d_nbf;
+    a.rdc = net->d_rdc;
+    a.rdf = net->d_rdf;
+    const int grid = std::max(1, std::min(max_items, big_slices(net)));
+    hipLaunchKernelGGL(net_infer_big_kernel, dim3(grid), dim3(64 * kBigWaves), sizeof(float) * (size_t)a.g.m, st, a);
+    return hipGetLastError();
+}
+// Inference of max_items shots (a.list / a.count say which); ws: a feature workspace of
+// net_infer_workspace_bytes(net) for large graphs (nullptr: the net's own).
+static hipError_t run_forward(qlsd_net_s *net, const NetArgs &a, int max_items, unsigned char *ws, hipStream_t st) {
+    if (net->wave_infer) return launch_infer(a, max_items, net->num_cus, st);
+    if (!ws) {
+        if (!net->d_iws && hipMalloc((void **)&net->d_iws, net_infer_workspace_bytes(net)) != hipSuccess) {
+            net->d_iws = nullptr;
+            return hipErrorOutOfMemory;
+        }
+        ws = net->d_iws;
+    }
+    return launch_infer_big(net, a, ws, max_items, st);
+}
+}  // namespace qlsd
 
 extern "C" {
 
@@ -723,10 +1009,9 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
     if (!out || !code || !priors || !params) { set_last_error("NULL argument"); return QLSD_E_INVALID; }
     *out = nullptr;
     const DevGraph g = code_graph(code);
-    // u16 tables: CSR entries, and byte offsets of feature rows (64 B each) in inference
-    if (g.n >= 65535 || g.nnz >= 65535 || pad16(g.n) + 1 > 1023 || pad16(g.m) + 1 > 1023 ||
-        net_lds_bytes(g, true) > 159 * 1024 || infer_lds_bytes(g) > 159 * 1024) {
-        set_last_error("graph too large for the LDS-resident refinement network");
+    // u16 CSR/CSC tables in LDS next to the weights
+    if (g.n >= 65535 || g.nnz >= 65535 || net_shared_bytes(g, true) > 159 * 1024) {
+        set_last_error("graph too large for the refinement network (u16 tables in LDS)");
         return QLSD_E_UNSUPPORTED;
     }
     std::vector<float> lam(g.n);
@@ -757,6 +1042,30 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
         return QLSD_E_NOMEM;
     }
     net->num_cus = prop.multiProcessorCount;
+    // wave-per-shot inference needs u16 byte offsets of feature rows (64 B each) and LDS room
+    net->wave_infer = pad16(g.n) + 1 <= 1023 && pad16(g.m) + 1 <= 1023 && infer_lds_bytes(g) <= 159 * 1024;
+    if (net_lds_bytes(g, true) > 159 * 1024) {  // training activations in a device workspace (allocated at first use)
+        net->act_stride = (net_act_bytes(g, true) + 255) & ~size_t(255);
+        net->act_slices = net->num_cus;
+    }
+    if (!net->wave_infer) {
+        const int NP = pad16(g.n), MP = pad16(g.m);
+        ok = (size_t)(NP + 1) * 64 < (1ull << 32) && (size_t)(MP + 1) * 64 < (1ull << 32) &&
+             hipMalloc((void **)&net->d_nbc, sizeof(uint32_t) * (size_t)MP * g.max_rw) == hipSuccess &&
+             hipMalloc((void **)&net->d_nbf, sizeof(uint32_t) * (size_t)NP * g.max_cw) == hipSuccess &&
+             hipMalloc((void **)&net->d_rdc, sizeof(float) * MP) == hipSuccess &&
+             hipMalloc((void **)&net->d_rdf, sizeof(float) * NP) == hipSuccess;
+        if (ok) {
+            hipLaunchKernelGGL(big_tables_kernel, dim3(256), dim3(256), 0, 0, g, net->d_nbc, net->d_nbf, net->d_rdc,
+                               net->d_rdf);
+            ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
+        }
+        if (!ok) {
+            qlsd_net_destroy(net);
+            set_last_error("device allocation of the inference tables failed");
+            return QLSD_E_NOMEM;
+        }
+    }
     *out = net;
     return QLSD_OK;
 }
@@ -812,7 +1121,7 @@ qlsd_status qlsd_net_forward(qlsd_net net, const uint8_t *syndromes, const float
     a.llr = llr;
     a.llr_out = llr_out;
     a.count = B;
-    if (launch_infer(a, B, net->num_cus, (hipStream_t)stream) != hipSuccess) {
+    if (run_forward(net, a, B, nullptr, (hipStream_t)stream) != hipSuccess) {
         set_last_error("net launch failed");
         return QLSD_E_DEVICE;
     }
@@ -833,7 +1142,7 @@ static qlsd_status grad_impl(qlsd_net net, const uint8_t *syn, const float *llr,
     a.inv_total = 1.f / ((float)B * (float)net->g.n);
     a.train = 1;
     const int grid = std::min(B, net->num_cus);
-    if (launch_net(a, grid, st) != hipSuccess) { set_last_error("net launch failed"); return QLSD_E_DEVICE; }
+    if (launch_net(net, a, grid, st) != hipSuccess) { set_last_error("net launch failed"); return QLSD_E_DEVICE; }
     return QLSD_OK;
 }
 
@@ -865,6 +1174,12 @@ void qlsd_net_destroy(qlsd_net net) {
     hipFree(net->d_m2);
     hipFree(net->d_grad);
     hipFree(net->d_loss);
+    hipFree(net->d_act);
+    hipFree(net->d_nbc);
+    hipFree(net->d_nbf);
+    hipFree(net->d_rdc);
+    hipFree(net->d_rdf);
+    hipFree(net->d_iws);
     delete net;
 }
 
@@ -873,7 +1188,7 @@ void qlsd_net_destroy(qlsd_net net) {
 namespace qlsd {
 // Refinement of the LLRs of the listed shots, in place (decode path).
 hipError_t net_refine_listed(qlsd_net_s *net, const float *lam, const uint8_t *syn, float *llr, const int *list,
-                             const int *list_count, int max_count, hipStream_t st) {
+                             const int *list_count, int max_count, unsigned char *ws, hipStream_t st) {
     NetArgs a = net_args(net);
     a.lam = lam;  // the decoder's prior LLRs, so one net serves decoders of any noise strength
     a.syn = syn;
@@ -882,7 +1197,11 @@ hipError_t net_refine_listed(qlsd_net_s *net, const float *lam, const uint8_t *s
     a.list = list;
     a.list_count = list_count;
     a.count = max_count;
-    return launch_infer(a, max_count, net->num_cus, st);
+    return run_forward(net, a, max_count, ws, st);
+}
+void net_graph_dims(const qlsd_net_s *net, int *m, int *n) {
+    *m = net->g.m;
+    *n = net->g.n;
 }
 const float *net_loss_ptr(qlsd_net net) { return net->d_loss; }
 }  // namespace qlsd

@@ -226,9 +226,17 @@ qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_param
 qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net) {
     if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
     if (s->started.load()) return serr(s, QLSD_E_INVALID, "nets must be attached before qlsd_server_start");
+    // a net on a large graph gives every lane's decoder a feature workspace: charge it to the budget
     for (Lane &l : s->codes[code_id]->lanes) {
+        const size_t before = qlsd::decoder_device_bytes(l.dec);
         const qlsd_status st = qlsd_decoder_set_net(l.dec, net);
         if (st != QLSD_OK) return st;
+        const size_t after = qlsd::decoder_device_bytes(l.dec);
+        if (after > before && s->used + (after - before) > s->budget) {
+            qlsd_decoder_set_net(l.dec, nullptr);
+            return serr(s, QLSD_E_NOMEM, "device budget too small for the refinement workspace of every lane");
+        }
+        s->used = s->used + after - before;
     }
     return QLSD_OK;
 }

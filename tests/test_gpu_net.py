@@ -174,3 +174,91 @@ def test_trained_net_gain():
         z = (b - c) / np.sqrt(max(b + c, 1))
         print(f"vs {base}: fixes {b}, breaks {c}, z = {z:.1f}")
         assert z > 3.0, (base, b, c)
+
+
+@pytest.mark.parametrize("which", ["hgp16", "dem"])
+def test_large_graph_forward_and_gradient_match_oracle(which):
+    """Graphs whose activations do not fit in LDS (HGP n=400 and the 936 x 8800 detector error
+    model): the same kernels with activations in a device workspace, forward and gradient
+    against the float64 oracle."""
+    from paper_2406_18655_amd.workloads import random_34_hgp, synthetic_dem
+    code = random_34_hgp(16, p=0.05) if which == "hgp16" else synthetic_dem()
+    bc, e, S, L = _bp_failures(code, 3000 if which == "dem" else 2000, seed=14, T=20)
+    nf, ng = (6, 3) if which == "dem" else (32, 8)
+    assert len(S) >= nf
+    th = _theta(12)
+    net = binding.Net(bc, code.priors, th)
+    lam = np.log((1 - code.priors) / code.priors).astype(np.float32).astype(np.float64)
+    out = net.forward(torch.from_numpy(S[:nf]).cuda(), torch.from_numpy(L[:nf]).cuda())
+    torch.cuda.synchronize()
+    d_gpu = out.cpu().numpy().astype(np.float64) - L[:nf].astype(np.float64)
+    for b in range(nf):
+        d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
+        rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
+        assert rel <= 2e-2, (b, rel)
+    g, loss = net.gradient(torch.from_numpy(S[:ng]).cuda(), torch.from_numpy(L[:ng]).cuda(),
+                           torch.from_numpy(e[:ng]).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    l_ref, g_ref = ol.batch_loss_and_grad(th.astype(np.float64), code.H, [x.astype(np.float64) for x in L[:ng]],
+                                          lam, S[:ng], e[:ng])
+    assert abs(float(loss.item()) - l_ref) <= 1e-3 * max(1.0, abs(l_ref))
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
+    print(f"{which}: gradient relative L2 error {rel:.2e}, cosine {cos:.6f}")
+    assert rel <= 5e-2 and cos >= 0.998
+
+
+def test_net_rejects_other_code():
+    bb, sc = bivariate_bicycle(p=0.05), surface_hgp(5, 0.05)
+    net = binding.Net(binding.Code.from_dense(bb.H), bb.priors, _theta(1))
+    dec = binding.Decoder(binding.Code.from_dense(sc.H), sc.priors, 16, max_iter=5)
+    with pytest.raises(binding.QlsdError):
+        binding.attach_net(dec, net)
+
+
+def test_dem_zero_output_net_decodes_like_plain():
+    """Decoding the detector error model through the large-graph refinement path (decoder-owned
+    feature workspace) with a zero output layer leaves BP+LSD-10 unchanged."""
+    from paper_2406_18655_amd.workloads import synthetic_dem
+    code = synthetic_dem()
+    bc = binding.Code.from_dense(code.H)
+    e, S = sample(code, 4096, seed=15)
+    s = torch.from_numpy(S).cuda()
+    plain = binding.Decoder(bc, code.priors, 4096, max_iter=30, lsd_order=10)
+    c0 = plain.decode(s).cpu().numpy()
+    learned = binding.Decoder(bc, code.priors, 4096, max_iter=30, lsd_order=10)
+    net = binding.Net(bc, code.priors, ol.init_params(seed=4, zero_output=True).astype(np.float32))
+    binding.attach_net(learned, net)
+    c1 = learned.decode(s).cpu().numpy()
+    assert (c0 == c1).all()
+
+
+def test_dem_trained_net_gain():
+    """Trained refinement on the detector error model (weights from train_ordering --code dem,
+    BP 30 iterations): word errors on 2^20 held-out shots drawn on the GPU, paired against plain
+    BP (100 iterations) + LSD-10."""
+    import os
+    from paper_2406_18655_amd.workloads import synthetic_dem, DeviceSampler
+    code = synthetic_dem()
+    bc = binding.Code.from_dense(code.H)
+    w = os.path.join(os.path.dirname(binding.__file__), "weights", "dem_T30.npy")
+    net = binding.Net(bc, code.priors, np.load(w))
+    B = 65536
+    plain = binding.Decoder(bc, code.priors, B, max_iter=100, lsd_order=10)
+    learned = binding.Decoder(bc, code.priors, B, max_iter=30, lsd_order=10)
+    binding.attach_net(learned, net)
+    ds = DeviceSampler(code)
+    fixes = breaks = fp = fl = 0
+    for rep in range(16):
+        e, s = ds.sample(B, 5_000_000 + rep)
+        cp, cl = plain.decode(s), learned.decode(s)
+        assert torch.equal(ds.syndromes(cl), s) and torch.equal(ds.syndromes(cp), s)
+        f_p, f_l = ds.failures(e, cp), ds.failures(e, cl)
+        fixes += int((f_p & ~f_l).sum().item())
+        breaks += int((~f_p & f_l).sum().item())
+        fp += int(f_p.sum().item())
+        fl += int(f_l.sum().item())
+    z = (fixes - breaks) / np.sqrt(max(fixes + breaks, 1))
+    print(f"DEM word error plain {fp / (16 * B):.5f} learned {fl / (16 * B):.5f}; fixes {fixes} breaks {breaks} z {z:.1f}")
+    assert z > 3.0
