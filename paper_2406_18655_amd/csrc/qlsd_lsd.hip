@@ -96,7 +96,12 @@ struct LsdLds {
     uint64_t *zk;      // kMaxMu * W: solution change of each reprocessed column (LSD-mu)
     int32_t *tsel;     // kMaxMu: reprocessed columns of the current cluster (LSD-mu)
     int64_t *tw;       // kMaxMu: their weights
+    uint64_t *cand;    // K: cached smallest candidate key of each local row (kStale: recompute)
 };
+
+// A row's cached candidate stays exact while its column is not taken: the taken set only grows,
+// so the minimum over the row's remaining faults can change only when that column is taken.
+constexpr uint64_t kStale = ~0ull - 1ull;
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 
@@ -119,6 +124,7 @@ __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_l
     offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);
     offs[15] = off; off += sizeof(int32_t) * kMaxMu;
     offs[16] = off; off += sizeof(int64_t) * kMaxMu;
+    offs[17] = off; off += sizeof(uint64_t) * K;
     return align8(off);
 }
 
@@ -132,15 +138,16 @@ __device__ __forceinline__ int find_root(volatile int32_t *par, int x) {
     return x;
 }
 
-__device__ void unite(int32_t *par, int x, int y) {
+// Returns true iff it hooked one root under another (false: already in one set).
+__device__ bool unite(int32_t *par, int x, int y) {
     volatile int32_t *vp = par;
     for (;;) {
         x = find_root(vp, x);
         y = find_root(vp, y);
-        if (x == y) return;
+        if (x == y) return false;
         if (x < y) { const int tmp = x; x = y; y = tmp; }
         // hook the larger root under the smaller one
-        if (atomicCAS(&par[x], x, y) == x) return;
+        if (atomicCAS(&par[x], x, y) == x) return true;
     }
 }
 
@@ -395,6 +402,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
     };
     if (ballot(nan)) { finish(QLSD_ST_LSD_RUN | QLSD_ST_BAD_LLR, 0, 0); return; }
+    // capacity exceeded: the shot reports OVERFLOW with a zero correction
+    auto overflow = [&](uint8_t st) {
+        finish(st | QLSD_ST_OVERFLOW, 0, 0);
+        for (int j = lane; j < n; j += 64) corr[j] = 0;
+    };
 
     // clusters: one per flipped detector, local rows in ascending detector order
     int nrows = 0;
@@ -409,12 +421,13 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 S.rowOf[idx] = i;
                 S.croot[idx] = idx;
                 S.state[idx] = kInvalid;
+                S.cand[idx] = kStale;
             }
         }
         nrows += __popcll(bal);
     }
     if (nrows == 0) { finish(QLSD_ST_LSD_RUN, 0, 0); return; }
-    if (nrows > K) { finish(QLSD_ST_LSD_RUN | QLSD_ST_OVERFLOW, 0, 0); return; }
+    if (nrows > K) { overflow(QLSD_ST_LSD_RUN); return; }
     const int nseed = nrows;
     if (lane == 0) S.ctl[0] = nrows;
 
@@ -445,15 +458,19 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             if (r < nrows) {
                 const int c = S.croot[r];
                 if (grow_all ? S.state[c] != kFrozen : S.state[c] == kInvalid) {
-                    const int d = S.rowOf[r];
-                    uint64_t best = ~0ull;
-                    const int e1 = g.row_ptr(d + 1);
-                    for (int e = g.row_ptr(d); e < e1; e++) {
-                        const int j = g.col_idx(e);
-                        if (in_col(S.incol, j)) continue;
-                        const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
-                        const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)j;
-                        best = key < best ? key : best;
+                    uint64_t best = S.cand[r];
+                    if (best == kStale || (best != ~0ull && in_col(S.incol, (int)(uint32_t)best))) {
+                        const int d = S.rowOf[r];
+                        best = ~0ull;
+                        const int e1 = g.row_ptr(d + 1);
+                        for (int e = g.row_ptr(d); e < e1; e++) {
+                            const int j = g.col_idx(e);
+                            if (in_col(S.incol, j)) continue;
+                            const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
+                            const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)j;
+                            best = key < best ? key : best;
+                        }
+                        S.cand[r] = best;
                     }
                     if (best != ~0ull) atomicMin((unsigned long long *)&S.sel[c], (unsigned long long)best);
                 }
@@ -504,6 +521,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             }
         }
         wave_sync();
+        bool merged = false;
         for (int id = lane; id < npairs; id += 64) {
             const int p = id / cwm, u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
@@ -519,24 +537,29 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                             S.rowOf[idx] = d;
                             S.croot[idx] = c;
                             S.state[idx] = kValid;
+                            S.cand[idx] = kStale;
                             S.loc[d] = idx;
                         }
                     } else {
-                        unite(S.croot, c, cl);
+                        merged |= unite(S.croot, c, cl);
                     }
                 } else {
-                    unite(S.croot, c, S.croot[S.loc[d]]);
+                    merged |= unite(S.croot, c, S.croot[S.loc[d]]);
                 }
             }
         }
+        const bool any_merge = ballot(merged) != 0ull;
         wave_sync();
         const int nrows_new = S.ctl[0];
-        if (nrows_new > K) { finish(status | QLSD_ST_OVERFLOW, 0, 0); for (int j = lane; j < n; j += 64) corr[j] = 0; return; }
-        // flatten the forest; release this round's claims
+        if (nrows_new > K) { overflow(status); return; }
+        // flatten the forest (only after a merge: otherwise every row already points at a root,
+        // new rows at the round-start root that claimed them); release this round's claims
+        if (any_merge) {
 #pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            if (r < nrows_new) S.croot[r] = find_root(S.croot, r);
+            for (int s = 0; s < W; s++) {
+                const int r = s * 64 + lane;
+                if (r < nrows_new) S.croot[r] = find_root(S.croot, r);
+            }
         }
         for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
         nrows = nrows_new;
@@ -598,11 +621,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             mu_left = A.mu;
         }
     }
-    if (npc > K) {
-        finish(status | QLSD_ST_OVERFLOW, 0, 0);
-        for (int j = lane; j < n; j += 64) corr[j] = 0;
-        return;
-    }
+    if (npc > K) { overflow(status); return; }
 
     // solve: seed rows carry s = 1, claimed rows s = 0; frozen clusters contribute nothing
     uint64_t as[W];
@@ -656,7 +675,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
     }
     unsigned char *base = smem + gbytes + (size_t)wid * A.wave_bytes;
-    size_t offs[17];
+    size_t offs[18];
     lsd_layout(m, n, K, A.keys_in_lds != 0, offs);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
@@ -676,6 +695,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
     S.zk = (uint64_t *)(base + offs[14]);
     S.tsel = (int32_t *)(base + offs[15]);
     S.tw = (int64_t *)(base + offs[16]);
+    S.cand = (uint64_t *)(base + offs[17]);
 
     const int total = A.list ? *A.list_count : A.count;
     for (;;) {
@@ -727,7 +747,7 @@ hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hip
 }
 
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
-    size_t offs[17];
+    size_t offs[18];
     return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
 }
 
