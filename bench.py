@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-ordering leg")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch shapes (no qlsd_decoder_tune before the timed steps)")
     ap.add_argument("--learned-iter", type=int, default=None,
                     help="BP iterations of the learned form (default 10 for bb144, 30 for dem)")
     ap.add_argument("--serve", action="store_true",
@@ -117,6 +119,10 @@ def main():
             sys.exit(3)
         ler_gpu.append(logical_failures(code, e, c))
 
+    tuning = None
+    if not args.no_tune:
+        log("autotuning launch shapes on batch 0")
+        tuning = dec.tune(batches[0][1], reps=3)
     log("correctness pass done; warmup and timed steps")
     for k in range(args.warmup):
         dec.decode_into(batches[k % len(batches)][1], corr, None)
@@ -182,7 +188,8 @@ def main():
            "ler": {"gpu": round(float(np.mean([f.mean() for f in ler_gpu])), 6)},
            "bp_mean_iters": round(float(np.mean([it.mean() for it in iters_per_batch])), 3),
            "lsd_fraction": round(float(np.mean(lsd_frac)), 4),
-           "roofline": roofline}
+           "roofline": roofline,
+           "tuning": None if tuning is None else [l for l in tuning.splitlines() if "chosen" in l]}
 
     log(f"timed {args.steps} steps: {shots_per_s:.4g} shots/s")
     if not args.no_learned:
@@ -219,6 +226,8 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     net = binding.Net(bcode, code.priors, np.load(os.path.join(wdir, wname)))
     dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
     binding.attach_net(dec, net)
+    if not args.no_tune:
+        dec.tune(batches[0][1], reps=3)
     corr = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
     fails = []
     for e, s in batches:

@@ -108,6 +108,15 @@ qlsd_status qlsd_lsd(qlsd_decoder dec, const uint8_t *syndromes, const float *ll
  * waits for those events.  Either output pointer (host float) may be NULL. */
 qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms);
 
+/* Autotuner: times candidate launch shapes on a sample batch (syndromes device u8[B*m],
+ * B <= max_batch, typically one full batch of the workload) and keeps the fastest -- for BP
+ * with shot slots, the slots per workgroup and workgroups per compute unit; for LSD, the
+ * number of workgroups.  Outputs never depend on these shapes.  Synchronous on `stream`;
+ * allocates and frees scratch output buffers; must not overlap other calls on this decoder.
+ * `report` (host char[report_len], nullable) receives one line per candidate and the choice. */
+qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, int32_t reps,
+                              void *stream, char *report, int32_t report_len);
+
 /* Waits for the decoder's last work and reports a device failure, if any. */
 qlsd_status qlsd_sync(qlsd_decoder dec);
 

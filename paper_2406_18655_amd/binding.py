@@ -22,7 +22,7 @@ FLAG_STAGE_TIMING = 2
 
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
-           "qlsd_decoder_stage_ms", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
+           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
 
 INFO_DTYPE = np.dtype([("status", np.uint8), ("reserved", np.uint8), ("bp_iters", np.int16),
@@ -59,12 +59,13 @@ def lib():
         L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
         L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
+        L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
         L.qlsd_sync.argtypes = [P]
         L.qlsd_last_error.restype = ctypes.c_char_p
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
-                   "qlsd_decoder_stage_ms", "qlsd_sync"):
+                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -159,6 +160,13 @@ class Decoder:
 
     def sync(self):
         _check(lib().qlsd_sync(self._h))
+
+    def tune(self, syndromes, reps: int = 5, stream: Optional[int] = None) -> str:
+        """Autotune launch shapes on a sample batch (include/qlsd.h); returns the timing report."""
+        buf = ctypes.create_string_buffer(8192)
+        _check(lib().qlsd_decoder_tune(self._h, _ptr(syndromes), syndromes.shape[0], int(reps),
+                                       _stream() if stream is None else stream, buf, len(buf)))
+        return buf.value.decode()
 
     def stage_ms(self):
         """(bp_ms, lsd_ms) of the last decode call (needs FLAG_STAGE_TIMING)."""

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/qlsd_net.h"
@@ -382,6 +383,106 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     LsdArgs l = lsd_args(d, syndromes, llr, corrections, info);
     l.count = B;
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t B, int32_t reps, void *stream,
+                              char *report, int32_t report_len) {
+    qlsd_status st = check_call(d, syndromes, B, syndromes);
+    if (st != QLSD_OK) return st;
+    if (B == 0 || reps < 1) return fail(QLSD_E_INVALID, "need B >= 1 and reps >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const DevGraph &g = d->code->g;
+    std::string rep;
+    char line[160];
+    uint8_t *corr = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto cleanup = [&]() {
+        hipFree(corr);
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+    };
+    if (hipMalloc((void **)&corr, (size_t)B * g.n) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess) {
+        cleanup();
+        return fail(QLSD_E_NOMEM, "tuning scratch allocation failed");
+    }
+    // average device time (ms) of `reps` runs of f after one warm-up run
+    auto timeit = [&](auto &&f) -> float {
+        if (f() != hipSuccess) return -1.f;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps; r++)
+            if (f() != hipSuccess) return -1.f;
+        hipEventRecord(e1, s);
+        if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        return ms / reps;
+    };
+    auto bp_run = [&]() -> hipError_t {
+        hipError_t e = launch_zero(d->d_ctl, 8, s);
+        if (e != hipSuccess) return e;
+        BpArgs a = bp_args(d, syndromes, B);
+        a.corr = corr;
+        a.llr_lsd = d->d_llr;
+        a.lsd_flag = d->d_flag;
+        return run_bp(d, a, B, s);
+    };
+    // BP with shot slots: the largest slot count that fits each workgroups-per-CU tier
+    if (!d->bp_graph) {
+        int best_S = d->bp_slots, best_grid = d->bp_grid;
+        float best = 1e30f;
+        for (int wg : {1, 2, 3, 4, 5, 6, 8}) {
+            const size_t budget = kLdsPerCu / wg - 512;
+            int S = kMaxSlots;
+            while (S > 0 && bp_lds_bytes(g, S) > budget) S--;
+            if (S < 4) continue;
+            d->bp_slots = S;
+            d->bp_grid = wg * d->num_cus;
+            const float ms = timeit(bp_run);
+            snprintf(line, sizeof(line), "bp slots %d x %d workgroups/CU: %.4f ms\n", S, wg, ms);
+            rep += line;
+            if (ms > 0.f && ms < best) { best = ms; best_S = S; best_grid = d->bp_grid; }
+        }
+        d->bp_slots = best_S;
+        d->bp_grid = best_grid;
+        snprintf(line, sizeof(line), "bp chosen: slots %d, grid %d\n", best_S, best_grid);
+        rep += line;
+    }
+    // LSD on the shots this BP leaves unsolved
+    if (bp_run() != hipSuccess || launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s) != hipSuccess) {
+        cleanup();
+        return fail(QLSD_E_DEVICE, "tuning launch failed");
+    }
+    int best_lsd = d->lsd_grid;
+    float best = 1e30f;
+    for (int mult : {2, 4, 8, 16, 32}) {
+        const int grid = mult * d->num_cus;
+        auto lsd_run = [&]() -> hipError_t {
+            hipError_t e = launch_zero(d->d_ctl + 2, 1, s);
+            if (e != hipSuccess) return e;
+            LsdArgs l = lsd_args(d, syndromes, d->d_llr, corr, nullptr);
+            l.list = d->d_list;
+            l.list_count = d->d_ctl + 1;
+            l.bp_ran = 1;
+            return launch_lsd(l, d->lsd_W, grid, s);
+        };
+        const float ms = timeit(lsd_run);
+        snprintf(line, sizeof(line), "lsd %d workgroups: %.4f ms\n", grid, ms);
+        rep += line;
+        if (ms > 0.f && ms < best) { best = ms; best_lsd = grid; }
+    }
+    d->lsd_grid = best_lsd;
+    snprintf(line, sizeof(line), "lsd chosen: %d workgroups\n", best_lsd);
+    rep += line;
+    const hipError_t e = hipStreamSynchronize(s);
+    cleanup();
+    if (e != hipSuccess) return fail(QLSD_E_DEVICE, "tuning failed: %s", hipGetErrorString(e));
+    if (report && report_len > 0) {
+        const size_t k = std::min<size_t>(rep.size(), (size_t)report_len - 1);
+        memcpy(report, rep.data(), k);
+        report[k] = 0;
+    }
     return QLSD_OK;
 }
 
