@@ -56,6 +56,10 @@ def parse():
                     help="plain: BP+LSD for every code; learned: the [[144,12,12]] lanes run BP 10 + "
                          "the trained refinement + LSD")
     ap.add_argument("--serve-requests", type=int, default=200000)
+    ap.add_argument("--sweep", action="store_true",
+                    help="[[144,12,12]] over p in {0.01,0.02,0.04,0.05,0.06}: 10^6 shots per point "
+                         "(15 launches of 65,536 plus one of 16,960), GPU LER and shots/s, the oracle's "
+                         "LER on the first 65,536 shots, and the learned form")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (three launches), the "
                          "reference for scaling HBM byte counters")
@@ -357,6 +361,66 @@ def serve_main(args):
                           "latency_includes": "host staging, PCIe copies, scheduler polling"}), flush=True)
 
 
+def sweep_main(args):
+    """Logical error rate and throughput of plain BP (50) + LSD-0 and of the learned form across
+    the code-capacity noise sweep; inputs resident in HBM during the timed decodes."""
+    import torch
+    import oracle
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, sample, logical_failures, syndromes
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    sizes = [65536] * 15 + [16960]
+    w = np.load(os.path.join(HERE, "paper_2406_18655_amd", "weights", "bb144_mix_T10.npy"))
+    for p in (0.01, 0.02, 0.04, 0.05, 0.06):
+        code = bivariate_bicycle(p=p)
+        bc = binding.Code.from_dense(code.H)
+        plain = binding.Decoder(bc, code.priors, 65536, max_iter=50)
+        learned = binding.Decoder(bc, code.priors, 65536, max_iter=10)
+        net = binding.Net(bc, code.priors, w)
+        binding.attach_net(learned, net)
+        res = {}
+        e0 = s0 = None
+        for name, dec in (("plain", plain), ("learned", learned)):
+            fails, ms, start = 0, 0.0, 0
+            for k, B in enumerate(sizes):
+                e, S = sample(code, B, seed=args.seed + 1000 * int(round(p * 100)), start=start)
+                start += B
+                s = torch.from_numpy(S).cuda()
+                out = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+                dec.decode_into(s, out)  # warm
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                dec.decode_into(s, out)
+                b.record()
+                torch.cuda.synchronize()
+                ms += a.elapsed_time(b)
+                c = out.cpu().numpy()
+                if not (syndromes(code, c) == S).all():
+                    print("correction does not satisfy its syndrome", file=sys.stderr)
+                    sys.exit(3)
+                f = logical_failures(code, e, c)
+                fails += int(f.sum())
+                if k == 0 and name == "plain":
+                    e0, s0, f0 = e, S, f
+            n = sum(sizes)
+            q = fails / n
+            res[name] = {"ler": q, "sigma": float(np.sqrt(max(q, 1 / n) * (1 - q) / n)),
+                         "shots_per_s": round(n / (ms * 1e-3), 1)}
+        oc = oracle.Code.from_dense(code.H)
+        corr, st, it, _ = oracle.decode_batch(oc, oracle.llr_from_priors(code.priors), s0, 50,
+                                              nthreads=min(16, os.cpu_count() or 1))
+        fo = logical_failures(code, e0, corr)
+        q = max(fo.mean(), 1 / fo.size)
+        two_sigma = 2 * float(np.sqrt(q * (1 - q) / fo.size))
+        print(json.dumps({"workload": "bb144_codecap_sweep_bp50_lsd0", "p": p, "shots": sum(sizes), **res,
+                          "oracle_first_launch": {"shots": int(fo.size), "ler_oracle": float(fo.mean()),
+                                                  "ler_gpu": float(f0.mean()), "two_sigma": two_sigma,
+                                                  "matched": bool(abs(f0.mean() - fo.mean()) <= two_sigma)},
+                          "learned_weights": "bb144_mix_T10.npy"}), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the factor that turns
     the decoder kernels' counter readings into bytes."""
@@ -373,6 +437,8 @@ if __name__ == "__main__":
     _a = parse()
     if _a.copy_calibration:
         copy_calibration(_a.copy_calibration)
+    elif _a.sweep:
+        sweep_main(_a)
     elif _a.serve:
         serve_main(_a)
     else:
