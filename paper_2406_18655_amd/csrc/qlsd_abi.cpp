@@ -51,7 +51,7 @@ constexpr size_t kLdsPerCu = 160 * 1024;
 struct qlsd_code_s {
     int device;
     DevGraph g;
-    int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge;
+    int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge, *d_row_edge;
     int min_rw;
 };
 
@@ -118,7 +118,7 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
                 return fail(QLSD_E_INVALID, "columns of row %d not sorted/unique", i);
         }
     }
-    std::vector<int32_t> col_ptr(n + 1, 0), row_idx(nnz), col_edge(nnz), fill(n, 0);
+    std::vector<int32_t> col_ptr(n + 1, 0), row_idx(nnz), col_edge(nnz), row_edge(nnz), fill(n, 0);
     for (int64_t e = 0; e < nnz; e++) col_ptr[col_idx[e] + 1]++;
     int max_cw = 0, min_cw = 1 << 30;
     for (int j = 0; j < n; j++) {
@@ -132,6 +132,7 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             const int k = col_ptr[j] + fill[j]++;
             row_idx[k] = i;
             col_edge[k] = e;
+            row_edge[e] = k;
         }
     qlsd_code c = new (std::nothrow) qlsd_code_s();
     if (!c) return fail(QLSD_E_NOMEM, "host allocation failed");
@@ -141,6 +142,7 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     hipError_t e3 = dev_copy(&c->d_col_ptr, col_ptr.data(), (size_t)n + 1);
     hipError_t e4 = dev_copy(&c->d_row_idx, row_idx.data(), (size_t)nnz);
     hipError_t e5 = dev_copy(&c->d_col_edge, col_edge.data(), (size_t)nnz);
+    if (e5 == hipSuccess) e5 = dev_copy(&c->d_row_edge, row_edge.data(), (size_t)nnz);
     if (e1 || e2 || e3 || e4 || e5) {
         qlsd_code_destroy(c);
         return fail(QLSD_E_NOMEM, "device allocation/copy of H failed");
@@ -157,6 +159,7 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     c->g.col_ptr = c->d_col_ptr;
     c->g.row_idx = c->d_row_idx;
     c->g.col_edge = c->d_col_edge;
+    c->g.row_edge = c->d_row_edge;
     c->min_rw = min_rw;
     *out = c;
     return QLSD_OK;
@@ -168,6 +171,7 @@ void qlsd_code_destroy(qlsd_code c) {
     hipFree(c->d_col_idx);
     hipFree(c->d_col_ptr);
     hipFree(c->d_row_idx);
+    hipFree(c->d_row_edge);
     hipFree(c->d_col_edge);
     delete c;
 }

@@ -603,6 +603,178 @@ static hipError_t launch_bp_t(const BpArgs &a, int grid, size_t lds, hipStream_t
     return hipGetLastError();
 }
 
+// Large graphs, fault-major message order.  The messages of fault j sit contiguously at its CSC
+// positions col_ptr[j] .. col_ptr[j+1]; each thread keeps the graph structure it touches in
+// registers for the kernel's lifetime -- for each of its FPT faults (j = t + k*NT) the CSC start,
+// degree and prior, and for its check row (i = t; needs m <= NT) the CSC positions of the row's
+// edges -- so the iteration loop reads no graph tables (only the row indices of faults whose hard
+// decision is 1, for the parity words).  Same arithmetic, in the same order, as bp_graph_kernel.
+template <int MAXRW, int MAXCW, int FPT>
+__global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int t = threadIdx.x, NT = blockDim.x;
+    const int m = args.g.m, n = args.g.n, E = args.g.nnz;
+    const int PW = (m + 31) / 32;
+    float *msg = (float *)smem;  // CSC order
+    float *Lv = msg + E;
+    uint32_t *synw = (uint32_t *)(Lv + n);
+    uint32_t *parw = synw + PW;
+    int *ctl = (int *)(parw + PW);
+    const int32_t *row_idx = args.g.row_idx;
+    const float alpha = args.alpha;
+    const int T = args.max_iter;
+    const int lane = t & 63, wave = t >> 6;
+
+    uint32_t fmeta[FPT];  // CSC start | degree << 24
+    float flam[FPT];
+#pragma unroll
+    for (int k = 0; k < FPT; k++) {
+        const int j = t + k * NT;
+        uint32_t v = 0;
+        float l = 0.f;
+        if (j < n) {
+            const int c0 = args.g.col_ptr[j];
+            v = (uint32_t)c0 | ((uint32_t)(args.g.col_ptr[j + 1] - c0) << 24);
+            l = args.lam[j];
+        }
+        fmeta[k] = v;
+        flam[k] = l;
+    }
+    uint32_t rpos2[MAXRW / 2];  // CSC positions of the row's edges, two u16 per word (nnz < 65536)
+    int rw = 0;
+    if (t < m) {
+        const int e0 = args.g.row_ptr[t];
+        rw = args.g.row_ptr[t + 1] - e0;
+#pragma unroll
+        for (int u = 0; u < MAXRW; u += 2) {
+            const uint32_t lo = u < rw ? (uint32_t)args.g.row_edge[e0 + u] : 0u;
+            const uint32_t hi = u + 1 < rw ? (uint32_t)args.g.row_edge[e0 + u + 1] : 0u;
+            rpos2[u / 2] = lo | (hi << 16);
+        }
+    }
+
+    for (;;) {
+        if (t == 0) ctl[0] = atomicAdd(args.next_shot, 1);
+        __syncthreads();
+        const int shot = ctl[0];
+        if (shot >= args.B) break;
+        const uint8_t *syn = args.syn + (size_t)shot * m;
+        for (int i0 = wave * 64; i0 < m; i0 += NT) {
+            const int i = i0 + lane;
+            const uint64_t bits = __ballot(i < m && (syn[i] & 1));
+            if (lane == 0) {
+                synw[i0 >> 5] = (uint32_t)bits;
+                if ((i0 >> 5) + 1 < PW) synw[(i0 >> 5) + 1] = (uint32_t)(bits >> 32);
+            }
+        }
+        for (int w = t; w < PW; w += NT) parw[w] = 0u;
+        for (int e = t; e < E; e += NT) msg[e] = 0.f;  // r = 0: the first fault phase sets q = lambda
+        __syncthreads();
+        int it = 0;
+        bool conv = false;
+        for (;;) {
+            // fault phase
+#pragma unroll
+            for (int k = 0; k < FPT; k++) {
+                const int j = t + k * NT;
+                if (j < n) {
+                    const int c0 = (int)(fmeta[k] & 0xffffffu), cw = (int)(fmeta[k] >> 24);
+                    float r[MAXCW];
+#pragma unroll
+                    for (int u = 0; u < MAXCW; u++) r[u] = u < cw ? msg[c0 + u] : 0.f;
+                    float pre[MAXCW + 1];
+                    pre[0] = flam[k];
+#pragma unroll
+                    for (int u = 0; u < MAXCW; u++) pre[u + 1] = pre[u] + r[u];
+                    float suf = 0.f;
+#pragma unroll
+                    for (int u = MAXCW - 1; u >= 0; u--) {
+                        if (u < cw) {
+                            msg[c0 + u] = clampf(pre[u] + suf);
+                            suf += r[u];
+                        }
+                    }
+                    const float Lt = clampf(pre[MAXCW]);
+                    Lv[j] = Lt;
+                    if (Lt < 0.f) {
+                        for (int u = 0; u < cw; u++) {
+                            const int i = row_idx[c0 + u];
+                            atomicXor(parw + (i >> 5), 1u << (i & 31));
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // syndrome test of the hard decision after iteration it (it >= 1)
+            if (wave == 0) {
+                bool ok = true;
+                for (int w = lane; w < PW; w += 64) {
+                    ok &= parw[w] == synw[w];
+                    parw[w] = 0u;
+                }
+                const bool all = __ballot(!ok) == 0;
+                if (lane == 0) ctl[1] = all ? 1 : 0;
+            }
+            __syncthreads();
+            const bool sat = ctl[1] != 0;
+            conv = it >= 1 && sat;
+            if ((args.early_exit && conv) || it >= T) break;
+            it++;
+            // check phase: thread t owns check t; two passes over the row's messages (minima and
+            // sign, then the updates) instead of holding them in registers
+            if (t < m) {
+                const uint32_t sb = (synw[t >> 5] >> (t & 31)) & 1u;
+                uint32_t sg = sb << 31;
+                float mn1 = INFINITY, mn2 = INFINITY;
+#pragma unroll
+                for (int u = 0; u < MAXRW; u++) {
+                    if (u < rw) {
+                        const float q = msg[(rpos2[u / 2] >> (16 * (u & 1))) & 0xffffu];
+                        sg ^= __float_as_uint(q);
+                        const float a = fabsf(q);
+                        mn2 = __builtin_amdgcn_fmed3f(mn1, mn2, a);
+                        mn1 = fminf(mn1, a);
+                    }
+                }
+                const float m1 = alpha * mn1, m2 = alpha * mn2;
+#pragma unroll
+                for (int u = 0; u < MAXRW; u++) {
+                    if (u < rw) {
+                        const int p = (rpos2[u / 2] >> (16 * (u & 1))) & 0xffffu;
+                        const float q = msg[p];
+                        const float mag = (fabsf(q) == mn1) ? m2 : m1;
+                        const uint32_t sgn = (sg ^ __float_as_uint(q)) & 0x80000000u;
+                        msg[p] = __uint_as_float(__float_as_uint(mag) | sgn);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // outputs
+        const size_t row = (size_t)shot * n;
+        for (int j = t; j < n; j += NT) {
+            const float Lj = Lv[j];
+            if (args.corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
+            if (args.llr_out) args.llr_out[row + j] = Lj;
+            if (!conv && args.llr_lsd) args.llr_lsd[row + j] = Lj;
+        }
+        if (t == 0) {
+            if (args.info) {
+                qlsd_shot_info inf;
+                inf.status = conv ? QLSD_ST_BP_CONVERGED : 0;
+                inf.reserved = 0;
+                inf.bp_iters = (int16_t)it;
+                inf.n_clusters = 0;
+                inf.rounds = 0;
+                inf.max_cluster_cols = 0;
+                args.info[shot] = inf;
+            }
+            if (args.lsd_flag) args.lsd_flag[shot] = conv ? 0 : 1;
+        }
+        __syncthreads();
+    }
+}
+
 size_t bp_graph_lds_bytes(const DevGraph &g) {
     const size_t PW = ((size_t)g.m + 31) / 32;
     return align16(sizeof(float) * ((size_t)g.nnz + g.n) + sizeof(uint32_t) * 2 * PW + sizeof(int) * 4);
@@ -617,8 +789,22 @@ static hipError_t launch_bp_graph_t(const BpArgs &a, int grid, size_t lds, hipSt
     return hipGetLastError();
 }
 
+template <int RW, int CW, int FPT>
+static hipError_t launch_bp_graph2_t(const BpArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)bp_graph2_kernel<RW, CW, FPT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((bp_graph2_kernel<RW, CW, FPT>), dim3(grid), dim3(kBpGraphThreads), lds, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
     const size_t lds = bp_graph_lds_bytes(a.g);
+    // register-resident structure: checks <= threads, row weight <= 32, column weight <= 8, u16
+    // CSC positions, at most 9 faults per thread (the 936 x 8800 detector error model)
+    const DevGraph &g = a.g;
+    if (g.m <= kBpGraphThreads && g.max_rw <= 32 && g.max_cw <= 8 && g.nnz < 65536 && g.n <= 9 * kBpGraphThreads)
+        return launch_bp_graph2_t<32, 8, 9>(a, grid, lds, st);
     if (a.g.max_rw <= 8 && a.g.max_cw <= 4) return launch_bp_graph_t<8, 4>(a, grid, lds, st);
     if (a.g.max_rw <= 16 && a.g.max_cw <= 8) return launch_bp_graph_t<16, 8>(a, grid, lds, st);
     return launch_bp_graph_t<kMaxRowWeight, kMaxColWeight>(a, grid, lds, st);

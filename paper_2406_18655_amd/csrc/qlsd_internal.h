@@ -16,6 +16,7 @@ struct DevGraph {
     const int32_t *row_ptr, *col_idx;   // m+1, nnz
     const int32_t *col_ptr, *row_idx;   // n+1, nnz
     const int32_t *col_edge;            // nnz: CSR edge id of each CSC entry
+    const int32_t *row_edge;            // nnz: CSC position of each CSR edge (inverse of col_edge)
 };
 
 // Arguments of the BP kernel (messages resident in LDS, persistent slots).
