@@ -680,8 +680,10 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
 // accumulator, padded neighbour lists with a zero sentinel row (u32 byte offsets built once per
 // net by big_tables_kernel).  Neighbour loads are issued in groups of kGather before their MFMAs.
 // ------------------------------------------------------------------------------------------
-constexpr int kBigWaves = 8;
+constexpr int kBigWaves = 12;
 constexpr int kGather = 6;
+constexpr int kFaultGather = 6;  // neighbours of a fault gathered together (padded; heavier columns loop)
+constexpr int kFaultTiles = 1;   // fault tiles per pass
 
 __global__ void big_tables_kernel(DevGraph g, uint32_t *nbc, uint32_t *nbf, float *rdc, float *rdf) {
     const int NP = pad16(g.n), MP = pad16(g.m), dr = g.max_rw, dc = g.max_cw;
@@ -708,6 +710,11 @@ __global__ void big_tables_kernel(DevGraph g, uint32_t *nbc, uint32_t *nbf, floa
     }
 }
 
+// dynamic LDS of net_infer_big_kernel: syndrome signs and the u16 fault neighbour table (the
+// kernel also holds 20 KB of static LDS)
+__host__ __device__ inline size_t big_dyn_lds(const DevGraph &g) {
+    return al16(sizeof(float) * (size_t)g.m) + al16(sizeof(uint16_t) * (size_t)pad16(g.n) * g.max_cw);
+}
 __host__ __device__ inline size_t big_slice_bytes(int n, int m) {
     return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID);
 }
@@ -718,10 +725,14 @@ __device__ __forceinline__ short4v gfrag(const unsigned char *base, uint32_t off
 
 __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A) {
     __shared__ float sv[SV_N];
-    extern __shared__ __align__(16) unsigned char smem[];  // sg: m floats
+    __shared__ uint2 wfl[9 * 2 * 2 * 64];  // weight fragments, [mat][ks][ot][lane] (lane-contiguous)
+    extern __shared__ __align__(16) unsigned char smem[];  // sg: m floats; then fault neighbour rows
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int n = A.g.n, m = A.g.m, NP = pad16(n), MP = pad16(m), dr = A.g.max_rw, dc = A.g.max_cw;
     float *sg = (float *)smem;
+    // the fault phase's neighbour lists as u16 check rows (MP = the zero row), read from LDS
+    uint16_t *nbf16 = (uint16_t *)(smem + al16(sizeof(float) * (size_t)m));
+    for (int x = t; x < NP * dc; x += blockDim.x) nbf16[x] = (uint16_t)(A.nbf[x] >> 6);
     unsigned char *Hb = A.act + (size_t)blockIdx.x * A.act_stride;
     unsigned char *Cb = Hb + (size_t)(NP + 1) * 64;
     const uint16_t *H16 = (const uint16_t *)Hb;
@@ -736,25 +747,21 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
         else v = A.theta[P_BO];
         sv[x] = v;
     }
+    // A-operand fragment (mat, ks, ot) of lane l: W[ot*16 + (l&15)][ks*16 + 4(l>>4) .. +3]
+    for (int x = t; x < 9 * 2 * 2 * 64; x += blockDim.x) {
+        const int l = x & 63, ot = (x >> 6) & 1, ks = (x >> 7) & 1, mat = x >> 8;
+        const int layer = mat / 3, which = mat % 3;
+        const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
+        const float *w = W + (ot * 16 + (l & 15)) * HID + ks * 16 + (l >> 4) * 4;
+        wfl[x] = make_uint2(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3]));
+    }
     if (t < 16) {  // sentinel rows (never written again)
         ((uint32_t *)(Hb + (size_t)NP * 64))[t] = 0u;
         ((uint32_t *)(Cb + (size_t)MP * 64))[t] = 0u;
     }
     const int r16 = lane & 15, kq = (lane >> 4) * 4;
-    short4v wf[9][2][2];
-#pragma unroll
-    for (int mat = 0; mat < 9; mat++) {
-        const int layer = mat / 3, which = mat % 3;
-        const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
-#pragma unroll
-        for (int ks = 0; ks < 2; ks++)
-#pragma unroll
-            for (int ot = 0; ot < 2; ot++) {
-                const float *w = W + (ot * 16 + r16) * HID + ks * 16 + kq;
-                wf[mat][ks][ot] = __builtin_bit_cast(short4v, make_uint2(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3])));
-            }
-    }
     __syncthreads();
+    auto frag = [&](int mat, int ks, int ot) { return __builtin_bit_cast(short4v, wfl[((mat * 2 + ks) * 2 + ot) * 64 + lane]); };
 
     const int total = A.list ? *A.list_count : A.count;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -783,76 +790,104 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
             }
         }
         __syncthreads();
-#pragma unroll
         for (int l = 0; l < NL; l++) {
             // checks: c_i = relu((1/deg_i) sum_j A h_j + sigma_i a)
-            for (int rt = wave; rt < MP / 16; rt += kBigWaves) {
-                const int i = rt * 16 + r16;
-                float4v acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-                const uint32_t *nb = A.nbc + (size_t)i * dr;
-                for (int k0 = 0; k0 < dr; k0 += kGather) {
-                    short4v x0[kGather], x1[kGather];
+            {
+                const short4v a00 = frag(l * 3, 0, 0), a01 = frag(l * 3, 0, 1), a10 = frag(l * 3, 1, 0),
+                              a11 = frag(l * 3, 1, 1);
+                for (int rt = wave; rt < MP / 16; rt += kBigWaves) {
+                    const int i = rt * 16 + r16;
+                    float4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+                    const uint32_t *nb = A.nbc + (size_t)i * dr;
+                    for (int k0 = 0; k0 < dr; k0 += kGather) {
+                        short4v x0[kGather], x1[kGather];
 #pragma unroll
-                    for (int k = 0; k < kGather; k++) {
-                        const uint32_t off = k0 + k < dr ? nb[k0 + k] : (uint32_t)NP * 64u;
-                        x0[k] = gfrag(Hb, off + kq * 2);
-                        x1[k] = gfrag(Hb, off + 32 + kq * 2);
-                    }
-#pragma unroll
-                    for (int k = 0; k < kGather; k++)
-#pragma unroll
-                        for (int ot = 0; ot < 2; ot++) {
-                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][0][ot], x0[k], acc[ot], 0, 0, 0);
-                            acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][1][ot], x1[k], acc[ot], 0, 0, 0);
+                        for (int k = 0; k < kGather; k++) {
+                            const uint32_t off = k0 + k < dr ? nb[k0 + k] : (uint32_t)NP * 64u;
+                            x0[k] = gfrag(Hb, off + kq * 2);
+                            x1[k] = gfrag(Hb, off + 32 + kq * 2);
                         }
-                }
-                const float rd = A.rdc[i], sgn = i < m ? sg[i] : 0.f;
 #pragma unroll
-                for (int ot = 0; ot < 2; ot++) {
+                        for (int k = 0; k < kGather; k++) {
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a00, x0[k], acc0, 0, 0, 0);
+                            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a10, x1[k], acc0, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a01, x0[k], acc1, 0, 0, 0);
+                            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a11, x1[k], acc1, 0, 0, 0);
+                        }
+                    }
+                    const float rd = A.rdc[i], sgn = i < m ? sg[i] : 0.f;
                     float v[4];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc[ot][q] + sgn * sv[SV_A + l * HID + ot * 16 + kq + q], 0.f);
-                    *(uint2 *)(Cb + (size_t)i * 64 + ot * 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc0[q] + sgn * sv[SV_A + l * HID + kq + q], 0.f);
+                    *(uint2 *)(Cb + (size_t)i * 64 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+#pragma unroll
+                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc1[q] + sgn * sv[SV_A + l * HID + 16 + kq + q], 0.f);
+                    *(uint2 *)(Cb + (size_t)i * 64 + 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
                 }
             }
             __syncthreads();
-            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b), in place (own rows only)
-            for (int rt = wave; rt < NP / 16; rt += kBigWaves) {
-                const int j = rt * 16 + r16;
-                const short4v h0 = gfrag(Hb, (uint32_t)j * 64u + kq * 2), h1 = gfrag(Hb, (uint32_t)j * 64u + 32 + kq * 2);
-                float4v as[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-                float4v an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-                const uint32_t *nb = A.nbf + (size_t)j * dc;
-                for (int k0 = 0; k0 < dc; k0 += kGather) {
-                    short4v y0[kGather], y1[kGather];
+            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b), in place (own rows only); every
+            // gather of a pass's tiles in flight together
+            {
+                const short4v b00 = frag(l * 3 + 1, 0, 0), b01 = frag(l * 3 + 1, 0, 1), b10 = frag(l * 3 + 1, 1, 0),
+                              b11 = frag(l * 3 + 1, 1, 1);
+                const short4v c00 = frag(l * 3 + 2, 0, 0), c01 = frag(l * 3 + 2, 0, 1), c10 = frag(l * 3 + 2, 1, 0),
+                              c11 = frag(l * 3 + 2, 1, 1);
+                const int ntiles = NP / 16;
+                for (int rt0 = wave; rt0 < ntiles; rt0 += kFaultTiles * kBigWaves) {
+                    short4v h0[kFaultTiles], h1[kFaultTiles], y0[kFaultTiles][kFaultGather], y1[kFaultTiles][kFaultGather];
 #pragma unroll
-                    for (int k = 0; k < kGather; k++) {
-                        const uint32_t off = k0 + k < dc ? nb[k0 + k] : (uint32_t)MP * 64u;
-                        y0[k] = gfrag(Cb, off + kq * 2);
-                        y1[k] = gfrag(Cb, off + 32 + kq * 2);
+                    for (int tt = 0; tt < kFaultTiles; tt++) {
+                        const int rt = rt0 + tt * kBigWaves;
+                        const int j = (rt < ntiles ? rt : rt0) * 16 + r16;
+                        h0[tt] = gfrag(Hb, (uint32_t)j * 64u + kq * 2);
+                        h1[tt] = gfrag(Hb, (uint32_t)j * 64u + 32 + kq * 2);
+                        const uint16_t *nb = nbf16 + (size_t)j * dc;
+#pragma unroll
+                        for (int k = 0; k < kFaultGather; k++) {
+                            const uint32_t off = (k < dc ? (uint32_t)nb[k] : (uint32_t)MP) * 64u;
+                            y0[tt][k] = gfrag(Cb, off + kq * 2);
+                            y1[tt][k] = gfrag(Cb, off + 32 + kq * 2);
+                        }
                     }
 #pragma unroll
-                    for (int k = 0; k < kGather; k++)
+                    for (int tt = 0; tt < kFaultTiles; tt++) {
+                        const int rt = rt0 + tt * kBigWaves;
+                        if (rt >= ntiles) continue;
+                        const int j = rt * 16 + r16;
+                        float4v as0 = {0.f, 0.f, 0.f, 0.f}, as1 = {0.f, 0.f, 0.f, 0.f};
+                        float4v an0 = {0.f, 0.f, 0.f, 0.f}, an1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int ot = 0; ot < 2; ot++) {
-                            an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][0][ot], y0[k], an[ot], 0, 0, 0);
-                            an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][1][ot], y1[k], an[ot], 0, 0, 0);
+                        for (int k = 0; k < kFaultGather; k++) {
+                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c00, y0[tt][k], an0, 0, 0, 0);
+                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c10, y1[tt][k], an0, 0, 0, 0);
+                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c01, y0[tt][k], an1, 0, 0, 0);
+                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c11, y1[tt][k], an1, 0, 0, 0);
                         }
-                }
+                        for (int k0 = kFaultGather; k0 < dc; k0++) {  // columns heavier than kFaultGather
+                            const uint32_t off = (uint32_t)nbf16[(size_t)j * dc + k0] * 64u;
+                            const short4v z0 = gfrag(Cb, off + kq * 2), z1 = gfrag(Cb, off + 32 + kq * 2);
+                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c00, z0, an0, 0, 0, 0);
+                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c10, z1, an0, 0, 0, 0);
+                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c01, z0, an1, 0, 0, 0);
+                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c11, z1, an1, 0, 0, 0);
+                        }
+                        as0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b00, h0[tt], as0, 0, 0, 0);
+                        as0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b10, h1[tt], as0, 0, 0, 0);
+                        as1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b01, h0[tt], as1, 0, 0, 0);
+                        as1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b11, h1[tt], as1, 0, 0, 0);
+                        const float rd = A.rdf[j];
+                        const bool live = j < n;
+                        float v[4];
 #pragma unroll
-                for (int ot = 0; ot < 2; ot++) {
-                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][0][ot], h0, as[ot], 0, 0, 0);
-                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][1][ot], h1, as[ot], 0, 0, 0);
-                }
-                const float rd = A.rdf[j];
-                const bool live = j < n;
+                        for (int q = 0; q < 4; q++)
+                            v[q] = live ? fmaxf(as0[q] + rd * an0[q] + sv[SV_BL + l * HID + kq + q], 0.f) : 0.f;
+                        *(uint2 *)(Hb + (size_t)j * 64 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
 #pragma unroll
-                for (int ot = 0; ot < 2; ot++) {
-                    float v[4];
-#pragma unroll
-                    for (int q = 0; q < 4; q++)
-                        v[q] = live ? fmaxf(as[ot][q] + rd * an[ot][q] + sv[SV_BL + l * HID + ot * 16 + kq + q], 0.f) : 0.f;
-                    *(uint2 *)(Hb + (size_t)j * 64 + ot * 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                        for (int q = 0; q < 4; q++)
+                            v[q] = live ? fmaxf(as1[q] + rd * an1[q] + sv[SV_BL + l * HID + 16 + kq + q], 0.f) : 0.f;
+                        *(uint2 *)(Hb + (size_t)j * 64 + 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    }
                 }
             }
             __syncthreads();
@@ -985,7 +1020,10 @@ static hipError_t launch_infer_big(const qlsd_net_s *net, NetArgs a, unsigned ch
     a.rdc = net->d_rdc;
     a.rdf = net->d_rdf;
     const int grid = std::max(1, std::min(max_items, big_slices(net)));
-    hipLaunchKernelGGL(net_infer_big_kernel, dim3(grid), dim3(64 * kBigWaves), sizeof(float) * (size_t)a.g.m, st, a);
+    const size_t lds = big_dyn_lds(a.g);
+    hipError_t e = hipFuncSetAttribute((const void *)net_infer_big_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(net_infer_big_kernel, dim3(grid), dim3(64 * kBigWaves), lds, st, a);
     return hipGetLastError();
 }
 // Inference of max_items shots (a.list / a.count say which); ws: a feature workspace of
@@ -1050,6 +1088,11 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
     }
     if (!net->wave_infer) {
         const int NP = pad16(g.n), MP = pad16(g.m);
+        if (MP + 1 > 65535 || big_dyn_lds(g) + 20 * 1024 > 159 * 1024) {
+            qlsd_net_destroy(net);
+            set_last_error("graph too large for the refinement's inference kernel");
+            return QLSD_E_UNSUPPORTED;
+        }
         ok = (size_t)(NP + 1) * 64 < (1ull << 32) && (size_t)(MP + 1) * 64 < (1ull << 32) &&
              hipMalloc((void **)&net->d_nbc, sizeof(uint32_t) * (size_t)MP * g.max_rw) == hipSuccess &&
              hipMalloc((void **)&net->d_nbf, sizeof(uint32_t) * (size_t)NP * g.max_cw) == hipSuccess &&
