@@ -79,10 +79,18 @@ void free_lane(Lane &l) {
     l = Lane();
 }
 
-// Launches one batch on a free lane from the requests of code c that have arrived.
-bool launch_batch(qlsd_server_s *s, Code &c, Lane &l, double t) {
+// Launches one batch on a free lane from the requests of code c that have arrived.  A lane
+// starts while another lane of the same code is still running only if at least half a batch has
+// arrived: at light load one batch per code is in flight (fewer small decodes contending for
+// the device), under backlog every lane works.
+bool launch_batch(qlsd_server_s *s, Code &c, Lane &l, double t, int busy_lanes) {
     {
         std::lock_guard<std::mutex> g(s->mu);
+        if (busy_lanes > 0) {
+            const auto end = std::upper_bound(c.pending.begin(), c.pending.end(), t,
+                                              [](double v, const Request &r) { return v < r.arrival_us; });
+            if ((end - c.pending.begin()) * 2 < c.batch_shots) return false;
+        }
         while (!c.pending.empty() && (int)l.batch.size() < c.batch_shots && c.pending.front().arrival_us <= t) {
             l.batch.push_back(c.pending.front());
             c.pending.pop_front();
@@ -132,11 +140,14 @@ void scheduler(qlsd_server_s *s) {
         const double t = now_us(s);
         for (size_t ci = 0; ci < s->codes.size(); ci++) {
             Code &c = *s->codes[ci];
+            int busy = 0;
+            for (Lane &l : c.lanes) busy += l.busy ? 1 : 0;
             for (Lane &l : c.lanes) {
                 if (l.busy) {
                     const hipError_t q = hipEventQuery(l.done);
                     if (q == hipSuccess) {
                         finish_batch(s, (int)ci, c, l);
+                        busy--;
                         progress = true;
                     } else if (q != hipErrorNotReady) {
                         snprintf(s->error, sizeof(s->error), "device failure: %s", hipGetErrorString(q));
@@ -145,7 +156,10 @@ void scheduler(qlsd_server_s *s) {
                         return;
                     }
                 }
-                if (!l.busy && launch_batch(s, c, l, t)) progress = true;
+                if (!l.busy && launch_batch(s, c, l, t, busy)) {
+                    busy++;
+                    progress = true;
+                }
                 any_busy |= l.busy;
             }
         }
