@@ -45,8 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-ordering leg")
-    ap.add_argument("--no-tune", action="store_true",
-                    help="keep the default launch shapes (no qlsd_decoder_tune before the timed steps)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run qlsd_decoder_tune on batch 0 before the timed steps (on the headline batch it "
+                         "lands on the default shapes within noise)")
     ap.add_argument("--learned-iter", type=int, default=None,
                     help="BP iterations of the learned form (default 10 for bb144, 30 for dem)")
     ap.add_argument("--serve", action="store_true",
@@ -124,7 +125,7 @@ def main():
         ler_gpu.append(logical_failures(code, e, c))
 
     tuning = None
-    if not args.no_tune:
+    if args.tune:
         log("autotuning launch shapes on batch 0")
         tuning = dec.tune(batches[0][1], reps=3)
     log("correctness pass done; warmup and timed steps")
@@ -230,7 +231,7 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     net = binding.Net(bcode, code.priors, np.load(os.path.join(wdir, wname)))
     dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
     binding.attach_net(dec, net)
-    if not args.no_tune:
+    if args.tune:
         dec.tune(batches[0][1], reps=3)
     corr = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
     fails = []
