@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--serve-ordering", default="plain,learned",
                     help="plain: BP+LSD for every code; learned: the [[144,12,12]] lanes run BP 10 + "
                          "the trained refinement + LSD")
-    ap.add_argument("--serve-requests", type=int, default=200000)
+    ap.add_argument("--serve-requests", type=int, default=1000000, help="requests per rate (all codes together)")
     ap.add_argument("--sweep", action="store_true",
                     help="[[144,12,12]] over p in {0.01,0.02,0.04,0.05,0.06}: 10^6 shots per point "
                          "(15 launches of 65,536 plus one of 16,960), GPU LER and shots/s, the oracle's "
@@ -316,11 +316,15 @@ def serve_main(args):
            ("hgp34_n32", random_34_hgp(32, p=0.03), 30, 0, 1024),
            ("bb144", bivariate_bicycle(p=0.05), 50, 0, 4096),
            ("dem936x8800", synthetic_dem(), 100, 10, 512)]
+    from paper_2406_18655_amd.workloads import DeviceSampler
     per_code = args.serve_requests // len(mix)
     pools = []
-    for k, (name, code, T, mu, bs) in enumerate(mix):
-        e, S = sample(code, per_code, seed=args.seed + 100 + k)
-        pools.append(S)
+    for k, (name, code, T, mu, bs) in enumerate(mix):  # request syndromes, drawn on the GPU, held on the host
+        e, S = DeviceSampler(code).sample(per_code, args.seed + 100 + k)
+        pools.append(S.cpu().numpy())
+        del e, S
+    torch.cuda.synchronize()
+    print(f"[serve] {per_code} requests per code sampled", file=sys.stderr, flush=True)
     weights = os.path.join(HERE, "paper_2406_18655_amd", "weights", "bb144_mix_T10.npy")
     for ordering, rate in [(o, float(x)) for o in args.serve_ordering.split(",") for x in args.serve_rates.split(",")]:
         rng = np.random.default_rng(args.seed)
