@@ -85,6 +85,17 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _need(t, shape, dtype_name: str, what: str, optional: bool = False):
+    """The ABI takes raw device pointers and trusts their sizes: check every tensor here."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{what} is required")
+    if str(t.dtype) != f"torch.{dtype_name}" or not t.is_cuda or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must be a {dtype_name} CUDA tensor of shape {tuple(shape)}, "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}")
+
+
 def _stream() -> int:
     import torch
     return torch.cuda.current_stream().cuda_stream
@@ -143,18 +154,29 @@ class Decoder:
             self._h = None
 
     # -- raw entry points (device pointers, caller-owned outputs) --------------------
+    def _check_io(self, syndromes, B, **outs):
+        _need(syndromes, (B, self.code.m), "uint8", "syndromes")
+        spec = {"corrections": ((B, self.code.n), "uint8"), "hard_out": ((B, self.code.n), "uint8"),
+                "llr": ((B, self.code.n), "float32"), "llr_out": ((B, self.code.n), "float32"),
+                "info": ((B, 12), "uint8")}
+        for name, t in outs.items():
+            _need(t, spec[name][0], spec[name][1], name, optional=name in ("info", "hard_out"))
+
     def decode_into(self, syndromes, corrections, info=None, stream: Optional[int] = None):
         B = syndromes.shape[0]
+        self._check_io(syndromes, B, corrections=corrections, info=info)
         _check(lib().qlsd_decode(self._h, _ptr(syndromes), B, _ptr(corrections), _ptr(info),
                                  _stream() if stream is None else stream))
 
     def bp_into(self, syndromes, llr_out, hard_out=None, info=None, stream: Optional[int] = None):
         B = syndromes.shape[0]
+        self._check_io(syndromes, B, llr_out=llr_out, hard_out=hard_out, info=info)
         _check(lib().qlsd_bp(self._h, _ptr(syndromes), B, _ptr(llr_out), _ptr(hard_out), _ptr(info),
                              _stream() if stream is None else stream))
 
     def lsd_into(self, syndromes, llr, corrections, info=None, stream: Optional[int] = None):
         B = syndromes.shape[0]
+        self._check_io(syndromes, B, llr=llr, corrections=corrections, info=info)
         _check(lib().qlsd_lsd(self._h, _ptr(syndromes), _ptr(llr), B, _ptr(corrections), _ptr(info),
                               _stream() if stream is None else stream))
 
@@ -163,6 +185,7 @@ class Decoder:
 
     def tune(self, syndromes, reps: int = 5, stream: Optional[int] = None) -> str:
         """Autotune launch shapes on a sample batch (include/qlsd.h); returns the timing report."""
+        self._check_io(syndromes, syndromes.shape[0])
         buf = ctypes.create_string_buffer(8192)
         _check(lib().qlsd_decoder_tune(self._h, _ptr(syndromes), syndromes.shape[0], int(reps),
                                        _stream() if stream is None else stream, buf, len(buf)))
@@ -377,14 +400,23 @@ class Net:
         _check(_net_lib().qlsd_net_get_params(self._h, out.ctypes.data))
         return out
 
+    def _check_in(self, syndromes, llr, errors=None):
+        B = llr.shape[0]
+        _need(syndromes, (B, self.code.m), "uint8", "syndromes")
+        _need(llr, (B, self.code.n), "float32", "llr")
+        if errors is not None:
+            _need(errors, (B, self.code.n), "uint8", "errors")
+
     def forward(self, syndromes, llr):
         import torch
+        self._check_in(syndromes, llr)
         out = torch.empty_like(llr)
         _check(_net_lib().qlsd_net_forward(self._h, _ptr(syndromes), _ptr(llr), llr.shape[0], _ptr(out), _stream()))
         return out
 
     def gradient(self, syndromes, llr, errors):
         import torch
+        self._check_in(syndromes, llr, errors)
         g = torch.empty(NET_PARAMS, dtype=torch.float32, device=llr.device)
         loss = torch.empty(1, dtype=torch.float32, device=llr.device)
         _check(_net_lib().qlsd_net_gradient(self._h, _ptr(syndromes), _ptr(llr), _ptr(errors), llr.shape[0],
@@ -392,6 +424,7 @@ class Net:
         return g, loss
 
     def train_step(self, syndromes, llr, errors, lr: float):
+        self._check_in(syndromes, llr, errors)
         _check(_net_lib().qlsd_net_train_step(self._h, _ptr(syndromes), _ptr(llr), _ptr(errors), llr.shape[0],
                                               float(lr), _stream()))
 

@@ -52,13 +52,25 @@ struct qlsd_server_s {
     std::condition_variable cv;
     std::vector<qlsd_completion> done;  // not yet drained by the caller
     int64_t completed = 0;
-    std::atomic<bool> stop{false}, started{false};
+    std::atomic<bool> stop{false}, started{false}, failed{false};
     std::thread worker;
     std::chrono::steady_clock::time_point epoch;
-    char error[256] = "";
+    char error[256] = "";  // first asynchronous (device or decode) failure; written under mu
 };
 
 namespace {
+
+// Records the first failure (under the lock qlsd_server_wait reads it with), stops the
+// scheduler and wakes waiters.
+void fail_server(qlsd_server_s *s, const char *fmt, const char *detail) {
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (!s->error[0]) snprintf(s->error, sizeof(s->error), fmt, detail);
+        s->failed = true;
+    }
+    s->stop = true;
+    s->cv.notify_all();
+}
 
 double now_us(const qlsd_server_s *s) {
     if (!s->started.load()) return 0.0;
@@ -99,12 +111,19 @@ bool launch_batch(qlsd_server_s *s, Code &c, Lane &l, double t, int busy_lanes) 
     const int B = (int)l.batch.size();
     if (B == 0) return false;
     for (int b = 0; b < B; b++) memcpy(l.h_syn + (size_t)b * c.m, l.batch[b].syn, c.m);
-    hipMemcpyAsync(l.d_syn, l.h_syn, (size_t)B * c.m, hipMemcpyHostToDevice, l.stream);
-    qlsd_status st = qlsd_decode(l.dec, l.d_syn, B, l.d_corr, (qlsd_shot_info *)l.d_info, l.stream);
-    if (st != QLSD_OK) snprintf(s->error, sizeof(s->error), "decode failed: %s", qlsd_last_error());
-    hipMemcpyAsync(l.h_corr, l.d_corr, (size_t)B * c.n, hipMemcpyDeviceToHost, l.stream);
-    hipMemcpyAsync(l.h_info, l.d_info, (size_t)B * sizeof(qlsd_shot_info), hipMemcpyDeviceToHost, l.stream);
-    hipEventRecord(l.done, l.stream);
+    bool ok = hipMemcpyAsync(l.d_syn, l.h_syn, (size_t)B * c.m, hipMemcpyHostToDevice, l.stream) == hipSuccess;
+    if (ok && qlsd_decode(l.dec, l.d_syn, B, l.d_corr, (qlsd_shot_info *)l.d_info, l.stream) != QLSD_OK) {
+        fail_server(s, "decode failed: %s", qlsd_last_error());
+        return false;  // the batch's requests are not completed; waiters see the error
+    }
+    ok = ok && hipMemcpyAsync(l.h_corr, l.d_corr, (size_t)B * c.n, hipMemcpyDeviceToHost, l.stream) == hipSuccess &&
+         hipMemcpyAsync(l.h_info, l.d_info, (size_t)B * sizeof(qlsd_shot_info), hipMemcpyDeviceToHost, l.stream) ==
+             hipSuccess &&
+         hipEventRecord(l.done, l.stream) == hipSuccess;
+    if (!ok) {
+        fail_server(s, "%s", "enqueueing a batch failed");
+        return false;
+    }
     l.busy = true;
     return true;
 }
@@ -150,13 +169,15 @@ void scheduler(qlsd_server_s *s) {
                         busy--;
                         progress = true;
                     } else if (q != hipErrorNotReady) {
-                        snprintf(s->error, sizeof(s->error), "device failure: %s", hipGetErrorString(q));
-                        s->stop = true;
-                        s->cv.notify_all();
+                        fail_server(s, "device failure: %s", hipGetErrorString(q));
+                        // let in-flight work drain before the thread ends
+                        for (Code *cc : s->codes)
+                            for (Lane &ll : cc->lanes)
+                                if (ll.busy) hipStreamSynchronize(ll.stream);
                         return;
                     }
                 }
-                if (!l.busy && launch_batch(s, c, l, t, busy)) {
+                if (!l.busy && !s->failed.load() && launch_batch(s, c, l, t, busy)) {
                     busy++;
                     progress = true;
                 }
@@ -168,8 +189,8 @@ void scheduler(qlsd_server_s *s) {
     }
 }
 
-qlsd_status serr(qlsd_server_s *s, qlsd_status st, const char *msg) {
-    if (s) snprintf(s->error, sizeof(s->error), "%s", msg);
+// Synchronous errors of an API call: reported to that caller only (the server stays usable).
+qlsd_status serr(qlsd_server_s *, qlsd_status st, const char *msg) {
     qlsd::set_last_error("%s", msg);
     return st;
 }
@@ -285,8 +306,8 @@ qlsd_status qlsd_server_wait(qlsd_server s, int64_t count, double timeout_s) {
     if (!s) return serr(s, QLSD_E_INVALID, "server is NULL");
     std::unique_lock<std::mutex> g(s->mu);
     const bool ok = s->cv.wait_for(g, std::chrono::duration<double>(timeout_s),
-                                   [&] { return s->completed >= count || s->error[0] != 0; });
-    if (s->error[0]) {
+                                   [&] { return s->completed >= count || s->failed.load(); });
+    if (s->failed.load()) {
         qlsd::set_last_error("%s", s->error);
         return QLSD_E_DEVICE;
     }

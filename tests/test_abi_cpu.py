@@ -95,3 +95,30 @@ def test_generated_syndromes_are_row_major():
     from paper_2406_18655_amd.workloads import bivariate_bicycle, sample
     e, s = sample(bivariate_bicycle(), 64, seed=1)
     assert e.flags["C_CONTIGUOUS"] and s.flags["C_CONTIGUOUS"]
+
+
+def test_binding_rejects_mis_shaped_tensors():
+    """The C ABI trusts buffer sizes; the binding must refuse tensors that do not match the
+    decoder's (m, n) before any pointer reaches it (checked here without a GPU: the shape check
+    runs first, so a CPU tensor of the right shape fails on the device check instead)."""
+    import torch
+    from paper_2406_18655_amd import binding
+
+    class FakeCode:
+        m, n = 4, 7
+
+    class FakeDecoder(binding.Decoder):
+        def __init__(self):
+            self.code = FakeCode()
+            self.max_batch = 8
+
+    d = FakeDecoder()
+    s = torch.zeros((3, 4), dtype=torch.uint8)
+    with pytest.raises(ValueError, match="shape"):
+        d.decode_into(torch.zeros((3, 5), dtype=torch.uint8), torch.zeros((3, 7), dtype=torch.uint8))
+    with pytest.raises(ValueError, match="CUDA"):
+        d.decode_into(s, torch.zeros((3, 7), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        d.lsd_into(s, torch.zeros((3, 7), dtype=torch.float64), torch.zeros((3, 7), dtype=torch.uint8))
+    with pytest.raises(ValueError):
+        d.bp_into(s, torch.zeros((3, 6), dtype=torch.float32))
