@@ -103,3 +103,36 @@ def test_bb_lsd_mu_bit_exact(oracle_mod):
     for b in range(400):
         want, st, stats = oracle_mod.lsd(oc, S[b], L[b].astype(np.float64), mu=4, omega=om)
         assert (corr[b] == want).all(), b
+
+
+def test_dem_capacity_overflow_is_flagged(dem):
+    """A syndrome with more flipped detectors than LSD's local-row capacity (256 with LSD order
+    10) cannot be decoded in LDS: the shot must come back flagged OVERFLOW with a zero
+    correction, and its neighbours in the batch must be unaffected."""
+    code = dem
+    bc = binding.Code.from_dense(code.H)
+    rng = np.random.default_rng(5)
+    e, S = sample(code, 64, seed=8)
+    S = S.copy()
+    S[7] = (rng.random(code.m) < 0.5).astype(np.uint8)  # ~470 flipped detectors
+    dec = binding.Decoder(bc, code.priors, 64, max_iter=20, lsd_order=10)
+    corr, info = dec.decode(torch.from_numpy(S).cuda(), want_info=True)
+    corr, inf = corr.cpu().numpy(), binding.parse_info(info)
+    assert inf["status"][7] & binding.ST_OVERFLOW and not corr[7].any()
+    ok = np.ones(64, dtype=bool)
+    ok[7] = False
+    ref = dec.decode(torch.from_numpy(np.ascontiguousarray(S[ok])).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(corr[ok], ref)
+
+
+def test_dem_batch_size_invariance(dem):
+    """Shots decode the same alone, in small ragged batches and in a full batch (one workgroup per
+    shot, no cross-shot state)."""
+    code = dem
+    bc = binding.Code.from_dense(code.H)
+    e, S = sample(code, 300, seed=9)
+    dec = binding.Decoder(bc, code.priors, 300, max_iter=100, lsd_order=10)
+    full = dec.decode(torch.from_numpy(S).cuda()).cpu().numpy()
+    for lo, hi in ((0, 1), (1, 4), (4, 37), (37, 300)):
+        part = dec.decode(torch.from_numpy(np.ascontiguousarray(S[lo:hi])).cuda()).cpu().numpy()
+        np.testing.assert_array_equal(part, full[lo:hi])
