@@ -171,15 +171,27 @@ __device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
 template <int W, class G>
 __device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col, int lane) {
-    const int c0 = g.col_ptr(col), c1 = g.col_ptr(col + 1);
-    uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
-    for (int u = c0; u < c1; u++) {
-        const int lr = S.loc[g.row_idx(u)];
-        if (lr >= 0 && lr < 64 * W && (lr & 63) == lane) bf |= 1u << (lr >> 6);
+    const int c0 = g.col_ptr(col), cw = g.col_ptr(col + 1) - c0;
+    // the column's support over local rows, as W wave-uniform masks: lane u looks up its entry,
+    // then the masks are assembled from the lanes' results
+    const int lr_mine = lane < cw ? S.loc[g.row_idx(c0 + lane)] : -1;
+    uint64_t cm[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) cm[s] = 0;
+    for (int u = 0; u < cw; u++) {
+        const int lr = __builtin_amdgcn_readlane(lr_mine, u);
+        if (lr >= 0 && lr < 64 * W) {
+#pragma unroll
+            for (int s = 0; s < W; s++)
+                if ((lr >> 6) == s) cm[s] |= 1ull << (lr & 63);
+        }
     }
+    uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
+#pragma unroll
+    for (int s = 0; s < W; s++) bf |= (uint32_t)((cm[s] >> lane) & 1ull) << s;
     uint64_t a[W];
 #pragma unroll
-    for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
+    for (int s = 0; s < W; s++) a[s] = cm[s] & B.piv[s];
     uint32_t bpf = 0;
 #pragma unroll
     for (int s = 0; s < W; s++) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_and<W>(B.Mrow[s], a)) << s;
@@ -565,25 +577,35 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         nrows = nrows_new;
         wave_sync();
 
-        // (4) the round's distinct new columns, ascending key, each reduced on the fly
-        uint32_t done = 0;  // bit q: list entry lane + 64 q consumed
-        for (;;) {
-            uint64_t mine = ~0ull;
-            for (int q = 0; q * 64 + lane < nsel; q++)
-                if (!((done >> q) & 1u)) {
-                    const uint64_t k = S.lkey[q * 64 + lane];
-                    mine = k < mine ? k : mine;
+        // (4) the round's distinct new columns, ascending key, each reduced on the fly.  Order:
+        // entry p goes to position rank(p) = number of entries with a smaller key (distinct keys get
+        // distinct positions; a column picked by several clusters is placed once, by its first
+        // entry).  The selection array is free at this point and holds the order.
+        {
+            int32_t *order = (int32_t *)S.sel;
+            for (int p = lane; p < nsel; p += 64) order[p] = -1;
+            wave_sync();
+            for (int p = lane; p < nsel; p += 64) {
+                const uint64_t kp = S.lkey[p];
+                int rank = 0;
+                bool dup = false;
+                for (int q = 0; q < nsel; q++) {
+                    const uint64_t kq = S.lkey[q];
+                    rank += kq < kp ? 1 : 0;
+                    dup |= kq == kp && q < p;
                 }
-            const uint64_t kmin = wave_min_u64(mine);
-            if (kmin == ~0ull) break;
-            for (int q = 0; q * 64 + lane < nsel; q++)
-                if (S.lkey[q * 64 + lane] == kmin) done |= 1u << q;
-            const int col = (int)(uint32_t)kmin;
-            if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
-            const bool pivot = insert_column<W>(B, S, g, col, lane);
-            if (!pivot && A.mu > 0) {
-                if (lane == 0 && npc < K) S.colNP[npc] = col;
-                npc++;
+                if (!dup) order[rank] = (int)(uint32_t)kp;
+            }
+            wave_sync();
+            for (int r = 0; r < nsel; r++) {
+                const int col = order[r];
+                if (col < 0) continue;
+                if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
+                const bool pivot = insert_column<W>(B, S, g, col, lane);
+                if (!pivot && A.mu > 0) {
+                    if (lane == 0 && npc < K) S.colNP[npc] = col;
+                    npc++;
+                }
             }
         }
         wave_sync();
