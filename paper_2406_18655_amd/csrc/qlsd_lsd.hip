@@ -397,7 +397,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     }
     for (int w = lane; w < (n + 31) / 32; w += 64) S.incol[w] = 0u;
     for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
-    for (int j = lane; j < n; j += 64) corr[j] = 0;
+    if ((n & 15) == 0 && (((uintptr_t)corr) & 15) == 0) {
+        for (int j = lane; j < (n >> 4); j += 64) ((uint4 *)corr)[j] = make_uint4(0u, 0u, 0u, 0u);
+    } else {
+        for (int j = lane; j < n; j += 64) corr[j] = 0;
+    }
     __threadfence_block();  // the zero stores complete before any later scatter to this row
     wave_sync();
 
@@ -474,12 +478,14 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                     if (best == kStale || (best != ~0ull && in_col(S.incol, (int)(uint32_t)best))) {
                         const int d = S.rowOf[r];
                         best = ~0ull;
-                        const int e1 = g.row_ptr(d + 1);
-                        for (int e = g.row_ptr(d); e < e1; e++) {
+                        const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
+                        // branch-free and unrolled so that the loads of several faults are in
+                        // flight together (graph and keys may live in global memory)
+#pragma unroll 8
+                        for (int e = e0; e < e1; e++) {
                             const int j = g.col_idx(e);
-                            if (in_col(S.incol, j)) continue;
                             const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
-                            const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)j;
+                            const uint64_t key = in_col(S.incol, j) ? ~0ull : (((uint64_t)kj << 32) | (uint32_t)j);
                             best = key < best ? key : best;
                         }
                         S.cand[r] = best;
