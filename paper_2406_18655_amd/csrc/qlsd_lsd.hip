@@ -529,8 +529,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         // (3) claims and unions (Def. 4.4): pairs (selection, detector of its fault)
         const int cwm = g.max_cw;
         const int npairs = nsel * cwm;
+        // pair id -> (selection, entry): id / cwm as a multiply-high by ceil(2^32 / cwm), exact for
+        // id < 2^16 and cwm <= 16
+        const uint64_t cw_magic = (0x100000000ull + (uint64_t)cwm - 1ull) / (uint64_t)cwm;  // 2^32 when cwm = 1
         for (int id = lane; id < npairs; id += 64) {
-            const int p = id / cwm, u = id - p * cwm;
+            const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
             const int c0 = g.col_ptr(col);
             if (u < g.col_ptr(col + 1) - c0) {
@@ -541,7 +544,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         wave_sync();
         bool merged = false;
         for (int id = lane; id < npairs; id += 64) {
-            const int p = id / cwm, u = id - p * cwm;
+            const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
             const int c0 = g.col_ptr(col);
             if (u < g.col_ptr(col + 1) - c0) {
