@@ -95,8 +95,9 @@ struct FaultItem {
         slot = slot_;
         c0 = REG ? j * CW : L.cp[j];
         cw = REG ? CW : L.cp[j + 1] - c0;
-        const bool fresh = L.siter[L.act[slot]] == 0;
-        const float *mk = L.msg + L.actm[slot];
+        const int am = L.actm[slot];
+        const bool fresh = am < 0;  // the slot's shot starts this iteration (sign bit, see slot management)
+        const float *mk = L.msg + (am & 0x7fffffff);
 #pragma unroll
         for (int u = 0; u < CW; u++) {
             if (REG || u < cw) {
@@ -109,7 +110,7 @@ struct FaultItem {
         }
     }
     __device__ __forceinline__ void store(const BpLds &L, bool count_parity) const {
-        float *mk = L.msg + L.actm[slot];
+        float *mk = L.msg + (L.actm[slot] & 0x7fffffff);
         const float lam = L.lam[j];
         float pre[CW + 1];
         pre[0] = lam;
@@ -149,7 +150,7 @@ struct CheckItem {
         slot = slot_;
         e0 = REG ? i * RW : L.rp[i];
         rw = REG ? RW : L.rp[i + 1] - e0;
-        const float *mk = L.msg + L.actm[slot] + e0;
+        const float *mk = L.msg + (L.actm[slot] & 0x7fffffff) + e0;
         sb = (L.synw[(size_t)L.act[slot] * L.PW + (i >> 5)] >> (i & 31)) & 1u;
 #pragma unroll
         for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? mk[u] : INFINITY;
@@ -165,7 +166,7 @@ struct CheckItem {
             mn1 = fminf(mn1, a);
         }
         const float m1 = alpha * mn1, m2 = alpha * mn2;
-        float *mk = L.msg + L.actm[slot] + e0;
+        float *mk = L.msg + (L.actm[slot] & 0x7fffffff) + e0;
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             if (REG || u < rw) {
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             if (on) {
                 const int a = __popcll(amask & lt);
                 L.act[a] = lane;
-                L.actm[a] = lane * L.SE;
+                L.actm[a] = (lane * L.SE) | (it == 0 ? (int)0x80000000u : 0);  // sign bit: fresh shot
                 L.actl[a] = lane * L.SN;
             }
             if (lane == 0) {
