@@ -29,7 +29,7 @@ struct BpLds {
     int C;           // shots per queue chunk
     float *msg, *Lv, *lam;
     uint32_t *synw, *parw;
-    int *sshot, *siter, *act, *actm, *actl, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
+    int *act, *actm, *actl, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
     uint16_t *rp, *ci, *cp, *ce, *ri;
     uint8_t *stg;    // 2 chunk buffers of C syndromes (raw bytes)
 };
@@ -37,7 +37,7 @@ struct BpLds {
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 __host__ __device__ inline int odd_stride(int x) { return x | 1; }
 
-constexpr int kSlotArrays = 12;  // int arrays of S entries in the slot-state block
+constexpr int kSlotArrays = 9;   // int arrays of S entries in the slot-state block
 constexpr int kCtl = 16;         // control words
 
 __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S) {
@@ -53,10 +53,10 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     L.synw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
     L.parw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
     int *ip = (int *)(base + off);
-    L.sshot = ip; L.siter = ip + S; L.act = ip + 2 * S; L.actm = ip + 3 * S; L.actl = ip + 4 * S;
-    L.newk = ip + 5 * S; L.newq = ip + 6 * S; L.rk = ip + 7 * S; L.rshot = ip + 8 * S; L.rit = ip + 9 * S;
-    L.rconv = ip + 10 * S; L.ctl = ip + 11 * S;
-    off += sizeof(int) * ((size_t)(kSlotArrays - 1) * S + kCtl);
+    L.act = ip; L.actm = ip + S; L.actl = ip + 2 * S; L.newk = ip + 3 * S; L.newq = ip + 4 * S;
+    L.rk = ip + 5 * S; L.rshot = ip + 6 * S; L.rit = ip + 7 * S; L.rconv = ip + 8 * S;
+    L.ctl = ip + kSlotArrays * S;
+    off += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
     L.rp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (m + 1);
     L.ci = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
     L.cp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (n + 1);
@@ -178,10 +178,10 @@ struct CheckItem {
     }
 };
 
-// Control words (L.ctl): [0] retired, [1] fresh, [2] active this iteration; [3] current
-// staging buffer, [4] cursor into it; [5] request pending; [6] load scheduled (base, -1 none),
-// [7] its count, [8] its buffer; [9] queue exhausted; [10 + 2b] base of staging buffer b
-// (-1 free, -2 drained this iteration, free from the next), [11 + 2b] its shot count.
+// Control words (L.ctl), written by slot management for every wavefront: [0] retired, [1] fresh,
+// [2] active this iteration; [5] request pending; [6] load scheduled (base, -1 none), [7] its
+// count, [8] its buffer.  Before the loop: [9] queue exhausted, [10] / [11] base (-1: none) and
+// count of the first chunk.
 template <int MAXRW, int MAXCW, bool REG>
 __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -197,21 +197,14 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
     for (int x = t; x < E; x += NT) L.ce[x] = (uint16_t)args.g.col_edge[x];
     for (int x = t; x < E; x += NT) L.ri[x] = (uint16_t)args.g.row_idx[x];
     for (int x = t; x < n; x += NT) L.lam[x] = args.lam[x];
-    for (int k = t; k < S; k += NT) { L.sshot[k] = -1; L.siter[k] = 0; }
     for (int x = t; x < S * L.PW; x += NT) { L.parw[x] = 0u; L.synw[x] = 0u; }
     // first chunk: fetched synchronously into staging buffer 0
     if (t == 0) {
         const int b0 = atomicAdd(args.next_shot, C);
         const int c0 = max(0, min(C, args.B - b0));
-        L.ctl[3] = 0;
-        L.ctl[4] = 0;
-        L.ctl[5] = 0;
-        L.ctl[6] = -1;
         L.ctl[9] = b0 + C >= args.B;
         L.ctl[10] = c0 > 0 ? b0 : -1;
         L.ctl[11] = c0;
-        L.ctl[12] = -1;
-        L.ctl[13] = 0;
     }
     __syncthreads();
     if (L.ctl[10] >= 0) {
@@ -224,7 +217,15 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
     const int T = args.max_iter;
     const int PW = L.PW;
     const uint64_t lt = (1ull << lane) - 1ull;
-    int req = 0;  // wavefront 0, lane 0: result of the queue request issued one iteration earlier
+    // Queue state, held in wavefront 0's registers (uniform across its lanes; no other wavefront
+    // reads it): staging buffer k holds shots [qb_k, qb_k + qc_k) (qb_k = -1: free, -2: drained
+    // this iteration, still readable); cur / cursor: next staged shot; pending: a chunk request
+    // issued one iteration ago (its base in req); exhausted: no shots left to request.  A slot's
+    // shot and iteration count live in the lane of wavefront 0 that manages the slot.
+    int qb0 = L.ctl[10], qc0 = L.ctl[11], qb1 = -1, qc1 = 0;
+    int q_cur = 0, q_cursor = 0, q_pending = 0, q_exh = L.ctl[9];
+    int req_v = 0;  // lane 0: base returned by the request in flight (read once it has landed)
+    int my_shot = -1, my_it = 0;
 
     for (;;) {
         // ---- slot management (wavefront 0, one lane per slot): test convergence (parity of the
@@ -232,8 +233,8 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
         // free slots the next staged shots, list the active slots, keep the queue pipeline full.
         if (wave == 0) {
             const bool valid = lane < S;
-            int shot = valid ? L.sshot[lane] : -1;
-            int it = valid ? L.siter[lane] : 0;
+            int shot = valid ? my_shot : -1;
+            int it = valid ? my_it : 0;
             const bool active = shot >= 0;
             bool sat = active;
             if (active) {
@@ -254,9 +255,9 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
                 L.rconv[p] = conv ? 1 : 0;
             }
             // staged shots: the rest of the current buffer, then the other buffer if loaded
-            const int cur = L.ctl[3], cursor = L.ctl[4];
-            const int cbase = L.ctl[10 + 2 * cur], ccount = L.ctl[11 + 2 * cur];
-            const int obase = L.ctl[10 + 2 * (1 - cur)], ocount = L.ctl[11 + 2 * (1 - cur)];
+            const int cur = q_cur, cursor = q_cursor;
+            const int cbase = cur ? qb1 : qb0, ccount = cur ? qc1 : qc0;
+            const int obase = cur ? qb0 : qb1, ocount = cur ? qc0 : qc1;
             const int avail0 = cbase >= 0 ? ccount - cursor : 0;
             const int avail1 = obase >= 0 ? ocount : 0;
             const uint64_t nmask = __ballot(need);
@@ -278,7 +279,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             } else if (active) {
                 it = it + 1;
             }
-            if (valid) { L.sshot[lane] = shot; L.siter[lane] = it; }
+            if (valid) { my_shot = shot; my_it = it; }
             const uint64_t fmask = __ballot(fresh);
             const int nfresh = __popcll(fmask);
             if (fresh) L.newk[r] = lane;  // fresh lanes are exactly the first nfresh needing ones
@@ -290,67 +291,70 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
                 L.actm[a] = (lane * L.SE) | (it == 0 ? (int)0x80000000u : 0);  // sign bit: fresh shot
                 L.actl[a] = lane * L.SN;
             }
+            // buffers drained last iteration are free now
+            if (qb0 == -2) qb0 = -1;
+            if (qb1 == -2) qb1 = -1;
+            auto set_buf = [&](int k, int base, int cnt) {
+                if (k) { qb1 = base; qc1 = cnt; } else { qb0 = base; qc0 = cnt; }
+            };
+            // advance the cursor; a buffer drained now stays readable for this iteration
+            int ncur = cur, ncursor = cursor;
+            if (nfresh < avail0) {
+                ncursor = cursor + nfresh;
+            } else if (cbase >= 0) {
+                set_buf(cur, -2, 0);
+                if (obase >= 0) {
+                    ncur = 1 - cur;
+                    ncursor = nfresh - avail0;
+                    if (ncursor >= ocount) {
+                        set_buf(ncur, -2, 0);
+                        ncursor = 0;
+                    }
+                } else {
+                    ncursor = 0;
+                }
+            } else if (obase >= 0) {
+                // the current buffer holds nothing (drained or free): every fresh shot came
+                // from the other buffer, which becomes the current one
+                ncur = 1 - cur;
+                ncursor = nfresh;
+                if (ncursor >= ocount) {
+                    set_buf(ncur, -2, 0);
+                    ncursor = 0;
+                }
+            }
+            q_cur = ncur;
+            q_cursor = ncursor;
+            // a request issued one iteration ago has landed: stage that chunk now
+            int ldb = -1, ldc = 0, ldbuf = 0;
+            if (q_pending) {
+                q_pending = 0;
+                const int req = __builtin_amdgcn_readfirstlane(req_v);
+                const int cnt = max(0, min(C, args.B - req));
+                if (req + C >= args.B) q_exh = 1;
+                if (cnt > 0) {
+                    // a free buffer exists: requests are only issued when one is free
+                    const int dst = (ncur ? qb1 : qb0) == -1 ? ncur : 1 - ncur;
+                    set_buf(dst, req, cnt);
+                    if (dst == ncur) q_cursor = 0;
+                    ldb = req;
+                    ldc = cnt;
+                    ldbuf = dst;
+                }
+            }
+            // keep one request in flight while a buffer is free and shots remain
+            if (!q_exh && (qb0 == -1 || qb1 == -1)) {
+                if (lane == 0) req_v = atomicAdd(args.next_shot, C);
+                q_pending = 1;
+            }
             if (lane == 0) {
                 L.ctl[0] = (int)__popcll(rmask);
                 L.ctl[1] = nfresh;
                 L.ctl[2] = (int)__popcll(amask);
-                // buffers drained last iteration are free now
-                for (int bb = 0; bb < 2; bb++)
-                    if (L.ctl[10 + 2 * bb] == -2) L.ctl[10 + 2 * bb] = -1;
-                // advance the cursor; a buffer drained now stays readable for this iteration
-                int ncur = cur, ncursor = cursor;
-                if (nfresh < avail0) {
-                    ncursor = cursor + nfresh;
-                } else if (cbase >= 0) {
-                    L.ctl[10 + 2 * cur] = -2;
-                    L.ctl[11 + 2 * cur] = 0;
-                    if (obase >= 0) {
-                        ncur = 1 - cur;
-                        ncursor = nfresh - avail0;
-                        if (ncursor >= ocount) {
-                            L.ctl[10 + 2 * ncur] = -2;
-                            L.ctl[11 + 2 * ncur] = 0;
-                            ncursor = 0;
-                        }
-                    } else {
-                        ncursor = 0;
-                    }
-                } else if (obase >= 0) {
-                    // the current buffer holds nothing (drained or free): every fresh shot came
-                    // from the other buffer, which becomes the current one
-                    ncur = 1 - cur;
-                    ncursor = nfresh;
-                    if (ncursor >= ocount) {
-                        L.ctl[10 + 2 * ncur] = -2;
-                        L.ctl[11 + 2 * ncur] = 0;
-                        ncursor = 0;
-                    }
-                }
-                L.ctl[3] = ncur;
-                L.ctl[4] = ncursor;
-                // a request issued one iteration ago has landed: stage that chunk now
-                L.ctl[6] = -1;
-                if (L.ctl[5]) {
-                    L.ctl[5] = 0;
-                    const int cnt = max(0, min(C, args.B - req));
-                    if (req + C >= args.B) L.ctl[9] = 1;
-                    if (cnt > 0) {
-                        // a free buffer exists: requests are only issued when one is free
-                        const int dst = L.ctl[10 + 2 * ncur] == -1 ? ncur : 1 - ncur;
-                        L.ctl[10 + 2 * dst] = req;
-                        L.ctl[11 + 2 * dst] = cnt;
-                        if (dst == ncur) L.ctl[4] = 0;
-                        L.ctl[6] = req;
-                        L.ctl[7] = cnt;
-                        L.ctl[8] = dst;
-                    }
-                }
-                // keep one request in flight while a buffer is free and shots remain
-                const bool free_buf = L.ctl[10] == -1 || L.ctl[12] == -1;
-                if (!L.ctl[9] && !L.ctl[5] && free_buf) {
-                    req = atomicAdd(args.next_shot, C);
-                    L.ctl[5] = 1;
-                }
+                L.ctl[5] = q_pending;
+                L.ctl[6] = ldb;
+                L.ctl[7] = ldc;
+                L.ctl[8] = ldbuf;
             }
         }
         __syncthreads();
@@ -589,7 +593,7 @@ size_t bp_lds_bytes(const DevGraph &g, int S) {
     size_t b = 0;
     b += sizeof(float) * ((size_t)odd_stride(g.nnz) * S + (size_t)odd_stride(g.n) * S + g.n);
     b += sizeof(uint32_t) * 2 * PW * S;
-    b += sizeof(int) * ((size_t)(kSlotArrays - 1) * S + kCtl);
+    b += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
     b += sizeof(uint16_t) * ((size_t)g.m + 1 + g.nnz + g.n + 1 + 2 * (size_t)g.nnz);
     b += (size_t)2 * S * g.m;  // two staging buffers of S syndromes
     return align16(b);
