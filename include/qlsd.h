@@ -59,6 +59,7 @@ typedef struct {
 
 #define QLSD_FLAG_NO_EARLY_EXIT 1u /* run all max_iter BP iterations for every shot */
 #define QLSD_FLAG_STAGE_TIMING 2u  /* record HIP events around each kernel of qlsd_decode */
+#define QLSD_FLAG_SEPARATE_LSD 4u  /* qlsd_decode: BP and LSD as two kernels, never overlapped */
 
 /* Per-shot status bits (qlsd_shot_info.status). */
 #define QLSD_ST_BP_CONVERGED 1u /* BP's hard decision satisfies s; no LSD was needed   */
@@ -88,7 +89,12 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
                                 int32_t max_batch, qlsd_decoder *out);
 
 /* BP then LSD (Sec. 2.3): syndromes device u8[B*m] -> corrections device u8[B*n];
- * info device qlsd_shot_info[B] or NULL.  0 <= B <= max_batch. */
+ * info device qlsd_shot_info[B] or NULL.  0 <= B <= max_batch.
+ * With slot BP and no refinement net (and without QLSD_FLAG_SEPARATE_LSD) BP and LSD share
+ * one kernel: a workgroup whose BP shots have drained decodes, with LSD, the shots other
+ * workgroups' BP left unsolved; a stand-alone LSD launch then finishes any shot not yet
+ * taken.  Outputs are identical either way (every shot's LSD is the same function of its
+ * syndrome and BP posterior). */
 qlsd_status qlsd_decode(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
                         qlsd_shot_info *info, void *stream);
 
@@ -103,7 +109,8 @@ qlsd_status qlsd_lsd(qlsd_decoder dec, const uint8_t *syndromes, const float *ll
                      uint8_t *corrections, qlsd_shot_info *info, void *stream);
 
 /* Device time (ms) of the BP kernel and of the LSD kernel in the decoder's last
- * qlsd_decode call, from HIP events recorded on that call's stream around each kernel.
+ * qlsd_decode call, from HIP events recorded on that call's stream around each kernel
+ * (BP and LSD in one kernel: that kernel, then the stand-alone LSD launch after it).
  * Needs QLSD_FLAG_STAGE_TIMING in the decoder's params (QLSD_E_INVALID otherwise);
  * waits for those events.  Either output pointer (host float) may be NULL. */
 qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms);

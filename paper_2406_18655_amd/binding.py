@@ -19,6 +19,7 @@ QLSD_OK = 0
 ST_BP_CONVERGED, ST_LSD_RUN, ST_UNSAT, ST_BAD_LLR, ST_OVERFLOW = 1, 2, 4, 8, 16
 FLAG_NO_EARLY_EXIT = 1
 FLAG_STAGE_TIMING = 2
+FLAG_SEPARATE_LSD = 4
 
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",

@@ -61,7 +61,8 @@ struct qlsd_decoder_s {
     int max_batch;
     float *d_lam;
     int64_t *d_omega;
-    int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter
+    int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter (one-kernel path:
+                         // tickets), [3] BP workgroups done, [4] work counter of the LSD launch after it
     uint8_t *d_flag;     // max_batch: shot goes from BP to LSD
     int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
@@ -263,6 +264,7 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     hipError_t e1 = dev_copy(&d->d_lam, lam.data(), lam.size());
     if (e1 == hipSuccess) e1 = dev_copy(&d->d_omega, omega.data(), omega.size());
     hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * 8);
+    if (e2 == hipSuccess) e2 = hipMemset(d->d_ctl, 0, sizeof(int) * 8);
     hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
     if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
     hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
@@ -301,6 +303,18 @@ static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
     a.S = d->bp_slots;
     a.next_shot = d->d_ctl + 0;
     return a;
+}
+
+// Wavefronts per BP workgroup that can run LSD in the BP kernel's LDS block (past the graph
+// tables); 0: BP and LSD run as separate kernels.  Only for LSD with up to 128 local rows (the
+// one-kernel form then needs at most 128 VGPRs, i.e. 4 workgroups per CU, the BP default).
+constexpr bool kOneKernel = false;  // BP + LSD in one kernel: off
+
+static int fuse_waves(qlsd_decoder d) {
+    if (!kOneKernel || d->bp_graph || d->net || (d->params.flags & QLSD_FLAG_SEPARATE_LSD)) return 0;
+    if (d->lsd_W > 2 || d->params.lsd_order > 0 || !d->lsd_keys_in_lds || d->bp_grid > 4 * d->num_cus) return 0;
+    const size_t avail = bp_lds_bytes(d->code->g, d->bp_slots) - bp_tables_bytes(d->code->g);
+    return (int)std::min<size_t>(4, avail / (size_t)d->lsd_wave_bytes);
 }
 
 static int bp_grid(qlsd_decoder d, int B) {
@@ -343,6 +357,38 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     qlsd_status st = check_call(d, syndromes, B, corrections);
     if (st != QLSD_OK || B == 0) return st;
     hipStream_t s = (hipStream_t)stream;
+    const int fw = fuse_waves(d);
+    if (fw > 0) {
+        HIP_OK(launch_fill(d->d_list, B, -1, s));
+        HIP_OK(launch_zero(d->d_ctl, 8, s));
+        BpArgs a = bp_args(d, syndromes, B);
+        a.corr = corrections;
+        a.llr_lsd = d->d_llr;
+        a.info = info;
+        FuseArgs f;
+        memset(&f, 0, sizeof(f));
+        f.lsd = lsd_args(d, syndromes, d->d_llr, corrections, info);
+        f.lsd.list = d->d_list;
+        f.lsd.list_count = d->d_ctl + 1;
+        f.lsd.bp_iters = d->params.max_iter;
+        f.lsd.coherent_llr = 1;
+        f.list_w = d->d_list;
+        f.tail = d->d_ctl + 1;
+        f.bp_done = d->d_ctl + 3;
+        f.lsd_waves = fw;
+        f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
+        if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
+        HIP_OK(launch_bp_fused(a, f, d->lsd_W, bp_grid(d, B), s));
+        if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
+        // every published entry not marked done (normally none), on a fresh work counter
+        LsdArgs rest = f.lsd;
+        rest.next_item = d->d_ctl + 4;
+        rest.skip_done = 1;
+        rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
+        HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
+        if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
+        return QLSD_OK;
+    }
     HIP_OK(launch_zero(d->d_ctl, 8, s));
     BpArgs a = bp_args(d, syndromes, B);
     if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
@@ -357,7 +403,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
     l.list_count = d->d_ctl + 1;
-    l.bp_ran = 1;
+    l.bp_iters = d->params.max_iter;
     HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
     return QLSD_OK;
@@ -468,7 +514,7 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
             LsdArgs l = lsd_args(d, syndromes, d->d_llr, corr, nullptr);
             l.list = d->d_list;
             l.list_count = d->d_ctl + 1;
-            l.bp_ran = 1;
+            l.bp_iters = d->params.max_iter;
             return launch_lsd(l, d->lsd_W, grid, s);
         };
         const float ms = timeit(lsd_run);

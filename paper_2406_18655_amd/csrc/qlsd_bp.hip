@@ -13,7 +13,11 @@
 // immediately refilled from a global queue, so early-exiting shots never leave lanes idle; the
 // number of work items shrinks only once the queue is empty.  HBM traffic is only the syndrome
 // in, the correction out, and the posterior LLRs of shots that go on to LSD.
+#include <algorithm>
+#include <cstring>
+
 #include "qlsd_internal.h"
+#include "qlsd_lsd_dev.h"
 
 namespace qlsd {
 
@@ -36,6 +40,9 @@ struct BpLds {
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 __host__ __device__ inline int odd_stride(int x) { return x | 1; }
+__host__ __device__ inline size_t tables_bytes(int m, int n, int E) {
+    return align16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + 2 * (size_t)E));
+}
 
 constexpr int kSlotArrays = 9;   // int arrays of S entries in the slot-state block
 constexpr int kCtl = 16;         // control words
@@ -46,7 +53,14 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     L.SN = odd_stride(n);
     L.PW = (m + 31) / 32;
     L.C = S;
+    // graph tables first: they stay valid for LSD once the slots are retired (fused kernel)
     size_t off = 0;
+    L.rp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (m + 1);
+    L.ci = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
+    L.cp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (n + 1);
+    L.ce = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
+    L.ri = (uint16_t *)(base + off);
+    off = tables_bytes(m, n, E);
     L.msg = (float *)(base + off); off += sizeof(float) * (size_t)L.SE * S;
     L.Lv = (float *)(base + off); off += sizeof(float) * (size_t)L.SN * S;
     L.lam = (float *)(base + off); off += sizeof(float) * n;
@@ -57,11 +71,6 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     L.rk = ip + 5 * S; L.rshot = ip + 6 * S; L.rit = ip + 7 * S; L.rconv = ip + 8 * S;
     L.ctl = ip + kSlotArrays * S;
     off += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
-    L.rp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (m + 1);
-    L.ci = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
-    L.cp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (n + 1);
-    L.ce = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
-    L.ri = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
     L.stg = (uint8_t *)(base + off);
     return L;
 }
@@ -179,11 +188,73 @@ struct CheckItem {
 };
 
 // Control words (L.ctl), written by slot management for every wavefront: [0] retired, [1] fresh,
-// [2] active this iteration; [5] request pending; [6] load scheduled (base, -1 none), [7] its
+// [2] active this iteration; [3] retired without converging; [5] request pending; [6] load scheduled (base, -1 none), [7] its
 // count, [8] its buffer.  Before the loop: [9] queue exhausted, [10] / [11] base (-1: none) and
 // count of the first chunk.
-template <int MAXRW, int MAXCW, bool REG>
-__global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
+// Hand-over between workgroups in the fused kernel.  The L2 caches of different XCDs are not
+// coherent with each other, so every word that crosses workgroups during the kernel -- the LLR
+// row of an unsolved shot, its list entry, the counters -- is written and read only with
+// device-scope read-modify-write atomics, which are performed at the device's point of
+// coherence: a poll never sees a line cached by its own XCD, and no write leaves a dirty line
+// whose later write-back could restore stale neighbouring words.  A publisher's row atomics
+// complete before the barrier that precedes the list entries naming them; a consumer's row
+// reads are issued after, and depend on, the entry it read.  The correction row and info record
+// of an unsolved shot are written only by the LSD side.
+// A compare-and-swap whose new value equals its compare value never changes memory and always
+// returns the word from the point of coherence (an idempotent add would be turned into a load).
+__device__ __forceinline__ int poll_agent(int *p) { return atomicCAS(p, 0, 0); }
+
+// Longest wait of a fused LSD wavefront for its ticket's entry (wall-clock ticks of 10 ns)
+// before it leaves the entry to the stand-alone LSD launch.  It only matters when not every
+// workgroup of the grid is resident at once; normally entries arrive within microseconds.
+constexpr unsigned long long kFuseIdleTicks = 20000;  // 200 us
+
+// Everything a fused LSD wavefront does between two shots, as one call that the whole wavefront
+// makes with uniform control flow: mark entry done_h decoded (done_h >= 0), take a ticket h,
+// wait for entry h.  Returns {shot, h}, uniform across the wavefront; shot = -1 if entry h
+// will never be published (every BP workgroup done with fewer entries, or h >= B) or the wait
+// ran out.  Polls back off to one per ~7 us.  The lane-0 atomics live here, not in the caller's
+// loop, because the compiler does not guarantee that a wavefront reconverges after a lane-0
+// region inside a loop: it may split lane 0 off at the loop latch and run the loop body (a
+// whole LSD shot, which needs all 64 lanes) with the other lanes only.  A call returns with the
+// caller's execution mask.
+__device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, int *tail, int nwg, int B,
+                                       int done_h, int done_shot) {
+    const int lane = threadIdx.x & 63;
+    int hv = 0;
+    if (lane == 0) {
+        if (done_h >= 0) atomicExch(list + done_h, ~done_shot);  // the stand-alone launch skips it
+        hv = atomicAdd(next_item, 1);
+    }
+    const int h = __builtin_amdgcn_readfirstlane(hv);
+    if (h >= B) return make_int2(-1, h);  // at most B entries
+    const unsigned long long t0 = wall_clock64();
+    int nap = 1;
+    for (int poll = 0;; poll++) {
+        int v = 0, done = 0, tl = 0;
+        const bool check = (poll & 3) == 3;
+        if (lane == 0) {
+            v = poll_agent(list + h);
+            if (check) {
+                done = poll_agent(bp_done);
+                tl = poll_agent(tail);
+            }
+        }
+        const int shot = __builtin_amdgcn_readfirstlane(v);
+        if (shot >= 0) return make_int2(shot, h);
+        if (check) {
+            if (__builtin_amdgcn_readfirstlane(done) >= nwg && __builtin_amdgcn_readfirstlane(tl) <= h)
+                return make_int2(-1, h);
+            if (wall_clock64() - t0 > kFuseIdleTicks) return make_int2(-1, h);
+        }
+        for (int k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(64);  // 4096 cycles, ~1.7 us each
+        nap = min(nap * 2, 4);
+    }
+}
+
+// LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots.
+template <int MAXRW, int MAXCW, bool REG, int LSDW>
+__global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArgs f) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = threadIdx.x, NT = blockDim.x;
     const int lane = t & 63, wave = t >> 6;
@@ -247,6 +318,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             const bool retire = active && ((args.early_exit && conv) || it >= T);
             const bool need = valid && (!active || retire);
             const uint64_t rmask = __ballot(retire);
+            const uint64_t fmask_unsolved = __ballot(retire && !conv);
             if (retire) {
                 const int p = __popcll(rmask & lt);
                 L.rk[p] = lane;
@@ -349,6 +421,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             }
             if (lane == 0) {
                 L.ctl[0] = (int)__popcll(rmask);
+                L.ctl[3] = (int)__popcll(fmask_unsolved);
                 L.ctl[1] = nfresh;
                 L.ctl[2] = (int)__popcll(amask);
                 L.ctl[5] = q_pending;
@@ -358,7 +431,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             }
         }
         __syncthreads();
-        const int nret = L.ctl[0], nfresh = L.ctl[1], A = L.ctl[2];
+        const int nret = L.ctl[0], nfresh = L.ctl[1], A = L.ctl[2], nunsolved = L.ctl[3];
         const int ldb = L.ctl[6], ldc = L.ctl[7], ldbuf = L.ctl[8];
         const bool pending = L.ctl[5] != 0;
 
@@ -373,14 +446,18 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
             const int k = L.rk[r], shot = L.rshot[r];
             const bool conv = L.rconv[r] != 0;
             const size_t row = (size_t)shot * n;
+            const bool write_corr = args.corr && (LSDW == 0 || conv);  // fused: LSD writes the rest
             for (int j = t; j < n; j += NT) {
                 const float Lj = L.Lv[k * L.SN + j];
-                if (args.corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
+                if (write_corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
                 if (args.llr_out) args.llr_out[row + j] = Lj;
-                if (!conv && args.llr_lsd) args.llr_lsd[row + j] = Lj;
+                if (!conv && args.llr_lsd) {
+                    if (LSDW > 0) atomicExch((int *)args.llr_lsd + row + j, __float_as_int(Lj));
+                    else args.llr_lsd[row + j] = Lj;
+                }
             }
             if (t == 0) {
-                if (args.info) {
+                if (args.info && (LSDW == 0 || conv)) {
                     qlsd_shot_info inf;
                     inf.status = conv ? QLSD_ST_BP_CONVERGED : 0;
                     inf.reserved = 0;
@@ -393,9 +470,23 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
                 if (args.lsd_flag) args.lsd_flag[shot] = conv ? 0 : 1;
             }
         }
-        for (int f = wave; f < nfresh; f += NT / 64) {
-            const int k = L.newk[f];
-            const uint8_t *sq = L.stg + (size_t)L.newq[f] * m;
+        if constexpr (LSDW > 0) {
+            // publish the unsolved shots: their LLR rows and info records reach device scope
+            // before the list entries that name them
+            if (nunsolved > 0) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_s_waitcnt(0);  // this thread's row atomics have completed
+                __syncthreads();
+                if (t == 0) {
+                    int pos = atomicAdd(f.tail, nunsolved);
+                    for (int r = 0; r < nret; r++)
+                        if (!L.rconv[r]) atomicExch(f.list_w + pos++, L.rshot[r]);
+                }
+            }
+        }
+        for (int fi = wave; fi < nfresh; fi += NT / 64) {
+            const int k = L.newk[fi];
+            const uint8_t *sq = L.stg + (size_t)L.newq[fi] * m;
             for (int i0 = 0; i0 < m; i0 += 64) {
                 const int i = i0 + lane;
                 const uint64_t bits = __ballot(i < m && (sq[i] & 1));
@@ -439,8 +530,34 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args) {
         }
         __syncthreads();
     }
-}
 
+    if constexpr (LSDW > 0) {
+        // ---- LSD on published shots: the slot arrays are dead, the graph tables stay
+        __syncthreads();
+        if (t == 0) atomicAdd(f.bp_done, 1);  // after this workgroup's last reservation
+        if (wave >= f.lsd_waves) return;
+        constexpr int K = 64 * LSDW;
+        unsigned char *lbase = smem + tables_bytes(m, n, E) + (size_t)wave * f.lsd.wave_bytes;
+        const LsdLds S2 = carve_lsd(lbase, m, n, K, f.lsd.keys_in_lds != 0);
+        GView<true> gv;
+        gv.rp = L.rp; gv.ci = L.ci; gv.cp = L.cp; gv.ri = L.ri;
+        gv.max_cw = args.g.max_cw;
+        const int nwg = (int)gridDim.x;
+        // no lane-dependent branch in this loop: see fuse_step
+        int done_h = -1, done_shot = 0;
+        for (;;) {
+            const int2 r = fuse_step(f.list_w, f.lsd.next_item, f.bp_done, f.tail, nwg, args.B, done_h, done_shot);
+            const int shot = __builtin_amdgcn_readfirstlane(r.x);
+            const int h = __builtin_amdgcn_readfirstlane(r.y);
+            if (shot < 0) break;  // no entry h, or it is left to the stand-alone launch (the call
+                                  // that returned it has marked the previous shot done)
+            decode_shot<LSDW>(f.lsd, S2, gv, shot, lane);
+            wave_sync();
+            done_h = h;
+            done_shot = shot;
+        }
+    }
+}
 
 // ------------------------------------------------------------------------------------------
 // Large graphs (e.g. a 936 x 8800 detector error model): one workgroup per shot.  The shot's
@@ -588,23 +705,25 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph_kernel(BpArgs args) 
 
 }  // namespace
 
+size_t bp_tables_bytes(const DevGraph &g) { return tables_bytes(g.m, g.n, g.nnz); }
+
 size_t bp_lds_bytes(const DevGraph &g, int S) {
+    // carve_bp's order: graph tables, messages, posteriors, priors, bit vectors, slot state, staging
     const size_t PW = ((size_t)g.m + 31) / 32;
-    size_t b = 0;
+    size_t b = tables_bytes(g.m, g.n, g.nnz);
     b += sizeof(float) * ((size_t)odd_stride(g.nnz) * S + (size_t)odd_stride(g.n) * S + g.n);
     b += sizeof(uint32_t) * 2 * PW * S;
     b += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
-    b += sizeof(uint16_t) * ((size_t)g.m + 1 + g.nnz + g.n + 1 + 2 * (size_t)g.nnz);
     b += (size_t)2 * S * g.m;  // two staging buffers of S syndromes
     return align16(b);
 }
 
-template <int RW, int CW, bool REG>
-static hipError_t launch_bp_t(const BpArgs &a, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW, REG>,
+template <int RW, int CW, bool REG, int LSDW>
+static hipError_t launch_bp_t(const BpArgs &a, const FuseArgs &f, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW, REG, LSDW>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG>), dim3(grid), dim3(kBpThreads), lds, st, a);
+    hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG, LSDW>), dim3(grid), dim3(kBpThreads), lds, st, a, f);
     return hipGetLastError();
 }
 
@@ -815,29 +934,47 @@ hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
     return launch_bp_graph_t<kMaxRowWeight, kMaxColWeight>(a, grid, lds, st);
 }
 
-hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
-    const size_t lds = bp_lds_bytes(a.g, a.S);
+template <int LSDW>
+static hipError_t launch_bp_w(const BpArgs &a, const FuseArgs &f, int grid, size_t lds, hipStream_t st) {
     const DevGraph &g = a.g;
     const bool regular = g.min_rw == g.max_rw && g.min_cw == g.max_cw;
-    if (regular && g.max_rw == 6 && g.max_cw == 3) return launch_bp_t<6, 3, true>(a, grid, lds, st);
-    if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false>(a, grid, lds, st);
-    if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false>(a, grid, lds, st);
-    return launch_bp_t<kMaxRowWeight, kMaxColWeight, false>(a, grid, lds, st);
+    if (regular && g.max_rw == 6 && g.max_cw == 3) return launch_bp_t<6, 3, true, LSDW>(a, f, grid, lds, st);
+    if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false, LSDW>(a, f, grid, lds, st);
+    if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false, LSDW>(a, f, grid, lds, st);
+    return launch_bp_t<kMaxRowWeight, kMaxColWeight, false, LSDW>(a, f, grid, lds, st);
+}
+
+hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
+    FuseArgs f;
+    memset(&f, 0, sizeof(f));
+    return launch_bp_w<0>(a, f, grid, bp_lds_bytes(a.g, a.S), st);
+}
+
+hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st) {
+    const size_t lds = std::max(bp_lds_bytes(a.g, a.S), (size_t)f.lsd_bytes);
+    switch (W) {
+        case 1: return launch_bp_w<1>(a, f, grid, lds, st);
+        case 2: return launch_bp_w<2>(a, f, grid, lds, st);
+        default: return hipErrorInvalidValue;  // W = 4 would double the registers of the BP part
+    }
 }
 
 namespace {
-__global__ void zero_kernel(int *p, int count) {
+__global__ void fill_kernel(int *p, int count, int value) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < count) p[i] = 0;
+    if (i < count) p[i] = value;
 }
 
 }  // namespace
 
 
 
-hipError_t launch_zero(int *p, int count, hipStream_t st) {
-    hipLaunchKernelGGL(zero_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, count);
+hipError_t launch_fill(int *p, int count, int value, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3((count + 255) / 256), dim3(256), 0, st, p, count, value);
     return hipGetLastError();
 }
+
+hipError_t launch_zero(int *p, int count, hipStream_t st) { return launch_fill(p, count, 0, st); }
 
 }  // namespace qlsd

@@ -48,12 +48,31 @@ struct LsdArgs {
     int *next_item;            // work counter (zeroed before launch)
     uint8_t *corr;             // B x n
     qlsd_shot_info *info;      // B (nullable)
-    int bp_ran;                // info: keep bp_iters written by BP
+    int bp_iters;              // info.bp_iters of every shot decoded: BP's budget when BP ran first
+                               // (a shot BP leaves unsolved ran all of it), 0 otherwise
     int keys_in_lds;
     int graph_in_lds;          // H staged as u16 CSR/CSC in LDS once per workgroup
     int mu;                    // LSD order (0 = LSD-0)
     const int64_t *omega;      // n: integer fault weights for the order-mu search (mu > 0)
     int wave_bytes;            // LDS bytes per wavefront
+    int coherent_llr;          // llr rows written during this kernel by other workgroups: read them
+                               // with device-scope atomics
+    int skip_done;             // list entries < 0 were decoded already (after the fused kernel)
+};
+
+// BP with LSD folded in (plain decode with slot BP): a workgroup whose slots have drained turns
+// its wavefronts to LSD on shots that BP workgroups have published as unsolved.  lsd.list is the
+// published list (every entry -1 before launch), lsd.list_count (tail) its reservation count and
+// lsd.next_item a ticket counter: a wavefront takes ticket h, waits for entry h, decodes it and
+// marks it done (~shot).  It leaves when entry h will never exist or after a bounded wait, so
+// the stand-alone LSD kernel launched afterwards (skip_done) decodes every entry not marked done.
+struct FuseArgs {
+    LsdArgs lsd;
+    int *list_w;               // writable alias of lsd.list
+    int *tail;                 // == lsd.list_count
+    int *bp_done;              // BP workgroups finished
+    int lsd_waves;             // wavefronts per workgroup that run LSD (LDS permitting)
+    int lsd_bytes;             // dynamic LDS the kernel needs (>= the BP carve)
 };
 
 // LDS carve sizes (bytes) shared by host (launch config) and device.
@@ -63,7 +82,10 @@ size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds);
 size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds);
 
 hipError_t launch_zero(int *p, int count, hipStream_t st);
+hipError_t launch_fill(int *p, int count, int value, hipStream_t st);
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);        // S slots per workgroup
+hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st);
+size_t bp_tables_bytes(const DevGraph &g);  // u16 copies of H at the start of the BP LDS block
 hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st);  // one workgroup per shot
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);

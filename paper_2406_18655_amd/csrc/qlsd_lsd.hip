@@ -22,666 +22,11 @@
 // solving are then per-lane AND/XOR/popcount plus a few ballots -- no cross-lane reductions.
 // Union-find over local rows lives in LDS (lock-free CAS hooking of the larger root under the
 // smaller one); candidate selection is a per-row scan plus an LDS 64-bit atomic min per root.
-#include <type_traits>
-
-#include "qlsd_internal.h"
+#include "qlsd_lsd_dev.h"
 
 namespace qlsd {
 
 namespace {
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
-    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t lo = __shfl_xor((int)(uint32_t)v, off, 64);
-        const uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), off, 64);
-        const uint64_t o = ((uint64_t)hi << 32) | lo;
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
-// Order-preserving map of a float32 LLR to uint32 (-0 treated as +0).
-__device__ __forceinline__ uint32_t ordered_key(float x) {
-    uint32_t u = __float_as_uint(x);
-    if (u == 0x80000000u) u = 0u;
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
-// Read-only view of H used by the LSD kernel: u16 copies in LDS (small codes) or the int32
-// arrays in global memory.
-template <bool InLds>
-struct GView {
-    using T = typename std::conditional<InLds, uint16_t, int32_t>::type;
-    const T *rp, *ci, *cp, *ri;
-    int max_cw;
-    __device__ __forceinline__ int row_ptr(int i) const { return rp[i]; }
-    __device__ __forceinline__ int col_idx(int e) const { return ci[e]; }
-    __device__ __forceinline__ int col_ptr(int j) const { return cp[j]; }
-    __device__ __forceinline__ int row_idx(int e) const { return ri[e]; }
-};
-
-constexpr int kFree = 0x7fffffff;
-constexpr int kMaxMu = 12;  // largest supported order mu (2^mu patterns per cluster)
-constexpr uint8_t kValid = 0, kInvalid = 1, kFrozen = 2;
-
-struct LsdLds {
-    uint32_t *keys;    // n (when keys_in_lds)
-    uint64_t *sel;     // K: per-root best candidate key
-    uint64_t *lkey;    // K: selection list keys
-    int32_t *lroot;    // K: selection list roots
-    int32_t *colAt;    // K: column that created the pivot at this local row
-    int32_t *croot;    // K: union-find parent over local rows
-    int32_t *rowOf;    // K: detector of each local row
-    int32_t *loc;      // m: local row of each detector, -1 if unclustered
-    int32_t *claimer;  // m: smallest root claiming an unclustered detector this round
-    uint32_t *incol;   // ceil(n/32): fault already in a cluster
-    uint8_t *state;    // K: kValid / kInvalid / kFrozen (meaningful at roots)
-    int32_t *ctl;      // 4: [0] local row count
-    int32_t *colNP;    // K: clustered columns that were dependent when added (LSD-mu)
-    int64_t *wq;       // K: integer weight of the column that created each pivot (LSD-mu)
-    uint64_t *zk;      // kMaxMu * W: solution change of each reprocessed column (LSD-mu)
-    int32_t *tsel;     // kMaxMu: reprocessed columns of the current cluster (LSD-mu)
-    int64_t *tw;       // kMaxMu: their weights
-    uint64_t *cand;    // K: cached smallest candidate key of each local row (kStale: recompute)
-};
-
-// A row's cached candidate stays exact while its column is not taken: the taken set only grows,
-// so the minimum over the row's remaining faults can change only when that column is taken.
-constexpr uint64_t kStale = ~0ull - 1ull;
-
-__host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
-
-__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, size_t *offs) {
-    size_t off = 0;
-    offs[0] = off; off += keys_in_lds ? align8(sizeof(uint32_t) * n) : 0;
-    offs[1] = off; off += sizeof(uint64_t) * K;
-    offs[2] = off; off += sizeof(uint64_t) * K;
-    offs[3] = off; off += sizeof(int32_t) * K;
-    offs[4] = off; off += sizeof(int32_t) * K;
-    offs[5] = off; off += sizeof(int32_t) * K;
-    offs[6] = off; off += sizeof(int32_t) * K;
-    offs[7] = off; off += sizeof(int32_t) * m;
-    offs[8] = off; off += sizeof(int32_t) * m;
-    offs[9] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
-    offs[10] = off; off += align8(K);
-    offs[11] = off; off += sizeof(int32_t) * 4;
-    offs[12] = off; off += sizeof(int32_t) * K;
-    offs[13] = off; off += sizeof(int64_t) * K;
-    offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);
-    offs[15] = off; off += sizeof(int32_t) * kMaxMu;
-    offs[16] = off; off += sizeof(int64_t) * kMaxMu;
-    offs[17] = off; off += sizeof(uint64_t) * K;
-    return align8(off);
-}
-
-__host__ __device__ inline size_t lsd_graph_bytes(int m, int n, int nnz) {
-    return align8(sizeof(uint16_t) * ((size_t)m + 1 + nnz + n + 1 + nnz));
-}
-
-__device__ __forceinline__ int find_root(volatile int32_t *par, int x) {
-    int p = par[x];
-    while (p != x) { x = p; p = par[x]; }
-    return x;
-}
-
-// Returns true iff it hooked one root under another (false: already in one set).
-__device__ bool unite(int32_t *par, int x, int y) {
-    volatile int32_t *vp = par;
-    for (;;) {
-        x = find_root(vp, x);
-        y = find_root(vp, y);
-        if (x == y) return false;
-        if (x < y) { const int tmp = x; x = y; y = tmp; }
-        // hook the larger root under the smaller one
-        if (atomicCAS(&par[x], x, y) == x) return true;
-    }
-}
-
-template <int W>
-struct Basis {
-    uint64_t Mrow[W][W];  // per lane row s: bits over pivot local rows (rows of the reduced pivot vectors)
-    uint64_t CT[W][W];    // per lane row s (if a pivot row): pivots whose combination uses its column
-    uint64_t piv[W];      // uniform: pivot local rows
-    uint64_t sp[W];       // uniform: reduced syndrome over local rows
-};
-
-template <int W>
-__device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t (&b)[W]) {
-    int c = 0;
-#pragma unroll
-    for (int w = 0; w < W; w++) c += __popcll(a[w] & b[w]);
-    return c & 1;
-}
-
-// Adds column g (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
-// it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
-template <int W, class G>
-__device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col, int lane) {
-    const int c0 = g.col_ptr(col), cw = g.col_ptr(col + 1) - c0;
-    // the column's support over local rows, as W wave-uniform masks: lane u looks up its entry,
-    // then the masks are assembled from the lanes' results
-    const int lr_mine = lane < cw ? S.loc[g.row_idx(c0 + lane)] : -1;
-    uint64_t cm[W];
-#pragma unroll
-    for (int s = 0; s < W; s++) cm[s] = 0;
-    for (int u = 0; u < cw; u++) {
-        const int lr = __builtin_amdgcn_readlane(lr_mine, u);
-        if (lr >= 0 && lr < 64 * W) {
-#pragma unroll
-            for (int s = 0; s < W; s++)
-                if ((lr >> 6) == s) cm[s] |= 1ull << (lr & 63);
-        }
-    }
-    uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
-#pragma unroll
-    for (int s = 0; s < W; s++) bf |= (uint32_t)((cm[s] >> lane) & 1ull) << s;
-    uint64_t a[W];
-#pragma unroll
-    for (int s = 0; s < W; s++) a[s] = cm[s] & B.piv[s];
-    uint32_t bpf = 0;
-#pragma unroll
-    for (int s = 0; s < W; s++) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_and<W>(B.Mrow[s], a)) << s;
-    uint64_t bp[W];
-    int rs = -1;
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        bp[s] = ballot((bpf >> s) & 1u);
-        if (rs < 0 && bp[s]) rs = s;
-    }
-    if (rs < 0) return false;
-    // rs is wave-uniform but not a compile-time index: select by unrolled compare so that the
-    // basis stays in registers (a runtime array index would put it in scratch memory)
-    uint64_t bprs = 0;
-#pragma unroll
-    for (int s = 0; s < W; s++)
-        if (s == rs) bprs = bp[s];
-    const int rl = __builtin_ctzll(bprs);
-    uint64_t R[W];
-#pragma unroll
-    for (int w = 0; w < W; w++) {
-        uint64_t v = 0;
-#pragma unroll
-        for (int s = 0; s < W; s++)
-            if (s == rs) v = readlane64(B.Mrow[s][w], rl);
-        R[w] = v;
-    }
-    // rows in the reduced column's support: eliminate the new pivot row from the old pivots
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        if ((bpf >> s) & 1u) {
-#pragma unroll
-            for (int w = 0; w < W; w++) B.Mrow[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
-        }
-    }
-    // combination tracking
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        const bool is_piv = (B.piv[s] >> lane) & 1ull;
-        if (is_piv && parity_and<W>(B.CT[s], a)) {
-#pragma unroll
-            for (int w = 0; w < W; w++) B.CT[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
-        }
-        if (s == rs && lane == rl) {
-#pragma unroll
-            for (int w = 0; w < W; w++) B.CT[s][w] = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
-        }
-    }
-    bool sp_hit = false;
-#pragma unroll
-    for (int s = 0; s < W; s++)
-        if (s == rs) {
-            B.piv[s] |= 1ull << rl;
-            sp_hit = (B.sp[s] >> rl) & 1ull;
-        }
-    if (lane == 0) S.colAt[rs * 64 + rl] = col;
-    if (sp_hit) {
-#pragma unroll
-        for (int s = 0; s < W; s++) B.sp[s] ^= bp[s];
-    }
-    return true;
-}
-
-__device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
-
-
-// Local exhaustive reprocessing of order w (Appendix D) for every cluster that is not frozen.
-// T = the cluster's dependent columns in ascending key, T_w its first w = min(mu, |T|).  Every
-// pattern t over T_w fixes x_T = t and the pivot part x_P = x0 + sum_{k in t} z_k, where z_k is
-// the pivot combination of column T_k (every T_k lies in the span of the pivots).  The cost is
-// the integer weight of the set columns; the strictly smallest cost wins, the smaller t on ties.
-// Patterns are spread over the lanes.
-template <int W, class G>
-__device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const Basis<W> &B,
-                               const uint64_t (&x0)[W], int nrows, int npc, const float *llr,
-                               uint8_t *corr, int lane) {
-    constexpr int K = 64 * W;
-    const int mu = A.mu < kMaxMu ? A.mu : kMaxMu;
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        const int r = s * 64 + lane;
-        if ((B.piv[s] >> lane) & 1ull) S.wq[r] = A.omega[S.colAt[r]];
-    }
-    uint64_t roots[W];
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        const int r = s * 64 + lane;
-        roots[s] = ballot(r < nrows && S.croot[r] == r && S.state[r] != kFrozen);
-    }
-    wave_sync();
-    const int nnp = npc < K ? npc : K;
-#pragma unroll
-    for (int s0 = 0; s0 < W; s0++) {
-        while (roots[s0]) {
-            const int c = s0 * 64 + __builtin_ctzll(roots[s0]);
-            roots[s0] &= roots[s0] - 1;
-            uint64_t inC[W];
-#pragma unroll
-            for (int s = 0; s < W; s++) {
-                const int r = s * 64 + lane;
-                inC[s] = ballot(r < nrows && S.croot[r] == c);
-            }
-            // T_w: the cluster's dependent columns of smallest key
-            uint32_t chosen = 0;  // bit u: entry lane + 64 u taken
-            int w = 0;
-            for (; w < mu; w++) {
-                uint64_t mine = ~0ull;
-                for (int u = 0; u * 64 + lane < nnp; u++) {
-                    if ((chosen >> u) & 1u) continue;
-                    const int col = S.colNP[u * 64 + lane];
-                    const int rr = S.loc[g.row_idx(g.col_ptr(col))];
-                    if (S.croot[rr] != c) continue;
-                    const uint32_t kj = A.keys_in_lds ? S.keys[col] : ordered_key(llr[col]);
-                    const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)col;
-                    mine = key < mine ? key : mine;
-                }
-                const uint64_t kmin = wave_min_u64(mine);
-                if (kmin == ~0ull) break;
-                const int col = (int)(uint32_t)kmin;
-                for (int u = 0; u * 64 + lane < nnp; u++)
-                    if (S.colNP[u * 64 + lane] == col) chosen |= 1u << u;
-                // z_w: pivot rows of this cluster whose combination reproduces column col
-                uint32_t bf = 0;
-                for (int e = g.col_ptr(col); e < g.col_ptr(col + 1); e++) {
-                    const int lr = S.loc[g.row_idx(e)];
-                    if (lr >= 0 && lr < K && (lr & 63) == lane) bf |= 1u << (lr >> 6);
-                }
-                uint64_t a[W];
-#pragma unroll
-                for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
-#pragma unroll
-                for (int s = 0; s < W; s++) {
-                    const uint64_t z = ballot(((B.piv[s] & inC[s]) >> lane) & 1ull && parity_and<W>(B.CT[s], a));
-                    if (lane == 0) S.zk[w * W + s] = z;
-                }
-                if (lane == 0) {
-                    S.tsel[w] = col;
-                    S.tw[w] = A.omega[col];
-                }
-            }
-            wave_sync();
-            // search the 2^w patterns
-            uint64_t xc[W];
-#pragma unroll
-            for (int s = 0; s < W; s++) xc[s] = x0[s] & inC[s];
-            const int npat = 1 << w;
-            uint64_t best = ~0ull;
-            for (int pt = lane; pt < npat; pt += 64) {
-                uint64_t x[W];
-                int64_t cost = 0;
-#pragma unroll
-                for (int s = 0; s < W; s++) x[s] = xc[s];
-                for (int k = 0; k < w; k++) {
-                    if ((pt >> k) & 1) {
-                        cost += S.tw[k];
-#pragma unroll
-                        for (int s = 0; s < W; s++) x[s] ^= S.zk[k * W + s];
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < W; s++) {
-                    uint64_t v = x[s];
-                    while (v) {
-                        cost += S.wq[s * 64 + __builtin_ctzll(v)];
-                        v &= v - 1;
-                    }
-                }
-                const uint64_t key = ((uint64_t)(cost + (1ll << 50)) << 12) | (uint64_t)pt;
-                best = key < best ? key : best;
-            }
-            const int tb = (int)(wave_min_u64(best) & 4095ull);
-            uint64_t x[W];
-#pragma unroll
-            for (int s = 0; s < W; s++) x[s] = xc[s];
-            for (int k = 0; k < w; k++) {
-                if ((tb >> k) & 1) {
-#pragma unroll
-                    for (int s = 0; s < W; s++) x[s] ^= S.zk[k * W + s];
-                    if (lane == 0) corr[S.tsel[k]] = 1;
-                }
-            }
-#pragma unroll
-            for (int s = 0; s < W; s++)
-                if ((x[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
-            wave_sync();
-        }
-    }
-}
-
-template <int W, class G>
-__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane) {
-    constexpr int K = 64 * W;
-    const int m = A.g.m, n = A.g.n;
-    const float *llr = A.llr + (size_t)shot * n;
-    const uint8_t *syn = A.syn + (size_t)shot * m;
-    uint8_t *corr = A.corr + (size_t)shot * n;
-
-    bool nan = false;
-    for (int j = lane; j < n; j += 64) {
-        const float v = llr[j];
-        nan |= (v != v);
-        if (A.keys_in_lds) S.keys[j] = ordered_key(v);
-    }
-    for (int w = lane; w < (n + 31) / 32; w += 64) S.incol[w] = 0u;
-    for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
-    if ((n & 15) == 0 && (((uintptr_t)corr) & 15) == 0) {
-        for (int j = lane; j < (n >> 4); j += 64) ((uint4 *)corr)[j] = make_uint4(0u, 0u, 0u, 0u);
-    } else {
-        for (int j = lane; j < n; j += 64) corr[j] = 0;
-    }
-    __threadfence_block();  // the zero stores complete before any later scatter to this row
-    wave_sync();
-
-    uint8_t status = QLSD_ST_LSD_RUN;
-    int rounds = 0;
-    auto finish = [&](uint8_t st, int ncl, int maxc) {
-        if (A.info && lane == 0) {
-            qlsd_shot_info *inf = A.info + shot;
-            inf->status = st;
-            if (!A.bp_ran) inf->bp_iters = 0;
-            inf->n_clusters = (int16_t)ncl;
-            inf->rounds = (int16_t)rounds;
-            inf->max_cluster_cols = maxc;
-        }
-    };
-    if (ballot(nan)) { finish(QLSD_ST_LSD_RUN | QLSD_ST_BAD_LLR, 0, 0); return; }
-    // capacity exceeded: the shot reports OVERFLOW with a zero correction
-    auto overflow = [&](uint8_t st) {
-        finish(st | QLSD_ST_OVERFLOW, 0, 0);
-        for (int j = lane; j < n; j += 64) corr[j] = 0;
-    };
-
-    // clusters: one per flipped detector, local rows in ascending detector order
-    int nrows = 0;
-    for (int i0 = 0; i0 < m; i0 += 64) {
-        const int i = i0 + lane;
-        const bool f = i < m && (syn[i] & 1);
-        const uint64_t bal = ballot(f);
-        if (f) {
-            const int idx = nrows + __popcll(bal & ((1ull << lane) - 1ull));
-            if (idx < K) {
-                S.loc[i] = idx;
-                S.rowOf[idx] = i;
-                S.croot[idx] = idx;
-                S.state[idx] = kInvalid;
-                S.cand[idx] = kStale;
-            }
-        }
-        nrows += __popcll(bal);
-    }
-    if (nrows == 0) { finish(QLSD_ST_LSD_RUN, 0, 0); return; }
-    if (nrows > K) { overflow(QLSD_ST_LSD_RUN); return; }
-    const int nseed = nrows;
-    if (lane == 0) S.ctl[0] = nrows;
-
-    Basis<W> B;
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-#pragma unroll
-        for (int w = 0; w < W; w++) { B.Mrow[s][w] = 0; B.CT[s][w] = 0; }
-        B.piv[s] = 0;
-        const int lo = s * 64;
-        B.sp[s] = nseed >= lo + 64 ? ~0ull : (nseed > lo ? ((1ull << (nseed - lo)) - 1ull) : 0ull);
-    }
-    wave_sync();
-
-    // LSD-0 rounds grow the invalid clusters until none is left; LSD-mu then runs mu more
-    // rounds in which every cluster that is not frozen grows (Appendix D).
-    bool grow_all = false;
-    int mu_left = 0;
-    int npc = 0;  // dependent columns recorded in colNP
-    for (;;) {
-        // (1) selection: per growing root, the candidate of smallest key (round-start state)
-#pragma unroll
-        for (int s = 0; s < W; s++) S.sel[s * 64 + lane] = ~0ull;
-        wave_sync();
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            if (r < nrows) {
-                const int c = S.croot[r];
-                if (grow_all ? S.state[c] != kFrozen : S.state[c] == kInvalid) {
-                    uint64_t best = S.cand[r];
-                    if (best == kStale || (best != ~0ull && in_col(S.incol, (int)(uint32_t)best))) {
-                        const int d = S.rowOf[r];
-                        best = ~0ull;
-                        const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
-                        // branch-free and unrolled so that the loads of several faults are in
-                        // flight together (graph and keys may live in global memory)
-#pragma unroll 8
-                        for (int e = e0; e < e1; e++) {
-                            const int j = g.col_idx(e);
-                            const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
-                            const uint64_t key = in_col(S.incol, j) ? ~0ull : (((uint64_t)kj << 32) | (uint32_t)j);
-                            best = key < best ? key : best;
-                        }
-                        S.cand[r] = best;
-                    }
-                    if (best != ~0ull) atomicMin((unsigned long long *)&S.sel[c], (unsigned long long)best);
-                }
-            }
-        }
-        wave_sync();
-        // (2) compact list of (root, key); an invalid root with no candidate is frozen (UNSAT)
-        int nsel = 0;
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            bool take = false;
-            uint64_t key = ~0ull;
-            if (r < nrows && S.croot[r] == r && (grow_all ? S.state[r] != kFrozen : S.state[r] == kInvalid)) {
-                key = S.sel[r];
-                if (key != ~0ull) take = true;
-                else if (S.state[r] == kInvalid) { S.state[r] = kFrozen; status |= QLSD_ST_UNSAT; }
-            }
-            const uint64_t bal = ballot(take);
-            if (take) {
-                const int p = nsel + __popcll(bal & ((1ull << lane) - 1ull));
-                S.lkey[p] = key;
-                S.lroot[p] = r;
-            }
-            nsel += __popcll(bal);
-        }
-        if (ballot(status & QLSD_ST_UNSAT)) status |= QLSD_ST_UNSAT;
-        wave_sync();
-        if (nsel == 0) {
-            if (!grow_all && A.mu > 0) {  // every invalid cluster is frozen; valid ones may still grow
-                grow_all = true;
-                mu_left = A.mu;
-                continue;
-            }
-            break;
-        }
-
-        // (3) claims and unions (Def. 4.4): pairs (selection, detector of its fault)
-        const int cwm = g.max_cw;
-        const int npairs = nsel * cwm;
-        // pair id -> (selection, entry): id / cwm as a multiply-high by ceil(2^32 / cwm), exact for
-        // id < 2^16 and cwm <= 16
-        const uint64_t cw_magic = (0x100000000ull + (uint64_t)cwm - 1ull) / (uint64_t)cwm;  // 2^32 when cwm = 1
-        for (int id = lane; id < npairs; id += 64) {
-            const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
-            const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr(col);
-            if (u < g.col_ptr(col + 1) - c0) {
-                const int d = g.row_idx(c0 + u);
-                if (S.loc[d] < 0) atomicMin(&S.claimer[d], S.lroot[p]);
-            }
-        }
-        wave_sync();
-        bool merged = false;
-        for (int id = lane; id < npairs; id += 64) {
-            const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
-            const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr(col);
-            if (u < g.col_ptr(col + 1) - c0) {
-                const int d = g.row_idx(c0 + u);
-                const int c = S.lroot[p];
-                const int cl = S.claimer[d];
-                if (cl != kFree) {
-                    if (cl == c) {
-                        const int idx = atomicAdd(&S.ctl[0], 1);
-                        if (idx < K) {
-                            S.rowOf[idx] = d;
-                            S.croot[idx] = c;
-                            S.state[idx] = kValid;
-                            S.cand[idx] = kStale;
-                            S.loc[d] = idx;
-                        }
-                    } else {
-                        merged |= unite(S.croot, c, cl);
-                    }
-                } else {
-                    merged |= unite(S.croot, c, S.croot[S.loc[d]]);
-                }
-            }
-        }
-        const bool any_merge = ballot(merged) != 0ull;
-        wave_sync();
-        const int nrows_new = S.ctl[0];
-        if (nrows_new > K) { overflow(status); return; }
-        // flatten the forest (only after a merge: otherwise every row already points at a root,
-        // new rows at the round-start root that claimed them); release this round's claims
-        if (any_merge) {
-#pragma unroll
-            for (int s = 0; s < W; s++) {
-                const int r = s * 64 + lane;
-                if (r < nrows_new) S.croot[r] = find_root(S.croot, r);
-            }
-        }
-        for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
-        nrows = nrows_new;
-        wave_sync();
-
-        // (4) the round's distinct new columns, ascending key, each reduced on the fly.  Order:
-        // entry p goes to position rank(p) = number of entries with a smaller key (distinct keys get
-        // distinct positions; a column picked by several clusters is placed once, by its first
-        // entry).  The selection array is free at this point and holds the order.
-        {
-            int32_t *order = (int32_t *)S.sel;
-            for (int p = lane; p < nsel; p += 64) order[p] = -1;
-            wave_sync();
-            for (int p = lane; p < nsel; p += 64) {
-                const uint64_t kp = S.lkey[p];
-                int rank = 0;
-                bool dup = false;
-                for (int q = 0; q < nsel; q++) {
-                    const uint64_t kq = S.lkey[q];
-                    rank += kq < kp ? 1 : 0;
-                    dup |= kq == kp && q < p;
-                }
-                if (!dup) order[rank] = (int)(uint32_t)kp;
-            }
-            wave_sync();
-            for (int r = 0; r < nsel; r++) {
-                const int col = order[r];
-                if (col < 0) continue;
-                if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
-                const bool pivot = insert_column<W>(B, S, g, col, lane);
-                if (!pivot && A.mu > 0) {
-                    if (lane == 0 && npc < K) S.colNP[npc] = col;
-                    npc++;
-                }
-            }
-        }
-        wave_sync();
-
-        // (5) validity: a cluster is valid iff its reduced syndrome vanishes
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            if (r < nrows && S.croot[r] == r && S.state[r] != kFrozen) S.state[r] = kValid;
-        }
-        wave_sync();
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            if (r < nrows && ((B.sp[s] >> lane) & 1ull)) {
-                const int c = S.croot[r];
-                if (S.state[c] != kFrozen) S.state[c] = kInvalid;
-            }
-        }
-        wave_sync();
-        rounds++;
-        if (grow_all) {
-            if (--mu_left == 0) break;
-            continue;
-        }
-        bool any_invalid = false;
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            any_invalid |= (r < nrows && S.croot[r] == r && S.state[r] == kInvalid);
-        }
-        if (!ballot(any_invalid)) {
-            if (A.mu <= 0) break;
-            grow_all = true;
-            mu_left = A.mu;
-        }
-    }
-    if (npc > K) { overflow(status); return; }
-
-    // solve: seed rows carry s = 1, claimed rows s = 0; frozen clusters contribute nothing
-    uint64_t as[W];
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        const int r = s * 64 + lane;
-        const bool seed = r < nseed && S.state[S.croot[r]] != kFrozen;
-        as[s] = ballot(seed) & B.piv[s];
-    }
-    int ncl = 0;
-    uint64_t x0[W];  // LSD-0 solution: pivot rows whose column is set
-#pragma unroll
-    for (int s = 0; s < W; s++) {
-        const int r = s * 64 + lane;
-        const bool is_root = r < nrows && S.croot[r] == r;
-        ncl += __popcll(ballot(is_root));
-        x0[s] = ballot(((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as));
-    }
-    if (A.mu <= 0) {
-#pragma unroll
-        for (int s = 0; s < W; s++)
-            if ((x0[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
-        // faults of frozen clusters stay zero: their pivot rows never enter `as`
-        finish(status, ncl, 0);
-        return;
-    }
-    osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, corr, lane);
-    finish(status, ncl, 0);
-}
 
 template <int W, bool GL>
 __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
@@ -706,27 +51,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
     }
     unsigned char *base = smem + gbytes + (size_t)wid * A.wave_bytes;
-    size_t offs[18];
-    lsd_layout(m, n, K, A.keys_in_lds != 0, offs);
-    LsdLds S;
-    S.keys = (uint32_t *)(base + offs[0]);
-    S.sel = (uint64_t *)(base + offs[1]);
-    S.lkey = (uint64_t *)(base + offs[2]);
-    S.lroot = (int32_t *)(base + offs[3]);
-    S.colAt = (int32_t *)(base + offs[4]);
-    S.croot = (int32_t *)(base + offs[5]);
-    S.rowOf = (int32_t *)(base + offs[6]);
-    S.loc = (int32_t *)(base + offs[7]);
-    S.claimer = (int32_t *)(base + offs[8]);
-    S.incol = (uint32_t *)(base + offs[9]);
-    S.state = (uint8_t *)(base + offs[10]);
-    S.ctl = (int32_t *)(base + offs[11]);
-    S.colNP = (int32_t *)(base + offs[12]);
-    S.wq = (int64_t *)(base + offs[13]);
-    S.zk = (uint64_t *)(base + offs[14]);
-    S.tsel = (int32_t *)(base + offs[15]);
-    S.tw = (int64_t *)(base + offs[16]);
-    S.cand = (uint64_t *)(base + offs[17]);
+    const LsdLds S = carve_lsd(base, m, n, K, A.keys_in_lds != 0);
 
     const int total = A.list ? *A.list_count : A.count;
     for (;;) {
@@ -735,6 +60,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
         const int shot = A.list ? A.list[item] : item;
+        if (A.skip_done && shot < 0) continue;
         decode_shot<W>(A, S, g, shot, lane);
         wave_sync();
     }
