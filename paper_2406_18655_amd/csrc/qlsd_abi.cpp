@@ -62,7 +62,8 @@ struct qlsd_decoder_s {
     float *d_lam;
     int64_t *d_omega;
     int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter (one-kernel path:
-                         // tickets), [3] BP workgroups done, [4] work counter of the LSD launch after it
+                         // tickets), [3] BP workgroups done, [4] work counter of the LSD launch after it,
+                         // [5] shots decoded inside the one-kernel path
     uint8_t *d_flag;     // max_batch: shot goes from BP to LSD
     int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
@@ -308,10 +309,8 @@ static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
 // Wavefronts per BP workgroup that can run LSD in the BP kernel's LDS block (past the graph
 // tables); 0: BP and LSD run as separate kernels.  Only for LSD with up to 128 local rows (the
 // one-kernel form then needs at most 128 VGPRs, i.e. 4 workgroups per CU, the BP default).
-constexpr bool kOneKernel = false;  // BP + LSD in one kernel: off
-
 static int fuse_waves(qlsd_decoder d) {
-    if (!kOneKernel || d->bp_graph || d->net || (d->params.flags & QLSD_FLAG_SEPARATE_LSD)) return 0;
+    if (d->bp_graph || d->net || (d->params.flags & QLSD_FLAG_SEPARATE_LSD)) return 0;
     if (d->lsd_W > 2 || d->params.lsd_order > 0 || !d->lsd_keys_in_lds || d->bp_grid > 4 * d->num_cus) return 0;
     const size_t avail = bp_lds_bytes(d->code->g, d->bp_slots) - bp_tables_bytes(d->code->g);
     return (int)std::min<size_t>(4, avail / (size_t)d->lsd_wave_bytes);
@@ -375,6 +374,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
         f.list_w = d->d_list;
         f.tail = d->d_ctl + 1;
         f.bp_done = d->d_ctl + 3;
+        f.lsd_done = d->d_ctl + 5;
         f.lsd_waves = fw;
         f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
         if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
@@ -384,6 +384,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
         LsdArgs rest = f.lsd;
         rest.next_item = d->d_ctl + 4;
         rest.skip_done = 1;
+        rest.done_count = d->d_ctl + 5;
         rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
         HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
         if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));

@@ -218,12 +218,15 @@ constexpr unsigned long long kFuseIdleTicks = 20000;  // 200 us
 // region inside a loop: it may split lane 0 off at the loop latch and run the loop body (a
 // whole LSD shot, which needs all 64 lanes) with the other lanes only.  A call returns with the
 // caller's execution mask.
-__device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, int *tail, int nwg, int B,
-                                       int done_h, int done_shot) {
+__device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, int *tail, int *lsd_done, int nwg,
+                                       int B, int done_h, int done_shot) {
     const int lane = threadIdx.x & 63;
     int hv = 0;
     if (lane == 0) {
-        if (done_h >= 0) atomicExch(list + done_h, ~done_shot);  // the stand-alone launch skips it
+        if (done_h >= 0) {
+            atomicExch(list + done_h, ~done_shot);  // the stand-alone launch skips it
+            atomicAdd(lsd_done, 1);
+        }
         hv = atomicAdd(next_item, 1);
     }
     const int h = __builtin_amdgcn_readfirstlane(hv);
@@ -288,6 +291,9 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
     const int T = args.max_iter;
     const int PW = L.PW;
     const uint64_t lt = (1ull << lane) - 1ull;
+    // fused: BP wavefronts issue ahead of the LSD wavefronts of drained workgroups on the same CU
+    // (the last BP shots gate the last LSD shots)
+    if constexpr (LSDW > 0) __builtin_amdgcn_s_setprio(2);
     // Queue state, held in wavefront 0's registers (uniform across its lanes; no other wavefront
     // reads it): staging buffer k holds shots [qb_k, qb_k + qc_k) (qb_k = -1: free, -2: drained
     // this iteration, still readable); cur / cursor: next staged shot; pending: a chunk request
@@ -295,7 +301,9 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
     // shot and iteration count live in the lane of wavefront 0 that manages the slot.
     int qb0 = L.ctl[10], qc0 = L.ctl[11], qb1 = -1, qc1 = 0;
     int q_cur = 0, q_cursor = 0, q_pending = 0, q_exh = L.ctl[9];
-    int req_v = 0;  // lane 0: base returned by the request in flight (read once it has landed)
+    int req_v = 0;   // lane 0: base returned by the request in flight (read once it has landed)
+    int q_sz = C;    // shots asked for by that request
+    int q_seen = qb0 >= 0 ? qb0 : args.B;  // base of the latest chunk landed here (queue position)
     int my_shot = -1, my_it = 0;
 
     for (;;) {
@@ -402,8 +410,9 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
             if (q_pending) {
                 q_pending = 0;
                 const int req = __builtin_amdgcn_readfirstlane(req_v);
-                const int cnt = max(0, min(C, args.B - req));
-                if (req + C >= args.B) q_exh = 1;
+                const int cnt = max(0, min(q_sz, args.B - req));
+                if (req + q_sz >= args.B) q_exh = 1;
+                q_seen = req;
                 if (cnt > 0) {
                     // a free buffer exists: requests are only issued when one is free
                     const int dst = (ncur ? qb1 : qb0) == -1 ? ncur : 1 - ncur;
@@ -414,9 +423,12 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
                     ldbuf = dst;
                 }
             }
-            // keep one request in flight while a buffer is free and shots remain
+            // keep one request in flight while a buffer is free and shots remain; requests shrink
+            // as the queue drains (about a quarter of each workgroup's share of what is left, at
+            // most a chunk), so no workgroup still holds full chunks when the others run dry
             if (!q_exh && (qb0 == -1 || qb1 == -1)) {
-                if (lane == 0) req_v = atomicAdd(args.next_shot, C);
+                q_sz = max(1, min(C, (args.B - q_seen) / (4 * (int)gridDim.x)));
+                if (lane == 0) req_v = atomicAdd(args.next_shot, q_sz);
                 q_pending = 1;
             }
             if (lane == 0) {
@@ -536,6 +548,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         __syncthreads();
         if (t == 0) atomicAdd(f.bp_done, 1);  // after this workgroup's last reservation
         if (wave >= f.lsd_waves) return;
+        __builtin_amdgcn_s_setprio(0);
         constexpr int K = 64 * LSDW;
         unsigned char *lbase = smem + tables_bytes(m, n, E) + (size_t)wave * f.lsd.wave_bytes;
         const LsdLds S2 = carve_lsd(lbase, m, n, K, f.lsd.keys_in_lds != 0);
@@ -546,7 +559,8 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         // no lane-dependent branch in this loop: see fuse_step
         int done_h = -1, done_shot = 0;
         for (;;) {
-            const int2 r = fuse_step(f.list_w, f.lsd.next_item, f.bp_done, f.tail, nwg, args.B, done_h, done_shot);
+            const int2 r = fuse_step(f.list_w, f.lsd.next_item, f.bp_done, f.tail, f.lsd_done, nwg, args.B, done_h,
+                                     done_shot);
             const int shot = __builtin_amdgcn_readfirstlane(r.x);
             const int h = __builtin_amdgcn_readfirstlane(r.y);
             if (shot < 0) break;  // no entry h, or it is left to the stand-alone launch (the call

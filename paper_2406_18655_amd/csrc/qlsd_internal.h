@@ -58,6 +58,7 @@ struct LsdArgs {
     int coherent_llr;          // llr rows written during this kernel by other workgroups: read them
                                // with device-scope atomics
     int skip_done;             // list entries < 0 were decoded already (after the fused kernel)
+    int *done_count;           // with skip_done: how many were (nullable); all done -> no work
 };
 
 // BP with LSD folded in (plain decode with slot BP): a workgroup whose slots have drained turns
@@ -71,6 +72,7 @@ struct FuseArgs {
     int *list_w;               // writable alias of lsd.list
     int *tail;                 // == lsd.list_count
     int *bp_done;              // BP workgroups finished
+    int *lsd_done;             // shots decoded by the fused kernel (== lsd.done_count)
     int lsd_waves;             // wavefronts per workgroup that run LSD (LDS permitting)
     int lsd_bytes;             // dynamic LDS the kernel needs (>= the BP carve)
 };

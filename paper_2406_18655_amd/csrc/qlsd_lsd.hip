@@ -33,6 +33,8 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int K = 64 * W;
+    // after the fused kernel: nothing to do when every published shot was decoded there
+    if (A.skip_done && A.done_count && *A.done_count >= *A.list_count) return;
     const int m = A.g.m, n = A.g.n, E = A.g.nnz;
     GView<GL> g;
     g.max_cw = A.g.max_cw;

@@ -10,7 +10,7 @@ import pytest
 from paper_2406_18655_amd import binding
 from paper_2406_18655_amd.workloads import bivariate_bicycle, surface_hgp, sample
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skip(reason="one-kernel BP + LSD path is switched off in this build")]
+pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
