@@ -75,6 +75,12 @@ def bp_algorithmic_bytes(m, n, E, iters):
     return float(len(iters) * ((m + 7) // 8 + (n + 7) // 8) + iters.astype(np.float64).sum() * (8 * E + 8 * n))
 
 
+def lsd_algorithmic_bytes(n, n_lsd):
+    """Per shot that goes on to LSD: its float32 posterior row written by BP and read by LSD
+    (its syndrome and correction are already counted once in the BP figure)."""
+    return float(n_lsd) * 8 * n
+
+
 def main():
     args = parse()
     dem = args.workload == "dem"
@@ -110,13 +116,14 @@ def main():
     stream = torch.cuda.current_stream()
 
     # correctness + iteration counts of each batch (untimed)
-    iters_per_batch, ler_gpu, lsd_frac = [], [], []
+    iters_per_batch, ler_gpu, lsd_frac, lsd_count = [], [], [], []
     for e, s in batches:
         dec.decode_into(s, corr, info)
         torch.cuda.synchronize()
         inf = binding.parse_info(info)
         iters_per_batch.append(inf["bp_iters"].astype(np.int64))
         lsd_frac.append(float(((inf["status"] & binding.ST_LSD_RUN) != 0).mean()))
+        lsd_count.append(int(((inf["status"] & binding.ST_LSD_RUN) != 0).sum()))
         c = corr.cpu().numpy()
         Sn = s.cpu().numpy()
         if not (syndromes(code, c) == Sn).all():
@@ -154,9 +161,12 @@ def main():
     shots_per_s = args.steps * B / wall
     ms_per_step = wall * 1e3 / args.steps
 
-    # BP kernel roofline: algorithmic bytes per launch over its measured average duration
+    # Roofline of the dominant kernel: algorithmic bytes per launch over its measured average
+    # duration.  [[144,12,12]]: the slot BP kernel with LSD folded in (BP's bytes plus each LSD
+    # shot's posterior row); DEM: the large-graph BP kernel (LSD runs as its own kernel).
     E = code.nnz
-    bytes_per_launch = np.mean([bp_algorithmic_bytes(code.m, code.n, E, it) for it in iters_per_batch])
+    bp_bytes = np.mean([bp_algorithmic_bytes(code.m, code.n, E, it) for it in iters_per_batch])
+    bytes_per_launch = bp_bytes if dem else bp_bytes + lsd_algorithmic_bytes(code.n, np.mean(lsd_count))
     bp_avg_ms = float(np.mean(bp_ms))
     achieved = bytes_per_launch / (bp_avg_ms * 1e-3) / 1e9
     traffic = None
@@ -165,11 +175,29 @@ def main():
             tj = json.load(f)
         if tj.get("kernel_source_hash") == _kernel_hash():
             traffic = tj.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "bp_graph_kernel" if dem else "bp_lds_kernel", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm",
+                "kernel": "bp_graph2_kernel" if dem else "bp_lds_kernel (BP + LSD-0 in one kernel)",
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_ms": round(bp_avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "lsd_avg_launch_ms": round(float(np.mean(lsd_ms)), 4)}
+    if not dem:
+        # context: the same BP as a kernel of its own (two-kernel path), on batch 0
+        sep = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=args.lsd_order,
+                              flags=binding.FLAG_STAGE_TIMING | binding.FLAG_SEPARATE_LSD)
+        sms = []
+        for k in range(10):
+            sep.decode_into(batches[0][1], corr, None)
+            a, b = sep.stage_ms()
+            if k >= 2:
+                sms.append((a, b))
+        a_ms = float(np.mean([x[0] for x in sms]))
+        b0 = bp_algorithmic_bytes(code.m, code.n, E, iters_per_batch[0])
+        roofline["bp_kernel_alone"] = {"avg_launch_ms": round(a_ms, 4),
+                                       "frac": round(b0 / (a_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                       "lsd_kernel_ms": round(float(np.mean([x[1] for x in sms])), 4)}
+        del sep
 
     # logical error rate of the GPU run vs the oracle on the same shots (batch 0)
     e0, s0 = batches[0]
@@ -269,7 +297,7 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
 def _kernel_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("qlsd_bp.hip", "qlsd_internal.h"):
+    for f in ("qlsd_bp.hip", "qlsd_internal.h", "qlsd_lsd_dev.h"):
         with open(os.path.join(HERE, "paper_2406_18655_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -61,9 +61,9 @@ struct qlsd_decoder_s {
     int max_batch;
     float *d_lam;
     int64_t *d_omega;
-    int *d_ctl;          // [0] BP queue, [1] LSD list length, [2] LSD work counter (one-kernel path:
-                         // tickets), [3] BP workgroups done, [4] work counter of the LSD launch after it,
-                         // [5] shots decoded inside the one-kernel path
+    int *d_ctl;          // counters, one per 128-byte line (kCtl*): BP queue, LSD list length, LSD work
+                         // counter (one-kernel path: tickets), BP workgroups done, work counter of the
+                         // LSD launch after the one-kernel path, shots decoded inside it
     uint8_t *d_flag;     // max_batch: shot goes from BP to LSD
     int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
@@ -79,6 +79,10 @@ struct qlsd_decoder_s {
 };
 
 namespace qlsd {
+// Decoder counters, each on its own 128-byte line: the one-kernel path polls the list counters
+// while BP workgroups hit the queue counter, and atomics on a shared line would serialise.
+constexpr int kCtlQueue = 0, kCtlList = 32, kCtlItem = 64, kCtlBpDone = 96, kCtlItem2 = 128, kCtlLsdDone = 160;
+constexpr int kCtlWords = 192;
 void set_last_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -90,7 +94,7 @@ DevGraph code_graph(qlsd_code c) { return c->g; }
 int code_cols(qlsd_code c) { return c->g.n; }
 size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
-    return n * (sizeof(float) + sizeof(int64_t)) + 8 * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
+    return n * (sizeof(float) + sizeof(int64_t)) + kCtlWords * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
            d->netws_bytes;
 }
 }  // namespace qlsd
@@ -264,8 +268,8 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
 
     hipError_t e1 = dev_copy(&d->d_lam, lam.data(), lam.size());
     if (e1 == hipSuccess) e1 = dev_copy(&d->d_omega, omega.data(), omega.size());
-    hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * 8);
-    if (e2 == hipSuccess) e2 = hipMemset(d->d_ctl, 0, sizeof(int) * 8);
+    hipError_t e2 = hipMalloc((void **)&d->d_ctl, sizeof(int) * kCtlWords);
+    if (e2 == hipSuccess) e2 = hipMemset(d->d_ctl, 0, sizeof(int) * kCtlWords);
     hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
     if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
     hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
@@ -302,7 +306,7 @@ static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
     a.alpha = d->params.ms_scaling;
     a.early_exit = (d->params.flags & QLSD_FLAG_NO_EARLY_EXIT) ? 0 : 1;
     a.S = d->bp_slots;
-    a.next_shot = d->d_ctl + 0;
+    a.next_shot = d->d_ctl + kCtlQueue;
     return a;
 }
 
@@ -332,7 +336,7 @@ static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, ui
     a.g = d->code->g;
     a.syn = syn;
     a.llr = llr;
-    a.next_item = d->d_ctl + 2;
+    a.next_item = d->d_ctl + kCtlItem;
     a.corr = corr;
     a.info = info;
     a.keys_in_lds = d->lsd_keys_in_lds;
@@ -359,7 +363,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     const int fw = fuse_waves(d);
     if (fw > 0) {
         HIP_OK(launch_fill(d->d_list, B, -1, s));
-        HIP_OK(launch_zero(d->d_ctl, 8, s));
+        HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
         BpArgs a = bp_args(d, syndromes, B);
         a.corr = corrections;
         a.llr_lsd = d->d_llr;
@@ -368,13 +372,13 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
         memset(&f, 0, sizeof(f));
         f.lsd = lsd_args(d, syndromes, d->d_llr, corrections, info);
         f.lsd.list = d->d_list;
-        f.lsd.list_count = d->d_ctl + 1;
+        f.lsd.list_count = d->d_ctl + kCtlList;
         f.lsd.bp_iters = d->params.max_iter;
         f.lsd.coherent_llr = 1;
         f.list_w = d->d_list;
-        f.tail = d->d_ctl + 1;
-        f.bp_done = d->d_ctl + 3;
-        f.lsd_done = d->d_ctl + 5;
+        f.tail = d->d_ctl + kCtlList;
+        f.bp_done = d->d_ctl + kCtlBpDone;
+        f.lsd_done = d->d_ctl + kCtlLsdDone;
         f.lsd_waves = fw;
         f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
         if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
@@ -382,15 +386,15 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
         if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
         // every published entry not marked done (normally none), on a fresh work counter
         LsdArgs rest = f.lsd;
-        rest.next_item = d->d_ctl + 4;
+        rest.next_item = d->d_ctl + kCtlItem2;
         rest.skip_done = 1;
-        rest.done_count = d->d_ctl + 5;
+        rest.done_count = d->d_ctl + kCtlLsdDone;
         rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
         HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
         if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
         return QLSD_OK;
     }
-    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
     BpArgs a = bp_args(d, syndromes, B);
     if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
     a.corr = corrections;
@@ -399,11 +403,11 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     a.info = info;
     HIP_OK(run_bp(d, a, B, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
-    HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s));
-    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + 1, B, d->d_netws, s));
+    HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + kCtlList, s));
+    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + kCtlList, B, d->d_netws, s));
     LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
     l.list = d->d_list;
-    l.list_count = d->d_ctl + 1;
+    l.list_count = d->d_ctl + kCtlList;
     l.bp_iters = d->params.max_iter;
     HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
@@ -415,7 +419,7 @@ qlsd_status qlsd_bp(qlsd_decoder d, const uint8_t *syndromes, int32_t B, float *
     qlsd_status st = check_call(d, syndromes, B, llr_out);
     if (st != QLSD_OK || B == 0) return st;
     hipStream_t s = (hipStream_t)stream;
-    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
     BpArgs a = bp_args(d, syndromes, B);
     a.corr = hard_out;
     a.llr_out = llr_out;
@@ -430,7 +434,7 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     if (st != QLSD_OK || B == 0) return st;
     if (!llr) return fail(QLSD_E_INVALID, "llr is NULL");
     hipStream_t s = (hipStream_t)stream;
-    HIP_OK(launch_zero(d->d_ctl, 8, s));
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
     LsdArgs l = lsd_args(d, syndromes, llr, corrections, info);
     l.count = B;
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
@@ -471,7 +475,7 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
         return ms / reps;
     };
     auto bp_run = [&]() -> hipError_t {
-        hipError_t e = launch_zero(d->d_ctl, 8, s);
+        hipError_t e = launch_zero(d->d_ctl, kCtlWords, s);
         if (e != hipSuccess) return e;
         BpArgs a = bp_args(d, syndromes, B);
         a.corr = corr;
@@ -501,7 +505,7 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
         rep += line;
     }
     // LSD on the shots this BP leaves unsolved
-    if (bp_run() != hipSuccess || launch_compact(d->d_flag, B, d->d_list, d->d_ctl + 1, s) != hipSuccess) {
+    if (bp_run() != hipSuccess || launch_compact(d->d_flag, B, d->d_list, d->d_ctl + kCtlList, s) != hipSuccess) {
         cleanup();
         return fail(QLSD_E_DEVICE, "tuning launch failed");
     }
@@ -510,11 +514,11 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
     for (int mult : {2, 4, 8, 16, 32}) {
         const int grid = mult * d->num_cus;
         auto lsd_run = [&]() -> hipError_t {
-            hipError_t e = launch_zero(d->d_ctl + 2, 1, s);
+            hipError_t e = launch_zero(d->d_ctl + kCtlItem, 1, s);
             if (e != hipSuccess) return e;
             LsdArgs l = lsd_args(d, syndromes, d->d_llr, corr, nullptr);
             l.list = d->d_list;
-            l.list_count = d->d_ctl + 1;
+            l.list_count = d->d_ctl + kCtlList;
             l.bp_iters = d->params.max_iter;
             return launch_lsd(l, d->lsd_W, grid, s);
         };

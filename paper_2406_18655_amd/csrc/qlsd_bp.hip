@@ -204,52 +204,79 @@ struct CheckItem {
 // returns the word from the point of coherence (an idempotent add would be turned into a load).
 __device__ __forceinline__ int poll_agent(int *p) { return atomicCAS(p, 0, 0); }
 
-// Longest wait of a fused LSD wavefront for its ticket's entry (wall-clock ticks of 10 ns)
-// before it leaves the entry to the stand-alone LSD launch.  It only matters when not every
-// workgroup of the grid is resident at once; normally entries arrive within microseconds.
-constexpr unsigned long long kFuseIdleTicks = 20000;  // 200 us
+// How long a fused LSD wavefront waits without work before it leaves (wall-clock ticks of 10 ns).
+// Leaving only moves work to the stand-alone LSD launch after the kernel, so the wait is short:
+// long enough to pick up shots other workgroups publish in a steady stream, short enough that
+// waiting wavefronts do not keep polling while the last BP workgroups run (at low noise there
+// are only a few hundred LSD shots per batch).
+constexpr unsigned long long kFuseLingerTicks = 2000;  // 20 us
+// A wavefront that holds a ticket waits for its entry until the entry can no longer come (every
+// BP workgroup done with fewer entries) or nothing happened for this long -- a bound that only
+// matters if the grid is not co-resident (e.g. concurrent serving lanes).  Such tickets are few:
+// they come from races between wavefronts that saw the same published entry.
+constexpr unsigned long long kFuseTicketTicks = 20000;  // 200 us
 
 // Everything a fused LSD wavefront does between two shots, as one call that the whole wavefront
-// makes with uniform control flow: mark entry done_h decoded (done_h >= 0), take a ticket h,
-// wait for entry h.  Returns {shot, h}, uniform across the wavefront; shot = -1 if entry h
-// will never be published (every BP workgroup done with fewer entries, or h >= B) or the wait
-// ran out.  Polls back off to one per ~7 us.  The lane-0 atomics live here, not in the caller's
-// loop, because the compiler does not guarantee that a wavefront reconverges after a lane-0
-// region inside a loop: it may split lane 0 off at the loop latch and run the loop body (a
-// whole LSD shot, which needs all 64 lanes) with the other lanes only.  A call returns with the
-// caller's execution mask.
+// makes with uniform control flow: mark entry done_h decoded (done_h >= 0), then take a ticket h
+// for a published entry and wait for it.  A ticket is taken only while published entries exceed
+// the tickets handed out (a race can still hand out one beyond them; that ticket waits too).
+// Returns {shot, h}, uniform across the wavefront, or shot = -1 once no work is left (every BP
+// workgroup done and the list exhausted), or none came for kFuseLingerTicks (no ticket held) or
+// kFuseTicketTicks (ticket held).  The lane-0 atomics
+// live here, not in the caller's loop, because the compiler does not guarantee that a wavefront
+// reconverges after a lane-0 region inside a loop: it may split lane 0 off at the loop latch and
+// run the loop body (a whole LSD shot, which needs all 64 lanes) with the other lanes only.  A
+// call returns with the caller's execution mask.
 __device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, int *tail, int *lsd_done, int nwg,
                                        int B, int done_h, int done_shot) {
     const int lane = threadIdx.x & 63;
-    int hv = 0;
-    if (lane == 0) {
-        if (done_h >= 0) {
-            atomicExch(list + done_h, ~done_shot);  // the stand-alone launch skips it
-            atomicAdd(lsd_done, 1);
-        }
-        hv = atomicAdd(next_item, 1);
+    if (lane == 0 && done_h >= 0) {
+        atomicExch(list + done_h, ~done_shot);  // the stand-alone launch skips it
+        atomicAdd(lsd_done, 1);
     }
-    const int h = __builtin_amdgcn_readfirstlane(hv);
-    if (h >= B) return make_int2(-1, h);  // at most B entries
-    const unsigned long long t0 = wall_clock64();
+    unsigned long long t0 = wall_clock64();
     int nap = 1;
+    int h = -1;  // ticket held (wave-uniform)
     for (int poll = 0;; poll++) {
-        int v = 0, done = 0, tl = 0;
-        const bool check = (poll & 3) == 3;
+        int v = -1, tl = 0, nx = 0, done = 0;
         if (lane == 0) {
-            v = poll_agent(list + h);
-            if (check) {
-                done = poll_agent(bp_done);
+            if (h >= 0) {
+                v = poll_agent(list + h);
+                if (v < 0 && (poll & 3) == 3) {
+                    done = poll_agent(bp_done);
+                    tl = poll_agent(tail);
+                }
+            } else {
                 tl = poll_agent(tail);
+                nx = poll_agent(next_item);
+                if (tl > nx) v = -2 - atomicAdd(next_item, 1);  // a ticket: -2 - h
+                else done = poll_agent(bp_done);
             }
         }
-        const int shot = __builtin_amdgcn_readfirstlane(v);
-        if (shot >= 0) return make_int2(shot, h);
-        if (check) {
+        v = __builtin_amdgcn_readfirstlane(v);
+        if (h >= 0) {
+            if (v >= 0) return make_int2(v, h);
+            // entry h can no longer come: every BP workgroup done, fewer entries
             if (__builtin_amdgcn_readfirstlane(done) >= nwg && __builtin_amdgcn_readfirstlane(tl) <= h)
                 return make_int2(-1, h);
-            if (wall_clock64() - t0 > kFuseIdleTicks) return make_int2(-1, h);
+        } else if (v <= -2) {
+            h = -2 - v;
+            if (h >= B) return make_int2(-1, h);  // at most B entries
+            t0 = wall_clock64();
+            nap = 1;
+            poll = -1;
+            continue;  // poll the entry at once: it is published or about to be
+        } else if (__builtin_amdgcn_readfirstlane(done) >= nwg) {
+            // every BP workgroup is done: the list is final
+            int tl2 = 0, nx2 = 0;
+            if (lane == 0) {
+                tl2 = poll_agent(tail);
+                nx2 = poll_agent(next_item);
+            }
+            if (__builtin_amdgcn_readfirstlane(tl2) <= __builtin_amdgcn_readfirstlane(nx2)) return make_int2(-1, -1);
+            continue;
         }
+        if (wall_clock64() - t0 > (h >= 0 ? kFuseTicketTicks : kFuseLingerTicks)) return make_int2(-1, h);
         for (int k = 0; k < nap; k++) __builtin_amdgcn_s_sleep(64);  // 4096 cycles, ~1.7 us each
         nap = min(nap * 2, 4);
     }
