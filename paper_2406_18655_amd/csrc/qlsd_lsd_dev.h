@@ -113,18 +113,24 @@ __host__ __device__ inline size_t lsd_graph_bytes(int m, int n, int nnz) {
     return align8(sizeof(uint16_t) * ((size_t)m + 1 + nnz + n + 1 + nnz));
 }
 
-__device__ __forceinline__ int find_root(volatile int32_t *par, int x) {
-    int p = par[x];
-    while (p != x) { x = p; p = par[x]; }
+// Union-find parents live in LDS and other lanes hook roots concurrently, so every read goes to
+// LDS (volatile); the LDS-qualified pointer keeps those reads ds_read instructions (a generic
+// volatile pointer compiles to flat loads, which also wait on the vector-memory counter).
+typedef __attribute__((address_space(3))) int32_t lds_int32;
+__device__ __forceinline__ int parent_of(const int32_t *par, int x) {
+    return ((const volatile lds_int32 *)par)[x];
+}
+__device__ __forceinline__ int find_root(const int32_t *par, int x) {
+    int p = parent_of(par, x);
+    while (p != x) { x = p; p = parent_of(par, x); }
     return x;
 }
 
 // Returns true iff it hooked one root under another (false: already in one set).
 __device__ bool unite(int32_t *par, int x, int y) {
-    volatile int32_t *vp = par;
     for (;;) {
-        x = find_root(vp, x);
-        y = find_root(vp, y);
+        x = find_root(par, x);
+        y = find_root(par, y);
         if (x == y) return false;
         if (x < y) { const int tmp = x; x = y; y = tmp; }
         // hook the larger root under the smaller one
