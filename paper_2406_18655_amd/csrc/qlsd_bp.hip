@@ -33,7 +33,7 @@ struct BpLds {
     int C;           // shots per queue chunk
     float *msg, *Lv, *lam;
     uint32_t *synw, *parw;
-    int *act, *actm, *actl, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
+    int *act, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
     uint16_t *rp, *ci, *cp, *ce, *ri;
     uint8_t *stg;    // 2 chunk buffers of C syndromes (raw bytes)
 };
@@ -44,7 +44,7 @@ __host__ __device__ inline size_t tables_bytes(int m, int n, int E) {
     return align16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + 2 * (size_t)E));
 }
 
-constexpr int kSlotArrays = 9;   // int arrays of S entries in the slot-state block
+constexpr int kSlotArrays = 7;   // int arrays of S entries in the slot-state block
 constexpr int kCtl = 16;         // control words
 
 __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S) {
@@ -67,8 +67,8 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     L.synw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
     L.parw = (uint32_t *)(base + off); off += sizeof(uint32_t) * (size_t)L.PW * S;
     int *ip = (int *)(base + off);
-    L.act = ip; L.actm = ip + S; L.actl = ip + 2 * S; L.newk = ip + 3 * S; L.newq = ip + 4 * S;
-    L.rk = ip + 5 * S; L.rshot = ip + 6 * S; L.rit = ip + 7 * S; L.rconv = ip + 8 * S;
+    L.act = ip; L.newk = ip + S; L.newq = ip + 2 * S;
+    L.rk = ip + 3 * S; L.rshot = ip + 4 * S; L.rit = ip + 5 * S; L.rconv = ip + 6 * S;
     L.ctl = ip + kSlotArrays * S;
     off += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
     L.stg = (uint8_t *)(base + off);
@@ -94,19 +94,23 @@ struct ItemWalk {
 // Fault (variable-node) update of fault j in one active slot: posterior, exclusive sums, and
 // the hard decision's contribution to every check's parity.  REG: every column has exactly CW
 // edges (no predication).
+// An active slot's descriptor L.act[a] is the slot index, with the sign bit set while its shot
+// starts this iteration; the slot's message, posterior and parity blocks follow from the index.
 template <int CW, bool REG>
 struct FaultItem {
     float r[CW];
     int eid[CW];
-    int c0, cw, j, slot;
+    int c0, cw, j, k;
+    float lam;
     __device__ __forceinline__ void load(const BpLds &L, int j_, int slot_) {
         j = j_;
-        slot = slot_;
         c0 = REG ? j * CW : L.cp[j];
         cw = REG ? CW : L.cp[j + 1] - c0;
-        const int am = L.actm[slot];
-        const bool fresh = am < 0;  // the slot's shot starts this iteration (sign bit, see slot management)
-        const float *mk = L.msg + (am & 0x7fffffff);
+        const int av = L.act[slot_];
+        const bool fresh = av < 0;  // the slot's shot starts this iteration
+        k = av & 0x7fffffff;
+        lam = L.lam[j];
+        const float *mk = L.msg + k * L.SE;
 #pragma unroll
         for (int u = 0; u < CW; u++) {
             if (REG || u < cw) {
@@ -119,8 +123,7 @@ struct FaultItem {
         }
     }
     __device__ __forceinline__ void store(const BpLds &L, bool count_parity) const {
-        float *mk = L.msg + (L.actm[slot] & 0x7fffffff);
-        const float lam = L.lam[j];
+        float *mk = L.msg + k * L.SE;
         float pre[CW + 1];
         pre[0] = lam;
 #pragma unroll
@@ -134,9 +137,9 @@ struct FaultItem {
             }
         }
         const float Lt = clampf(pre[CW]);  // padding entries add exact zeros
-        L.Lv[L.actl[slot] + j] = Lt;
+        L.Lv[k * L.SN + j] = Lt;
         if (count_parity && Lt < 0.f) {
-            uint32_t *pw = L.parw + (size_t)L.act[slot] * L.PW;
+            uint32_t *pw = L.parw + k * L.PW;
 #pragma unroll
             for (int u = 0; u < CW; u++) {
                 if (REG || u < cw) {
@@ -153,14 +156,14 @@ struct FaultItem {
 template <int RW, bool REG>
 struct CheckItem {
     float q[RW];
-    int e0, rw, slot;
+    int e0, rw, k;
     uint32_t sb;
     __device__ __forceinline__ void load(const BpLds &L, int i, int slot_) {
-        slot = slot_;
+        k = L.act[slot_] & 0x7fffffff;
         e0 = REG ? i * RW : L.rp[i];
         rw = REG ? RW : L.rp[i + 1] - e0;
-        const float *mk = L.msg + (L.actm[slot] & 0x7fffffff) + e0;
-        sb = (L.synw[(size_t)L.act[slot] * L.PW + (i >> 5)] >> (i & 31)) & 1u;
+        const float *mk = L.msg + k * L.SE + e0;
+        sb = (L.synw[k * L.PW + (i >> 5)] >> (i & 31)) & 1u;
 #pragma unroll
         for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? mk[u] : INFINITY;
     }
@@ -175,7 +178,7 @@ struct CheckItem {
             mn1 = fminf(mn1, a);
         }
         const float m1 = alpha * mn1, m2 = alpha * mn2;
-        float *mk = L.msg + (L.actm[slot] & 0x7fffffff) + e0;
+        float *mk = L.msg + k * L.SE + e0;
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             if (REG || u < rw) {
@@ -394,9 +397,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
             const uint64_t amask = __ballot(on);
             if (on) {
                 const int a = __popcll(amask & lt);
-                L.act[a] = lane;
-                L.actm[a] = (lane * L.SE) | (it == 0 ? (int)0x80000000u : 0);  // sign bit: fresh shot
-                L.actl[a] = lane * L.SN;
+                L.act[a] = lane | (it == 0 ? (int)0x80000000u : 0);  // sign bit: fresh shot
             }
             // buffers drained last iteration are free now
             if (qb0 == -2) qb0 = -1;
@@ -476,7 +477,22 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
 
         // ---- outputs of retired shots (coalesced rows), staging of the next chunk, and the
         // syndromes of fresh shots (from staging, packed into bit words by wavefront ballots)
-        if (ldb >= 0) {
+        // The chunk that landed goes to a buffer no shot reads before the next slot management:
+        // its loads are issued here and their LDS stores wait until after the fault phase, so the
+        // HBM round trip overlaps that phase instead of stalling every thread at the next barrier
+        // (dwords held in registers when rows are 4-byte aligned and the chunk fits; else a copy).
+        constexpr int kPre = 4;
+        uint32_t pre[kPre];
+        const int nw = ldc * m / 4;
+        const bool pre_ok = ldb >= 0 && (m & 3) == 0 && (((uintptr_t)args.syn) & 3) == 0 && nw <= kPre * NT;
+        if (pre_ok) {
+            const uint32_t *src = (const uint32_t *)(args.syn + (size_t)ldb * m);
+#pragma unroll
+            for (int q = 0; q < kPre; q++) {
+                const int x = t + q * NT;
+                pre[q] = x < nw ? src[x] : 0u;
+            }
+        } else if (ldb >= 0) {
             uint8_t *dst = L.stg + (size_t)ldbuf * C * m;
             const uint8_t *src = args.syn + (size_t)ldb * m;
             for (int x = t; x < ldc * m; x += NT) dst[x] = src[x];
@@ -550,6 +566,14 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
                 b.load(L, hb ? w1.row : w0.row, hb ? w1.a : w0.a);
                 a.store(L, true);
                 b.store(L, hb);
+            }
+        }
+        if (pre_ok) {
+            uint32_t *dst = (uint32_t *)(L.stg + (size_t)ldbuf * C * m);
+#pragma unroll
+            for (int q = 0; q < kPre; q++) {
+                const int x = t + q * NT;
+                if (x < nw) dst[x] = pre[q];
             }
         }
         __syncthreads();
