@@ -497,12 +497,14 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
             const uint8_t *src = args.syn + (size_t)ldb * m;
             for (int x = t; x < ldc * m; x += NT) dst[x] = src[x];
         }
-        for (int r = 0; r < nret; r++) {
+        // Outputs are written by wavefronts 1.. only: wavefront 0 then has no global stores in
+        // flight when slot management waits for its queue request (one counter covers both).
+        for (int r = 0; r < nret && wave > 0; r++) {
             const int k = L.rk[r], shot = L.rshot[r];
             const bool conv = L.rconv[r] != 0;
             const size_t row = (size_t)shot * n;
             const bool write_corr = args.corr && (LSDW == 0 || conv);  // fused: LSD writes the rest
-            for (int j = t; j < n; j += NT) {
+            for (int j = t - 64; j < n; j += NT - 64) {
                 const float Lj = L.Lv[k * L.SN + j];
                 if (write_corr) args.corr[row + j] = Lj < 0.f ? 1 : 0;
                 if (args.llr_out) args.llr_out[row + j] = Lj;
@@ -511,7 +513,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
                     else args.llr_lsd[row + j] = Lj;
                 }
             }
-            if (t == 0) {
+            if (t == 64) {
                 if (args.info && (LSDW == 0 || conv)) {
                     qlsd_shot_info inf;
                     inf.status = conv ? QLSD_ST_BP_CONVERGED : 0;
@@ -530,9 +532,9 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
             // before the list entries that name them
             if (nunsolved > 0) {
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_s_waitcnt(0);  // this thread's row atomics have completed
+                if (wave > 0) __builtin_amdgcn_s_waitcnt(0);  // this thread's row atomics have completed
                 __syncthreads();
-                if (t == 0) {
+                if (t == 64) {
                     int pos = atomicAdd(f.tail, nunsolved);
                     for (int r = 0; r < nret; r++)
                         if (!L.rconv[r]) atomicExch(f.list_w + pos++, L.rshot[r]);
