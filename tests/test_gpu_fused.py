@@ -87,3 +87,31 @@ def test_irregular_small_code():
     _, one, two = _pair(code, 20, 5000)
     _, S = sample(code, 5000, seed=11)
     _same(code, one, two, S)
+
+
+def test_two_decoders_concurrently():
+    """Two one-kernel decodes in flight at once on two streams: together their grids exceed
+    what the GPU holds resident, so some BP workgroups start only after others have left --
+    the case the bounded waits exist for.  Each result equals the same decoder's result alone."""
+    code = bivariate_bicycle(p=0.05)
+    bc = binding.Code.from_dense(code.H)
+    decs = [binding.Decoder(bc, code.priors, 65536, max_iter=50) for _ in range(2)]
+    batches = [sample(code, 65536, seed=500 + k)[1] for k in range(2)]
+    alone = []
+    for d, S in zip(decs, batches):
+        s = torch.from_numpy(np.ascontiguousarray(S)).cuda()
+        alone.append(_run(d, s, code.n))
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    syn = [torch.from_numpy(np.ascontiguousarray(S)).cuda() for S in batches]
+    outs = [(torch.full((65536, code.n), 7, dtype=torch.uint8, device="cuda"),
+             torch.full((65536, 12), 0xAB, dtype=torch.uint8, device="cuda")) for _ in range(2)]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for k in range(2):
+            with torch.cuda.stream(streams[k]):
+                decs[k].decode_into(syn[k], outs[k][0], outs[k][1])
+        torch.cuda.synchronize()
+        for k in range(2):
+            decs[k].sync()
+            assert np.array_equal(outs[k][0].cpu().numpy(), alone[k][0]), (rep, k)
+            assert np.array_equal(outs[k][1].cpu().numpy(), alone[k][1]), (rep, k)
