@@ -117,8 +117,9 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms)
 
 /* Autotuner: times candidate launch shapes on a sample batch (syndromes device u8[B*m],
  * B <= max_batch, typically one full batch of the workload) and keeps the fastest -- for BP
- * with shot slots, the slots per workgroup and workgroups per compute unit; for LSD, the
- * number of workgroups.  Outputs never depend on these shapes.  Synchronous on `stream`;
+ * with shot slots, the slots per workgroup and workgroups per compute unit (timed on the whole
+ * qlsd_decode when no refinement net is attached, since the shape decides whether BP and LSD
+ * can share one kernel); for LSD, the number of workgroups.  Outputs never depend on these shapes.  Synchronous on `stream`;
  * allocates and frees scratch output buffers; must not overlap other calls on this decoder.
  * `report` (host char[report_len], nullable) receives one line per candidate and the choice. */
 qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, int32_t reps,

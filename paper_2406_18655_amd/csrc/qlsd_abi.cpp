@@ -483,6 +483,13 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
         a.lsd_flag = d->d_flag;
         return run_bp(d, a, B, s);
     };
+    // Whole decode (qlsd_decode: BP and LSD in one kernel where the shape allows it, else the
+    // separate kernels), the measure of a BP shape when no refinement net is attached: the
+    // one-kernel path needs at most 4 workgroups per CU, so BP alone would favour shapes that
+    // lose it.
+    auto decode_run = [&]() -> hipError_t {
+        return qlsd_decode(d, syndromes, B, corr, nullptr, stream) == QLSD_OK ? hipSuccess : hipErrorUnknown;
+    };
     // BP with shot slots: the largest slot count that fits each workgroups-per-CU tier
     if (!d->bp_graph) {
         int best_S = d->bp_slots, best_grid = d->bp_grid;
@@ -494,8 +501,11 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
             if (S < 4) continue;
             d->bp_slots = S;
             d->bp_grid = wg * d->num_cus;
-            const float ms = timeit(bp_run);
-            snprintf(line, sizeof(line), "bp slots %d x %d workgroups/CU: %.4f ms\n", S, wg, ms);
+            const bool whole = d->net == nullptr;
+            const float ms = whole ? timeit(decode_run) : timeit(bp_run);
+            snprintf(line, sizeof(line), "%s slots %d x %d workgroups/CU: %.4f ms\n",
+                     whole ? (fuse_waves(d) > 0 ? "decode (BP + LSD one kernel)," : "decode (BP, LSD),") : "bp",
+                     S, wg, ms);
             rep += line;
             if (ms > 0.f && ms < best) { best = ms; best_S = S; best_grid = d->bp_grid; }
         }
