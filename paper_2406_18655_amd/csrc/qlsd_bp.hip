@@ -556,18 +556,17 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         if (A == 0 && !pending && ldb < 0) break;
         __syncthreads();
 
-        // ---- fault phase (fresh slots start from q = lambda, i.e. zero incoming messages);
-        // two items per thread in flight: both loads before both stores
+        // ---- fault phase (fresh slots start from q = lambda, i.e. zero incoming messages); one
+        // item per thread at a time (the phases are bound by LDS throughput: more items in flight
+        // per thread measured slower, and padding a partial pass with repeated items costs LDS
+        // bandwidth)
         {
             const int total = n * A;
-            ItemWalk w0(t, 2 * NT, A > 0 ? A : 1), w1(t + NT, 2 * NT, A > 0 ? A : 1);
-            for (int idx = t; idx < total; idx += 2 * NT, w0.next(), w1.next()) {
-                const bool hb = idx + NT < total;
-                FaultItem<MAXCW, REG> a, b;
-                a.load(L, w0.row, w0.a);
-                b.load(L, hb ? w1.row : w0.row, hb ? w1.a : w0.a);
-                a.store(L, true);
-                b.store(L, hb);
+            ItemWalk w(t, NT, A > 0 ? A : 1);
+            for (int idx = t; idx < total; idx += NT, w.next()) {
+                FaultItem<MAXCW, REG> it;
+                it.load(L, w.row, w.a);
+                it.store(L, true);
             }
         }
         if (pre_ok) {
@@ -580,17 +579,14 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         }
         __syncthreads();
 
-        // ---- check phase: min-sum messages
+        // ---- check phase: min-sum messages, one item per thread at a time
         {
             const int total = m * A;
-            ItemWalk w0(t, 2 * NT, A > 0 ? A : 1), w1(t + NT, 2 * NT, A > 0 ? A : 1);
-            for (int idx = t; idx < total; idx += 2 * NT, w0.next(), w1.next()) {
-                const bool hb = idx + NT < total;
-                CheckItem<MAXRW, REG> a, b;
-                a.load(L, w0.row, w0.a);
-                b.load(L, hb ? w1.row : w0.row, hb ? w1.a : w0.a);
-                a.store(L, alpha);
-                b.store(L, alpha);  // a duplicate of item a when hb is false: same values, same places
+            ItemWalk w(t, NT, A > 0 ? A : 1);
+            for (int idx = t; idx < total; idx += NT, w.next()) {
+                CheckItem<MAXRW, REG> it;
+                it.load(L, w.row, w.a);
+                it.store(L, alpha);
             }
         }
         __syncthreads();
