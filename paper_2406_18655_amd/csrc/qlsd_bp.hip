@@ -35,18 +35,24 @@ struct BpLds {
     uint32_t *synw, *parw;
     int *act, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
     uint16_t *rp, *ci, *cp, *ce, *ri;
+    uint4 *nt;       // regular codes: per fault, its edge ids (x, y) and check indices (z, w) as
+                     // 16-bit pairs, so one 16-byte read gives everything a fault item indexes
     uint8_t *stg;    // 2 chunk buffers of C syndromes (raw bytes)
 };
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 __host__ __device__ inline int odd_stride(int x) { return x | 1; }
-__host__ __device__ inline size_t tables_bytes(int m, int n, int E) {
-    return align16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + 2 * (size_t)E));
+// Graph tables at the start of the BP block.  reg: the per-fault packed record (BpLds::nt) takes
+// the place of the CSC edge-id table.
+__host__ __device__ inline size_t tables_bytes(int m, int n, int E, bool reg) {
+    return reg ? sizeof(uint4) * (size_t)n + align16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + E))
+               : align16(sizeof(uint16_t) * ((size_t)m + 1 + E + n + 1 + 2 * (size_t)E));
 }
 
 constexpr int kSlotArrays = 7;   // int arrays of S entries in the slot-state block
 constexpr int kCtl = 16;         // control words
 
+template <bool REG>
 __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S) {
     BpLds L;
     L.SE = odd_stride(E);
@@ -55,12 +61,15 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     L.C = S;
     // graph tables first: they stay valid for LSD once the slots are retired (fused kernel)
     size_t off = 0;
+    L.nt = nullptr;
+    L.ce = nullptr;
+    if (REG) { L.nt = (uint4 *)base; off += sizeof(uint4) * n; }
     L.rp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (m + 1);
     L.ci = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
     L.cp = (uint16_t *)(base + off); off += sizeof(uint16_t) * (n + 1);
-    L.ce = (uint16_t *)(base + off); off += sizeof(uint16_t) * E;
+    if (!REG) { L.ce = (uint16_t *)(base + off); off += sizeof(uint16_t) * E; }
     L.ri = (uint16_t *)(base + off);
-    off = tables_bytes(m, n, E);
+    off = tables_bytes(m, n, E, REG);
     L.msg = (float *)(base + off); off += sizeof(float) * (size_t)L.SE * S;
     L.Lv = (float *)(base + off); off += sizeof(float) * (size_t)L.SN * S;
     L.lam = (float *)(base + off); off += sizeof(float) * n;
@@ -96,34 +105,46 @@ struct ItemWalk {
 // edges (no predication).
 // An active slot's descriptor L.act[a] is the slot index, with the sign bit set while its shot
 // starts this iteration; the slot's message, posterior and parity blocks follow from the index.
+// The slot descriptor, the fault's table entries and its prior are independent reads, and every
+// incoming message is read even for a fresh slot (whose stale values are then replaced by zeros),
+// so an item costs two dependent rounds of LDS reads.
 template <int CW, bool REG>
 struct FaultItem {
+    static_assert(!REG || CW <= 4, "the packed fault record holds up to 4 edges");
     float r[CW];
     int eid[CW];
     int c0, cw, j, k;
+    uint2 chk;  // REG: the fault's check indices, 16 bits each
     float lam;
     __device__ __forceinline__ void load(const BpLds &L, int j_, int slot_) {
         j = j_;
-        c0 = REG ? j * CW : L.cp[j];
-        cw = REG ? CW : L.cp[j + 1] - c0;
         const int av = L.act[slot_];
+        lam = L.lam[j];
+        if constexpr (REG) {
+            const uint4 rec = L.nt[j];
+            const uint32_t e[4] = {rec.x & 0xffffu, rec.x >> 16, rec.y & 0xffffu, rec.y >> 16};
+#pragma unroll
+            for (int u = 0; u < CW; u++) eid[u] = (int)e[u];
+            chk = make_uint2(rec.z, rec.w);
+            c0 = j * CW;
+            cw = CW;
+        } else {
+            c0 = L.cp[j];
+            cw = L.cp[j + 1] - c0;
+#pragma unroll
+            for (int u = 0; u < CW; u++) eid[u] = u < cw ? (int)L.ce[c0 + u] : 0;
+        }
         const bool fresh = av < 0;  // the slot's shot starts this iteration
         k = av & 0x7fffffff;
-        lam = L.lam[j];
-        const float *mk = L.msg + k * L.SE;
+        const float *mk = L.msg + __umul24(k, L.SE);
 #pragma unroll
         for (int u = 0; u < CW; u++) {
-            if (REG || u < cw) {
-                eid[u] = L.ce[c0 + u];
-                r[u] = fresh ? 0.f : mk[eid[u]];
-            } else {
-                eid[u] = 0;
-                r[u] = 0.f;
-            }
+            const float v = mk[eid[u]];  // padding entries read edge 0 of the slot
+            r[u] = (fresh || (!REG && u >= cw)) ? 0.f : v;
         }
     }
     __device__ __forceinline__ void store(const BpLds &L, bool count_parity) const {
-        float *mk = L.msg + k * L.SE;
+        float *mk = L.msg + __umul24(k, L.SE);
         float pre[CW + 1];
         pre[0] = lam;
 #pragma unroll
@@ -137,14 +158,20 @@ struct FaultItem {
             }
         }
         const float Lt = clampf(pre[CW]);  // padding entries add exact zeros
-        L.Lv[k * L.SN + j] = Lt;
+        L.Lv[__umul24(k, L.SN) + j] = Lt;
         if (count_parity && Lt < 0.f) {
-            uint32_t *pw = L.parw + k * L.PW;
+            uint32_t *pw = L.parw + __umul24(k, L.PW);
+            if constexpr (REG) {
+                const uint32_t c[4] = {chk.x & 0xffffu, chk.x >> 16, chk.y & 0xffffu, chk.y >> 16};
 #pragma unroll
-            for (int u = 0; u < CW; u++) {
-                if (REG || u < cw) {
-                    const int i = L.ri[c0 + u];
-                    atomicXor(pw + (i >> 5), 1u << (i & 31));
+                for (int u = 0; u < CW; u++) atomicXor(pw + (c[u] >> 5), 1u << (c[u] & 31));
+            } else {
+#pragma unroll
+                for (int u = 0; u < CW; u++) {
+                    if (u < cw) {
+                        const int i = L.ri[c0 + u];
+                        atomicXor(pw + (i >> 5), 1u << (i & 31));
+                    }
                 }
             }
         }
@@ -160,10 +187,10 @@ struct CheckItem {
     uint32_t sb;
     __device__ __forceinline__ void load(const BpLds &L, int i, int slot_) {
         k = L.act[slot_] & 0x7fffffff;
-        e0 = REG ? i * RW : L.rp[i];
+        e0 = REG ? __umul24(i, RW) : L.rp[i];
         rw = REG ? RW : L.rp[i + 1] - e0;
-        const float *mk = L.msg + k * L.SE + e0;
-        sb = (L.synw[k * L.PW + (i >> 5)] >> (i & 31)) & 1u;
+        const float *mk = L.msg + __umul24(k, L.SE) + e0;
+        sb = (L.synw[__umul24(k, L.PW) + (i >> 5)] >> (i & 31)) & 1u;
 #pragma unroll
         for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? mk[u] : INFINITY;
     }
@@ -178,7 +205,7 @@ struct CheckItem {
             mn1 = fminf(mn1, a);
         }
         const float m1 = alpha * mn1, m2 = alpha * mn2;
-        float *mk = L.msg + k * L.SE + e0;
+        float *mk = L.msg + __umul24(k, L.SE) + e0;
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             if (REG || u < rw) {
@@ -292,13 +319,24 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
     const int t = threadIdx.x, NT = blockDim.x;
     const int lane = t & 63, wave = t >> 6;
     const int m = args.g.m, n = args.g.n, E = args.g.nnz, S = args.S;
-    BpLds L = carve_bp(smem, m, n, E, S);
+    BpLds L = carve_bp<REG>(smem, m, n, E, S);
     const int C = L.C;
 
     for (int x = t; x <= m; x += NT) L.rp[x] = (uint16_t)args.g.row_ptr[x];
     for (int x = t; x < E; x += NT) L.ci[x] = (uint16_t)args.g.col_idx[x];
     for (int x = t; x <= n; x += NT) L.cp[x] = (uint16_t)args.g.col_ptr[x];
-    for (int x = t; x < E; x += NT) L.ce[x] = (uint16_t)args.g.col_edge[x];
+    if constexpr (REG) {
+        for (int x = t; x < n; x += NT) {
+            uint32_t e[4] = {0u, 0u, 0u, 0u}, c[4] = {0u, 0u, 0u, 0u};
+            for (int u = 0; u < MAXCW; u++) {
+                e[u] = (uint32_t)args.g.col_edge[x * MAXCW + u];
+                c[u] = (uint32_t)args.g.row_idx[x * MAXCW + u];
+            }
+            L.nt[x] = make_uint4(e[0] | e[1] << 16, e[2] | e[3] << 16, c[0] | c[1] << 16, c[2] | c[3] << 16);
+        }
+    } else {
+        for (int x = t; x < E; x += NT) L.ce[x] = (uint16_t)args.g.col_edge[x];
+    }
     for (int x = t; x < E; x += NT) L.ri[x] = (uint16_t)args.g.row_idx[x];
     for (int x = t; x < n; x += NT) L.lam[x] = args.lam[x];
     for (int x = t; x < S * L.PW; x += NT) { L.parw[x] = 0u; L.synw[x] = 0u; }
@@ -599,7 +637,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         if (wave >= f.lsd_waves) return;
         __builtin_amdgcn_s_setprio(0);
         constexpr int K = 64 * LSDW;
-        unsigned char *lbase = smem + tables_bytes(m, n, E) + (size_t)wave * f.lsd.wave_bytes;
+        unsigned char *lbase = smem + tables_bytes(m, n, E, REG) + (size_t)wave * f.lsd.wave_bytes;
         const LsdLds S2 = carve_lsd(lbase, m, n, K, f.lsd.keys_in_lds != 0);
         GView<true> gv;
         gv.rp = L.rp; gv.ci = L.ci; gv.cp = L.cp; gv.ri = L.ri;
@@ -768,12 +806,17 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph_kernel(BpArgs args) 
 
 }  // namespace
 
-size_t bp_tables_bytes(const DevGraph &g) { return tables_bytes(g.m, g.n, g.nnz); }
+// Codes decoded by the fully unrolled instantiation (every row weight 6, every column weight 3).
+static bool bp_regular63(const DevGraph &g) {
+    return g.min_rw == g.max_rw && g.min_cw == g.max_cw && g.max_rw == 6 && g.max_cw == 3;
+}
+
+size_t bp_tables_bytes(const DevGraph &g) { return tables_bytes(g.m, g.n, g.nnz, bp_regular63(g)); }
 
 size_t bp_lds_bytes(const DevGraph &g, int S) {
     // carve_bp's order: graph tables, messages, posteriors, priors, bit vectors, slot state, staging
     const size_t PW = ((size_t)g.m + 31) / 32;
-    size_t b = tables_bytes(g.m, g.n, g.nnz);
+    size_t b = bp_tables_bytes(g);
     b += sizeof(float) * ((size_t)odd_stride(g.nnz) * S + (size_t)odd_stride(g.n) * S + g.n);
     b += sizeof(uint32_t) * 2 * PW * S;
     b += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
@@ -1000,8 +1043,7 @@ hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
 template <int LSDW>
 static hipError_t launch_bp_w(const BpArgs &a, const FuseArgs &f, int grid, size_t lds, hipStream_t st) {
     const DevGraph &g = a.g;
-    const bool regular = g.min_rw == g.max_rw && g.min_cw == g.max_cw;
-    if (regular && g.max_rw == 6 && g.max_cw == 3) return launch_bp_t<6, 3, true, LSDW>(a, f, grid, lds, st);
+    if (bp_regular63(g)) return launch_bp_t<6, 3, true, LSDW>(a, f, grid, lds, st);
     if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false, LSDW>(a, f, grid, lds, st);
     if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false, LSDW>(a, f, grid, lds, st);
     return launch_bp_t<kMaxRowWeight, kMaxColWeight, false, LSDW>(a, f, grid, lds, st);

@@ -87,7 +87,7 @@ hipError_t launch_zero(int *p, int count, hipStream_t st);
 hipError_t launch_fill(int *p, int count, int value, hipStream_t st);
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);        // S slots per workgroup
 hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st);
-size_t bp_tables_bytes(const DevGraph &g);  // u16 copies of H at the start of the BP LDS block
+size_t bp_tables_bytes(const DevGraph &g);  // graph tables (u16 copies of H) at the start of the BP LDS block
 hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st);  // one workgroup per shot
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
