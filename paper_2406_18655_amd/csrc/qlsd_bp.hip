@@ -35,8 +35,9 @@ struct BpLds {
     uint32_t *synw, *parw;
     int *act, *newk, *newq, *rk, *rshot, *rit, *rconv, *ctl;
     uint16_t *rp, *ci, *cp, *ce, *ri;
-    uint4 *nt;       // regular codes: per fault, its edge ids (x, y) and check indices (z, w) as
-                     // 16-bit pairs, so one 16-byte read gives everything a fault item indexes
+    uint4 *nt;       // regular codes: per fault, its 3 edge ids and 3 check keys (16 bits each; a
+                     // check's key is (byte offset of its parity word) << 5 | bit) and its prior,
+                     // so one 16-byte read gives everything a fault item needs
     uint8_t *stg;    // 2 chunk buffers of C syndromes (raw bytes)
 };
 
@@ -84,94 +85,90 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     return L;
 }
 
-// Walks the flattened (row, active-slot) item space of one phase: item = row * A + a.
-struct ItemWalk {
-    int row, a, qd, rm, A;
-    __device__ ItemWalk(int t, int step, int A_) : A(A_) {
-        row = t / A;
-        a = t - row * A;
-        qd = step / A;
-        rm = step - qd * A;
-    }
-    __device__ __forceinline__ void next() {
-        a += rm;
-        row += qd;
-        if (a >= A) { a -= A; row++; }
-    }
+// The blocks of one active slot.  In each iteration a thread serves a single active slot in both
+// phases (slot t mod A, rows t div A, + R, + 2R, ... with R = NT div A), so the slot's block
+// addresses are computed once per iteration rather than once per work item.
+struct SlotView {
+    float *msg;           // messages, one per edge (q after the fault phase, r after the check phase)
+    float *Lv;            // posteriors
+    uint32_t *parw;       // parity of the hard decision, one bit per check
+    const uint32_t *synw; // syndrome bits
 };
 
 // Fault (variable-node) update of fault j in one active slot: posterior, exclusive sums, and
-// the hard decision's contribution to every check's parity.  REG: every column has exactly CW
-// edges (no predication).
-// An active slot's descriptor L.act[a] is the slot index, with the sign bit set while its shot
-// starts this iteration; the slot's message, posterior and parity blocks follow from the index.
-// The slot descriptor, the fault's table entries and its prior are independent reads, and every
-// incoming message is read even for a fresh slot (whose stale values are then replaced by zeros),
-// so an item costs two dependent rounds of LDS reads.
+// the hard decision's contribution to every check's parity.  A fresh slot's messages were zeroed
+// when its shot arrived, so its first pass reads q = lambda like any other.  REG: every column
+// has exactly CW = 3 edges, and one 16-byte read of the packed fault record gives the edge ids,
+// check indices and prior.
 template <int CW, bool REG>
 struct FaultItem {
-    static_assert(!REG || CW <= 4, "the packed fault record holds up to 4 edges");
+    static_assert(!REG || CW == 3, "the packed fault record describes 3 edges");
     float r[CW];
     int eid[CW];
-    int c0, cw, j, k;
-    uint2 chk;  // REG: the fault's check indices, 16 bits each
+    uint32_t chk[CW];  // REG: the fault's check keys (parity word byte offset << 5 | bit)
+    int c0, cw, j;
     float lam;
-    __device__ __forceinline__ void load(const BpLds &L, int j_, int slot_) {
+    __device__ __forceinline__ void load(const BpLds &L, const SlotView &V, int j_) {
         j = j_;
-        const int av = L.act[slot_];
-        lam = L.lam[j];
         if constexpr (REG) {
             const uint4 rec = L.nt[j];
-            const uint32_t e[4] = {rec.x & 0xffffu, rec.x >> 16, rec.y & 0xffffu, rec.y >> 16};
-#pragma unroll
-            for (int u = 0; u < CW; u++) eid[u] = (int)e[u];
-            chk = make_uint2(rec.z, rec.w);
+            eid[0] = (int)(rec.x & 0xffffu);
+            eid[1] = (int)(rec.x >> 16);
+            eid[2] = (int)(rec.y & 0xffffu);
+            chk[0] = rec.y >> 16;
+            chk[1] = rec.z & 0xffffu;
+            chk[2] = rec.z >> 16;
+            lam = __uint_as_float(rec.w);
             c0 = j * CW;
             cw = CW;
         } else {
+            lam = L.lam[j];
             c0 = L.cp[j];
             cw = L.cp[j + 1] - c0;
 #pragma unroll
             for (int u = 0; u < CW; u++) eid[u] = u < cw ? (int)L.ce[c0 + u] : 0;
         }
-        const bool fresh = av < 0;  // the slot's shot starts this iteration
-        k = av & 0x7fffffff;
-        const float *mk = L.msg + __umul24(k, L.SE);
 #pragma unroll
         for (int u = 0; u < CW; u++) {
-            const float v = mk[eid[u]];  // padding entries read edge 0 of the slot
-            r[u] = (fresh || (!REG && u >= cw)) ? 0.f : v;
+            const float v = V.msg[eid[u]];  // padding entries read edge 0 of the slot
+            r[u] = (REG || u < cw) ? v : 0.f;
         }
     }
-    __device__ __forceinline__ void store(const BpLds &L, bool count_parity) const {
-        float *mk = L.msg + __umul24(k, L.SE);
+    __device__ __forceinline__ void store(const BpLds &L, const SlotView &V, bool count_parity) const {
         float pre[CW + 1];
         pre[0] = lam;
 #pragma unroll
         for (int u = 0; u < CW; u++) pre[u + 1] = pre[u] + r[u];
-        float suf = 0.f;
+        if constexpr (REG) {
+            // The suffix sum starts at the last edge rather than at +0: the same values, since a
+            // prefix sum is -0 only if the prior is, and log((1-p)/p) never rounds to -0.
+            float suf = r[CW - 1];
+            V.msg[eid[CW - 1]] = clampf(pre[CW - 1]);
 #pragma unroll
-        for (int u = CW - 1; u >= 0; u--) {
-            if (REG || u < cw) {
-                mk[eid[u]] = clampf(pre[u] + suf);
+            for (int u = CW - 2; u >= 0; u--) {
+                V.msg[eid[u]] = clampf(pre[u] + suf);
                 suf += r[u];
+            }
+        } else {
+            float suf = 0.f;
+#pragma unroll
+            for (int u = CW - 1; u >= 0; u--) {
+                if (u < cw) {
+                    V.msg[eid[u]] = clampf(pre[u] + suf);
+                    suf += r[u];
+                }
             }
         }
         const float Lt = clampf(pre[CW]);  // padding entries add exact zeros
-        L.Lv[__umul24(k, L.SN) + j] = Lt;
+        V.Lv[j] = Lt;
         if (count_parity && Lt < 0.f) {
-            uint32_t *pw = L.parw + __umul24(k, L.PW);
-            if constexpr (REG) {
-                const uint32_t c[4] = {chk.x & 0xffffu, chk.x >> 16, chk.y & 0xffffu, chk.y >> 16};
 #pragma unroll
-                for (int u = 0; u < CW; u++) atomicXor(pw + (c[u] >> 5), 1u << (c[u] & 31));
-            } else {
-#pragma unroll
-                for (int u = 0; u < CW; u++) {
-                    if (u < cw) {
-                        const int i = L.ri[c0 + u];
-                        atomicXor(pw + (i >> 5), 1u << (i & 31));
-                    }
+            for (int u = 0; u < CW; u++) {
+                if (REG) {
+                    atomicXor((uint32_t *)((unsigned char *)V.parw + (chk[u] >> 5)), 1u << (chk[u] & 31));
+                } else if (u < cw) {
+                    const int i = L.ri[c0 + u];
+                    atomicXor(V.parw + (i >> 5), 1u << (i & 31));
                 }
             }
         }
@@ -183,35 +180,38 @@ struct FaultItem {
 template <int RW, bool REG>
 struct CheckItem {
     float q[RW];
-    int e0, rw, k;
+    int e0, rw;
     uint32_t sb;
-    __device__ __forceinline__ void load(const BpLds &L, int i, int slot_) {
-        k = L.act[slot_] & 0x7fffffff;
+    __device__ __forceinline__ void load(const BpLds &L, const SlotView &V, int i) {
         e0 = REG ? __umul24(i, RW) : L.rp[i];
         rw = REG ? RW : L.rp[i + 1] - e0;
-        const float *mk = L.msg + __umul24(k, L.SE) + e0;
-        sb = (L.synw[__umul24(k, L.PW) + (i >> 5)] >> (i & 31)) & 1u;
+        sb = (V.synw[i >> 5] >> (i & 31)) & 1u;
 #pragma unroll
-        for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? mk[u] : INFINITY;
+        for (int u = 0; u < RW; u++) q[u] = (REG || u < rw) ? V.msg[e0 + u] : INFINITY;
     }
-    __device__ __forceinline__ void store(const BpLds &L, float alpha) const {
+    // pinf / ninf: +inf and -inf held opaque to the compiler (see the kernel)
+    __device__ __forceinline__ void store(const BpLds &L, const SlotView &V, float alpha, float pinf,
+                                          float ninf) const {
         uint32_t sg = sb << 31;
-        float mn1 = INFINITY, mn2 = INFINITY;
+        float mn1 = pinf, mn2 = pinf;
+        // min(x, y) as med3(x, y, -inf): the same value for these non-NaN magnitudes, in one
+        // instruction (fminf costs a canonicalising one per operand)
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             sg ^= __float_as_uint(q[u]);
             const float a = fabsf(q[u]);
             mn2 = __builtin_amdgcn_fmed3f(mn1, mn2, a);
-            mn1 = fminf(mn1, a);
+            mn1 = __builtin_amdgcn_fmed3f(mn1, a, ninf);
         }
-        const float m1 = alpha * mn1, m2 = alpha * mn2;
-        float *mk = L.msg + __umul24(k, L.SE) + e0;
+        float m1 = alpha * mn1, m2 = alpha * mn2;
+        // keep the two products (otherwise the multiply is repeated after every select)
+        asm volatile("" : "+v"(m1), "+v"(m2));
 #pragma unroll
         for (int u = 0; u < RW; u++) {
             if (REG || u < rw) {
                 const float mag = (fabsf(q[u]) == mn1) ? m2 : m1;
                 const uint32_t sgn = (sg ^ __float_as_uint(q[u])) & 0x80000000u;
-                mk[u] = __uint_as_float(__float_as_uint(mag) | sgn);
+                V.msg[e0 + u] = __uint_as_float(__float_as_uint(mag) | sgn);
             }
         }
     }
@@ -327,12 +327,13 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
     for (int x = t; x <= n; x += NT) L.cp[x] = (uint16_t)args.g.col_ptr[x];
     if constexpr (REG) {
         for (int x = t; x < n; x += NT) {
-            uint32_t e[4] = {0u, 0u, 0u, 0u}, c[4] = {0u, 0u, 0u, 0u};
-            for (int u = 0; u < MAXCW; u++) {
-                e[u] = (uint32_t)args.g.col_edge[x * MAXCW + u];
-                c[u] = (uint32_t)args.g.row_idx[x * MAXCW + u];
+            uint32_t e[3], c[3];
+            for (int u = 0; u < 3; u++) {
+                const uint32_t i = (uint32_t)args.g.row_idx[x * 3 + u];
+                e[u] = (uint32_t)args.g.col_edge[x * 3 + u];
+                c[u] = (i >> 5) << 7 | (i & 31);  // fits 16 bits: m <= 16384 on this path
             }
-            L.nt[x] = make_uint4(e[0] | e[1] << 16, e[2] | e[3] << 16, c[0] | c[1] << 16, c[2] | c[3] << 16);
+            L.nt[x] = make_uint4(e[0] | e[1] << 16, e[2] | c[0] << 16, c[1] | c[2] << 16, __float_as_uint(args.lam[x]));
         }
     } else {
         for (int x = t; x < E; x += NT) L.ce[x] = (uint16_t)args.g.col_edge[x];
@@ -356,6 +357,10 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
     __syncthreads();
 
     const float alpha = args.alpha;
+    // infinities the compiler cannot see through, so the check update's med3 minima stay med3
+    // (with a known -inf it turns them back into fminf, which canonicalises its operands)
+    float pinf = INFINITY, ninf = -INFINITY;
+    asm volatile("" : "+v"(pinf), "+v"(ninf));
     const int T = args.max_iter;
     const int PW = L.PW;
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -435,7 +440,7 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
             const uint64_t amask = __ballot(on);
             if (on) {
                 const int a = __popcll(amask & lt);
-                L.act[a] = lane | (it == 0 ? (int)0x80000000u : 0);  // sign bit: fresh shot
+                L.act[a] = lane;
             }
             // buffers drained last iteration are free now
             if (qb0 == -2) qb0 = -1;
@@ -512,6 +517,28 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         const int nret = L.ctl[0], nfresh = L.ctl[1], A = L.ctl[2], nunsolved = L.ctl[3];
         const int ldb = L.ctl[6], ldc = L.ctl[7], ldbuf = L.ctl[8];
         const bool pending = L.ctl[5] != 0;
+        // this thread's active slot for both phases of the iteration: t = r0 * A + a with
+        // r0 < Rs = NT div A (the division by reciprocal is exact for t < 256, A <= 128); the
+        // NT mod A threads past Rs * A serve no slot
+        int r0 = 1 << 30, Rs = NT;
+        SlotView V;
+        {
+            int a = 0;
+            if (A > 0) {
+                const float rA = __builtin_amdgcn_rcpf((float)A);
+                Rs = (int)(((float)NT + 0.5f) * rA);
+                const int q = (int)(((float)t + 0.5f) * rA);
+                if (q < Rs) {
+                    r0 = q;
+                    a = t - q * A;
+                }
+            }
+            const int k = L.act[a];
+            V.msg = L.msg + k * L.SE;
+            V.Lv = L.Lv + k * L.SN;
+            V.parw = L.parw + k * PW;
+            V.synw = L.synw + k * PW;
+        }
 
         // ---- outputs of retired shots (coalesced rows), staging of the next chunk, and the
         // syndromes of fresh shots (from staging, packed into bit words by wavefront ballots)
@@ -582,6 +609,8 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         for (int fi = wave; fi < nfresh; fi += NT / 64) {
             const int k = L.newk[fi];
             const uint8_t *sq = L.stg + (size_t)L.newq[fi] * m;
+            float *mz = L.msg + k * L.SE;  // no incoming check messages yet
+            for (int e = lane; e < E; e += 64) mz[e] = 0.f;
             for (int i0 = 0; i0 < m; i0 += 64) {
                 const int i = i0 + lane;
                 const uint64_t bits = __ballot(i < m && (sq[i] & 1));
@@ -595,17 +624,11 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         __syncthreads();
 
         // ---- fault phase (fresh slots start from q = lambda, i.e. zero incoming messages); one
-        // item per thread at a time (the phases are bound by LDS throughput: more items in flight
-        // per thread measured slower, and padding a partial pass with repeated items costs LDS
-        // bandwidth)
-        {
-            const int total = n * A;
-            ItemWalk w(t, NT, A > 0 ? A : 1);
-            for (int idx = t; idx < total; idx += NT, w.next()) {
-                FaultItem<MAXCW, REG> it;
-                it.load(L, w.row, w.a);
-                it.store(L, true);
-            }
+        // item per thread at a time (more items in flight per thread measured slower)
+        for (int j = r0; j < n; j += Rs) {
+            FaultItem<MAXCW, REG> it;
+            it.load(L, V, j);
+            it.store(L, V, true);
         }
         if (pre_ok) {
             uint32_t *dst = (uint32_t *)(L.stg + (size_t)ldbuf * C * m);
@@ -618,14 +641,10 @@ __global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArg
         __syncthreads();
 
         // ---- check phase: min-sum messages, one item per thread at a time
-        {
-            const int total = m * A;
-            ItemWalk w(t, NT, A > 0 ? A : 1);
-            for (int idx = t; idx < total; idx += NT, w.next()) {
-                CheckItem<MAXRW, REG> it;
-                it.load(L, w.row, w.a);
-                it.store(L, alpha);
-            }
+        for (int i = r0; i < m; i += Rs) {
+            CheckItem<MAXRW, REG> it;
+            it.load(L, V, i);
+            it.store(L, V, alpha, pinf, ninf);
         }
         __syncthreads();
     }
@@ -806,9 +825,10 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph_kernel(BpArgs args) 
 
 }  // namespace
 
-// Codes decoded by the fully unrolled instantiation (every row weight 6, every column weight 3).
+// Codes decoded by the fully unrolled instantiation (every row weight 6, every column weight 3;
+// at most 16384 checks, so a check key of the packed fault record fits 16 bits).
 static bool bp_regular63(const DevGraph &g) {
-    return g.min_rw == g.max_rw && g.min_cw == g.max_cw && g.max_rw == 6 && g.max_cw == 3;
+    return g.min_rw == g.max_rw && g.min_cw == g.max_cw && g.max_rw == 6 && g.max_cw == 3 && g.m <= 16384;
 }
 
 size_t bp_tables_bytes(const DevGraph &g) { return tables_bytes(g.m, g.n, g.nnz, bp_regular63(g)); }
