@@ -106,7 +106,7 @@ hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hip
 }
 
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
-    size_t offs[18];
+    size_t offs[kLsdLayoutEntries];
     return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
 }
 

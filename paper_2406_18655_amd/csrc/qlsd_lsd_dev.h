@@ -78,6 +78,7 @@ struct LsdLds {
     int32_t *tsel;     // kMaxMu: reprocessed columns of the current cluster (LSD-mu)
     int64_t *tw;       // kMaxMu: their weights
     uint64_t *cand;    // K: cached smallest candidate key of each local row (kStale: recompute)
+    uint32_t *cbit;    // ceil(n/32): the correction, one bit per fault (the row is written once)
 };
 
 // A row's cached candidate stays exact while its column is not taken: the taken set only grows,
@@ -85,6 +86,8 @@ struct LsdLds {
 constexpr uint64_t kStale = ~0ull - 1ull;
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
+
+constexpr int kLsdLayoutEntries = 19;
 
 __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, size_t *offs) {
     size_t off = 0;
@@ -106,6 +109,7 @@ __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_l
     offs[15] = off; off += sizeof(int32_t) * kMaxMu;
     offs[16] = off; off += sizeof(int64_t) * kMaxMu;
     offs[17] = off; off += sizeof(uint64_t) * K;
+    offs[18] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
     return align8(off);
 }
 
@@ -253,8 +257,7 @@ __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (i
 // Patterns are spread over the lanes.
 template <int W, class G>
 __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const Basis<W> &B,
-                               const uint64_t (&x0)[W], int nrows, int npc, const float *llr,
-                               uint8_t *corr, int lane) {
+                               const uint64_t (&x0)[W], int nrows, int npc, const float *llr, int lane) {
     constexpr int K = 64 * W;
     const int mu = A.mu < kMaxMu ? A.mu : kMaxMu;
 #pragma unroll
@@ -357,12 +360,15 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                 if ((tb >> k) & 1) {
 #pragma unroll
                     for (int s = 0; s < W; s++) x[s] ^= S.zk[k * W + s];
-                    if (lane == 0) corr[S.tsel[k]] = 1;
+                    if (lane == 0) atomicOr(&S.cbit[S.tsel[k] >> 5], 1u << (S.tsel[k] & 31));
                 }
             }
 #pragma unroll
             for (int s = 0; s < W; s++)
-                if ((x[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
+                if ((x[s] >> lane) & 1ull) {
+                    const int col = S.colAt[s * 64 + lane];
+                    atomicOr(&S.cbit[col >> 5], 1u << (col & 31));
+                }
             wave_sync();
         }
     }
@@ -376,6 +382,12 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     const uint8_t *syn = A.syn + (size_t)shot * m;
     uint8_t *corr = A.corr + (size_t)shot * n;
 
+    // the syndrome of the first detectors is loaded together with the LLRs (one memory round trip
+    // before the seeds; the rest, if m > 256, is read where it is used)
+    constexpr int kSynPre = 4;
+    uint8_t sy[kSynPre];
+#pragma unroll
+    for (int q = 0; q < kSynPre; q++) sy[q] = q * 64 + lane < m ? syn[q * 64 + lane] : 0;
     bool nan = false;
     for (int j = lane; j < n; j += 64) {
         // coherent read: an equal compare-and-swap returns the word at the point of coherence
@@ -383,15 +395,28 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         nan |= (v != v);
         if (A.keys_in_lds) S.keys[j] = ordered_key(v);
     }
-    for (int w = lane; w < (n + 31) / 32; w += 64) S.incol[w] = 0u;
+    for (int w = lane; w < (n + 31) / 32; w += 64) { S.incol[w] = 0u; S.cbit[w] = 0u; }
     for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
-    if ((n & 15) == 0 && (((uintptr_t)corr) & 15) == 0) {
-        for (int j = lane; j < (n >> 4); j += 64) ((uint4 *)corr)[j] = make_uint4(0u, 0u, 0u, 0u);
-    } else {
-        for (int j = lane; j < n; j += 64) corr[j] = 0;
-    }
-    __threadfence_block();  // the zero stores complete before any later scatter to this row
     wave_sync();
+
+    // the correction row from the bit vector, written once on every exit
+    auto write_row = [&]() {
+        wave_sync();
+        if ((n & 15) == 0 && (((uintptr_t)corr) & 15) == 0) {
+            for (int c = lane; c < (n >> 4); c += 64) {
+                const uint32_t bits = (S.cbit[c >> 1] >> ((c & 1) * 16)) & 0xffffu;
+                uint32_t v[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const uint32_t nb = bits >> (4 * k);
+                    v[k] = (nb & 1u) | ((nb & 2u) << 7) | ((nb & 4u) << 14) | ((nb & 8u) << 21);
+                }
+                ((uint4 *)corr)[c] = make_uint4(v[0], v[1], v[2], v[3]);
+            }
+        } else {
+            for (int j = lane; j < n; j += 64) corr[j] = (uint8_t)((S.cbit[j >> 5] >> (j & 31)) & 1u);
+        }
+    };
 
     uint8_t status = QLSD_ST_LSD_RUN;
     int rounds = 0;
@@ -407,18 +432,28 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             A.info[shot] = inf;
         }
     };
-    if (ballot(nan)) { finish(QLSD_ST_LSD_RUN | QLSD_ST_BAD_LLR, 0, 0); return; }
-    // capacity exceeded: the shot reports OVERFLOW with a zero correction
+    if (ballot(nan)) {
+        write_row();
+        finish(QLSD_ST_LSD_RUN | QLSD_ST_BAD_LLR, 0, 0);
+        return;
+    }
+    // capacity exceeded: the shot reports OVERFLOW with a zero correction (the bit vector is
+    // only filled by the solve, after the last capacity check)
     auto overflow = [&](uint8_t st) {
+        write_row();
         finish(st | QLSD_ST_OVERFLOW, 0, 0);
-        for (int j = lane; j < n; j += 64) corr[j] = 0;
     };
 
     // clusters: one per flipped detector, local rows in ascending detector order
     int nrows = 0;
     for (int i0 = 0; i0 < m; i0 += 64) {
         const int i = i0 + lane;
-        const bool f = i < m && (syn[i] & 1);
+        uint8_t sv = 0;
+#pragma unroll
+        for (int q = 0; q < kSynPre; q++)
+            if (i0 == q * 64) sv = sy[q];
+        if (i0 >= kSynPre * 64 && i < m) sv = syn[i];
+        const bool f = i < m && (sv & 1);
         const uint64_t bal = ballot(f);
         if (f) {
             const int idx = nrows + __popcll(bal & ((1ull << lane) - 1ull));
@@ -432,7 +467,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         nrows += __popcll(bal);
     }
-    if (nrows == 0) { finish(QLSD_ST_LSD_RUN, 0, 0); return; }
+    if (nrows == 0) {
+        write_row();
+        finish(QLSD_ST_LSD_RUN, 0, 0);
+        return;
+    }
     if (nrows > K) { overflow(QLSD_ST_LSD_RUN); return; }
     const int nseed = nrows;
     if (lane == 0) S.ctl[0] = nrows;
@@ -469,14 +508,25 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                         const int d = S.rowOf[r];
                         best = ~0ull;
                         const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
-                        // branch-free and unrolled so that the loads of several faults are in
-                        // flight together (graph and keys may live in global memory)
-#pragma unroll 8
-                        for (int e = e0; e < e1; e++) {
-                            const int j = g.col_idx(e);
-                            const uint32_t kj = A.keys_in_lds ? S.keys[j] : ordered_key(llr[j]);
-                            const uint64_t key = in_col(S.incol, j) ? ~0ull : (((uint64_t)kj << 32) | (uint32_t)j);
-                            best = key < best ? key : best;
+                        // eight entries per pass, every load issued before any is used (entries
+                        // past the row's end re-read its last one and are masked out), so a row of
+                        // weight <= 8 costs two dependent rounds of loads
+                        for (int eb = e0; eb < e1; eb += 8) {
+                            int jj[8];
+#pragma unroll
+                            for (int u = 0; u < 8; u++) jj[u] = g.col_idx(min(eb + u, e1 - 1));
+                            uint32_t kk[8], ic[8];
+#pragma unroll
+                            for (int u = 0; u < 8; u++) {
+                                kk[u] = A.keys_in_lds ? S.keys[jj[u]] : ordered_key(llr[jj[u]]);
+                                ic[u] = S.incol[jj[u] >> 5];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; u++) {
+                                const bool ok = eb + u < e1 && !((ic[u] >> (jj[u] & 31)) & 1u);
+                                const uint64_t key = ok ? (((uint64_t)kk[u] << 32) | (uint32_t)jj[u]) : ~0ull;
+                                best = key < best ? key : best;
+                            }
                         }
                         S.cand[r] = best;
                     }
@@ -663,19 +713,25 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     }
     if (A.mu <= 0) {
 #pragma unroll
-        for (int s = 0; s < W; s++)
-            if ((x0[s] >> lane) & 1ull) corr[S.colAt[s * 64 + lane]] = 1;
+        for (int s = 0; s < W; s++) {
+            if ((x0[s] >> lane) & 1ull) {
+                const int col = S.colAt[s * 64 + lane];
+                atomicOr(&S.cbit[col >> 5], 1u << (col & 31));
+            }
+        }
         // faults of frozen clusters stay zero: their pivot rows never enter `as`
+        write_row();
         finish(status, ncl, 0);
         return;
     }
-    osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, corr, lane);
+    osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, lane);
+    write_row();
     finish(status, ncl, 0);
 }
 
 // Per-wavefront LDS block of decode_shot (lsd_layout order) at `base`.
 __device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, bool keys_in_lds) {
-    size_t offs[18];
+    size_t offs[kLsdLayoutEntries];
     lsd_layout(m, n, K, keys_in_lds, offs);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
@@ -696,6 +752,7 @@ __device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, boo
     S.tsel = (int32_t *)(base + offs[15]);
     S.tw = (int64_t *)(base + offs[16]);
     S.cand = (uint64_t *)(base + offs[17]);
+    S.cbit = (uint32_t *)(base + offs[18]);
     return S;
 }
 
