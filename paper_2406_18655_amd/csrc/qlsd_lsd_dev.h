@@ -497,14 +497,23 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
 #pragma unroll
         for (int s = 0; s < W; s++) S.sel[s * 64 + lane] = ~0ull;
         wave_sync();
+        // Branch-light: a row's root and cached candidate are read together, then the root's
+        // state and the candidate's taken bit (reads of rows past nrows are in bounds and unused).
 #pragma unroll
         for (int s = 0; s < W; s++) {
+            if (s * 64 >= nrows) break;
             const int r = s * 64 + lane;
-            if (r < nrows) {
-                const int c = S.croot[r];
-                if (grow_all ? S.state[c] != kFrozen : S.state[c] == kInvalid) {
-                    uint64_t best = S.cand[r];
-                    if (best == kStale || (best != ~0ull && in_col(S.incol, (int)(uint32_t)best))) {
+            const bool valid = r < nrows;
+            const int cr = S.croot[r];
+            uint64_t best = S.cand[r];
+            const int c = valid ? cr : 0;
+            const uint32_t bc = (uint32_t)best;
+            const uint32_t inc = S.incol[(bc < (uint32_t)n ? bc : 0u) >> 5];
+            const uint8_t st = S.state[c];
+            const bool grow = valid && (grow_all ? st != kFrozen : st == kInvalid);
+            {
+                {
+                    if (grow && (best == kStale || (best != ~0ull && ((inc >> (bc & 31)) & 1u)))) {
                         const int d = S.rowOf[r];
                         best = ~0ull;
                         const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
@@ -530,7 +539,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                         }
                         S.cand[r] = best;
                     }
-                    if (best != ~0ull) atomicMin((unsigned long long *)&S.sel[c], (unsigned long long)best);
+                    if (grow && best != ~0ull) atomicMin((unsigned long long *)&S.sel[c], (unsigned long long)best);
                 }
             }
         }
@@ -539,13 +548,16 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         int nsel = 0;
 #pragma unroll
         for (int s = 0; s < W; s++) {
+            if (s * 64 >= nrows) break;
             const int r = s * 64 + lane;
-            bool take = false;
-            uint64_t key = ~0ull;
-            if (r < nrows && S.croot[r] == r && (grow_all ? S.state[r] != kFrozen : S.state[r] == kInvalid)) {
-                key = S.sel[r];
-                if (key != ~0ull) take = true;
-                else if (S.state[r] == kInvalid) { S.state[r] = kFrozen; status |= QLSD_ST_UNSAT; }
+            const int cr = S.croot[r];
+            const uint8_t st = S.state[r];
+            const uint64_t key = S.sel[r];
+            const bool growing = r < nrows && cr == r && (grow_all ? st != kFrozen : st == kInvalid);
+            const bool take = growing && key != ~0ull;
+            if (growing && key == ~0ull && st == kInvalid) {
+                S.state[r] = kFrozen;
+                status |= QLSD_ST_UNSAT;
             }
             const uint64_t bal = ballot(take);
             if (take) {
@@ -572,42 +584,49 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         // pair id -> (selection, entry): id / cwm as a multiply-high by ceil(2^32 / cwm), exact for
         // id < 2^16 and cwm <= 16
         const uint64_t cw_magic = (0x100000000ull + (uint64_t)cwm - 1ull) / (uint64_t)cwm;  // 2^32 when cwm = 1
-        for (int id = lane; id < npairs; id += 64) {
+        // pair id -> (detector d, claiming root c); false for padding entries of short columns
+        auto pair_of = [&](int id, int &d, int &c) -> bool {
             const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
             const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr(col);
-            if (u < g.col_ptr(col + 1) - c0) {
-                const int d = g.row_idx(c0 + u);
-                if (S.loc[d] < 0) atomicMin(&S.claimer[d], S.lroot[p]);
-            }
+            const int c0 = g.col_ptr(col), c1 = g.col_ptr(col + 1);
+            c = S.lroot[p];
+            const bool ok = u < c1 - c0;
+            d = g.row_idx(ok ? c0 + u : c0);  // a picked fault has at least one detector
+            return ok;
+        };
+        // this lane's first pair is decoded once and kept for the unions
+        int d0 = 0, c0p = 0;
+        const bool has0 = lane < npairs && pair_of(lane, d0, c0p);
+        if (has0 && S.loc[d0] < 0) atomicMin(&S.claimer[d0], c0p);
+        for (int id = lane + 64; id < npairs; id += 64) {
+            int d, c;
+            if (pair_of(id, d, c) && S.loc[d] < 0) atomicMin(&S.claimer[d], c);
         }
         wave_sync();
         bool merged = false;
-        for (int id = lane; id < npairs; id += 64) {
-            const int p = (int)(((uint64_t)(uint32_t)id * cw_magic) >> 32), u = id - p * cwm;
-            const int col = (int)(uint32_t)S.lkey[p];
-            const int c0 = g.col_ptr(col);
-            if (u < g.col_ptr(col + 1) - c0) {
-                const int d = g.row_idx(c0 + u);
-                const int c = S.lroot[p];
-                const int cl = S.claimer[d];
-                if (cl != kFree) {
-                    if (cl == c) {
-                        const int idx = atomicAdd(&S.ctl[0], 1);
-                        if (idx < K) {
-                            S.rowOf[idx] = d;
-                            S.croot[idx] = c;
-                            S.state[idx] = kValid;
-                            S.cand[idx] = kStale;
-                            S.loc[d] = idx;
-                        }
-                    } else {
-                        merged |= unite(S.croot, c, cl);
+        auto join = [&](int d, int c) {
+            const int cl = S.claimer[d];
+            if (cl != kFree) {
+                if (cl == c) {
+                    const int idx = atomicAdd(&S.ctl[0], 1);
+                    if (idx < K) {
+                        S.rowOf[idx] = d;
+                        S.croot[idx] = c;
+                        S.state[idx] = kValid;
+                        S.cand[idx] = kStale;
+                        S.loc[d] = idx;
                     }
                 } else {
-                    merged |= unite(S.croot, c, S.croot[S.loc[d]]);
+                    merged |= unite(S.croot, c, cl);
                 }
+            } else {
+                merged |= unite(S.croot, c, S.croot[S.loc[d]]);
             }
+        };
+        if (has0) join(d0, c0p);
+        for (int id = lane + 64; id < npairs; id += 64) {
+            int d, c;
+            if (pair_of(id, d, c)) join(d, c);
         }
         const bool any_merge = ballot(merged) != 0ull;
         wave_sync();
@@ -659,34 +678,46 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         wave_sync();
 
-        // (5) validity: a cluster is valid iff its reduced syndrome vanishes
+        // (5) validity: a cluster is valid iff its reduced syndrome vanishes.  Every row points at
+        // its root here; per root (not frozen), a ballot over the rows tells whether one of its
+        // rows keeps a reduced-syndrome bit, so the states are written once without a second pass.
+        int crv[W];
+        uint64_t rootm[W], livem[W];
 #pragma unroll
         for (int s = 0; s < W; s++) {
             const int r = s * 64 + lane;
-            if (r < nrows && S.croot[r] == r && S.state[r] != kFrozen) S.state[r] = kValid;
+            crv[s] = S.croot[r];
+            const uint8_t st = S.state[r];
+            const bool isroot = r < nrows && crv[s] == r;
+            rootm[s] = ballot(isroot && st != kFrozen);
+            livem[s] = ballot(r < nrows) & B.sp[s];  // rows with a reduced-syndrome bit
         }
-        wave_sync();
+        uint64_t invm[W];
+        bool any_inv = false;
 #pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            if (r < nrows && ((B.sp[s] >> lane) & 1ull)) {
-                const int c = S.croot[r];
-                if (S.state[c] != kFrozen) S.state[c] = kInvalid;
+        for (int s0 = 0; s0 < W; s0++) {
+            invm[s0] = 0;
+            uint64_t rm = rootm[s0];
+            while (rm) {
+                const int c = s0 * 64 + __builtin_ctzll(rm);
+                rm &= rm - 1;
+                uint64_t hit = 0;
+#pragma unroll
+                for (int s = 0; s < W; s++) hit |= ballot(crv[s] == c) & livem[s];
+                if (hit) invm[s0] |= 1ull << (c & 63);
             }
+            any_inv |= invm[s0] != 0;
         }
+#pragma unroll
+        for (int s = 0; s < W; s++)
+            if ((rootm[s] >> lane) & 1ull) S.state[s * 64 + lane] = ((invm[s] >> lane) & 1ull) ? kInvalid : kValid;
         wave_sync();
         rounds++;
         if (grow_all) {
             if (--mu_left == 0) break;
             continue;
         }
-        bool any_invalid = false;
-#pragma unroll
-        for (int s = 0; s < W; s++) {
-            const int r = s * 64 + lane;
-            any_invalid |= (r < nrows && S.croot[r] == r && S.state[r] == kInvalid);
-        }
-        if (!ballot(any_invalid)) {
+        if (!any_inv) {
             if (A.mu <= 0) break;
             grow_all = true;
             mu_left = A.mu;
