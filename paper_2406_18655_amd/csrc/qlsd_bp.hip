@@ -312,9 +312,11 @@ __device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, 
     }
 }
 
-// LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots.
+// LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots.  At most
+// 128 VGPRs (4 wavefronts per SIMD), so that four BP workgroups fit on a CU.
 template <int MAXRW, int MAXCW, bool REG, int LSDW>
-__global__ __launch_bounds__(kBpThreads) void bp_lds_kernel(BpArgs args, FuseArgs f) {
+__global__ __launch_bounds__(kBpThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void bp_lds_kernel(BpArgs args, FuseArgs f) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int t = threadIdx.x, NT = blockDim.x;
     const int lane = t & 63, wave = t >> 6;

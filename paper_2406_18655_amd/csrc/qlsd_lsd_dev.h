@@ -158,19 +158,17 @@ __device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t
     return c & 1;
 }
 
-// Adds column g (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
+// Adds column col (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
-template <int W, class G>
-__device__ bool insert_column(Basis<W> &B, const LsdLds &S, const G &g, int col, int lane) {
-    const int c0 = g.col_ptr(col), cw = g.col_ptr(col + 1) - c0;
-    // the column's support over local rows, as W wave-uniform masks: lane u looks up its entry,
-    // then the masks are assembled from the lanes' results
-    const int lr_mine = lane < cw ? S.loc[g.row_idx(c0 + lane)] : -1;
+// The column's local rows are held by lanes base .. base + cw - 1 of lr_src (-1: no entry).
+template <int W>
+__device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
+    // the column's support over local rows, as W wave-uniform masks
     uint64_t cm[W];
 #pragma unroll
     for (int s = 0; s < W; s++) cm[s] = 0;
     for (int u = 0; u < cw; u++) {
-        const int lr = __builtin_amdgcn_readlane(lr_mine, u);
+        const int lr = __builtin_amdgcn_readlane(lr_src, base + u);
         if (lr >= 0 && lr < 64 * W) {
 #pragma unroll
             for (int s = 0; s < W; s++)
@@ -630,7 +628,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         const bool any_merge = ballot(merged) != 0ull;
         wave_sync();
-        const int nrows_new = S.ctl[0];
+        const int nrows_new = __builtin_amdgcn_readfirstlane(S.ctl[0]);
         if (nrows_new > K) { overflow(status); return; }
         // flatten the forest (only after a merge: otherwise every row already points at a root,
         // new rows at the round-start root that claimed them); release this round's claims
@@ -649,27 +647,66 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         // entry p goes to position rank(p) = number of entries with a smaller key (distinct keys get
         // distinct positions; a column picked by several clusters is placed once, by its first
         // entry).  The selection array is free at this point and holds the order.
+        // With at most 64 (selection, entry) pairs (the usual case) the ranks stay in registers
+        // (lane p: selection p) and each pair's local row is read once, here, for all columns of the
+        // round at the same time (lane id: pair id, as in the claims); otherwise an order array in
+        // LDS and per-column lookups.
         {
+            const bool fast = npairs <= 64;
             int32_t *order = (int32_t *)S.sel;
-            for (int p = lane; p < nsel; p += 64) order[p] = -1;
-            wave_sync();
-            for (int p = lane; p < nsel; p += 64) {
-                const uint64_t kp = S.lkey[p];
-                int rank = 0;
-                bool dup = false;
+            int rank = 0, colp = 0, lr_pair = -1;
+            bool dup = true;
+            if (fast) {
+                const uint64_t kp = lane < nsel ? S.lkey[lane] : ~0ull;
+                lr_pair = has0 ? S.loc[d0] : -1;
+                bool seen = false;
                 for (int q = 0; q < nsel; q++) {
-                    const uint64_t kq = S.lkey[q];
+                    const uint64_t kq = readlane64(kp, q);
                     rank += kq < kp ? 1 : 0;
-                    dup |= kq == kp && q < p;
+                    seen |= kq == kp && q < lane;
                 }
-                if (!dup) order[rank] = (int)(uint32_t)kp;
+                dup = lane >= nsel || seen;
+                colp = (int)(uint32_t)kp;
+            } else {
+                for (int p = lane; p < nsel; p += 64) order[p] = -1;
+                wave_sync();
+                for (int p = lane; p < nsel; p += 64) {
+                    const uint64_t kp = S.lkey[p];
+                    int rk = 0;
+                    bool dp = false;
+                    for (int q = 0; q < nsel; q++) {
+                        const uint64_t kq = S.lkey[q];
+                        rk += kq < kp ? 1 : 0;
+                        dp |= kq == kp && q < p;
+                    }
+                    if (!dp) order[rk] = (int)(uint32_t)kp;
+                }
+                wave_sync();
             }
-            wave_sync();
             for (int r = 0; r < nsel; r++) {
-                const int col = order[r];
-                if (col < 0) continue;
+                int col, lr_src, base, cwc;
+                if (fast) {
+                    const uint64_t at = ballot(!dup && rank == r);
+                    if (!at) continue;
+                    const int p = __builtin_ctzll(at);
+                    col = __builtin_amdgcn_readlane(colp, p);
+                    lr_src = lr_pair;
+                    base = p * cwm;
+                    cwc = cwm;
+                } else {
+                    col = order[r];
+                    if (col < 0) continue;
+                    const int c0 = g.col_ptr(col);
+                    cwc = g.col_ptr(col + 1) - c0;
+                    lr_src = lane < cwc ? S.loc[g.row_idx(c0 + lane)] : -1;
+                    base = 0;
+                }
+                // wave-uniform: lets the entry loop in insert_column run on scalar registers
+                col = __builtin_amdgcn_readfirstlane(col);
+                base = __builtin_amdgcn_readfirstlane(base);
+                cwc = __builtin_amdgcn_readfirstlane(cwc);
                 if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
-                const bool pivot = insert_column<W>(B, S, g, col, lane);
+                const bool pivot = insert_column<W>(B, S, col, lane, lr_src, base, cwc);
                 if (!pivot && A.mu > 0) {
                     if (lane == 0 && npc < K) S.colNP[npc] = col;
                     npc++;
