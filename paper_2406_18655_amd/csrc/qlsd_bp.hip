@@ -499,7 +499,11 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
             // keep one request in flight while a buffer is free and shots remain; requests shrink
             // as the queue drains (about a quarter of each workgroup's share of what is left, at
             // most a chunk), so no workgroup still holds full chunks when the others run dry
-            if (!q_exh && (qb0 == -1 || qb1 == -1)) {
+            // One kernel with LSD: odd-numbered workgroups stop taking new shots once less than a
+            // fifth of the batch is left and turn to LSD while the others finish BP, so LSD starts
+            // before the whole grid drains (the shared queue hands their share to the others).
+            const bool lsd_early = LSDW > 0 && (blockIdx.x & 1) == 1 && (long long)(args.B - q_seen) * 5 < (long long)args.B;
+            if (!q_exh && (qb0 == -1 || qb1 == -1) && !lsd_early) {
                 q_sz = max(1, min(C, (args.B - q_seen) / (4 * (int)gridDim.x)));
                 if (lane == 0) req_v = atomicAdd(args.next_shot, q_sz);
                 q_pending = 1;
