@@ -24,6 +24,15 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int lane) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// A wave-uniform 64-bit value, kept in scalar registers.  The compiler cannot always prove that
+// values updated across the LSD round loop stay uniform and then keeps them in vector registers,
+// where every test on them costs vector instructions.
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
@@ -89,27 +98,31 @@ __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7)
 
 constexpr int kLsdLayoutEntries = 19;
 
+// Arrays sized by K (a compile-time constant in the kernels) and by fixed constants come first, so
+// their offsets from the wavefront's block are constants the compiler folds into the LDS
+// instructions (no register per array); 8-byte arrays before 4-byte ones before bytes keeps every
+// array aligned.  The arrays sized by m and n follow.  offs[] keeps the field order of LsdLds.
 __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, size_t *offs) {
     size_t off = 0;
-    offs[0] = off; off += keys_in_lds ? align8(sizeof(uint32_t) * n) : 0;
-    offs[1] = off; off += sizeof(uint64_t) * K;
-    offs[2] = off; off += sizeof(uint64_t) * K;
-    offs[3] = off; off += sizeof(int32_t) * K;
-    offs[4] = off; off += sizeof(int32_t) * K;
-    offs[5] = off; off += sizeof(int32_t) * K;
-    offs[6] = off; off += sizeof(int32_t) * K;
-    offs[7] = off; off += sizeof(int32_t) * m;
-    offs[8] = off; off += sizeof(int32_t) * m;
-    offs[9] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
-    offs[10] = off; off += align8(K);
-    offs[11] = off; off += sizeof(int32_t) * 4;
-    offs[12] = off; off += sizeof(int32_t) * K;
-    offs[13] = off; off += sizeof(int64_t) * K;
-    offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);
-    offs[15] = off; off += sizeof(int32_t) * kMaxMu;
-    offs[16] = off; off += sizeof(int64_t) * kMaxMu;
-    offs[17] = off; off += sizeof(uint64_t) * K;
-    offs[18] = off; off += sizeof(uint32_t) * ((n + 31) / 32);
+    offs[1] = off; off += sizeof(uint64_t) * K;                      // sel
+    offs[2] = off; off += sizeof(uint64_t) * K;                      // lkey
+    offs[17] = off; off += sizeof(uint64_t) * K;                     // cand
+    offs[13] = off; off += sizeof(int64_t) * K;                      // wq
+    offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);     // zk
+    offs[16] = off; off += sizeof(int64_t) * kMaxMu;                 // tw
+    offs[3] = off; off += sizeof(int32_t) * K;                       // lroot
+    offs[4] = off; off += sizeof(int32_t) * K;                       // colAt
+    offs[5] = off; off += sizeof(int32_t) * K;                       // croot
+    offs[6] = off; off += sizeof(int32_t) * K;                       // rowOf
+    offs[12] = off; off += sizeof(int32_t) * K;                      // colNP
+    offs[15] = off; off += sizeof(int32_t) * kMaxMu;                 // tsel
+    offs[11] = off; off += sizeof(int32_t) * 4;                      // ctl
+    offs[10] = off; off += align8(K);                                // state
+    offs[0] = off; off += keys_in_lds ? sizeof(uint32_t) * n : 0;    // keys
+    offs[7] = off; off += sizeof(int32_t) * m;                       // loc
+    offs[8] = off; off += sizeof(int32_t) * m;                       // claimer
+    offs[9] = off; off += sizeof(uint32_t) * ((n + 31) / 32);        // incol
+    offs[18] = off; off += sizeof(uint32_t) * ((n + 31) / 32);       // cbit
     return align8(off);
 }
 
@@ -240,6 +253,11 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, i
     if (sp_hit) {
 #pragma unroll
         for (int s = 0; s < W; s++) B.sp[s] ^= bp[s];
+    }
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        B.piv[s] = uniform64(B.piv[s]);
+        B.sp[s] = uniform64(B.sp[s]);
     }
     return true;
 }
