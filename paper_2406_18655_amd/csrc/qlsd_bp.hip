@@ -85,9 +85,10 @@ __device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S
     return L;
 }
 
-// The blocks of one active slot.  In each iteration a thread serves a single active slot in both
-// phases (slot t mod A, rows t div A, + R, + 2R, ... with R = NT div A), so the slot's block
-// addresses are computed once per iteration rather than once per work item.
+// The blocks of one active slot.  In each iteration a thread serves a single active slot per
+// phase (fault phase: slot t mod A, rows t div A, + R, + 2R, ... with R = NT div A; check phase:
+// the same over wavefronts 1.., with t - 64 and NT - 64), so the slot's block addresses are
+// computed once per iteration rather than once per work item.
 struct SlotView {
     float *msg;           // messages, one per edge (q after the fault phase, r after the check phase)
     float *Lv;            // posteriors
@@ -380,11 +381,19 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
     int q_sz = C;    // shots asked for by that request
     int q_seen = qb0 >= 0 ? qb0 : args.B;  // base of the latest chunk landed here (queue position)
     int my_shot = -1, my_it = 0;
+    // the check phase's rows and slot (wavefronts 1..), kept from one loop pass to the next
+    int rc0 = 1 << 30, Rc = NT;
+    SlotView Vc;
+    Vc.msg = L.msg;
+    Vc.synw = L.synw;
 
     for (;;) {
         // ---- slot management (wavefront 0, one lane per slot): test convergence (parity of the
         // last hard decision against the syndrome), retire converged or exhausted shots, give
         // free slots the next staged shots, list the active slots, keep the queue pipeline full.
+        // Meanwhile wavefronts 1.. run the check phase of the iteration whose fault phase just
+        // ended: slot management needs only that fault phase's parity words, and the check phase
+        // reads no word that slot management writes (its slot's blocks are in registers).
         if (wave == 0) {
             const bool valid = lane < S;
             int shot = valid ? my_shot : -1;
@@ -518,12 +527,19 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
                 L.ctl[7] = ldc;
                 L.ctl[8] = ldbuf;
             }
+        } else {
+            // ---- check phase: min-sum messages, one item per thread at a time
+            for (int i = rc0; i < m; i += Rc) {
+                CheckItem<MAXRW, REG> it;
+                it.load(L, Vc, i);
+                it.store(L, Vc, alpha, pinf, ninf);
+            }
         }
         __syncthreads();
         const int nret = L.ctl[0], nfresh = L.ctl[1], A = L.ctl[2], nunsolved = L.ctl[3];
         const int ldb = L.ctl[6], ldc = L.ctl[7], ldbuf = L.ctl[8];
         const bool pending = L.ctl[5] != 0;
-        // this thread's active slot for both phases of the iteration: t = r0 * A + a with
+        // this thread's active slot for the fault phase of the iteration: t = r0 * A + a with
         // r0 < Rs = NT div A (the division by reciprocal is exact for t < 256, A <= 128); the
         // NT mod A threads past Rs * A serve no slot
         int r0 = 1 << 30, Rs = NT;
@@ -544,6 +560,24 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
             V.Lv = L.Lv + k * L.SN;
             V.parw = L.parw + k * PW;
             V.synw = L.synw + k * PW;
+        }
+        // the same for the check phase, over wavefronts 1.. (tc = t - 64 = rc0 * A + a)
+        {
+            int a = 0;
+            rc0 = 1 << 30;
+            Rc = NT - 64;
+            if (A > 0 && wave > 0) {
+                const float rA = __builtin_amdgcn_rcpf((float)A);
+                Rc = (int)(((float)(NT - 64) + 0.5f) * rA);
+                const int q = (int)(((float)(t - 64) + 0.5f) * rA);
+                if (q < Rc) {
+                    rc0 = q;
+                    a = (t - 64) - q * A;
+                }
+            }
+            const int k = L.act[a];
+            Vc.msg = L.msg + k * L.SE;
+            Vc.synw = L.synw + k * PW;
         }
 
         // ---- outputs of retired shots (coalesced rows), staging of the next chunk, and the
@@ -645,14 +679,7 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
             }
         }
         __syncthreads();
-
-        // ---- check phase: min-sum messages, one item per thread at a time
-        for (int i = r0; i < m; i += Rs) {
-            CheckItem<MAXRW, REG> it;
-            it.load(L, V, i);
-            it.store(L, V, alpha, pinf, ninf);
-        }
-        __syncthreads();
+        // (the check phase of this iteration runs at the top of the next pass)
     }
 
     if constexpr (LSDW > 0) {
