@@ -690,7 +690,7 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
         __builtin_amdgcn_s_setprio(0);
         constexpr int K = 64 * LSDW;
         unsigned char *lbase = smem + tables_bytes(m, n, E, REG) + (size_t)wave * f.lsd.wave_bytes;
-        const LsdLds S2 = carve_lsd(lbase, m, n, K, f.lsd.keys_in_lds != 0);
+        const LsdLds S2 = carve_lsd(lbase, m, n, K, f.lsd.keys_in_lds != 0, false);  // LSD-0 only
         GView<true> gv;
         gv.rp = L.rp; gv.ci = L.ci; gv.cp = L.cp; gv.ri = L.ri;
         gv.max_cw = args.g.max_cw;

@@ -80,8 +80,9 @@ struct FuseArgs {
 // LDS carve sizes (bytes) shared by host (launch config) and device.
 size_t bp_lds_bytes(const DevGraph &g, int S);
 size_t bp_graph_lds_bytes(const DevGraph &g);
-size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds);
-size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds);
+// with_mu: the decoder runs LSD-mu (order > 0) and needs the LSD-mu arrays
+size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu);
+size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds, bool with_mu);
 
 hipError_t launch_zero(int *p, int count, hipStream_t st);
 hipError_t launch_fill(int *p, int count, int value, hipStream_t st);

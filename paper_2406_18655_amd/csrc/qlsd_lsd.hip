@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
         g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
     }
     unsigned char *base = smem + gbytes + (size_t)wid * A.wave_bytes;
-    const LsdLds S = carve_lsd(base, m, n, K, A.keys_in_lds != 0);
+    const LsdLds S = carve_lsd(base, m, n, K, A.keys_in_lds != 0, A.mu > 0);
 
     const int total = A.list ? *A.list_count : A.count;
     for (;;) {
@@ -105,14 +105,14 @@ hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hip
     return hipGetLastError();
 }
 
-size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds) {
+size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu) {
     size_t offs[kLsdLayoutEntries];
-    return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, offs);
+    return lsd_layout(g.m, g.n, 64 * W, keys_in_lds, with_mu, offs);
 }
 
-size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds) {
+size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds, bool with_mu) {
     return (graph_in_lds ? lsd_graph_bytes(g.m, g.n, g.nnz) : 0) +
-           lsd_wave_bytes(g, W, keys_in_lds) * (kLsdThreads / 64);
+           lsd_wave_bytes(g, W, keys_in_lds, with_mu) * (kLsdThreads / 64);
 }
 
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st) {

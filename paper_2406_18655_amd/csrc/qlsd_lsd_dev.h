@@ -102,20 +102,22 @@ constexpr int kLsdLayoutEntries = 19;
 // their offsets from the wavefront's block are constants the compiler folds into the LDS
 // instructions (no register per array); 8-byte arrays before 4-byte ones before bytes keeps every
 // array aligned.  The arrays sized by m and n follow.  offs[] keeps the field order of LsdLds.
-__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, size_t *offs) {
+// with_mu: room for the LSD-mu arrays (wq, zk, tw, colNP, tsel); LSD-0 never touches them.
+__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, bool with_mu, size_t *offs) {
+    const size_t mu = with_mu ? 1 : 0;
     size_t off = 0;
     offs[1] = off; off += sizeof(uint64_t) * K;                      // sel
     offs[2] = off; off += sizeof(uint64_t) * K;                      // lkey
     offs[17] = off; off += sizeof(uint64_t) * K;                     // cand
-    offs[13] = off; off += sizeof(int64_t) * K;                      // wq
-    offs[14] = off; off += sizeof(uint64_t) * kMaxMu * (K / 64);     // zk
-    offs[16] = off; off += sizeof(int64_t) * kMaxMu;                 // tw
+    offs[13] = off; off += mu * sizeof(int64_t) * K;                 // wq
+    offs[14] = off; off += mu * sizeof(uint64_t) * kMaxMu * (K / 64);// zk
+    offs[16] = off; off += mu * sizeof(int64_t) * kMaxMu;            // tw
     offs[3] = off; off += sizeof(int32_t) * K;                       // lroot
     offs[4] = off; off += sizeof(int32_t) * K;                       // colAt
     offs[5] = off; off += sizeof(int32_t) * K;                       // croot
     offs[6] = off; off += sizeof(int32_t) * K;                       // rowOf
-    offs[12] = off; off += sizeof(int32_t) * K;                      // colNP
-    offs[15] = off; off += sizeof(int32_t) * kMaxMu;                 // tsel
+    offs[12] = off; off += mu * sizeof(int32_t) * K;                 // colNP
+    offs[15] = off; off += mu * sizeof(int32_t) * kMaxMu;            // tsel
     offs[11] = off; off += sizeof(int32_t) * 4;                      // ctl
     offs[10] = off; off += align8(K);                                // state
     offs[0] = off; off += keys_in_lds ? sizeof(uint32_t) * n : 0;    // keys
@@ -816,9 +818,9 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
 }
 
 // Per-wavefront LDS block of decode_shot (lsd_layout order) at `base`.
-__device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, bool keys_in_lds) {
+__device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, bool keys_in_lds, bool with_mu) {
     size_t offs[kLsdLayoutEntries];
-    lsd_layout(m, n, K, keys_in_lds, offs);
+    lsd_layout(m, n, K, keys_in_lds, with_mu, offs);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
     S.sel = (uint64_t *)(base + offs[1]);
