@@ -28,8 +28,10 @@ namespace qlsd {
 
 namespace {
 
+// At most 128 VGPRs (4 wavefronts per SIMD) for W <= 2, 256 (2 per SIMD) for W = 4.
 template <int W, bool GL>
-__global__ __launch_bounds__(kLsdThreads) void lsd_kernel(LsdArgs A) {
+__global__ __launch_bounds__(kLsdThreads) __attribute__((amdgpu_waves_per_eu(W <= 2 ? 4 : 2)))
+void lsd_kernel(LsdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int K = 64 * W;

@@ -415,6 +415,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     }
     for (int w = lane; w < (n + 31) / 32; w += 64) { S.incol[w] = 0u; S.cbit[w] = 0u; }
     for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
+    for (int r = lane; r < K; r += 64) S.lroot[r] = -1;  // validity stamps of an earlier shot
     wave_sync();
 
     // the correction row from the bit vector, written once on every exit
@@ -736,38 +737,33 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         wave_sync();
 
         // (5) validity: a cluster is valid iff its reduced syndrome vanishes.  Every row points at
-        // its root here; per root (not frozen), a ballot over the rows tells whether one of its
-        // rows keeps a reduced-syndrome bit, so the states are written once without a second pass.
+        // its root here.  Each row that keeps a reduced-syndrome bit stamps its root's entry of
+        // the selection-root array (free at this point) with K + rounds, which no entry written
+        // this shot holds otherwise (the array is cleared per shot and else holds roots < K);
+        // after a sync each root reads its own entry, and the states are written once.
+        int32_t *vmark = S.lroot;
+        const int stamp = K + rounds;
         int crv[W];
-        uint64_t rootm[W], livem[W];
+        uint8_t stv[W];
 #pragma unroll
         for (int s = 0; s < W; s++) {
             const int r = s * 64 + lane;
             crv[s] = S.croot[r];
-            const uint8_t st = S.state[r];
-            const bool isroot = r < nrows && crv[s] == r;
-            rootm[s] = ballot(isroot && st != kFrozen);
-            livem[s] = ballot(r < nrows) & B.sp[s];  // rows with a reduced-syndrome bit
+            stv[s] = S.state[r];
+            if (r < nrows && ((B.sp[s] >> lane) & 1ull)) vmark[crv[s]] = stamp;
         }
-        uint64_t invm[W];
-        bool any_inv = false;
+        wave_sync();
+        bool inv_mine = false;
 #pragma unroll
-        for (int s0 = 0; s0 < W; s0++) {
-            invm[s0] = 0;
-            uint64_t rm = rootm[s0];
-            while (rm) {
-                const int c = s0 * 64 + __builtin_ctzll(rm);
-                rm &= rm - 1;
-                uint64_t hit = 0;
-#pragma unroll
-                for (int s = 0; s < W; s++) hit |= ballot(crv[s] == c) & livem[s];
-                if (hit) invm[s0] |= 1ull << (c & 63);
+        for (int s = 0; s < W; s++) {
+            const int r = s * 64 + lane;
+            if (r < nrows && crv[s] == r && stv[s] != kFrozen) {
+                const bool inv = vmark[r] == stamp;
+                S.state[r] = inv ? kInvalid : kValid;
+                inv_mine |= inv;
             }
-            any_inv |= invm[s0] != 0;
         }
-#pragma unroll
-        for (int s = 0; s < W; s++)
-            if ((rootm[s] >> lane) & 1ull) S.state[s * 64 + lane] = ((invm[s] >> lane) & 1ull) ? kInvalid : kValid;
+        const bool any_inv = ballot(inv_mine) != 0ull;
         wave_sync();
         rounds++;
         if (grow_all) {
