@@ -704,7 +704,7 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
             const int h = __builtin_amdgcn_readfirstlane(r.y);
             if (shot < 0) break;  // no entry h, or it is left to the stand-alone launch (the call
                                   // that returned it has marked the previous shot done)
-            decode_shot<LSDW>(f.lsd, S2, gv, shot, lane);
+            decode_shot<LSDW, false>(f.lsd, S2, gv, shot, lane);  // LSD-0 only
             wave_sync();
             done_h = h;
             done_shot = shot;

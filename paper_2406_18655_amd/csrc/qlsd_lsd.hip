@@ -29,7 +29,7 @@ namespace qlsd {
 namespace {
 
 // At most 128 VGPRs (4 wavefronts per SIMD) for W <= 2, 256 (2 per SIMD) for W = 4.
-template <int W, bool GL>
+template <int W, bool GL, bool MU>
 __global__ __launch_bounds__(kLsdThreads) __attribute__((amdgpu_waves_per_eu(W <= 2 ? 4 : 2)))
 void lsd_kernel(LsdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -65,25 +65,25 @@ void lsd_kernel(LsdArgs A) {
         if (item >= total) break;
         const int shot = A.list ? A.list[item] : item;
         if (A.skip_done && shot < 0) continue;
-        decode_shot<W>(A, S, g, shot, lane);
+        decode_shot<W, MU>(A, S, g, shot, lane);
         wave_sync();
     }
 }
 
-template <int W>
+template <int W, bool MU>
 hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
     const size_t lds = (a.graph_in_lds ? lsd_graph_bytes(a.g.m, a.g.n, a.g.nnz) : 0) +
                        (size_t)a.wave_bytes * (kLsdThreads / 64);
     if (a.graph_in_lds) {
-        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, true>,
+        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, true, MU>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((lsd_kernel<W, true>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+        hipLaunchKernelGGL((lsd_kernel<W, true, MU>), dim3(grid), dim3(kLsdThreads), lds, st, a);
     } else {
-        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, false>,
+        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, false, MU>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((lsd_kernel<W, false>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+        hipLaunchKernelGGL((lsd_kernel<W, false, MU>), dim3(grid), dim3(kLsdThreads), lds, st, a);
     }
     return hipGetLastError();
 }
@@ -117,11 +117,14 @@ size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_l
            lsd_wave_bytes(g, W, keys_in_lds, with_mu) * (kLsdThreads / 64);
 }
 
+// LSD-mu decoders always use W = 4 (their extra growth rounds need the room), so LSD-mu code is
+// instantiated for W = 4 only.
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st) {
+    if (a.mu > 0) return W == 4 ? launch_lsd_w<4, true>(a, grid, st) : hipErrorInvalidValue;
     switch (W) {
-        case 1: return launch_lsd_w<1>(a, grid, st);
-        case 2: return launch_lsd_w<2>(a, grid, st);
-        case 4: return launch_lsd_w<4>(a, grid, st);
+        case 1: return launch_lsd_w<1, false>(a, grid, st);
+        case 2: return launch_lsd_w<2, false>(a, grid, st);
+        case 4: return launch_lsd_w<4, false>(a, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

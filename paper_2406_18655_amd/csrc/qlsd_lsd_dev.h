@@ -392,7 +392,9 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
     }
 }
 
-template <int W, class G>
+// MU: the decoder runs LSD-mu (A.mu > 0); decoders without it get no LSD-mu code at all, which
+// leaves the register allocator more room in the LSD-0 rounds.
+template <int W, bool MU, class G>
 __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane) {
     constexpr int K = 64 * W;
     const int m = A.g.m, n = A.g.n;
@@ -589,7 +591,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         if (ballot(status & QLSD_ST_UNSAT)) status |= QLSD_ST_UNSAT;
         wave_sync();
         if (nsel == 0) {
-            if (!grow_all && A.mu > 0) {  // every invalid cluster is frozen; valid ones may still grow
+            if (MU && !grow_all && A.mu > 0) {  // every invalid cluster is frozen; valid ones may still grow
                 grow_all = true;
                 mu_left = A.mu;
                 continue;
@@ -728,7 +730,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 cwc = __builtin_amdgcn_readfirstlane(cwc);
                 if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
                 const bool pivot = insert_column<W>(B, S, col, lane, lr_src, base, cwc);
-                if (!pivot && A.mu > 0) {
+                if (MU && !pivot && A.mu > 0) {
                     if (lane == 0 && npc < K) S.colNP[npc] = col;
                     npc++;
                 }
@@ -771,7 +773,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             continue;
         }
         if (!any_inv) {
-            if (A.mu <= 0) break;
+            if (!MU || A.mu <= 0) break;
             grow_all = true;
             mu_left = A.mu;
         }
@@ -795,7 +797,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         ncl += __popcll(ballot(is_root));
         x0[s] = ballot(((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as));
     }
-    if (A.mu <= 0) {
+    if (!MU || A.mu <= 0) {
 #pragma unroll
         for (int s = 0; s < W; s++) {
             if ((x0[s] >> lane) & 1ull) {
@@ -808,7 +810,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         finish(status, ncl, 0);
         return;
     }
-    osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, lane);
+    if constexpr (MU) osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, lane);
     write_row();
     finish(status, ncl, 0);
 }
