@@ -538,21 +538,23 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                         const int d = S.rowOf[r];
                         best = ~0ull;
                         const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
-                        // eight entries per pass, every load issued before any is used (entries
+                        // kScan entries per pass, every load issued before any is used (entries
                         // past the row's end re-read its last one and are masked out), so a row of
-                        // weight <= 8 costs two dependent rounds of loads
-                        for (int eb = e0; eb < e1; eb += 8) {
-                            int jj[8];
+                        // weight <= kScan costs two dependent rounds of loads (6 fits the small
+                        // codes' rows without masked slots; the large graphs' rows are longer)
+                        constexpr int kScan = W <= 2 ? 6 : 8;
+                        for (int eb = e0; eb < e1; eb += kScan) {
+                            int jj[kScan];
 #pragma unroll
-                            for (int u = 0; u < 8; u++) jj[u] = g.col_idx(min(eb + u, e1 - 1));
-                            uint32_t kk[8], ic[8];
+                            for (int u = 0; u < kScan; u++) jj[u] = g.col_idx(min(eb + u, e1 - 1));
+                            uint32_t kk[kScan], ic[kScan];
 #pragma unroll
-                            for (int u = 0; u < 8; u++) {
+                            for (int u = 0; u < kScan; u++) {
                                 kk[u] = A.keys_in_lds ? S.keys[jj[u]] : ordered_key(llr[jj[u]]);
                                 ic[u] = S.incol[jj[u] >> 5];
                             }
 #pragma unroll
-                            for (int u = 0; u < 8; u++) {
+                            for (int u = 0; u < kScan; u++) {
                                 const bool ok = eb + u < e1 && !((ic[u] >> (jj[u] & 31)) & 1u);
                                 const uint64_t key = ok ? (((uint64_t)kk[u] << 32) | (uint32_t)jj[u]) : ~0ull;
                                 best = key < best ? key : best;
