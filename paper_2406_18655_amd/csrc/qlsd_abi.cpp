@@ -250,7 +250,9 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     if (params->lsd_order > 0) W = 4;  // extra growth steps: room for 256 clustered checks
     d->lsd_W = W;
     d->lsd_keys_in_lds = (size_t)g.n * 4 <= 16384;
-    d->lsd_graph_in_lds = (2 * (size_t)g.nnz + g.m + g.n + 2) * 2 <= 24576 && g.n < 65536 && g.m < 65536;
+    // the graph goes to LDS only with the keys (the LSD kernel then reads keys from LDS without a test)
+    d->lsd_graph_in_lds = (2 * (size_t)g.nnz + g.m + g.n + 2) * 2 <= 24576 && g.n < 65536 && g.m < 65536 &&
+                          d->lsd_keys_in_lds;
     const bool with_mu = params->lsd_order > 0;
     d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0, with_mu);
     if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0, with_mu) > kLdsPerCu - 1024) {

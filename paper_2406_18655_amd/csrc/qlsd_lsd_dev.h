@@ -55,6 +55,7 @@ __device__ __forceinline__ uint32_t ordered_key(float x) {
 // arrays in global memory.
 template <bool InLds>
 struct GView {
+    static constexpr bool kInLds = InLds;  // graph in LDS implies keys in LDS (the host's placement rule)
     using T = typename std::conditional<InLds, uint16_t, int32_t>::type;
     const T *rp, *ci, *cp, *ri;
     int max_cw;
@@ -312,7 +313,7 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                     const int col = S.colNP[u * 64 + lane];
                     const int rr = S.loc[g.row_idx(g.col_ptr(col))];
                     if (S.croot[rr] != c) continue;
-                    const uint32_t kj = A.keys_in_lds ? S.keys[col] : ordered_key(llr[col]);
+                    const uint32_t kj = (G::kInLds || A.keys_in_lds) ? S.keys[col] : ordered_key(llr[col]);
                     const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)col;
                     mine = key < mine ? key : mine;
                 }
@@ -404,7 +405,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
 
     // the syndrome of the first detectors is loaded together with the LLRs (one memory round trip
     // before the seeds; the rest, if m > 256, is read where it is used)
-    constexpr int kSynPre = 4;
+    constexpr int kSynPre = W < 4 ? W : 4;  // chunks of 64 detectors (m <= 64 W for W < 4)
     uint8_t sy[kSynPre];
 #pragma unroll
     for (int q = 0; q < kSynPre; q++) sy[q] = q * 64 + lane < m ? syn[q * 64 + lane] : 0;
@@ -413,7 +414,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         // coherent read: an equal compare-and-swap returns the word at the point of coherence
         const float v = A.coherent_llr ? __int_as_float(atomicCAS((int *)llr + j, 0, 0)) : llr[j];
         nan |= (v != v);
-        if (A.keys_in_lds) S.keys[j] = ordered_key(v);
+        if (G::kInLds || A.keys_in_lds) S.keys[j] = ordered_key(v);
     }
     for (int w = lane; w < (n + 31) / 32; w += 64) { S.incol[w] = 0u; S.cbit[w] = 0u; }
     for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
@@ -550,7 +551,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                             uint32_t kk[kScan], ic[kScan];
 #pragma unroll
                             for (int u = 0; u < kScan; u++) {
-                                kk[u] = A.keys_in_lds ? S.keys[jj[u]] : ordered_key(llr[jj[u]]);
+                                kk[u] = (G::kInLds || A.keys_in_lds) ? S.keys[jj[u]] : ordered_key(llr[jj[u]]);
                                 ic[u] = S.incol[jj[u] >> 5];
                             }
 #pragma unroll
