@@ -532,7 +532,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const uint32_t bc = (uint32_t)best;
             const uint32_t inc = S.incol[(bc < (uint32_t)n ? bc : 0u) >> 5];
             const uint8_t st = S.state[c];
-            const bool grow = valid && (grow_all ? st != kFrozen : st == kInvalid);
+            const bool grow = valid && ((MU && grow_all) ? st != kFrozen : st == kInvalid);
             {
                 {
                     if (grow && (best == kStale || (best != ~0ull && ((inc >> (bc & 31)) & 1u)))) {
@@ -577,7 +577,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const int cr = S.croot[r];
             const uint8_t st = S.state[r];
             const uint64_t key = S.sel[r];
-            const bool growing = r < nrows && cr == r && (grow_all ? st != kFrozen : st == kInvalid);
+            const bool growing = r < nrows && cr == r && ((MU && grow_all) ? st != kFrozen : st == kInvalid);
             const bool take = growing && key != ~0ull;
             if (growing && key == ~0ull && st == kInvalid) {
                 S.state[r] = kFrozen;
@@ -665,7 +665,13 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 if (r < nrows_new) S.croot[r] = find_root(S.croot, r);
             }
         }
-        for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
+        // release this round's claims: with at most 64 pairs each pair's lane holds its detector
+        // (detectors clustered before the round were never claimed: writing kFree is a no-op)
+        if (npairs <= 64) {
+            if (has0) S.claimer[d0] = kFree;
+        } else {
+            for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
+        }
         nrows = nrows_new;
         wave_sync();
 
@@ -771,7 +777,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         const bool any_inv = ballot(inv_mine) != 0ull;
         wave_sync();
         rounds++;
-        if (grow_all) {
+        if (MU && grow_all) {
             if (--mu_left == 0) break;
             continue;
         }
