@@ -294,12 +294,18 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
             "shots_scored": int(f.size)}
 
 
-def _kernel_hash():
+def _kernel_hash(root=None):
+    """Hash of the fused kernel's sources with comments and whitespace removed: the stored HBM
+    traffic stays valid across comment-only edits and is dropped when the code changes."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("qlsd_bp.hip", "qlsd_internal.h", "qlsd_lsd_dev.h"):
-        with open(os.path.join(HERE, "paper_2406_18655_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(root or HERE, "paper_2406_18655_amd", "csrc", f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

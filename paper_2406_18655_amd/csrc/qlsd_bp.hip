@@ -98,9 +98,9 @@ struct SlotView {
 
 // Fault (variable-node) update of fault j in one active slot: posterior, exclusive sums, and
 // the hard decision's contribution to every check's parity.  A fresh slot's messages were zeroed
-// when its shot arrived, so its first pass reads q = lambda like any other.  REG: every column
-// has exactly CW = 3 edges, and one 16-byte read of the packed fault record gives the edge ids,
-// check indices and prior.
+// when its shot arrived, so in its first pass the incoming check messages are zero and the
+// posterior is the prior, with no special case.  REG: every column has exactly CW = 3 edges, and
+// one 16-byte read of the packed fault record gives the edge ids, check keys and prior.
 template <int CW, bool REG>
 struct FaultItem {
     static_assert(!REG || CW == 3, "the packed fault record describes 3 edges");
