@@ -365,8 +365,7 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     hipStream_t s = (hipStream_t)stream;
     const int fw = fuse_waves(d);
     if (fw > 0) {
-        HIP_OK(launch_fill(d->d_list, B, -1, s));
-        HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
+        HIP_OK(launch_fill2(d->d_list, B, -1, d->d_ctl, kCtlWords, 0, s));
         BpArgs a = bp_args(d, syndromes, B);
         a.corr = corrections;
         a.llr_lsd = d->d_llr;

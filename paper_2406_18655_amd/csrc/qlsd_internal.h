@@ -86,6 +86,7 @@ size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_l
 
 hipError_t launch_zero(int *p, int count, hipStream_t st);
 hipError_t launch_fill(int *p, int count, int value, hipStream_t st);
+hipError_t launch_fill2(int *p1, int n1, int v1, int *p2, int n2, int v2, hipStream_t st);
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st);        // S slots per workgroup
 hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st);
 size_t bp_tables_bytes(const DevGraph &g);  // graph tables (u16 copies of H) at the start of the BP LDS block
