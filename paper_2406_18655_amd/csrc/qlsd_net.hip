@@ -448,14 +448,21 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
 // the maximum degree with a zero sentinel row.  Compared with forward_shot (the training
 // forward) the means are not rounded to bf16 before the product; everything else matches.
 // ------------------------------------------------------------------------------------------
-constexpr int kInferWaves = 5;
+constexpr int kInferWavesMax = 11;  // one workgroup of up to 11 wavefronts per CU, else 5 (two per CU)
 
 __host__ __device__ inline size_t infer_shared_bytes(int n, int m, int dr, int dc) {
     return al16(sizeof(float) * SV_N) + al16(sizeof(uint16_t) * ((size_t)pad16(m) * dr + (size_t)pad16(n) * dc)) +
            al16(sizeof(float) * ((size_t)pad16(m) + pad16(n) + n));
 }
-__host__ __device__ inline size_t infer_wave_bytes(int n, int m) {
-    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID) + al16(sizeof(float) * (size_t)m);
+// Per wavefront: fault and check feature rows (bf16 x 32 each), plus one zero sentinel row each
+// for the padding of irregular neighbour lists (a code with every row and every column of full
+// weight pads nothing but its 16-row tiles, whose results are discarded), and one signed byte
+// per check for the syndrome sign.
+__host__ __device__ inline bool infer_regular(const DevGraph &g) {
+    return g.min_rw == g.max_rw && g.min_cw == g.max_cw;
+}
+__host__ __device__ inline size_t infer_wave_bytes(int n, int m, bool regular) {
+    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + pad16(m) + (regular ? 0 : 2)) * HID) + al16((size_t)m);
 }
 
 // Feature rows are 64 B (32 bf16 = 8 chunks of 4).  Chunk c of node v is stored at chunk
@@ -475,7 +482,7 @@ __device__ __forceinline__ int pair_off(int node, int q2, bool &swap) {
 }
 
 template <int DR, int DC>
-__global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) {
+__global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
     const int n = A.g.n, m = A.g.m, NP = pad16(n), MP = pad16(m);
@@ -485,10 +492,13 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
     uint16_t *nbf = nbc + (size_t)MP * dr;                             // [NP][dc] byte offsets into C
     float *rdc = (float *)((unsigned char *)nbc + al16(sizeof(uint16_t) * ((size_t)MP * dr + (size_t)NP * dc)));
     float *rdf = rdc + MP, *lam = rdf + NP;
-    unsigned char *wbase = smem + infer_shared_bytes(n, m, dr, dc) + (size_t)wave * infer_wave_bytes(n, m);
-    uint16_t *H = (uint16_t *)wbase;                 // (NP + 1) x 32, row NP is zero
-    uint16_t *Cf = H + (size_t)(NP + 1) * HID;       // (MP + 1) x 32, row MP is zero
-    float *sg = (float *)(wbase + al16(sizeof(uint16_t) * ((size_t)NP + 1 + MP + 1) * HID));  // +-1 per check
+    const bool reg = infer_regular(A.g);
+    const int nwav = blockDim.x >> 6;
+    unsigned char *wbase = smem + infer_shared_bytes(n, m, dr, dc) + (size_t)wave * infer_wave_bytes(n, m, reg);
+    const int sent = reg ? 0 : 1;                    // sentinel rows present
+    uint16_t *H = (uint16_t *)wbase;                 // (NP + sent) x 32, row NP (if present) is zero
+    uint16_t *Cf = H + (size_t)(NP + sent) * HID;    // (MP + sent) x 32, row MP (if present) is zero
+    int8_t *sg = (int8_t *)(wbase + al16(sizeof(uint16_t) * ((size_t)NP + MP + 2 * sent) * HID));  // +-1 per check
     unsigned char *Hb = (unsigned char *)H, *Cb = (unsigned char *)Cf;
 
     for (int x = t; x < SV_N; x += blockDim.x) {
@@ -503,7 +513,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
     }
     for (int x = t; x < MP * dr; x += blockDim.x) {
         const int i = x / dr, k = x - i * dr;
-        int off = NP * HID * 2;
+        int off = sent * NP * HID * 2;
         if (i < m) {
             const int e0 = A.g.row_ptr[i], e1 = A.g.row_ptr[i + 1];
             if (e0 + k < e1) off = A.g.col_idx[e0 + k] * HID * 2;
@@ -512,7 +522,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
     }
     for (int x = t; x < NP * dc; x += blockDim.x) {
         const int j = x / dc, k = x - j * dc;
-        int off = MP * HID * 2;
+        int off = sent * MP * HID * 2;
         if (j < n) {
             const int c0 = A.g.col_ptr[j], c1 = A.g.col_ptr[j + 1];
             if (c0 + k < c1) off = A.g.row_idx[c0 + k] * HID * 2;
@@ -529,7 +539,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
         if (x < n) lam[x] = A.lam[x];
     }
     // sentinel rows (never written again)
-    if (lane < 16) {
+    if (sent && lane < 16) {
         ((uint32_t *)(H + (size_t)NP * HID))[lane] = 0u;
         ((uint32_t *)(Cf + (size_t)MP * HID))[lane] = 0u;
     }
@@ -553,11 +563,11 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
     }
 
     const int total = A.list ? *A.list_count : A.count;
-    for (int item = blockIdx.x * kInferWaves + wave; item < total; item += gridDim.x * kInferWaves) {
+    for (int item = blockIdx.x * nwav + wave; item < total; item += gridDim.x * nwav) {
         const int shot = A.list ? A.list[item] : item;
         const uint8_t *syn = A.syn + (size_t)shot * m;
         const float *llr = A.llr + (size_t)shot * n;
-        for (int i = lane; i < m; i += 64) sg[i] = (syn[i] & 1) ? -1.f : 1.f;
+        for (int i = lane; i < m; i += 64) sg[i] = (syn[i] & 1) ? -1 : 1;
         // input layer: lane j computes tanh once and writes its fault's 32 features (4 x 16 B)
         for (int j = lane; j < NP; j += 64) {
             float x0 = 0.f, x1 = 0.f;
@@ -599,7 +609,7 @@ __global__ __launch_bounds__(64 * kInferWaves) void net_infer_kernel(NetArgs A) 
                         acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][1][ot], x1, acc[ot], 0, 0, 0);
                     }
                 }
-                const float rd = rdc[i], sgn = i < m ? sg[i] : 0.f;
+                const float rd = rdc[i], sgn = i < m ? (float)sg[i] : 0.f;
 #pragma unroll
                 for (int ot = 0; ot < 2; ot++) {
                     const float4v av = *(const float4v *)(sv + SV_A + l * HID + ot * 16 + kq);
@@ -939,8 +949,15 @@ static size_t net_act_bytes(const DevGraph &g, bool train) {
 }
 size_t net_lds_bytes(const DevGraph &g, bool train) { return net_shared_bytes(g, train) + net_act_bytes(g, train); }
 
+// Wavefronts per inference workgroup: 11 in one workgroup when they fit in a CU's 160 KB of LDS
+// (11 wavefronts need 170 VGPRs or fewer: three per SIMD), else 5 (two workgroups per CU).
+static int infer_waves(const DevGraph &g) {
+    const size_t sh = infer_shared_bytes(g.n, g.m, g.max_rw, g.max_cw), w = infer_wave_bytes(g.n, g.m, infer_regular(g));
+    return sh + (size_t)kInferWavesMax * w <= 160 * 1024 ? kInferWavesMax : 5;
+}
 static size_t infer_lds_bytes(const DevGraph &g) {
-    return infer_shared_bytes(g.n, g.m, g.max_rw, g.max_cw) + kInferWaves * infer_wave_bytes(g.n, g.m);
+    return infer_shared_bytes(g.n, g.m, g.max_rw, g.max_cw) +
+           (size_t)infer_waves(g) * infer_wave_bytes(g.n, g.m, infer_regular(g));
 }
 
 // Inference launch: grid sized for the device, one wavefront per shot; the neighbour loops are
@@ -952,9 +969,10 @@ static hipError_t launch_infer_t(const NetArgs &a, int max_items, int num_cus, h
     hipError_t e = hipFuncSetAttribute((const void *)net_infer_kernel<UR, UF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    const int nw = infer_waves(a.g);
     const int per_cu = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int grid = std::max(1, std::min((max_items + kInferWaves - 1) / kInferWaves, num_cus * per_cu));
-    hipLaunchKernelGGL((net_infer_kernel<UR, UF>), dim3(grid), dim3(64 * kInferWaves), lds, st, a);
+    const int grid = std::max(1, std::min((max_items + nw - 1) / nw, num_cus * per_cu));
+    hipLaunchKernelGGL((net_infer_kernel<UR, UF>), dim3(grid), dim3(64 * nw), lds, st, a);
     return hipGetLastError();
 }
 static hipError_t launch_infer(const NetArgs &a, int max_items, int num_cus, hipStream_t st) {
@@ -1081,7 +1099,7 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
     }
     net->num_cus = prop.multiProcessorCount;
     // wave-per-shot inference needs u16 byte offsets of feature rows (64 B each) and LDS room
-    net->wave_infer = pad16(g.n) + 1 <= 1023 && pad16(g.m) + 1 <= 1023 && infer_lds_bytes(g) <= 159 * 1024;
+    net->wave_infer = pad16(g.n) + 1 <= 1023 && pad16(g.m) + 1 <= 1023 && infer_lds_bytes(g) <= 160 * 1024;
     if (net_lds_bytes(g, true) > 159 * 1024) {  // training activations in a device workspace (allocated at first use)
         net->act_stride = (net_act_bytes(g, true) + 255) & ~size_t(255);
         net->act_slices = net->num_cus;
