@@ -264,8 +264,11 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     net = binding.Net(bcode, code.priors, np.load(os.path.join(wdir, wname)))
     dec = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
     binding.attach_net(dec, net)
-    if args.tune:
-        dec.tune(batches[0][1], reps=3)
+    tuning = None
+    if args.tune or args.workload != "dem":
+        # BP with the learned form's budget (10 iterations) retires shots sooner than plain's 50,
+        # so the autotuner picks its BP launch shape (at 50 it keeps the default the plain leg uses)
+        tuning = [l for l in dec.tune(batches[0][1], reps=3).splitlines() if "chosen" in l]
     f, rate, ms, lat = _score_and_time(code, dec, batches, args.steps, args.warmup, "learned")
     out = {"weights": wname, "bp_max_iter": args.learned_iter, "value": round(rate, 1),
            "unit": "shots/s", "ms_per_step": round(ms, 4),
@@ -273,7 +276,7 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
                           "p99": round(float(np.percentile(lat, 99)), 4)},
            "ler": round(float(f.mean()), 6), "ler_plain": ler_plain,
            "speedup_vs_plain": round(rate / plain_shots_per_s, 3),
-           "shots_scored": int(f.size)}
+           "shots_scored": int(f.size), "tuning": tuning}
     dec2 = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
     binding.attach_net(dec2, net)
     out["two_streams_value"] = round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1)
