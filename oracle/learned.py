@@ -24,6 +24,7 @@ Parameters are one flat float vector in the order of PARAM_LAYOUT.
 from __future__ import annotations
 
 import numpy as np
+from scipy.special import expit
 
 HID = 32
 LAYERS = 3
@@ -102,7 +103,7 @@ def loss_and_grad(theta, H, L, lam, s, e):
     e = np.asarray(e, np.float64)
     loss = float(np.mean(np.logaddexp(0.0, -Lp) + e * Lp))
     # d loss / d L'_j = (e_j - sigmoid(-L'_j)) / n ; L' = L + Delta
-    dD = (e - 1.0 / (1.0 + np.exp(Lp))) / n
+    dD = (e - expit(-Lp)) / n
     sigma = 1.0 - 2.0 * (np.asarray(s) & 1)
     g = {k: np.zeros_like(v) for k, v in p.items()}
     g["w"] = A[f"h{LAYERS}"].T @ dD

@@ -318,3 +318,32 @@ def test_bp_lsd_vs_osd0_ler_reported(oracle_mod, capsys):
     with capsys.disabled():
         print(f"\n[BB 144 p=0.05] LER BP+LSD={f_lsd:.4f} BP+OSD0={f_osd:.4f} (2sigma={2*sig:.4f})")
     assert abs(f_lsd - f_osd) < 6 * sig + 0.01
+
+
+def test_omega_hand_computed_values(oracle_mod):
+    """omega_j = round(2^20 lambda_j), halves away from zero: values computed to 50 digits by
+    hand (decimal arithmetic), and rounding cases that truncation or round-half-even fail."""
+    g = _gold("omega_values.json")
+    for case in g["from_priors"]:
+        lam = oracle_mod.llr_from_priors(np.array([case["p"]]))
+        assert abs(lam[0] - float(case["lambda"])) <= 4e-16 * max(1.0, abs(lam[0]))
+        assert int(oracle_mod.omega_from_llr(lam)[0]) == case["omega"], case
+    for case in g["rounding"]:
+        lam = np.array([case["lambda_times_2^20"] * 2.0 ** -20])
+        assert int(oracle_mod.omega_from_llr(lam)[0]) == case["omega"], case
+
+
+def test_lsd_mu_truncated_reprocessing_worked_example(oracle_mod):
+    """w = min(mu, |T|) < |T|: only the first w dependent columns in key order are enumerated,
+    so LSD-1 misses the global minimum that LSD-2 finds (hand-derived, see the fixture)."""
+    g = _gold("lsd_mu_truncation_example.json")
+    H = np.array(g["H"], dtype=np.uint8)
+    code = oracle_mod.Code.from_dense(H)
+    s = np.array(g["syndrome"], dtype=np.uint8)
+    llr = np.array(g["llr"], dtype=np.float64)
+    om = np.array(g["omega"], dtype=np.int64)
+    for case in g["cases"]:
+        corr, st, stats = oracle_mod.lsd(code, s, llr, mu=case["mu"], omega=om)
+        assert st == 0
+        assert corr.tolist() == case["correction"], case["mu"]
+        assert (stats[0], stats[1], stats[2]) == (case["clusters"], case["max_cluster_cols"], case["rounds"])
