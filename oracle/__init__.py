@@ -51,6 +51,7 @@ def lib():
             L.oracle_lambda.argtypes = [P, I, P]
             L.oracle_omega.argtypes = [P, I, P]
             L.oracle_bp.argtypes = [P, P, P, I, D, I, P, P, P]
+            L.oracle_bp_traj.argtypes = [P, P, P, I, D, I, P, P, P, P]
             L.oracle_lsd.argtypes = [P, P, P, I, P, I, P, P]
             L.oracle_osd0.argtypes = [P, P, P, P]
             L.oracle_decode_batch.argtypes = [P, P, P, I, I, D, I, P, P, P, P, P, I]
@@ -116,6 +117,16 @@ def bp(code: Code, lam: np.ndarray, s: np.ndarray, max_iter: int, alpha: float =
     conv = lib().oracle_bp(code._h, _p(lam), _p(s), int(max_iter), float(alpha), int(early_exit),
                            _p(L), _p(hard), _p(it))
     return bool(conv), int(it[0]), L, hard
+
+
+def bp_min_magnitude(code: Code, lam: np.ndarray, s: np.ndarray, iters: int, alpha: float = 0.625) -> float:
+    """Smallest |q_{j->i}| or |L_j| over the first `iters` BP iterations (all run, no early exit).
+    A shot whose float64 trajectory comes this close to zero can take a different sign in float32."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    mm = np.zeros(1, dtype=np.float64)
+    lib().oracle_bp_traj(code._h, _p(lam), _p(s), int(iters), float(alpha), 0, None, None, None, _p(mm))
+    return float(mm[0])
 
 
 def lsd(code: Code, s: np.ndarray, llr: np.ndarray, mu: int = 0, omega: np.ndarray | None = None,

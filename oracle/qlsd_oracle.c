@@ -129,10 +129,16 @@ static double clamp64(double x) {
  * Min-sum BP with the parallel schedule.  Returns 1 if H e = s was reached.
  * With early_exit == 0 all max_iter iterations run (the return value then says
  * whether the last one satisfies the syndrome).  *iters_out = iterations run.
+ * *min_mag_out (nullable) receives the smallest |q_{j->i}| and |L_j| met over the iterations
+ * run: a float32 run cannot be expected to reproduce the sign of a value that close to zero,
+ * so shots whose trajectory passes near zero are where the two may part.  oracle_bp is the
+ * same without it.
  */
-int oracle_bp(const void *code, const double *lam, const uint8_t *s, int max_iter, double alpha,
-              int early_exit, double *L_out, uint8_t *hard_out, int32_t *iters_out) {
+int oracle_bp_traj(const void *code, const double *lam, const uint8_t *s, int max_iter, double alpha,
+                   int early_exit, double *L_out, uint8_t *hard_out, int32_t *iters_out,
+                   double *min_mag_out) {
     const ocode *c = (const ocode *)code;
+    double min_mag = INFINITY;
     int E = c->nnz;
     double *q = (double *)malloc(sizeof(double) * (E > 0 ? E : 1));
     double *r = (double *)malloc(sizeof(double) * (E > 0 ? E : 1));
@@ -161,11 +167,13 @@ int oracle_bp(const void *code, const double *lam, const uint8_t *s, int max_ite
             double tot = lam[j];
             for (int k = c->col_ptr[j]; k < c->col_ptr[j + 1]; k++) tot += r[c->col_edge[k]];
             L[j] = clamp64(tot);
+            if (fabs(L[j]) < min_mag) min_mag = fabs(L[j]);
             for (int k = c->col_ptr[j]; k < c->col_ptr[j + 1]; k++) {
                 double x = lam[j];
                 for (int k2 = c->col_ptr[j]; k2 < c->col_ptr[j + 1]; k2++)
                     if (k2 != k) x += r[c->col_edge[k2]];
                 q[c->col_edge[k]] = clamp64(x);
+                if (fabs(q[c->col_edge[k]]) < min_mag) min_mag = fabs(q[c->col_edge[k]]);
             }
             hard[j] = L[j] < 0.0 ? 1 : 0;
         }
@@ -176,8 +184,14 @@ int oracle_bp(const void *code, const double *lam, const uint8_t *s, int max_ite
     if (L_out) memcpy(L_out, L, sizeof(double) * c->n);
     if (hard_out) memcpy(hard_out, hard, c->n);
     if (iters_out) *iters_out = it;
+    if (min_mag_out) *min_mag_out = min_mag;
     free(q); free(r); free(L); free(hard);
     return conv;
+}
+
+int oracle_bp(const void *code, const double *lam, const uint8_t *s, int max_iter, double alpha,
+              int early_exit, double *L_out, uint8_t *hard_out, int32_t *iters_out) {
+    return oracle_bp_traj(code, lam, s, max_iter, alpha, early_exit, L_out, hard_out, iters_out, NULL);
 }
 
 /* ---------------------------------------------------- GF(2) elimination */

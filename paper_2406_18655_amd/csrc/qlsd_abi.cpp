@@ -76,13 +76,20 @@ struct qlsd_decoder_s {
     qlsd_net net;       // optional refinement between BP and LSD
     unsigned char *d_netws;  // feature workspace of the refinement on large graphs (else nullptr)
     size_t netws_bytes;
+    // shots whose clusters can outgrow the LSD kernel's 64 * lsd_W local rows (or, with LSD-mu,
+    // its dependent-column list) go on to the wide LSD kernel
+    bool wide;
+    int wide_grid, wide_keys_in_lds;
+    int *d_ovf_list;     // max_batch: shots the LSD kernel could not hold
+    uint64_t *d_wide_ws; // wide_grid * lsd_wide_ws_words(): the wide kernel's Gauss-Jordan bases
 };
 
 namespace qlsd {
 // Decoder counters, each on its own 128-byte line: the one-kernel path polls the list counters
 // while BP workgroups hit the queue counter, and atomics on a shared line would serialise.
-constexpr int kCtlQueue = 0, kCtlList = 32, kCtlItem = 64, kCtlBpDone = 96, kCtlItem2 = 128, kCtlLsdDone = 160;
-constexpr int kCtlWords = 192;
+constexpr int kCtlQueue = 0, kCtlList = 32, kCtlItem = 64, kCtlBpDone = 96, kCtlItem2 = 128, kCtlLsdDone = 160,
+              kCtlOvf = 192, kCtlItemW = 224;
+constexpr int kCtlWords = 256;
 void set_last_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -95,7 +102,8 @@ int code_cols(qlsd_code c) { return c->g.n; }
 size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
     return n * (sizeof(float) + sizeof(int64_t)) + kCtlWords * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
-           d->netws_bytes;
+           d->netws_bytes +
+           (d->wide ? B * sizeof(int) + (size_t)d->wide_grid * lsd_wide_ws_words() * sizeof(uint64_t) : 0);
 }
 }  // namespace qlsd
 
@@ -260,6 +268,16 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         return fail(QLSD_E_UNSUPPORTED, "LSD workspace per wavefront too large");
     }
     d->lsd_grid = 8 * d->num_cus;
+    // capacity of lsd_kernel: 64 W local rows (one per clustered detector, so never more than m)
+    // and, with LSD-mu, 64 W dependent columns (never more than n)
+    d->wide = g.m > 64 * W || (with_mu && g.n > 64 * W);
+    if (d->wide) {
+        // keys in LDS when they fit, else read from the LLR rows; a graph too large for either
+        // keeps the OVERFLOW status on such shots
+        d->wide_keys_in_lds = lsd_wide_lds(g, true, with_mu) <= kLdsPerCu - 1024;
+        d->wide = d->wide_keys_in_lds || lsd_wide_lds(g, false, with_mu) <= kLdsPerCu - 1024;
+        d->wide_grid = std::min(d->num_cus, 64);
+    }
     d->timing = (params->flags & QLSD_FLAG_STAGE_TIMING) != 0;
     for (int k = 0; k < 3; k++) d->ev[k] = nullptr;
     if (d->timing)
@@ -276,6 +294,11 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
     if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
     hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
+    if (e4 == hipSuccess && d->wide) {
+        e4 = hipMalloc((void **)&d->d_ovf_list, sizeof(int) * (size_t)max_batch);
+        if (e4 == hipSuccess)
+            e4 = hipMalloc((void **)&d->d_wide_ws, sizeof(uint64_t) * (size_t)d->wide_grid * lsd_wide_ws_words());
+    }
     if (e1 || e2 || e3 || e4) {
         qlsd_decoder_destroy(d);
         return fail(QLSD_E_NOMEM, "device workspace allocation failed (max_batch=%d)", max_batch);
@@ -293,6 +316,8 @@ void qlsd_decoder_destroy(qlsd_decoder d) {
     hipFree(d->d_list);
     hipFree(d->d_llr);
     hipFree(d->d_netws);
+    hipFree(d->d_ovf_list);
+    hipFree(d->d_wide_ws);
     for (int k = 0; k < 3; k++)
         if (d->ev[k]) hipEventDestroy(d->ev[k]);
     delete d;
@@ -348,6 +373,27 @@ static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, ui
     a.omega = d->d_omega;
     a.wave_bytes = d->lsd_wave_bytes;
     return a;
+}
+
+// LSD kernel arguments list overflowing shots for the wide kernel (decoders that can overflow)
+static void with_overflow_list(qlsd_decoder d, LsdArgs &l) {
+    if (!d->wide) return;
+    l.ovf_list = d->d_ovf_list;
+    l.ovf_count = d->d_ctl + kCtlOvf;
+}
+
+// The wide LSD kernel over the shots the LSD kernel listed (it exits at once when none was).
+static hipError_t run_wide(qlsd_decoder d, const uint8_t *syn, const float *llr, uint8_t *corr,
+                           qlsd_shot_info *info, int bp_iters, hipStream_t s) {
+    if (!d->wide) return hipSuccess;
+    LsdArgs w = lsd_args(d, syn, llr, corr, info);
+    w.list = d->d_ovf_list;
+    w.list_count = d->d_ctl + kCtlOvf;
+    w.next_item = d->d_ctl + kCtlItemW;
+    w.bp_iters = bp_iters;
+    w.keys_in_lds = d->wide_keys_in_lds;
+    w.graph_in_lds = 0;
+    return launch_lsd_wide(w, d->d_wide_ws, d->wide_grid, s);
 }
 
 static qlsd_status check_call(qlsd_decoder d, const void *syn, int B, const void *out) {
@@ -411,7 +457,9 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
     l.list = d->d_list;
     l.list_count = d->d_ctl + kCtlList;
     l.bp_iters = d->params.max_iter;
+    with_overflow_list(d, l);
     HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
+    HIP_OK(run_wide(d, syndromes, d->d_llr, corrections, info, d->params.max_iter, s));
     if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
     return QLSD_OK;
 }
@@ -439,7 +487,9 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
     LsdArgs l = lsd_args(d, syndromes, llr, corrections, info);
     l.count = B;
+    with_overflow_list(d, l);
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
+    HIP_OK(run_wide(d, syndromes, llr, corrections, info, 0, s));
     return QLSD_OK;
 }
 

@@ -59,6 +59,8 @@ struct LsdArgs {
                                // with device-scope atomics
     int skip_done;             // list entries < 0 were decoded already (after the fused kernel)
     int *done_count;           // with skip_done: how many were (nullable); all done -> no work
+    int *ovf_list;             // nullable: shots whose clusters outgrew the kernel's capacity are
+    int *ovf_count;            //   appended here for the wide kernel (max_batch entries)
 };
 
 // BP with LSD folded in (plain decode with slot BP): a workgroup whose slots have drained turns
@@ -92,6 +94,14 @@ hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, 
 size_t bp_tables_bytes(const DevGraph &g);  // graph tables (u16 copies of H) at the start of the BP LDS block
 hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st);  // one workgroup per shot
 hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
+// Wide LSD: one wavefront per workgroup, local-row capacity kWideRows, the Gauss-Jordan basis in
+// ws (grid * lsd_wide_ws_words() words); decodes the shots listed in a.list / *a.list_count.
+constexpr int kWideW = 16;
+constexpr int kWideRows = 64 * kWideW;
+constexpr int kWideDependent = 4096;  // LSD-mu: dependent clustered columns the wide kernel can list
+size_t lsd_wide_ws_words();                 // per workgroup
+size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
+hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
 // Host helpers shared by the ABI files.

@@ -65,7 +65,7 @@ void lsd_kernel(LsdArgs A) {
         if (item >= total) break;
         const int shot = A.list ? A.list[item] : item;
         if (A.skip_done && shot < 0) continue;
-        decode_shot<W, MU>(A, S, g, shot, lane);
+        decode_shot<W, MU, GView<GL>, false, true>(A, S, g, shot, lane);
         wave_sync();
     }
 }
@@ -86,6 +86,30 @@ hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
         hipLaunchKernelGGL((lsd_kernel<W, false, MU>), dim3(grid), dim3(kLsdThreads), lds, st, a);
     }
     return hipGetLastError();
+}
+
+// Wide LSD for the shots whose clusters outgrew the register basis of lsd_kernel (listed by it):
+// one wavefront per workgroup runs the same per-shot code with 64 * kWideW local rows, its
+// Gauss-Jordan basis in this workgroup's slice of device memory and only the slices of local
+// rows in use visited.  Shots beyond even this capacity keep the OVERFLOW status.
+template <bool MU>
+__global__ __launch_bounds__(64) void lsd_wide_kernel(LsdArgs A, uint64_t *ws) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    GView<false> g;
+    g.max_cw = A.g.max_cw;
+    g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
+    const LsdLds S = carve_lsd(smem, A.g.m, A.g.n, kWideRows, A.keys_in_lds != 0, A.mu > 0, kWideDependent);
+    uint64_t *mem = ws + (size_t)blockIdx.x * (2 * kWideW * kWideW * 64);
+    const int total = *A.list_count;
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(A.next_item, 1);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= total) break;
+        decode_shot<kWideW, MU, GView<false>, true>(A, S, g, A.list[item], lane, mem);
+        wave_sync();
+    }
 }
 
 // Shots flagged by BP -> a dense list (one 64-shot ballot and one atomic per wavefront).
@@ -115,6 +139,26 @@ size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu) 
 size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds, bool with_mu) {
     return (graph_in_lds ? lsd_graph_bytes(g.m, g.n, g.nnz) : 0) +
            lsd_wave_bytes(g, W, keys_in_lds, with_mu) * (kLsdThreads / 64);
+}
+
+size_t lsd_wide_ws_words() { return (size_t)2 * kWideW * kWideW * 64; }
+
+size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu) {
+    size_t offs[kLsdLayoutEntries];
+    return lsd_layout(g.m, g.n, kWideRows, keys_in_lds, with_mu, offs, kWideDependent);
+}
+
+hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st) {
+    size_t offs[kLsdLayoutEntries];
+    const size_t lds = lsd_layout(a.g.m, a.g.n, kWideRows, a.keys_in_lds != 0, a.mu > 0, offs, kWideDependent);
+    const void *fn = a.mu > 0 ? (const void *)lsd_wide_kernel<true> : (const void *)lsd_wide_kernel<false>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.mu > 0)
+        hipLaunchKernelGGL((lsd_wide_kernel<true>), dim3(grid), dim3(64), lds, st, a, ws);
+    else
+        hipLaunchKernelGGL((lsd_wide_kernel<false>), dim3(grid), dim3(64), lds, st, a, ws);
+    return hipGetLastError();
 }
 
 // LSD-mu decoders always use W = 4 (their extra growth rounds need the room), so LSD-mu code is

@@ -82,7 +82,7 @@ struct LsdLds {
     uint32_t *incol;   // ceil(n/32): fault already in a cluster
     uint8_t *state;    // K: kValid / kInvalid / kFrozen (meaningful at roots)
     int32_t *ctl;      // 4: [0] local row count
-    int32_t *colNP;    // K: clustered columns that were dependent when added (LSD-mu)
+    int32_t *colNP;    // KNP: clustered columns that were dependent when added (LSD-mu)
     int64_t *wq;       // K: integer weight of the column that created each pivot (LSD-mu)
     uint64_t *zk;      // kMaxMu * W: solution change of each reprocessed column (LSD-mu)
     int32_t *tsel;     // kMaxMu: reprocessed columns of the current cluster (LSD-mu)
@@ -104,7 +104,10 @@ constexpr int kLsdLayoutEntries = 19;
 // instructions (no register per array); 8-byte arrays before 4-byte ones before bytes keeps every
 // array aligned.  The arrays sized by m and n follow.  offs[] keeps the field order of LsdLds.
 // with_mu: room for the LSD-mu arrays (wq, zk, tw, colNP, tsel); LSD-0 never touches them.
-__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, bool with_mu, size_t *offs) {
+// knp: entries of colNP (0: K).
+__host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_lds, bool with_mu, size_t *offs,
+                                             int knp = 0) {
+    if (knp <= 0) knp = K;
     const size_t mu = with_mu ? 1 : 0;
     size_t off = 0;
     offs[1] = off; off += sizeof(uint64_t) * K;                      // sel
@@ -117,7 +120,7 @@ __host__ __device__ inline size_t lsd_layout(int m, int n, int K, bool keys_in_l
     offs[4] = off; off += sizeof(int32_t) * K;                       // colAt
     offs[5] = off; off += sizeof(int32_t) * K;                       // croot
     offs[6] = off; off += sizeof(int32_t) * K;                       // rowOf
-    offs[12] = off; off += mu * sizeof(int32_t) * K;                 // colNP
+    offs[12] = off; off += mu * sizeof(int32_t) * knp;               // colNP
     offs[15] = off; off += mu * sizeof(int32_t) * kMaxMu;            // tsel
     offs[11] = off; off += sizeof(int32_t) * 4;                      // ctl
     offs[10] = off; off += align8(K);                                // state
@@ -158,12 +161,52 @@ __device__ bool unite(int32_t *par, int x, int y) {
     }
 }
 
+// The shot's Gauss-Jordan basis.  Mrow(s, w): lane row s's bits over pivot local rows 64w..64w+63
+// (rows of the reduced pivot vectors); CT(s, w): for a pivot row, the pivots whose combination uses
+// the column that created it.  InMem = false keeps both in registers (the LSD kernels, W <= 4);
+// InMem = true keeps them in a per-wavefront slice of device memory ([2][W][W][64] words, lane
+// fastest) for the wide kernel that takes the shots whose clusters outgrow the register basis.
+template <int W, bool InMem>
+struct Basis;
+
 template <int W>
-struct Basis {
-    uint64_t Mrow[W][W];  // per lane row s: bits over pivot local rows (rows of the reduced pivot vectors)
-    uint64_t CT[W][W];    // per lane row s (if a pivot row): pivots whose combination uses its column
-    uint64_t piv[W];      // uniform: pivot local rows
-    uint64_t sp[W];       // uniform: reduced syndrome over local rows
+struct Basis<W, false> {
+    uint64_t Mrow[W][W];
+    uint64_t CT[W][W];
+    uint64_t piv[W];  // uniform: pivot local rows
+    uint64_t sp[W];   // uniform: reduced syndrome over local rows
+    __device__ __forceinline__ uint64_t &M(int s, int w) { return Mrow[s][w]; }
+    __device__ __forceinline__ uint64_t &C(int s, int w) { return CT[s][w]; }
+    __device__ __forceinline__ uint64_t M(int s, int w) const { return Mrow[s][w]; }
+    __device__ __forceinline__ uint64_t C(int s, int w) const { return CT[s][w]; }
+    // slice s of local rows (or of pivot rows) may be non-zero
+    __device__ __forceinline__ bool active(int) const { return true; }
+    // word w of Mrow at lane row (64 rs + rl); rs is wave-uniform but not a compile-time index,
+    // so it is selected by unrolled compares (a runtime array index would put the basis in
+    // scratch memory)
+    __device__ __forceinline__ uint64_t row_word(int rs, int w, int rl) const {
+        uint64_t v = 0;
+#pragma unroll
+        for (int s = 0; s < W; s++)
+            if (s == rs) v = readlane64(Mrow[s][w], rl);
+        return v;
+    }
+};
+
+template <int W>
+struct Basis<W, true> {
+    uint64_t *mem;  // this wavefront's slice, offset by its lane
+    int ns;         // uniform: slices 0..ns-1 of local rows are in use
+    uint64_t piv[W];
+    uint64_t sp[W];
+    __device__ __forceinline__ uint64_t &M(int s, int w) { return mem[(s * W + w) * 64]; }
+    __device__ __forceinline__ uint64_t &C(int s, int w) { return mem[((W + s) * W + w) * 64]; }
+    __device__ __forceinline__ uint64_t M(int s, int w) const { return mem[(s * W + w) * 64]; }
+    __device__ __forceinline__ uint64_t C(int s, int w) const { return mem[((W + s) * W + w) * 64]; }
+    __device__ __forceinline__ bool active(int s) const { return s < ns; }
+    __device__ __forceinline__ uint64_t row_word(int rs, int w, int rl) const {
+        return readlane64(mem[(rs * W + w) * 64], rl);
+    }
 };
 
 template <int W>
@@ -174,11 +217,29 @@ __device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t
     return c & 1;
 }
 
+// parity of (row s of Mrow, or of CT) AND b over the slices in use
+template <int W, class BB>
+__device__ __forceinline__ int parity_M(const BB &B, int s, const uint64_t (&b)[W]) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (B.active(w)) c += __popcll(B.M(s, w) & b[w]);
+    return c & 1;
+}
+template <int W, class BB>
+__device__ __forceinline__ int parity_C(const BB &B, int s, const uint64_t (&b)[W]) {
+    int c = 0;
+#pragma unroll
+    for (int w = 0; w < W; w++)
+        if (B.active(w)) c += __popcll(B.C(s, w) & b[w]);
+    return c & 1;
+}
+
 // Adds column col (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
 // The column's local rows are held by lanes base .. base + cw - 1 of lr_src (-1: no entry).
-template <int W>
-__device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
+template <int W, class BB>
+__device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
     // the column's support over local rows, as W wave-uniform masks
     uint64_t cm[W];
 #pragma unroll
@@ -199,7 +260,8 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, i
     for (int s = 0; s < W; s++) a[s] = cm[s] & B.piv[s];
     uint32_t bpf = 0;
 #pragma unroll
-    for (int s = 0; s < W; s++) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_and<W>(B.Mrow[s], a)) << s;
+    for (int s = 0; s < W; s++)
+        if (B.active(s)) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W>(B, s, a)) << s;
     uint64_t bp[W];
     int rs = -1;
 #pragma unroll
@@ -208,8 +270,6 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, i
         if (rs < 0 && bp[s]) rs = s;
     }
     if (rs < 0) return false;
-    // rs is wave-uniform but not a compile-time index: select by unrolled compare so that the
-    // basis stays in registers (a runtime array index would put it in scratch memory)
     uint64_t bprs = 0;
 #pragma unroll
     for (int s = 0; s < W; s++)
@@ -217,32 +277,30 @@ __device__ bool insert_column(Basis<W> &B, const LsdLds &S, int col, int lane, i
     const int rl = __builtin_ctzll(bprs);
     uint64_t R[W];
 #pragma unroll
-    for (int w = 0; w < W; w++) {
-        uint64_t v = 0;
-#pragma unroll
-        for (int s = 0; s < W; s++)
-            if (s == rs) v = readlane64(B.Mrow[s][w], rl);
-        R[w] = v;
-    }
+    for (int w = 0; w < W; w++) R[w] = B.active(w) ? B.row_word(rs, w, rl) : 0ull;
     // rows in the reduced column's support: eliminate the new pivot row from the old pivots
 #pragma unroll
     for (int s = 0; s < W; s++) {
         if ((bpf >> s) & 1u) {
 #pragma unroll
-            for (int w = 0; w < W; w++) B.Mrow[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.M(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
     // combination tracking
 #pragma unroll
     for (int s = 0; s < W; s++) {
+        if (!B.active(s)) continue;
         const bool is_piv = (B.piv[s] >> lane) & 1ull;
-        if (is_piv && parity_and<W>(B.CT[s], a)) {
+        if (is_piv && parity_C<W>(B, s, a)) {
 #pragma unroll
-            for (int w = 0; w < W; w++) B.CT[s][w] ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.C(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
         }
         if (s == rs && lane == rl) {
 #pragma unroll
-            for (int w = 0; w < W; w++) B.CT[s][w] = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.C(s, w) = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
     bool sp_hit = false;
@@ -274,8 +332,9 @@ __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (i
 // the pivot combination of column T_k (every T_k lies in the span of the pivots).  The cost is
 // the integer weight of the set columns; the strictly smallest cost wins, the smaller t on ties.
 // Patterns are spread over the lanes.
-template <int W, class G>
-__device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const Basis<W> &B,
+// KNP: capacity of the dependent-column list colNP (at most 64 * 64 entries).
+template <int W, int KNP, class G, class BB>
+__device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const BB &B,
                                const uint64_t (&x0)[W], int nrows, int npc, const float *llr, int lane) {
     constexpr int K = 64 * W;
     const int mu = A.mu < kMaxMu ? A.mu : kMaxMu;
@@ -291,7 +350,8 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
         roots[s] = ballot(r < nrows && S.croot[r] == r && S.state[r] != kFrozen);
     }
     wave_sync();
-    const int nnp = npc < K ? npc : K;
+    const int nnp = npc < KNP ? npc : KNP;
+    using Chosen = typename std::conditional<(KNP > 32 * 64), uint64_t, uint32_t>::type;
 #pragma unroll
     for (int s0 = 0; s0 < W; s0++) {
         while (roots[s0]) {
@@ -304,12 +364,12 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                 inC[s] = ballot(r < nrows && S.croot[r] == c);
             }
             // T_w: the cluster's dependent columns of smallest key
-            uint32_t chosen = 0;  // bit u: entry lane + 64 u taken
+            Chosen chosen = 0;  // bit u: entry lane + 64 u taken
             int w = 0;
             for (; w < mu; w++) {
                 uint64_t mine = ~0ull;
                 for (int u = 0; u * 64 + lane < nnp; u++) {
-                    if ((chosen >> u) & 1u) continue;
+                    if ((chosen >> u) & Chosen(1)) continue;
                     const int col = S.colNP[u * 64 + lane];
                     const int rr = S.loc[g.row_idx(g.col_ptr(col))];
                     if (S.croot[rr] != c) continue;
@@ -321,7 +381,7 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                 if (kmin == ~0ull) break;
                 const int col = (int)(uint32_t)kmin;
                 for (int u = 0; u * 64 + lane < nnp; u++)
-                    if (S.colNP[u * 64 + lane] == col) chosen |= 1u << u;
+                    if (S.colNP[u * 64 + lane] == col) chosen |= Chosen(1) << u;
                 // z_w: pivot rows of this cluster whose combination reproduces column col
                 uint32_t bf = 0;
                 for (int e = g.col_ptr(col); e < g.col_ptr(col + 1); e++) {
@@ -333,7 +393,7 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                 for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
 #pragma unroll
                 for (int s = 0; s < W; s++) {
-                    const uint64_t z = ballot(((B.piv[s] & inC[s]) >> lane) & 1ull && parity_and<W>(B.CT[s], a));
+                    const uint64_t z = ballot(((B.piv[s] & inC[s]) >> lane) & 1ull && parity_C<W>(B, s, a));
                     if (lane == 0) S.zk[w * W + s] = z;
                 }
                 if (lane == 0) {
@@ -395,9 +455,14 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
 
 // MU: the decoder runs LSD-mu (A.mu > 0); decoders without it get no LSD-mu code at all, which
 // leaves the register allocator more room in the LSD-0 rounds.
-template <int W, bool MU, class G>
-__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane) {
+// WIDE: the basis lives in device memory at basis_mem (this wavefront's [2][W][W][64] words) and
+// only the slices of local rows in use are visited; the other kernels keep it in registers.
+// OVF: a shot that outgrows the capacity is appended to A.ovf_list (when set) for the wide kernel.
+template <int W, bool MU, class G, bool WIDE = false, bool OVF = false>
+__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane,
+                            uint64_t *basis_mem = nullptr) {
     constexpr int K = 64 * W;
+    constexpr int KNP = WIDE ? kWideDependent : K;  // capacity of the dependent-column list
     const int m = A.g.m, n = A.g.n;
     const float *llr = A.llr + (size_t)shot * n;
     const uint8_t *syn = A.syn + (size_t)shot * m;
@@ -464,6 +529,10 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     auto overflow = [&](uint8_t st) {
         write_row();
         finish(st | QLSD_ST_OVERFLOW, 0, 0);
+        // hand the shot to the wide kernel (launched after this one), which rewrites both
+        if constexpr (OVF) {
+            if (A.ovf_list && lane == 0) A.ovf_list[atomicAdd(A.ovf_count, 1)] = shot;
+        }
     };
 
     // clusters: one per flipped detector, local rows in ascending detector order
@@ -498,11 +567,21 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     const int nseed = nrows;
     if (lane == 0) S.ctl[0] = nrows;
 
-    Basis<W> B;
+    Basis<W, WIDE> B;
+    if constexpr (WIDE) {
+        // rows and pivots only ever occupy the first ceil(m/64) slices; the rest stays untouched
+        B.mem = basis_mem + lane;
+        const int msl = (m + 63) >> 6;
+        for (int s = 0; s < msl; s++)
+            for (int w = 0; w < msl; w++) { B.M(s, w) = 0; B.C(s, w) = 0; }
+        B.ns = (nrows + 63) >> 6;
+    }
 #pragma unroll
     for (int s = 0; s < W; s++) {
+        if constexpr (!WIDE) {
 #pragma unroll
-        for (int w = 0; w < W; w++) { B.Mrow[s][w] = 0; B.CT[s][w] = 0; }
+            for (int w = 0; w < W; w++) { B.M(s, w) = 0; B.C(s, w) = 0; }
+        }
         B.piv[s] = 0;
         const int lo = s * 64;
         B.sp[s] = nseed >= lo + 64 ? ~0ull : (nseed > lo ? ((1ull << (nseed - lo)) - 1ull) : 0ull);
@@ -673,6 +752,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
         }
         nrows = nrows_new;
+        if constexpr (WIDE) B.ns = (nrows + 63) >> 6;
         wave_sync();
 
         // (4) the round's distinct new columns, ascending key, each reduced on the fly.  Order:
@@ -740,7 +820,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
                 const bool pivot = insert_column<W>(B, S, col, lane, lr_src, base, cwc);
                 if (MU && !pivot && A.mu > 0) {
-                    if (lane == 0 && npc < K) S.colNP[npc] = col;
+                    if (lane == 0 && npc < KNP) S.colNP[npc] = col;
                     npc++;
                 }
             }
@@ -787,7 +867,28 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             mu_left = A.mu;
         }
     }
-    if (npc > K) { overflow(status); return; }
+    if (npc > KNP) { overflow(status); return; }
+
+    // Largest cluster in columns (only when the caller asked for the info record): every
+    // clustered fault counts once at the final root of its first detector's local row.  The
+    // selection array is free after the last round (osd_e_clusters does not use it).
+    auto max_cluster_cols = [&]() -> int {
+        if (!A.info) return 0;
+        uint32_t *cnt = (uint32_t *)S.sel;
+        for (int r = lane; r < K; r += 64) cnt[r] = 0u;
+        wave_sync();
+        for (int j = lane; j < n; j += 64)
+            if (in_col(S.incol, j)) atomicAdd(&cnt[find_root(S.croot, S.loc[g.row_idx(g.col_ptr(j))])], 1u);
+        wave_sync();
+        uint32_t mx = 0u;
+        for (int r = lane; r < K; r += 64) mx = cnt[r] > mx ? cnt[r] : mx;
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)mx, off, 64);
+            mx = o > mx ? o : mx;
+        }
+        return (int)mx;
+    };
 
     // solve: seed rows carry s = 1, claimed rows s = 0; frozen clusters contribute nothing
     uint64_t as[W];
@@ -804,7 +905,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         const int r = s * 64 + lane;
         const bool is_root = r < nrows && S.croot[r] == r;
         ncl += __popcll(ballot(is_root));
-        x0[s] = ballot(((B.piv[s] >> lane) & 1ull) && parity_and<W>(B.CT[s], as));
+        x0[s] = ballot(((B.piv[s] >> lane) & 1ull) && parity_C<W>(B, s, as));
     }
     if (!MU || A.mu <= 0) {
 #pragma unroll
@@ -816,18 +917,19 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         // faults of frozen clusters stay zero: their pivot rows never enter `as`
         write_row();
-        finish(status, ncl, 0);
+        finish(status, ncl, max_cluster_cols());
         return;
     }
-    if constexpr (MU) osd_e_clusters<W>(A, S, g, B, x0, nrows, npc, llr, lane);
+    if constexpr (MU) osd_e_clusters<W, KNP>(A, S, g, B, x0, nrows, npc, llr, lane);
     write_row();
-    finish(status, ncl, 0);
+    finish(status, ncl, max_cluster_cols());
 }
 
 // Per-wavefront LDS block of decode_shot (lsd_layout order) at `base`.
-__device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, bool keys_in_lds, bool with_mu) {
+__device__ inline LsdLds carve_lsd(unsigned char *base, int m, int n, int K, bool keys_in_lds, bool with_mu,
+                                   int knp = 0) {
     size_t offs[kLsdLayoutEntries];
-    lsd_layout(m, n, K, keys_in_lds, with_mu, offs);
+    lsd_layout(m, n, K, keys_in_lds, with_mu, offs, knp);
     LsdLds S;
     S.keys = (uint32_t *)(base + offs[0]);
     S.sel = (uint64_t *)(base + offs[1]);

@@ -27,8 +27,10 @@ def _dec(code, T, B, mu=0, flags=0):
     return bc, binding.Decoder(bc, code.priors, B, max_iter=T, lsd_order=mu, flags=flags)
 
 
-@pytest.mark.parametrize("T", [3, 40])
+@pytest.mark.parametrize("T", [3, 40, 100])
 def test_dem_bp_posteriors(oracle_mod, dem, T):
+    """Fixed T, no early exit; T = 100 is the configured budget, where magnitudes reach the 2^64
+    clamp on both sides."""
     print(f"case dem_bp T={T}", flush=True)
     e, S = sample(dem, 12, seed=5)
     _, dec = _dec(dem, T, 12, flags=binding.FLAG_NO_EARLY_EXIT)
@@ -105,10 +107,11 @@ def test_bb_lsd_mu_bit_exact(oracle_mod):
         assert (corr[b] == want).all(), b
 
 
-def test_dem_capacity_overflow_is_flagged(dem):
-    """A syndrome with more flipped detectors than LSD's local-row capacity (256 with LSD order
-    10) cannot be decoded in LDS: the shot must come back flagged OVERFLOW with a zero
-    correction, and its neighbours in the batch must be unaffected."""
+def test_dem_overflowing_shot_decoded_in_batch(oracle_mod, dem):
+    """A syndrome with more flipped detectors than the LSD kernel's capacity (256 local rows with
+    LSD order 10) goes on to the wide LSD kernel: it comes back decoded (H e_hat = s, equal to the
+    oracle on the same posteriors, no OVERFLOW flag), and its neighbours in the batch are
+    unaffected."""
     code = dem
     bc = binding.Code.from_dense(code.H)
     rng = np.random.default_rng(5)
@@ -116,9 +119,17 @@ def test_dem_capacity_overflow_is_flagged(dem):
     S = S.copy()
     S[7] = (rng.random(code.m) < 0.5).astype(np.uint8)  # ~470 flipped detectors
     dec = binding.Decoder(bc, code.priors, 64, max_iter=20, lsd_order=10)
-    corr, info = dec.decode(torch.from_numpy(S).cuda(), want_info=True)
+    s = torch.from_numpy(S).cuda()
+    corr, info = dec.decode(s, want_info=True)
+    llr, _, _ = dec.bp(s)
     corr, inf = corr.cpu().numpy(), binding.parse_info(info)
-    assert inf["status"][7] & binding.ST_OVERFLOW and not corr[7].any()
+    assert not (inf["status"][7] & binding.ST_OVERFLOW)
+    assert (((corr[7].astype(np.int64) @ code.H.T.astype(np.int64)) & 1) == S[7]).all()
+    oc = oracle_mod.Code.from_dense(code.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(code.priors))
+    want, st, stats = oracle_mod.lsd(oc, S[7], llr.cpu().numpy()[7].astype(np.float64), mu=10, omega=om)
+    assert stats[4] > 256
+    np.testing.assert_array_equal(corr[7], want)
     ok = np.ones(64, dtype=bool)
     ok[7] = False
     ref = dec.decode(torch.from_numpy(np.ascontiguousarray(S[ok])).cuda()).cpu().numpy()
@@ -136,3 +147,33 @@ def test_dem_batch_size_invariance(dem):
     for lo, hi in ((0, 1), (1, 4), (4, 37), (37, 300)):
         part = dec.decode(torch.from_numpy(np.ascontiguousarray(S[lo:hi])).cuda()).cpu().numpy()
         np.testing.assert_array_equal(part, full[lo:hi])
+
+
+def test_dem_lsd10_bit_exact_on_every_failed_shot(oracle_mod, dem):
+    """LSD-10 on all BP-100 failures of an 8,192-shot batch (more than a thousand shots, clusters
+    of up to ~130 detectors) against the oracle on the same float32 posteriors, through the full
+    decode: corrections, status, cluster counts and rounds."""
+    B = 8192
+    print("case dem_lsd10_all_failed", flush=True)
+    e, S = sample(dem, B, seed=88)
+    _, dec = _dec(dem, 100, B, mu=10)
+    s = torch.from_numpy(S).cuda()
+    corr, info = dec.decode(s, want_info=True)
+    llr, hard, binfo = dec.bp(s)
+    torch.cuda.synchronize()
+    corr, L = corr.cpu().numpy(), llr.cpu().numpy()
+    inf, bi = binding.parse_info(info), binding.parse_info(binfo)
+    idx = np.nonzero((bi["status"] & 1) == 0)[0]
+    assert len(idx) >= 1000, len(idx)
+    oc = oracle_mod.Code.from_dense(dem.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(dem.priors))
+    biggest = 0
+    for b in idx:
+        want, st, stats = oracle_mod.lsd(oc, S[b], L[b].astype(np.float64), mu=10, omega=om)
+        assert not (inf["status"][b] & binding.ST_OVERFLOW), b
+        assert (corr[b] == want).all(), b
+        assert (inf["status"][b] & 0x0C) == (st & 0x0C), b
+        assert inf["rounds"][b] == stats[2] and inf["n_clusters"][b] == stats[0], b
+        assert inf["max_cluster_cols"][b] == stats[1], b
+        biggest = max(biggest, int(stats[5]))
+    print(f"{len(idx)} LSD-10 shots bit-exact; largest cluster {biggest} detectors")

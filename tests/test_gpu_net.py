@@ -36,6 +36,35 @@ def _theta(seed):
     return (th + rng.normal(size=th.shape) * 0.05).astype(np.float32)
 
 
+# Per-value bounds.  The kernels round weights and activations to bf16 (unit roundoff 2^-8) and
+# accumulate in float32; an emulation of that arithmetic in float64 on these workloads put the
+# largest per-value deviation at 1.2e-2 of (|value| + the shot's RMS) for Delta and 7e-2 of
+# (|value| + the block's RMS) for a gradient entry.  The bounds below leave about 3x of margin; a
+# wrong neighbour, sign or layer moves a value by the order of the RMS itself.
+FWD_TOL = 0.04
+GRAD_TOL = 0.2
+
+
+def _assert_delta_close(d_gpu, d_ref, what):
+    bound = FWD_TOL * (np.abs(d_ref) + np.sqrt(np.mean(d_ref ** 2)))
+    ratio = float((np.abs(d_gpu - d_ref) / np.maximum(bound, 1e-12)).max())
+    assert ratio <= 1.0, (what, ratio)
+    return ratio
+
+
+def _assert_grad_close(g, g_ref, what):
+    worst, off = 0.0, 0
+    for name, shp in ol.PARAM_LAYOUT:
+        k = int(np.prod(shp))
+        gr, gg = g_ref[off:off + k], g[off:off + k]
+        bound = GRAD_TOL * (np.abs(gr) + np.sqrt(np.mean(gr ** 2)))
+        r = float((np.abs(gg - gr) / np.maximum(bound, 1e-12)).max())
+        assert r <= 1.0, (what, name, r)
+        worst = max(worst, r)
+        off += k
+    return worst
+
+
 def test_forward_matches_oracle():
     code = bivariate_bicycle(p=0.06)
     bc, e, S, L = _bp_failures(code, 2000, seed=4)
@@ -50,9 +79,9 @@ def test_forward_matches_oracle():
     for b in range(len(S)):
         d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
         rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
-        worst = max(worst, rel)
         assert rel <= 2e-2, (b, rel)
-    print(f"worst relative L2 error of Delta: {worst:.2e}")
+        worst = max(worst, _assert_delta_close(d_gpu[b], d_ref, b))
+    print(f"worst per-value deviation of Delta: {worst:.2f} of the bound")
 
 
 def test_gradient_matches_oracle():
@@ -71,14 +100,9 @@ def test_gradient_matches_oracle():
     cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
     print(f"gradient relative L2 error {rel:.2e}, cosine {cos:.6f}")
     assert rel <= 5e-2 and cos >= 0.998
-    # every parameter block is right, not only the dominant ones
-    off = 0
-    for name, shp in ol.PARAM_LAYOUT:
-        k = int(np.prod(shp))
-        gr, gg = g_ref[off:off + k], g[off:off + k]
-        if np.linalg.norm(gr) > 1e-6:
-            assert np.linalg.norm(gg - gr) / np.linalg.norm(gr) <= 0.1, name
-        off += k
+    # every entry of every parameter block, not only the dominant ones
+    worst = _assert_grad_close(g, g_ref, "bb144")
+    print(f"worst per-value gradient deviation: {worst:.2f} of the bound")
 
 
 def test_zero_output_net_decodes_like_plain():
@@ -128,6 +152,7 @@ def test_forward_matches_oracle_irregular_code():
         d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
         rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
         assert rel <= 2e-2, (b, rel)
+        _assert_delta_close(d_gpu[b], d_ref, b)
 
 
 def test_set_priors_equals_fresh_net():
@@ -196,6 +221,7 @@ def test_large_graph_forward_and_gradient_match_oracle(which):
         d_ref = ol.forward(th.astype(np.float64), code.H, L[b].astype(np.float64), lam, S[b])
         rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
         assert rel <= 2e-2, (b, rel)
+        _assert_delta_close(d_gpu[b], d_ref, (which, b))
     g, loss = net.gradient(torch.from_numpy(S[:ng]).cuda(), torch.from_numpy(L[:ng]).cuda(),
                            torch.from_numpy(e[:ng]).cuda())
     torch.cuda.synchronize()
@@ -207,6 +233,8 @@ def test_large_graph_forward_and_gradient_match_oracle(which):
     cos = float(g @ g_ref / (np.linalg.norm(g) * np.linalg.norm(g_ref)))
     print(f"{which}: gradient relative L2 error {rel:.2e}, cosine {cos:.6f}")
     assert rel <= 5e-2 and cos >= 0.998
+    worst = _assert_grad_close(g, g_ref, which)
+    print(f"{which}: worst per-value gradient deviation {worst:.2f} of the bound")
 
 
 def test_net_rejects_other_code():
