@@ -66,7 +66,9 @@ typedef struct {
 #define QLSD_ST_LSD_RUN 2u      /* LSD produced the correction                          */
 #define QLSD_ST_UNSAT 4u        /* some cluster could not be made valid (s not in image) */
 #define QLSD_ST_BAD_LLR 8u      /* NaN soft information; correction left at zero        */
-#define QLSD_ST_OVERFLOW 16u    /* clusters outgrew the kernel's capacity; correction zero */
+#define QLSD_ST_OVERFLOW 16u    /* clusters outgrew even the wide LSD kernel (more than 1024
+                                   clustered detectors, or more than 4096 dependent columns
+                                   with LSD-mu); correction zero */
 
 typedef struct {
     uint8_t status;           /* QLSD_ST_* bits */
@@ -94,9 +96,23 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
  * one kernel: a workgroup whose BP shots have drained decodes, with LSD, the shots other
  * workgroups' BP left unsolved; a stand-alone LSD launch then finishes any shot not yet
  * taken.  Outputs are identical either way (every shot's LSD is the same function of its
- * syndrome and BP posterior). */
+ * syndrome and BP posterior).  Shots whose clusters outgrow the LSD kernel's register basis
+ * (64 W local rows, W = 1, 2 or 4 chosen from m; 4 with LSD-mu) are finished by a wide LSD
+ * kernel with up to 1024 local rows (same results, slower per shot). */
 qlsd_status qlsd_decode(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
                         qlsd_shot_info *info, void *stream);
+
+/* qlsd_decode without the decoder's own device workspace, for callers that cannot allocate
+ * (work under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * per-call scratch (counters, shot lists, the BP-to-LSD posterior rows, the wide-LSD bases) is
+ * carved from one static device array of the library, 48 MiB per GPU, held until the process
+ * ends.  Same arguments, kernels and outputs as qlsd_decode; no allocation, memset or host
+ * synchronisation.  QLSD_E_BATCH if B's scratch (about B * (4n + 9) bytes plus 2 MiB when
+ * clusters can outgrow the LSD kernel) exceeds 48 MiB; QLSD_E_UNSUPPORTED for a decoder whose
+ * attached refinement net needs its own workspace (large graphs).  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (any decoder, any stream) race. */
+qlsd_status qlsd_decode_static(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
+                               qlsd_shot_info *info, void *stream);
 
 /* BP only: llr_out device float[B*n] receives the posterior LLRs L_j of the last
  * iteration run; hard_out device u8[B*n] (nullable) receives [L_j < 0]. */

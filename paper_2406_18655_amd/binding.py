@@ -22,7 +22,7 @@ FLAG_STAGE_TIMING = 2
 FLAG_SEPARATE_LSD = 4
 
 # every symbol include/qlsd.h declares
-EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
+EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
            "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
 
@@ -57,6 +57,7 @@ def lib():
         L.qlsd_code_create.argtypes = [I32, I32, I64, P, P, ctypes.POINTER(P)]
         L.qlsd_decoder_create.argtypes = [P, ctypes.POINTER(QlsdParams), P, I32, ctypes.POINTER(P)]
         L.qlsd_decode.argtypes = [P, P, I32, P, P, P]
+        L.qlsd_decode_static.argtypes = [P, P, I32, P, P, P]
         L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
         L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
@@ -65,7 +66,7 @@ def lib():
         L.qlsd_last_error.restype = ctypes.c_char_p
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
-        for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_bp", "qlsd_lsd",
+        for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
                    "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -169,6 +170,13 @@ class Decoder:
         _check(lib().qlsd_decode(self._h, _ptr(syndromes), B, _ptr(corrections), _ptr(info),
                                  _stream() if stream is None else stream))
 
+    def decode_static_into(self, syndromes, corrections, info=None, stream: Optional[int] = None):
+        """qlsd_decode_static: the same decode with its scratch in the library's static array."""
+        B = syndromes.shape[0]
+        self._check_io(syndromes, B, corrections=corrections, info=info)
+        _check(lib().qlsd_decode_static(self._h, _ptr(syndromes), B, _ptr(corrections), _ptr(info),
+                                        _stream() if stream is None else stream))
+
     def bp_into(self, syndromes, llr_out, hard_out=None, info=None, stream: Optional[int] = None):
         B = syndromes.shape[0]
         self._check_io(syndromes, B, llr_out=llr_out, hard_out=hard_out, info=info)
@@ -213,6 +221,15 @@ class Decoder:
         corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
         info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
         self.decode_into(s, corr, info)
+        return (corr, info) if want_info else corr
+
+    def decode_static(self, syndromes, want_info: bool = False):
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.decode_static_into(s, corr, info)
         return (corr, info) if want_info else corr
 
     def bp(self, syndromes, want_info: bool = True):

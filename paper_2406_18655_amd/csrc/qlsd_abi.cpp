@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -42,11 +43,22 @@ hipError_t dev_copy(T **dst, const T *src, size_t count) {
     return e;
 }
 
+constexpr size_t kStaticScratchBytes = (size_t)48 << 20;
+constexpr int kStaticMaxDevices = 64;
+constexpr int kStaticWideGrid = 8;  // wide-LSD workgroups (and bases) in the static scratch
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kStaticMaxDevices];  // device address of `scratch`, per device
+
 constexpr size_t kBpLdsBudget = 40 * 1024;  // four BP workgroups per CU
 constexpr int kMaxSlots = 64;
 constexpr size_t kLdsPerCu = 160 * 1024;
 
 }  // namespace
+
+// Scratch of qlsd_decode_static: one array per GPU the library runs on, held until the process
+// ends.  Host code never passes `scratch` itself (on the host it is only a stand-in for the
+// symbol): it uses the device address hipGetSymbolAddress returns on each device.
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 
 struct qlsd_code_s {
     int device;
@@ -323,7 +335,23 @@ void qlsd_decoder_destroy(qlsd_decoder d) {
     delete d;
 }
 
-static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
+// Per-call device scratch of a decode: the decoder's own workspace (qlsd_decode and the other
+// entry points) or a carve of the library's static scratch array (qlsd_decode_static).
+struct Ws {
+    int *ctl;           // kCtlWords counters
+    uint8_t *flag;      // B: shot goes from BP to LSD
+    int *list;          // B: shots for LSD
+    float *llr;         // B x n: posteriors handed from BP to LSD
+    int *ovf_list;      // B (decoders that can overflow): shots for the wide LSD kernel
+    uint64_t *wide_ws;  // wide_grid * lsd_wide_ws_words()
+    int wide_grid;
+};
+
+static Ws decoder_ws(qlsd_decoder d) {
+    return Ws{d->d_ctl, d->d_flag, d->d_list, d->d_llr, d->d_ovf_list, d->d_wide_ws, d->wide_grid};
+}
+
+static BpArgs bp_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, int B) {
     BpArgs a;
     memset(&a, 0, sizeof(a));
     a.g = d->code->g;
@@ -334,7 +362,7 @@ static BpArgs bp_args(qlsd_decoder d, const uint8_t *syn, int B) {
     a.alpha = d->params.ms_scaling;
     a.early_exit = (d->params.flags & QLSD_FLAG_NO_EARLY_EXIT) ? 0 : 1;
     a.S = d->bp_slots;
-    a.next_shot = d->d_ctl + kCtlQueue;
+    a.next_shot = w.ctl + kCtlQueue;
     return a;
 }
 
@@ -357,14 +385,14 @@ static hipError_t run_bp(qlsd_decoder d, const BpArgs &a, int B, hipStream_t s) 
     return d->bp_graph ? launch_bp_graph(a, bp_grid(d, B), s) : launch_bp(a, bp_grid(d, B), s);
 }
 
-static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, uint8_t *corr,
+static LsdArgs lsd_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, const float *llr, uint8_t *corr,
                         qlsd_shot_info *info) {
     LsdArgs a;
     memset(&a, 0, sizeof(a));
     a.g = d->code->g;
     a.syn = syn;
     a.llr = llr;
-    a.next_item = d->d_ctl + kCtlItem;
+    a.next_item = w.ctl + kCtlItem;
     a.corr = corr;
     a.info = info;
     a.keys_in_lds = d->lsd_keys_in_lds;
@@ -376,24 +404,24 @@ static LsdArgs lsd_args(qlsd_decoder d, const uint8_t *syn, const float *llr, ui
 }
 
 // LSD kernel arguments list overflowing shots for the wide kernel (decoders that can overflow)
-static void with_overflow_list(qlsd_decoder d, LsdArgs &l) {
+static void with_overflow_list(qlsd_decoder d, const Ws &w, LsdArgs &l) {
     if (!d->wide) return;
-    l.ovf_list = d->d_ovf_list;
-    l.ovf_count = d->d_ctl + kCtlOvf;
+    l.ovf_list = w.ovf_list;
+    l.ovf_count = w.ctl + kCtlOvf;
 }
 
 // The wide LSD kernel over the shots the LSD kernel listed (it exits at once when none was).
-static hipError_t run_wide(qlsd_decoder d, const uint8_t *syn, const float *llr, uint8_t *corr,
+static hipError_t run_wide(qlsd_decoder d, const Ws &ws, const uint8_t *syn, const float *llr, uint8_t *corr,
                            qlsd_shot_info *info, int bp_iters, hipStream_t s) {
     if (!d->wide) return hipSuccess;
-    LsdArgs w = lsd_args(d, syn, llr, corr, info);
-    w.list = d->d_ovf_list;
-    w.list_count = d->d_ctl + kCtlOvf;
-    w.next_item = d->d_ctl + kCtlItemW;
+    LsdArgs w = lsd_args(d, ws, syn, llr, corr, info);
+    w.list = ws.ovf_list;
+    w.list_count = ws.ctl + kCtlOvf;
+    w.next_item = ws.ctl + kCtlItemW;
     w.bp_iters = bp_iters;
     w.keys_in_lds = d->wide_keys_in_lds;
     w.graph_in_lds = 0;
-    return launch_lsd_wide(w, d->d_wide_ws, d->wide_grid, s);
+    return launch_lsd_wide(w, ws.wide_ws, ws.wide_grid, s);
 }
 
 static qlsd_status check_call(qlsd_decoder d, const void *syn, int B, const void *out) {
@@ -404,64 +432,120 @@ static qlsd_status check_call(qlsd_decoder d, const void *syn, int B, const void
     return QLSD_OK;
 }
 
+// BP then LSD on the per-call scratch w; timing: record the decoder's stage events.
+static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndromes, int B, uint8_t *corrections,
+                               qlsd_shot_info *info, hipStream_t s, bool timing) {
+    const int fw = fuse_waves(d);
+    if (fw > 0) {
+        HIP_OK(launch_fill2(w.list, B, -1, w.ctl, kCtlWords, 0, s));
+        BpArgs a = bp_args(d, w, syndromes, B);
+        a.corr = corrections;
+        a.llr_lsd = w.llr;
+        a.info = info;
+        FuseArgs f;
+        memset(&f, 0, sizeof(f));
+        f.lsd = lsd_args(d, w, syndromes, w.llr, corrections, info);
+        f.lsd.list = w.list;
+        f.lsd.list_count = w.ctl + kCtlList;
+        f.lsd.bp_iters = d->params.max_iter;
+        f.lsd.coherent_llr = 1;
+        f.list_w = w.list;
+        f.tail = w.ctl + kCtlList;
+        f.bp_done = w.ctl + kCtlBpDone;
+        f.lsd_done = w.ctl + kCtlLsdDone;
+        f.lsd_waves = fw;
+        f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
+        if (timing) HIP_OK(hipEventRecord(d->ev[0], s));
+        HIP_OK(launch_bp_fused(a, f, d->lsd_W, bp_grid(d, B), s));
+        if (timing) HIP_OK(hipEventRecord(d->ev[1], s));
+        // every published entry not marked done (normally none), on a fresh work counter
+        LsdArgs rest = f.lsd;
+        rest.next_item = w.ctl + kCtlItem2;
+        rest.skip_done = 1;
+        rest.done_count = w.ctl + kCtlLsdDone;
+        rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
+        HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
+        if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
+        return QLSD_OK;
+    }
+    HIP_OK(launch_zero(w.ctl, kCtlWords, s));
+    BpArgs a = bp_args(d, w, syndromes, B);
+    if (timing) HIP_OK(hipEventRecord(d->ev[0], s));
+    a.corr = corrections;
+    a.llr_lsd = w.llr;
+    a.lsd_flag = w.flag;
+    a.info = info;
+    HIP_OK(run_bp(d, a, B, s));
+    if (timing) HIP_OK(hipEventRecord(d->ev[1], s));
+    HIP_OK(launch_compact(w.flag, B, w.list, w.ctl + kCtlList, s));
+    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, w.llr, w.list, w.ctl + kCtlList, B, d->d_netws, s));
+    LsdArgs l = lsd_args(d, w, syndromes, w.llr, corrections, info);
+    l.list = w.list;
+    l.list_count = w.ctl + kCtlList;
+    l.bp_iters = d->params.max_iter;
+    with_overflow_list(d, w, l);
+    HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
+    HIP_OK(run_wide(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
+    if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
+    return QLSD_OK;
+}
+
 qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
                         qlsd_shot_info *info, void *stream) {
     qlsd_status st = check_call(d, syndromes, B, corrections);
     if (st != QLSD_OK || B == 0) return st;
-    hipStream_t s = (hipStream_t)stream;
-    const int fw = fuse_waves(d);
-    if (fw > 0) {
-        HIP_OK(launch_fill2(d->d_list, B, -1, d->d_ctl, kCtlWords, 0, s));
-        BpArgs a = bp_args(d, syndromes, B);
-        a.corr = corrections;
-        a.llr_lsd = d->d_llr;
-        a.info = info;
-        FuseArgs f;
-        memset(&f, 0, sizeof(f));
-        f.lsd = lsd_args(d, syndromes, d->d_llr, corrections, info);
-        f.lsd.list = d->d_list;
-        f.lsd.list_count = d->d_ctl + kCtlList;
-        f.lsd.bp_iters = d->params.max_iter;
-        f.lsd.coherent_llr = 1;
-        f.list_w = d->d_list;
-        f.tail = d->d_ctl + kCtlList;
-        f.bp_done = d->d_ctl + kCtlBpDone;
-        f.lsd_done = d->d_ctl + kCtlLsdDone;
-        f.lsd_waves = fw;
-        f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
-        if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
-        HIP_OK(launch_bp_fused(a, f, d->lsd_W, bp_grid(d, B), s));
-        if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
-        // every published entry not marked done (normally none), on a fresh work counter
-        LsdArgs rest = f.lsd;
-        rest.next_item = d->d_ctl + kCtlItem2;
-        rest.skip_done = 1;
-        rest.done_count = d->d_ctl + kCtlLsdDone;
-        rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
-        HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
-        if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
-        return QLSD_OK;
+    return decode_with(d, decoder_ws(d), syndromes, B, corrections, info, (hipStream_t)stream, d->timing);
+}
+
+// Device address of this device's `scratch` (looked up once per device, with it current).
+static qlsd_status static_scratch(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(QLSD_E_DEVICE, "device %d beyond the static scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(QLSD_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = (unsigned char *)p;
     }
-    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
-    BpArgs a = bp_args(d, syndromes, B);
-    if (d->timing) HIP_OK(hipEventRecord(d->ev[0], s));
-    a.corr = corrections;
-    a.llr_lsd = d->d_llr;
-    a.lsd_flag = d->d_flag;
-    a.info = info;
-    HIP_OK(run_bp(d, a, B, s));
-    if (d->timing) HIP_OK(hipEventRecord(d->ev[1], s));
-    HIP_OK(launch_compact(d->d_flag, B, d->d_list, d->d_ctl + kCtlList, s));
-    if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, d->d_llr, d->d_list, d->d_ctl + kCtlList, B, d->d_netws, s));
-    LsdArgs l = lsd_args(d, syndromes, d->d_llr, corrections, info);
-    l.list = d->d_list;
-    l.list_count = d->d_ctl + kCtlList;
-    l.bp_iters = d->params.max_iter;
-    with_overflow_list(d, l);
-    HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
-    HIP_OK(run_wide(d, syndromes, d->d_llr, corrections, info, d->params.max_iter, s));
-    if (d->timing) HIP_OK(hipEventRecord(d->ev[2], s));
+    *out = g_scratch_dev[dev];
     return QLSD_OK;
+}
+
+qlsd_status qlsd_decode_static(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
+                               qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK || B == 0) return st;
+    if (d->netws_bytes) return fail(QLSD_E_UNSUPPORTED, "qlsd_decode_static: the attached net needs a device workspace");
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev != d->code->device) return fail(QLSD_E_INVALID, "decoder lives on device %d, current is %d", d->code->device, dev);
+    const size_t n = (size_t)d->code->g.n;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = (off + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    const size_t o_ctl = take(sizeof(int) * kCtlWords), o_flag = take((size_t)B), o_list = take(sizeof(int) * (size_t)B),
+                 o_llr = take(sizeof(float) * (size_t)B * n);
+    const size_t o_ovf = d->wide ? take(sizeof(int) * (size_t)B) : 0;
+    const size_t o_wide = d->wide ? take(sizeof(uint64_t) * lsd_wide_ws_words() * kStaticWideGrid) : 0;
+    if (off > kStaticScratchBytes)
+        return fail(QLSD_E_BATCH, "qlsd_decode_static: B=%d needs %zu bytes of scratch, the library holds %zu",
+                    B, off, kStaticScratchBytes);
+    unsigned char *base = nullptr;
+    st = static_scratch(dev, &base);
+    if (st != QLSD_OK) return st;
+    Ws w;
+    w.ctl = (int *)(base + o_ctl);
+    w.flag = base + o_flag;
+    w.list = (int *)(base + o_list);
+    w.llr = (float *)(base + o_llr);
+    w.ovf_list = d->wide ? (int *)(base + o_ovf) : nullptr;
+    w.wide_ws = d->wide ? (uint64_t *)(base + o_wide) : nullptr;
+    w.wide_grid = kStaticWideGrid;
+    return decode_with(d, w, syndromes, B, corrections, info, (hipStream_t)stream, false);
 }
 
 qlsd_status qlsd_bp(qlsd_decoder d, const uint8_t *syndromes, int32_t B, float *llr_out, uint8_t *hard_out,
@@ -470,7 +554,7 @@ qlsd_status qlsd_bp(qlsd_decoder d, const uint8_t *syndromes, int32_t B, float *
     if (st != QLSD_OK || B == 0) return st;
     hipStream_t s = (hipStream_t)stream;
     HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
-    BpArgs a = bp_args(d, syndromes, B);
+    BpArgs a = bp_args(d, decoder_ws(d), syndromes, B);
     a.corr = hard_out;
     a.llr_out = llr_out;
     a.info = info;
@@ -485,11 +569,12 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     if (!llr) return fail(QLSD_E_INVALID, "llr is NULL");
     hipStream_t s = (hipStream_t)stream;
     HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
-    LsdArgs l = lsd_args(d, syndromes, llr, corrections, info);
+    const Ws w = decoder_ws(d);
+    LsdArgs l = lsd_args(d, w, syndromes, llr, corrections, info);
     l.count = B;
-    with_overflow_list(d, l);
+    with_overflow_list(d, w, l);
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
-    HIP_OK(run_wide(d, syndromes, llr, corrections, info, 0, s));
+    HIP_OK(run_wide(d, w, syndromes, llr, corrections, info, 0, s));
     return QLSD_OK;
 }
 
@@ -529,7 +614,7 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
     auto bp_run = [&]() -> hipError_t {
         hipError_t e = launch_zero(d->d_ctl, kCtlWords, s);
         if (e != hipSuccess) return e;
-        BpArgs a = bp_args(d, syndromes, B);
+        BpArgs a = bp_args(d, decoder_ws(d), syndromes, B);
         a.corr = corr;
         a.llr_lsd = d->d_llr;
         a.lsd_flag = d->d_flag;
@@ -578,7 +663,7 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
         auto lsd_run = [&]() -> hipError_t {
             hipError_t e = launch_zero(d->d_ctl + kCtlItem, 1, s);
             if (e != hipSuccess) return e;
-            LsdArgs l = lsd_args(d, syndromes, d->d_llr, corr, nullptr);
+            LsdArgs l = lsd_args(d, decoder_ws(d), syndromes, d->d_llr, corr, nullptr);
             l.list = d->d_list;
             l.list_count = d->d_ctl + kCtlList;
             l.bp_iters = d->params.max_iter;
