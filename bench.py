@@ -66,6 +66,17 @@ def parse():
                          "reference for scaling HBM byte counters")
     ap.add_argument("--traffic-json", default=os.path.join(HERE, "profiles", "bp_traffic_bb144.json"),
                     help="HBM bytes per BP launch measured with rocprofv3 counters, if present")
+    ap.add_argument("--counters-json", default=os.path.join(HERE, "profiles", "issue_counters_bb144.json"),
+                    help="VALU / LDS instruction counts per launch of the headline kernel (rocprofv3 SQ "
+                         "counters), if present and taken on the current kernel sources")
+    ap.add_argument("--record-counters", nargs=2, metavar=("PASS1_CSV", "PASS2_CSV"), default=None,
+                    help="write --counters-json from two rocprofv3 counter_collection.csv files of a "
+                         "bench run (SQ_INSTS_VALU SQ_ACTIVE_INST_VALU ... / SQ_ACTIVE_INST_LDS ...)")
+    ap.add_argument("--latency-launches", type=int, default=200,
+                    help="isolated launches timed for the per-launch latency percentiles")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming (per-request latency) leg")
+    ap.add_argument("--no-osd", action="store_true", help="skip the BP + OSD-0 comparator leg")
+    ap.add_argument("--stream-requests", type=int, default=100000)
     return ap.parse_args()
 
 
@@ -76,9 +87,9 @@ def bp_algorithmic_bytes(m, n, E, iters):
 
 
 def lsd_algorithmic_bytes(n, n_lsd):
-    """Per shot that goes on to LSD: its float32 posterior row written by BP and read by LSD
-    (its syndrome and correction are already counted once in the BP figure)."""
-    return float(n_lsd) * 8 * n
+    """Per shot that goes on to LSD: its float32 posterior row read once (4n bytes; its syndrome
+    and correction are already counted once in the BP figure)."""
+    return float(n_lsd) * 4 * n
 
 
 def main():
@@ -157,9 +168,13 @@ def main():
             lsd_ms.append(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    lat = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
+    lat_pipe = np.array([s.elapsed_time(e) for s, e in zip(starts, ends)])
     shots_per_s = args.steps * B / wall
     ms_per_step = wall * 1e3 / args.steps
+
+    # per-launch latency outside the timed steps: isolated launches (each waited for), so the
+    # figure is one batch's decode time, not its place in a queue of launches
+    lat = isolated_latencies(dec, batches, corr, args.latency_launches)
 
     # Roofline of the dominant kernel: algorithmic bytes per launch over its measured average
     # duration.  [[144,12,12]]: the slot BP kernel with LSD folded in (BP's bytes plus each LSD
@@ -182,6 +197,8 @@ def main():
                 "traffic": traffic, "avg_launch_ms": round(bp_avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
                 "lsd_avg_launch_ms": round(float(np.mean(lsd_ms)), 4)}
+    if not dem:
+        roofline["binding"] = issue_roofline(args.counters_json, bp_avg_ms)
     if not dem:
         # context: the same BP as a kernel of its own (two-kernel path), on batch 0
         sep = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=args.lsd_order,
@@ -217,7 +234,10 @@ def main():
            "data": "synthetic",
            "config": cfg,
            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
-                          "p99": round(float(np.percentile(lat, 99)), 4), "per": f"launch of {B} shots"},
+                          "p99": round(float(np.percentile(lat, 99)), 4),
+                          "per": f"launch of {B} shots, {len(lat)} isolated launches after the timed steps",
+                          "pipelined_p50": round(float(np.percentile(lat_pipe, 50)), 4),
+                          "pipelined_p99": round(float(np.percentile(lat_pipe, 99)), 4)},
            "ler": {"gpu": round(float(np.mean([f.mean() for f in ler_gpu])), 6)},
            "bp_mean_iters": round(float(np.mean([it.mean() for it in iters_per_batch])), 3),
            "lsd_fraction": round(float(np.mean(lsd_frac)), 4),
@@ -230,6 +250,12 @@ def main():
                           "unit": "shots/s", "note": "consecutive batches on two streams, one launch per "
                                                      "batch each; context, not the headline"}
     del dec2
+    if not dem and not args.no_stream:
+        log("stream leg")
+        out["stream"] = stream_leg(code, bcode, args)
+    if not dem and not args.no_osd:
+        log("BP + OSD-0 leg")
+        out["osd0"] = osd0_leg(code, bcode, batches, args, np.concatenate(ler_gpu), shots_per_s)
     if not args.no_learned:
         log("learned leg")
         out["learned"] = learned_leg(code, bcode, batches, args, out["ler"]["gpu"], shots_per_s)
@@ -289,19 +315,154 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
         grid, best = [], None
         for T in (10, 20, 50):
             for mu in (0, 2, 4, 8, 12):
+                # every grid point gets the autotuner and the timing of the learned leg
                 d = binding.Decoder(bcode, code.priors, B, max_iter=T, lsd_order=mu)
-                fm, rate_m, ms_m, _ = _score_and_time(code, d, batches, max(1, args.steps // 8), 2,
+                chosen = [l for l in d.tune(batches[0][1], reps=3).splitlines() if "chosen" in l]
+                fm, rate_m, ms_m, _ = _score_and_time(code, d, batches, args.steps, args.warmup,
                                                       f"plain BP {T} LSD-{mu}")
                 qm = float(fm.mean())
                 two_sigma = 2 * float(np.sqrt(max(q, 1 / n) * (1 - q) / n + max(qm, 1 / n) * (1 - qm) / n))
                 grid.append([T, mu, round(qm, 6), round(rate_m / 1e6, 2)])
                 if qm <= q + two_sigma and (best is None or rate_m > best["value"]):
                     best = {"bp_max_iter": T, "lsd_order": mu, "ler": round(qm, 6), "value": round(rate_m, 1),
-                            "ler_difference_two_sigma": round(two_sigma, 6)}
+                            "ler_difference_two_sigma": round(two_sigma, 6), "tuning": chosen,
+                            "mcnemar": _mcnemar(f, fm)}
         out["plain_at_matched_ler"] = {
             "best": best, "speedup_of_learned": None if best is None else round(rate / best["value"], 3),
+            "timing": f"every leg autotuned, {args.steps} timed steps after {args.warmup} warm-up",
             "grid": {"columns": ["bp_max_iter", "lsd_order", "ler", "M_shots_per_s"], "rows": grid}}
     return out
+
+
+def _mcnemar(f_a, f_b):
+    """Paired comparison on the same shots: b = failures of b only, c = failures of a only."""
+    b = int(np.sum(~f_a & f_b))
+    c = int(np.sum(f_a & ~f_b))
+    return {"only_learned_fails": c, "only_plain_fails": b,
+            "z": round((b - c) / float(np.sqrt(max(b + c, 1))), 2)}
+
+
+def isolated_latencies(dec, batches, corr, n):
+    """Device time of n decode launches, each started on an idle GPU and waited for."""
+    import torch
+    out = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    for k in range(n):
+        a.record(stream)
+        dec.decode_into(batches[k % len(batches)][1], corr, None)
+        b.record(stream)
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return np.array(out)
+
+
+# VALU issue peak: 256 CUs x 4 SIMDs, one 64-lane VALU instruction per SIMD per clock at 2.4 GHz
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9
+CLOCK_HZ = 2.4e9
+
+
+def issue_roofline(path, launch_ms):
+    """The resources the headline kernel is bound by (its DRAM traffic is ~1 % of the algorithmic
+    bytes): VALU instructions per launch against the VALU issue peak, and LDS busy cycles against
+    every CU's cycles, from rocprofv3 SQ counters of the same kernel (stored with a hash of its
+    sources, null when the code has changed since) over the launch duration measured here."""
+    if not path or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        c = json.load(f)
+    if c.get("kernel_source_hash") != _kernel_hash():
+        return {"stale": True, "note": "counters were taken on other kernel sources"}
+    t = launch_ms * 1e-3
+    cycles = t * CLOCK_HZ
+    valu = c["SQ_INSTS_VALU"] / t
+    lds_busy = 4.0 * c["SQ_ACTIVE_INST_LDS"] / (256 * cycles)
+    valu_busy = 4.0 * c["SQ_ACTIVE_INST_VALU"] / (1024 * cycles)
+    return {"bound": "lds" if lds_busy > valu_busy else "alu",
+            "valu_wave_instr_per_launch": c["SQ_INSTS_VALU"],
+            "valu_achieved_per_s": round(valu, 1), "valu_peak_per_s": VALU_PEAK_WAVE_INSTR_PER_S,
+            "valu_issue_frac": round(valu / VALU_PEAK_WAVE_INSTR_PER_S, 4),
+            "valu_busy_frac": round(valu_busy, 4),
+            "lds_instr_per_launch": c["SQ_INSTS_LDS"],
+            "lds_busy_frac": round(lds_busy, 4),
+            "lds_bank_conflict_frac": round(c["SQ_LDS_BANK_CONFLICT"] / (256 * cycles), 4),
+            "source": os.path.relpath(path, HERE), "clock_hz": CLOCK_HZ}
+
+
+def record_counters(pass1, pass2, path):
+    """Median per-dispatch SQ counters of the fused BP + LSD kernel from two rocprofv3 CSVs."""
+    import csv
+    vals = {}
+    for fn in (pass1, pass2):
+        rows = list(csv.DictReader(open(fn)))
+        by = {}
+        for r in rows:
+            if "bp_lds_kernel<6, 3, true, 2>" not in r.get("Kernel_Name", ""):
+                continue
+            by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        for k, v in by.items():
+            vals[k] = float(np.median(v))
+    vals["kernel_source_hash"] = _kernel_hash()
+    vals["kernel"] = "bp_lds_kernel<6, 3, true, 2> (BP 50 + LSD-0 in one kernel)"
+    with open(path, "w") as f:
+        json.dump(vals, f, indent=1)
+    print(json.dumps(vals))
+
+
+def osd0_leg(code, bcode, batches, args, f_plain, plain_rate):
+    """The comparator of Sec. 2.2: the same BP followed by global OSD-0 instead of LSD on the shots
+    BP leaves unsolved, on the same batches, timed like the headline."""
+    from paper_2406_18655_amd import binding
+    B = batches[0][1].shape[0]
+    dec = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, flags=binding.FLAG_OSD0_POST)
+    f, rate, ms, lat = _score_and_time(code, dec, batches, args.steps, args.warmup, "BP + OSD-0")
+    q, qp, n = float(f.mean()), float(f_plain.mean()), f.size
+    two_sigma = 2 * float(np.sqrt(max(q, 1 / n) * (1 - q) / n + max(qp, 1 / n) * (1 - qp) / n))
+    return {"bp_max_iter": args.max_iter, "value": round(rate, 1), "unit": "shots/s", "ms_per_step": round(ms, 4),
+            "ler": round(q, 6), "ler_bp_lsd": round(qp, 6), "ler_difference_two_sigma": round(two_sigma, 6),
+            "equal_ler": bool(abs(q - qp) <= two_sigma),
+            "mcnemar_vs_bp_lsd": {"only_osd_fails": int(np.sum(f & ~f_plain)),
+                                  "only_lsd_fails": int(np.sum(~f & f_plain))},
+            "bp_lsd_speedup": round(plain_rate / rate, 3), "shots_scored": int(n)}
+
+
+def stream_leg(code, bcode, args):
+    """Per-request latency of the decode service on the headline code: the service's maximum
+    throughput (every request arriving at once), then Poisson arrivals at 50 % and 90 % of it;
+    latency = completion - arrival per request, host staging and PCIe both ways included."""
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import sample
+    N = args.stream_requests
+    e, S = sample(code, 2 * N, seed=args.seed + 777)
+
+    def run(arrivals, pool):
+        srv = binding.Server(16 << 30)
+        cid, lanes = srv.add_code(bcode, code.priors, batch_shots=16384, max_lanes=3, max_iter=args.max_iter)
+        out = np.zeros((pool.shape[0], code.n), dtype=np.uint8)
+        srv.submit_many(cid, pool, out, np.arange(pool.shape[0], dtype=np.uint64), arrivals)
+        srv.start()
+        srv.wait(pool.shape[0], timeout_s=300)
+        comp = srv.completions()
+        srv.close()
+        lat = comp["done_us"] - comp["arrival_us"]
+        span = (comp["done_us"].max() - comp["arrival_us"].min()) * 1e-6
+        return lat, pool.shape[0] / span, comp["batch_size"].mean()
+
+    _, max_rate, _ = run(np.zeros(2 * N), S)
+    res = {"code": "[[144,12,12]] p=0.05, BP 50 + LSD-0", "requests_per_point": N,
+           "max_throughput_shots_per_s": round(max_rate, 1), "points": []}
+    rng = np.random.default_rng(args.seed)
+    for frac in (0.5, 0.9):
+        rate = frac * max_rate
+        arr = np.cumsum(rng.exponential(1e6 / rate, size=N))
+        lat, thr, mb = run(arr, S[:N])
+        res["points"].append({"offered_frac_of_max": frac, "offered_shots_per_s": round(rate, 1),
+                              "served_shots_per_s": round(thr, 1),
+                              "p50_us": round(float(np.percentile(lat, 50)), 1),
+                              "p99_us": round(float(np.percentile(lat, 99)), 1),
+                              "mean_batch": round(float(mb), 1)})
+    res["latency_includes"] = "host staging, PCIe copies both ways, scheduler polling"
+    return res
 
 
 _STREAMS = []
@@ -384,7 +545,11 @@ def cpu_baseline(code, errors, S, args):
     from paper_2406_18655_amd.workloads import logical_failures
     oc = oracle.Code.from_dense(code.H)
     lam = oracle.llr_from_priors(code.priors)
-    threads = min(16, os.cpu_count() or 1)
+    host = host_cpu()
+    # one worker per physical core available to this process, within the CPU share the GPU host
+    # gives one GPU (OMP_NUM_THREADS there)
+    threads = min(x for x in (host["physical_cores"], host["available_cpus"],
+                              int(os.environ.get("OMP_NUM_THREADS", "0")) or None) if x)
     mu = args.lsd_order
     omega = oracle.omega_from_llr(lam) if mu > 0 else None
     if args.workload == "dem":  # the float64 oracle takes ~ms per DEM shot: a bounded sample
@@ -400,9 +565,37 @@ def cpu_baseline(code, errors, S, args):
         tot += time.perf_counter() - t0
         done += S.shape[0]
     ler_ref = logical_failures(code, errors, corr)
+    # single-thread rate on a slice of the same sample (about 3 s)
+    k = max(1, min(S.shape[0], int(3.0 * S.shape[0] / (dt * threads))))
+    t0 = time.perf_counter()
+    oracle.decode_batch(oc, lam, S[:k], args.max_iter, mu=mu, omega=omega, nthreads=1)
+    one = k / (time.perf_counter() - t0)
     base = {"value": round(done / tot, 1), "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {S.shape[0]} shots of batch 0 decoded {done // S.shape[0]}x, {tot:.1f} s"}
+            "sample": f"first {S.shape[0]} shots of batch 0 decoded {done // S.shape[0]}x, {tot:.1f} s",
+            "single_thread_value": round(one, 1), "host": host}
     return base, ler_ref
+
+
+def host_cpu():
+    """CPU model and counts of the host this runs on (from /proc/cpuinfo and the affinity mask)."""
+    model, cores, cur = None, set(), {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k == "model name" and model is None:
+                    model = v
+                elif k == "physical id":
+                    cur["p"] = v
+                elif k == "core id":
+                    cores.add((cur.get("p"), v))
+    except OSError:
+        pass
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return {"model": model, "physical_cores": len(cores) or None, "logical_cpus": os.cpu_count(),
+            "available_cpus": avail, "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def serve_main(args):
@@ -419,7 +612,7 @@ def serve_main(args):
            ("hgp34_n32", random_34_hgp(32, p=0.03), 30, 0, 1024),
            ("bb144", bivariate_bicycle(p=0.05), 50, 0, 4096),
            ("dem936x8800", synthetic_dem(), 100, 10, 512)]
-    from paper_2406_18655_amd.workloads import DeviceSampler
+    from paper_2406_18655_amd.binding import DeviceSampler
     per_code = args.serve_requests // len(mix)
     pools = []
     for k, (name, code, T, mu, bs) in enumerate(mix):  # request syndromes, drawn on the GPU, held on the host
@@ -543,7 +736,9 @@ def copy_calibration(nbytes):
 
 if __name__ == "__main__":
     _a = parse()
-    if _a.copy_calibration:
+    if _a.record_counters:
+        record_counters(_a.record_counters[0], _a.record_counters[1], _a.counters_json)
+    elif _a.copy_calibration:
         copy_calibration(_a.copy_calibration)
     elif _a.sweep:
         sweep_main(_a)

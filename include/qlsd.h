@@ -60,6 +60,8 @@ typedef struct {
 #define QLSD_FLAG_NO_EARLY_EXIT 1u /* run all max_iter BP iterations for every shot */
 #define QLSD_FLAG_STAGE_TIMING 2u  /* record HIP events around each kernel of qlsd_decode */
 #define QLSD_FLAG_SEPARATE_LSD 4u  /* qlsd_decode: BP and LSD as two kernels, never overlapped */
+#define QLSD_FLAG_OSD0_POST 8u     /* qlsd_decode: global OSD-0 (qlsd_osd0) instead of LSD after
+                                      BP, the comparator of Sec. 2.2; needs n <= 4096, m <= 1024 */
 
 /* Per-shot status bits (qlsd_shot_info.status). */
 #define QLSD_ST_BP_CONVERGED 1u /* BP's hard decision satisfies s; no LSD was needed   */
@@ -123,6 +125,16 @@ qlsd_status qlsd_bp(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, float
  * in error; ties broken by the smaller fault index) -> corrections device u8[B*n]. */
 qlsd_status qlsd_lsd(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
                      uint8_t *corrections, qlsd_shot_info *info, void *stream);
+
+/* Global OSD-0 only (Sec. 2.2, inversion decoding): on soft information llr device float[B*n]
+ * (lower = more likely in error, ties broken by the smaller fault index) every column of H is
+ * taken in ascending (llr_j, j), the greedy pivot set over all m detectors is formed, and
+ * corrections device u8[B*n] receive the unique solution of H e = s on it (bit-exact with
+ * reducing all n columns).  info: status LSD_RUN (plus UNSAT, all-zero correction, when s is not
+ * in the image of H; BAD_LLR for NaN input), n_clusters 1, rounds and max_cluster_cols = the
+ * columns reduced before s was spanned.  QLSD_E_UNSUPPORTED beyond n = 4096 or m = 1024. */
+qlsd_status qlsd_osd0(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
+                      uint8_t *corrections, qlsd_shot_info *info, void *stream);
 
 /* Device time (ms) of the BP kernel and of the LSD kernel in the decoder's last
  * qlsd_decode call, from HIP events recorded on that call's stream around each kernel

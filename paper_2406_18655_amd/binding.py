@@ -20,9 +20,11 @@ ST_BP_CONVERGED, ST_LSD_RUN, ST_UNSAT, ST_BAD_LLR, ST_OVERFLOW = 1, 2, 4, 8, 16
 FLAG_NO_EARLY_EXIT = 1
 FLAG_STAGE_TIMING = 2
 FLAG_SEPARATE_LSD = 4
+FLAG_OSD0_POST = 8
 
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
+           "qlsd_osd0",
            "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
 
@@ -60,6 +62,7 @@ def lib():
         L.qlsd_decode_static.argtypes = [P, P, I32, P, P, P]
         L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
         L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
+        L.qlsd_osd0.argtypes = [P, P, P, I32, P, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
         L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
         L.qlsd_sync.argtypes = [P]
@@ -67,6 +70,7 @@ def lib():
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
+                   "qlsd_osd0",
                    "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -189,6 +193,12 @@ class Decoder:
         _check(lib().qlsd_lsd(self._h, _ptr(syndromes), _ptr(llr), B, _ptr(corrections), _ptr(info),
                               _stream() if stream is None else stream))
 
+    def osd0_into(self, syndromes, llr, corrections, info=None, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        self._check_io(syndromes, B, llr=llr, corrections=corrections, info=info)
+        _check(lib().qlsd_osd0(self._h, _ptr(syndromes), _ptr(llr), B, _ptr(corrections), _ptr(info),
+                               _stream() if stream is None else stream))
+
     def sync(self):
         _check(lib().qlsd_sync(self._h))
 
@@ -253,11 +263,121 @@ class Decoder:
         self.lsd_into(s, llr.contiguous(), corr, info)
         return corr, info
 
+    def osd0(self, syndromes, llr, want_info: bool = True):
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        if llr.dtype != torch.float32 or tuple(llr.shape) != (B, self.code.n) or not llr.is_cuda:
+            raise ValueError("llr must be a float32 CUDA tensor [B, n]")
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.osd0_into(s, llr.contiguous(), corr, info)
+        return corr, info
+
 
 def parse_info(info) -> np.ndarray:
     """uint8 tensor/array [B, 12] -> structured numpy array with INFO_DTYPE fields."""
     a = info.cpu().numpy() if hasattr(info, "cpu") else np.asarray(info)
     return np.ascontiguousarray(a).view(INFO_DTYPE).reshape(-1)
+
+
+# --------------------------------------------------------------------------- sampler
+SAMPLE_EXPORTS = ["qlsd_sampler_create", "qlsd_sample", "qlsd_syndromes", "qlsd_failures", "qlsd_sampler_destroy"]
+
+
+def _sample_lib():
+    L = lib()
+    if not getattr(L, "_sample_ready", False):
+        P, I32, I64, U64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64
+        L.qlsd_sampler_create.argtypes = [P, P, I32, P, P, ctypes.POINTER(P)]
+        L.qlsd_sample.argtypes = [P, U64, I64, I32, P, P, P]
+        L.qlsd_syndromes.argtypes = [P, P, I32, P, P]
+        L.qlsd_failures.argtypes = [P, P, P, I32, P, P]
+        L.qlsd_sampler_destroy.argtypes = [P]
+        for fn in SAMPLE_EXPORTS[:-1]:
+            getattr(L, fn).restype = ctypes.c_int
+        L._sample_ready = True
+    return L
+
+
+class Sampler:
+    """qlsd_sampler: the library's Philox4x64-10 code-capacity sampler (include/qlsd_sample.h).
+    Shots (seed, start .. start+B-1) equal the host generator's (workloads.sample) bit for bit."""
+
+    def __init__(self, code: Code, priors: np.ndarray, logicals: Optional[np.ndarray] = None):
+        self.code = code
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        if pri.shape != (code.n,):
+            raise ValueError("priors must have shape (n,)")
+        k = 0
+        self._lrp = np.zeros(1, dtype=np.int32)
+        self._lci = np.zeros(1, dtype=np.int32)
+        if logicals is not None and len(logicals):
+            L = np.asarray(logicals, dtype=np.uint8)
+            k = L.shape[0]
+            self._lrp, self._lci = csr_of(L)
+        h = ctypes.c_void_p()
+        _check(_sample_lib().qlsd_sampler_create(code._h, pri.ctypes.data, k, self._lrp.ctypes.data,
+                                                 self._lci.ctypes.data, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qlsd_sampler_destroy(self._h)
+            self._h = None
+
+    def sample_into(self, seed: int, start: int, errors, syndromes=None, stream: Optional[int] = None):
+        B = errors.shape[0]
+        _need(errors, (B, self.code.n), "uint8", "errors")
+        _need(syndromes, (B, self.code.m), "uint8", "syndromes", optional=True)
+        _check(_sample_lib().qlsd_sample(self._h, int(seed) & (2 ** 64 - 1), int(start), B, _ptr(errors),
+                                         _ptr(syndromes), _stream() if stream is None else stream))
+
+    def syndromes_into(self, x, out, stream: Optional[int] = None):
+        B = x.shape[0]
+        _need(x, (B, self.code.n), "uint8", "x")
+        _need(out, (B, self.code.m), "uint8", "syndromes")
+        _check(_sample_lib().qlsd_syndromes(self._h, _ptr(x), B, _ptr(out), _stream() if stream is None else stream))
+
+    def failures_into(self, errors, corrections, out, stream: Optional[int] = None):
+        B = errors.shape[0]
+        _need(errors, (B, self.code.n), "uint8", "errors")
+        _need(corrections, (B, self.code.n), "uint8", "corrections")
+        _need(out, (B,), "uint8", "fail")
+        _check(_sample_lib().qlsd_failures(self._h, _ptr(errors), _ptr(corrections), B, _ptr(out),
+                                           _stream() if stream is None else stream))
+
+
+class DeviceSampler:
+    """Bulk shots on the GPU for training, serving pools and scoring: the library's sampler with
+    device tensors in and out.  sample(shots, seed) returns shots 0..shots-1 of stream `seed`,
+    identical to workloads.sample(code, shots, seed); failures and syndromes run in the library."""
+
+    def __init__(self, code_matrix, device="cuda"):
+        self.code = code_matrix
+        self.bc = Code.from_dense(code_matrix.H)
+        self.smp = Sampler(self.bc, code_matrix.priors, code_matrix.logicals)
+
+    def sample(self, shots: int, seed: int, start: int = 0):
+        """(errors uint8 [shots,n], syndromes uint8 [shots,m]) as device tensors."""
+        import torch
+        e = torch.empty((shots, self.code.n), dtype=torch.uint8, device="cuda")
+        s = torch.empty((shots, self.code.m), dtype=torch.uint8, device="cuda")
+        self.smp.sample_into(seed, start, e, s)
+        return e, s
+
+    def failures(self, errors, corrections):
+        """bool [shots] on the device: logical failure (or word error without logicals)."""
+        import torch
+        f = torch.empty((errors.shape[0],), dtype=torch.uint8, device="cuda")
+        self.smp.failures_into(errors.contiguous(), corrections.contiguous(), f)
+        return f.bool()
+
+    def syndromes(self, corrections):
+        import torch
+        out = torch.empty((corrections.shape[0], self.code.m), dtype=torch.uint8, device="cuda")
+        self.smp.syndromes_into(corrections.contiguous(), out)
+        return out
 
 
 # --------------------------------------------------------------------------- serving

@@ -94,6 +94,9 @@ struct qlsd_decoder_s {
     int wide_grid, wide_keys_in_lds;
     int *d_ovf_list;     // max_batch: shots the LSD kernel could not hold
     uint64_t *d_wide_ws; // wide_grid * lsd_wide_ws_words(): the wide kernel's Gauss-Jordan bases
+    // global OSD-0 (qlsd_osd0, QLSD_FLAG_OSD0_POST): basis words per lane row, sort length
+    int osd_W, osd_P, osd_wave_bytes;
+    bool osd_ok;
 };
 
 namespace qlsd {
@@ -290,6 +293,18 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         d->wide = d->wide_keys_in_lds || lsd_wide_lds(g, false, with_mu) <= kLdsPerCu - 1024;
         d->wide_grid = std::min(d->num_cus, 64);
     }
+    // OSD-0: register basis for m <= 256, the wide (device-memory) basis up to 1024 rows, which
+    // reuses the wide LSD kernel's workspace (a decoder with m > 256 always has one)
+    d->osd_W = g.m <= 64 ? 1 : g.m <= 128 ? 2 : g.m <= 256 ? 4 : kWideW;
+    d->osd_P = 1;
+    while (d->osd_P < g.n) d->osd_P <<= 1;
+    d->osd_wave_bytes = (int)osd0_wave_bytes(g, d->osd_W, d->osd_P);
+    d->osd_ok = d->osd_P <= kOsdMaxSort && g.m <= kWideRows && (d->osd_W != kWideW || d->wide) &&
+                (size_t)d->osd_wave_bytes * (d->osd_W == kWideW ? 1 : 4) <= kLdsPerCu - 1024;
+    if ((params->flags & QLSD_FLAG_OSD0_POST) && !d->osd_ok) {
+        delete d;
+        return fail(QLSD_E_UNSUPPORTED, "OSD-0 supports n <= %d and m <= %d (n=%d, m=%d)", kOsdMaxSort, kWideRows, g.n, g.m);
+    }
     d->timing = (params->flags & QLSD_FLAG_STAGE_TIMING) != 0;
     for (int k = 0; k < 3; k++) d->ev[k] = nullptr;
     if (d->timing)
@@ -370,7 +385,7 @@ static BpArgs bp_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, int B) {
 // tables); 0: BP and LSD run as separate kernels.  Only for LSD with up to 128 local rows (the
 // one-kernel form then needs at most 128 VGPRs, i.e. 4 workgroups per CU, the BP default).
 static int fuse_waves(qlsd_decoder d) {
-    if (d->bp_graph || d->net || (d->params.flags & QLSD_FLAG_SEPARATE_LSD)) return 0;
+    if (d->bp_graph || d->net || (d->params.flags & (QLSD_FLAG_SEPARATE_LSD | QLSD_FLAG_OSD0_POST))) return 0;
     if (d->lsd_W > 2 || d->params.lsd_order > 0 || !d->lsd_keys_in_lds || d->bp_grid > 4 * d->num_cus) return 0;
     const size_t avail = bp_lds_bytes(d->code->g, d->bp_slots) - bp_tables_bytes(d->code->g);
     return (int)std::min<size_t>(4, avail / (size_t)d->lsd_wave_bytes);
@@ -422,6 +437,29 @@ static hipError_t run_wide(qlsd_decoder d, const Ws &ws, const uint8_t *syn, con
     w.keys_in_lds = d->wide_keys_in_lds;
     w.graph_in_lds = 0;
     return launch_lsd_wide(w, ws.wide_ws, ws.wide_grid, s);
+}
+
+// Global OSD-0 over the listed shots (list != nullptr) or shots 0..count-1.
+static hipError_t run_osd0(qlsd_decoder d, const Ws &w, const uint8_t *syn, const float *llr, int count,
+                           const int *list, const int *list_count, uint8_t *corr, qlsd_shot_info *info,
+                           int bp_iters, hipStream_t s) {
+    OsdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.g = d->code->g;
+    a.syn = syn;
+    a.llr = llr;
+    a.list = list;
+    a.list_count = list_count;
+    a.count = count;
+    a.next_item = w.ctl + kCtlItem;
+    a.corr = corr;
+    a.info = info;
+    a.bp_iters = bp_iters;
+    a.P = d->osd_P;
+    a.wave_bytes = d->osd_wave_bytes;
+    a.ws = w.wide_ws;
+    const int grid = d->osd_W == kWideW ? w.wide_grid : 8 * d->num_cus;
+    return launch_osd0(a, d->osd_W, grid, s);
 }
 
 static qlsd_status check_call(qlsd_decoder d, const void *syn, int B, const void *out) {
@@ -479,6 +517,11 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
     if (timing) HIP_OK(hipEventRecord(d->ev[1], s));
     HIP_OK(launch_compact(w.flag, B, w.list, w.ctl + kCtlList, s));
     if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, w.llr, w.list, w.ctl + kCtlList, B, d->d_netws, s));
+    if (d->params.flags & QLSD_FLAG_OSD0_POST) {
+        HIP_OK(run_osd0(d, w, syndromes, w.llr, 0, w.list, w.ctl + kCtlList, corrections, info, d->params.max_iter, s));
+        if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
+        return QLSD_OK;
+    }
     LsdArgs l = lsd_args(d, w, syndromes, w.llr, corrections, info);
     l.list = w.list;
     l.list_count = w.ctl + kCtlList;
@@ -575,6 +618,20 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     with_overflow_list(d, w, l);
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
     HIP_OK(run_wide(d, w, syndromes, llr, corrections, info, 0, s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_osd0(qlsd_decoder d, const uint8_t *syndromes, const float *llr, int32_t B,
+                      uint8_t *corrections, qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK || B == 0) return st;
+    if (!llr) return fail(QLSD_E_INVALID, "llr is NULL");
+    if (!d->osd_ok)
+        return fail(QLSD_E_UNSUPPORTED, "OSD-0 supports n <= %d and m <= %d (n=%d, m=%d)", kOsdMaxSort, kWideRows,
+                    d->code->g.n, d->code->g.m);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
+    HIP_OK(run_osd0(d, decoder_ws(d), syndromes, llr, B, nullptr, nullptr, corrections, info, 0, s));
     return QLSD_OK;
 }
 

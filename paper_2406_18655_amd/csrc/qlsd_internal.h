@@ -104,6 +104,26 @@ size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
 hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
+// Global OSD-0 (one wavefront per shot; qlsd_osd.hip).
+struct OsdArgs {
+    DevGraph g;
+    const uint8_t *syn;        // B x m
+    const float *llr;          // B x n soft information
+    const int *list;           // shots to decode (nullable: shots 0..count-1)
+    const int *list_count;
+    int count;
+    int *next_item;            // work counter (zeroed before launch)
+    uint8_t *corr;             // B x n
+    qlsd_shot_info *info;      // B (nullable)
+    int bp_iters;
+    int P;                     // sort length: a power of two >= n
+    int wave_bytes;            // LDS per wavefront (osd0_wave_bytes)
+    uint64_t *ws;              // W = kWideW: grid * 2 * W * W * 64 words of basis
+};
+constexpr int kOsdMaxSort = 4096;  // OSD-0 sorts n <= 4096 keys in LDS
+size_t osd0_wave_bytes(const DevGraph &g, int W, int P);
+hipError_t launch_osd0(const OsdArgs &a, int W, int grid, hipStream_t st);  // W in {1, 2, 4, kWideW}
+
 // Host helpers shared by the ABI files.
 void set_last_error(const char *fmt, ...);
 int code_rows(qlsd_code c);

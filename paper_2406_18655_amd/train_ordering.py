@@ -15,7 +15,7 @@ learned_iter iterations, refinement, LSD), and reports logical error rates and t
 (--p 0.01,0.02,0.04,0.05,0.06) the training batches cycle over them, each decoded by BP with its
 own priors and fed to the net with those priors; scoring runs at every listed strength.
 Detector error model (--code dem): 936 x 8800, LSD order 10, shots drawn on the GPU
-(workloads.DeviceSampler), word error as the failure criterion.
+(the library's Philox sampler, binding.DeviceSampler), word error as the failure criterion.
 """
 from __future__ import annotations
 
@@ -58,7 +58,7 @@ class Workload:
         self._dev = {}
 
     def _sampler(self, ci):
-        from .workloads import DeviceSampler
+        from .binding import DeviceSampler
         if ci not in self._dev:
             self._dev[ci] = DeviceSampler(self.codes[ci])
         return self._dev[ci]

@@ -54,42 +54,3 @@ def logical_failures(code: CheckMatrix, errors: np.ndarray, corrections: np.ndar
     if code.logicals is None:
         return r.any(axis=1)
     return ((r @ code.logicals.T.astype(np.int32)) & 1).any(axis=1)
-
-
-class DeviceSampler:
-    """The same noise model drawn on the GPU, for bulk training and scoring data (millions of
-    detector-error-model shots, which the host sampler would take minutes to draw).  Shots come
-    from torch's Philox generator seeded per call, so a (seed, shots) pair regenerates the same
-    batch on the same software stack; they are not the host sampler's shots.  s = H e is an
-    exact float32 product (row weights are far below 2^24)."""
-
-    def __init__(self, code: CheckMatrix, device="cuda"):
-        import torch
-        self.code = code
-        self.device = torch.device(device)
-        self.priors = torch.as_tensor(code.priors, dtype=torch.float32, device=self.device)
-        self.HT = torch.as_tensor(code.H.T.astype(np.float32), device=self.device).contiguous()
-        self.logicals = None if code.logicals is None else torch.as_tensor(
-            code.logicals.T.astype(np.float32), device=self.device).contiguous()
-
-    def sample(self, shots: int, seed: int):
-        """(errors uint8 [shots,n], syndromes uint8 [shots,m]) as device tensors."""
-        import torch
-        g = torch.Generator(device=self.device)
-        g.manual_seed(int(seed))
-        u = torch.rand((shots, self.code.n), generator=g, device=self.device)
-        e = (u < self.priors).to(torch.uint8)
-        s = torch.remainder(e.to(torch.float32) @ self.HT, 2.0).to(torch.uint8).contiguous()
-        return e, s
-
-    def failures(self, errors, corrections):
-        """bool [shots] on the device, as logical_failures."""
-        import torch
-        r = (errors ^ corrections)
-        if self.logicals is None:
-            return r.any(dim=1)
-        return (torch.remainder(r.to(torch.float32) @ self.logicals, 2.0) != 0).any(dim=1)
-
-    def syndromes(self, corrections):
-        import torch
-        return torch.remainder(corrections.to(torch.float32) @ self.HT, 2.0).to(torch.uint8)

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared_symbols(header="qlsd.h"):
     with open(os.path.join(ROOT, "include", header)) as f:
         txt = f.read()
-    return sorted(set(re.findall(r"\b(qlsd_[a-z_]+)\(", txt)))
+    return sorted(set(re.findall(r"\b(qlsd_[a-z_0-9]+)\(", txt)))
 
 
 @pytest.fixture(scope="module")
@@ -33,7 +33,9 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(serve) == set(binding.SERVE_EXPORTS)
     net = [x for x in _declared_symbols("qlsd_net.h") if x.startswith(("qlsd_net", "qlsd_decoder_set_net"))]
     assert set(net) == set(binding.NET_EXPORTS)
-    for name in decl + serve + net:
+    smp = [x for x in _declared_symbols("qlsd_sample.h") if x != "qlsd_last_error"]
+    assert set(smp) == set(binding.SAMPLE_EXPORTS)
+    for name in decl + serve + net + smp:
         assert hasattr(lib, name), name
 
 

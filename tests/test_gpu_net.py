@@ -267,7 +267,8 @@ def test_dem_trained_net_gain():
     BP 30 iterations): word errors on 2^20 held-out shots drawn on the GPU, paired against plain
     BP (100 iterations) + LSD-10."""
     import os
-    from paper_2406_18655_amd.workloads import synthetic_dem, DeviceSampler
+    from paper_2406_18655_amd.workloads import synthetic_dem
+    from paper_2406_18655_amd.binding import DeviceSampler
     code = synthetic_dem()
     bc = binding.Code.from_dense(code.H)
     w = os.path.join(os.path.dirname(binding.__file__), "weights", "dem_T30.npy")
