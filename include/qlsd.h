@@ -52,9 +52,14 @@ typedef struct qlsd_decoder_s *qlsd_decoder; /* params, priors and workspace; li
 typedef struct {
     int32_t max_iter;   /* BP iterations, >= 1 (30 in the paper; 50/100 for larger graphs) */
     float ms_scaling;   /* min-sum scaling factor alpha (0.625 in the paper) */
-    int32_t lsd_order;  /* mu: extra growth steps + local exhaustive OSD order (0 = LSD-0) */
-    int32_t osd_method; /* 0 = exhaustive (OSD-E); others rejected */
+    int32_t lsd_order;  /* mu: extra growth steps per cluster after LSD-0 (0 = LSD-0); with OSD-E
+                           also the local search order, so at most 12; with OSD-CS at most 4096 */
+    int32_t osd_method; /* local reprocessing of LSD-mu: 0 = exhaustive (OSD-E) over the first
+                           min(mu, |T|) dependent columns of each cluster; 1 = combination sweep
+                           (OSD-CS): every single dependent column, then pairs among the first
+                           min(osd_order, |T|) (Appendix D's bivariate bicycle study) */
     uint32_t flags;     /* QLSD_FLAG_* */
+    int32_t osd_order;  /* OSD-CS order w in [1, 12] (osd_method 1 only) */
 } qlsd_params;
 
 #define QLSD_FLAG_NO_EARLY_EXIT 1u /* run all max_iter BP iterations for every shot */

@@ -53,6 +53,7 @@ def lib():
             L.oracle_bp.argtypes = [P, P, P, I, D, I, P, P, P]
             L.oracle_bp_traj.argtypes = [P, P, P, I, D, I, P, P, P, P]
             L.oracle_lsd.argtypes = [P, P, P, I, P, I, P, P]
+            L.oracle_lsd_cs.argtypes = [P, P, P, I, I, P, P, P]
             L.oracle_osd0.argtypes = [P, P, P, P]
             L.oracle_decode_batch.argtypes = [P, P, P, I, I, D, I, P, P, P, P, P, I]
             L.oracle_max_threads.restype = I
@@ -141,6 +142,18 @@ def lsd(code: Code, s: np.ndarray, llr: np.ndarray, mu: int = 0, omega: np.ndarr
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.int64)
     st = lib().oracle_lsd(code._h, _p(s), _p(llr), int(mu), None if om is None else _p(om),
                           int(force_merge), _p(corr), _p(stats))
+    return corr, int(st), stats
+
+
+def lsd_cs(code: Code, s: np.ndarray, llr: np.ndarray, mu: int, cs_order: int, omega: np.ndarray):
+    """One shot of LSD-mu (mu extra growth rounds) with local OSD-CS of order cs_order
+    -> (corr uint8[n], status, stats[6]) as lsd()."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    corr = np.empty(code.n, dtype=np.uint8)
+    stats = np.zeros(6, dtype=np.int32)
+    om = np.ascontiguousarray(omega, dtype=np.int64)
+    st = lib().oracle_lsd_cs(code._h, _p(s), _p(llr), int(mu), int(cs_order), _p(om), _p(corr), _p(stats))
     return corr, int(st), stats
 
 

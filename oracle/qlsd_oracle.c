@@ -41,6 +41,12 @@
  *          then per cluster: T = its non-pivot columns in ascending key, T_w its first
  *          w = min(mu,|T|); every pattern t over T_w is scored by the integer weight
  *          sum_{x_j=1} omega_j of x = (x_P(t), t); strict minimum, smaller t on ties.
+ *   LSD-mu with local OSD-CS of order w (the combination sweep of the cited OSD work, used
+ *          by Appendix D's bivariate bicycle study with growth steps and OSD order chosen
+ *          separately): candidates in this order -- the zero pattern, every single column
+ *          of T in key order, every pair (a, b), a < b < w' = min(w, |T|), of the first w'
+ *          columns of T in lexicographic order; the strictly smallest integer weight wins,
+ *          so ties go to the candidate met first.
  */
 #include <math.h>
 #include <stdint.h>
@@ -332,7 +338,7 @@ static int cluster_is_valid(const ocode *c, const cluster_t *cl, const uint8_t *
  * columns in key order, keeping the pattern of strictly smallest integer weight.
  */
 static void cluster_solve(const ocode *c, const cluster_t *cl, const uint8_t *s, const double *llr,
-                          int mu, const int64_t *omega, int *rowpos, uint8_t *corr) {
+                          int mu, int cs_order, const int64_t *omega, int *rowpos, uint8_t *corr) {
     for (int t = 0; t < cl->nrows; t++) rowpos[cl->rows[t]] = t;
     elim_t el;
     elim_build(&el, c, rowpos, cl->nrows, cl->cols, cl->ncols);
@@ -352,27 +358,57 @@ static void cluster_solve(const ocode *c, const cluster_t *cl, const uint8_t *s,
         while (b >= 0 && key_less(llr, cl->cols[v], cl->cols[T[b]])) { T[b + 1] = T[b]; b--; }
         T[b + 1] = v;
     }
-    int w = mu < nt ? mu : nt;
-    if (w > 24) w = 24;
     int64_t best_cost = 0;
     int have = 0;
-    for (uint64_t pat = 0; pat < (1ull << w); pat++) {
-        memcpy(rhs, rhs0, sizeof(uint64_t) * el.W);
-        for (int k = 0; k < w; k++)
-            if ((pat >> k) & 1) {
-                col_bits(c, cl->cols[T[k]], rowpos, tmp, el.W);
-                for (int q = 0; q < el.W; q++) rhs[q] ^= tmp[q];
+    /* score one candidate: the columns T[sel[0..ns-1]] set, the pivot part solved */
+    int sel[2];
+    #define TRY_CANDIDATE(ns)                                                                    \
+    do {                                                                                         \
+        memcpy(rhs, rhs0, sizeof(uint64_t) * el.W);                                              \
+        for (int q_ = 0; q_ < (ns); q_++) {                                                      \
+            col_bits(c, cl->cols[T[sel[q_]]], rowpos, tmp, el.W);                                \
+            for (int r_ = 0; r_ < el.W; r_++) rhs[r_] ^= tmp[r_];                                \
+        }                                                                                        \
+        if (elim_solve(&el, rhs, x)) {                                                           \
+            for (int q_ = 0; q_ < (ns); q_++) bit_set(x, T[sel[q_]]);                            \
+            int64_t cost_ = 0;                                                                   \
+            for (int t_ = 0; t_ < cl->ncols; t_++)                                               \
+                if (bit_get(x, t_)) cost_ += omega ? omega[cl->cols[t_]] : 1;                    \
+            if (!have || cost_ < best_cost) {                                                    \
+                have = 1; best_cost = cost_;                                                     \
+                memcpy(best, x, sizeof(uint64_t) * el.Wc);                                       \
+            }                                                                                    \
+        }                                                                                        \
+    } while (0)
+    if (cs_order > 0) {
+        /* combination sweep: zero pattern, all singles of T, pairs among its first w' */
+        int w = cs_order < nt ? cs_order : nt;
+        TRY_CANDIDATE(0);
+        for (int a = 0; a < nt; a++) { sel[0] = a; TRY_CANDIDATE(1); }
+        for (int a = 0; a < w; a++)
+            for (int b = a + 1; b < w; b++) { sel[0] = a; sel[1] = b; TRY_CANDIDATE(2); }
+    } else {
+        int w = mu < nt ? mu : nt;
+        if (w > 24) w = 24;
+        for (uint64_t pat = 0; pat < (1ull << w); pat++) {
+            memcpy(rhs, rhs0, sizeof(uint64_t) * el.W);
+            for (int k = 0; k < w; k++)
+                if ((pat >> k) & 1) {
+                    col_bits(c, cl->cols[T[k]], rowpos, tmp, el.W);
+                    for (int q = 0; q < el.W; q++) rhs[q] ^= tmp[q];
+                }
+            int ok = elim_solve(&el, rhs, x);
+            if (!ok) continue; /* cannot happen for a valid cluster; kept for plainness */
+            for (int k = 0; k < w; k++) if ((pat >> k) & 1) bit_set(x, T[k]);
+            int64_t cost = 0;
+            for (int t = 0; t < cl->ncols; t++) if (bit_get(x, t)) cost += omega ? omega[cl->cols[t]] : 1;
+            if (!have || cost < best_cost) {
+                have = 1; best_cost = cost;
+                memcpy(best, x, sizeof(uint64_t) * el.Wc);
             }
-        int ok = elim_solve(&el, rhs, x);
-        if (!ok) continue; /* cannot happen for a valid cluster; kept for plainness */
-        for (int k = 0; k < w; k++) if ((pat >> k) & 1) bit_set(x, T[k]);
-        int64_t cost = 0;
-        for (int t = 0; t < cl->ncols; t++) if (bit_get(x, t)) cost += omega ? omega[cl->cols[t]] : 1;
-        if (!have || cost < best_cost) {
-            have = 1; best_cost = cost;
-            memcpy(best, x, sizeof(uint64_t) * el.Wc);
         }
     }
+    #undef TRY_CANDIDATE
     if (have)
         for (int t = 0; t < cl->ncols; t++) if (bit_get(best, t)) corr[cl->cols[t]] = 1;
     free(T); free(rhs0); free(rhs); free(x); free(best); free(tmp);
@@ -492,8 +528,23 @@ static int lsd_round(const ocode *c, cluster_t *cl, int ncl, int *owner, int *in
  * force_merge != 0 puts every check into one cluster that may grow by any column:
  * the result is then global OSD-0.
  */
+static int lsd_impl(const void *code, const uint8_t *s, const double *llr, int mu, int cs_order,
+                    const int64_t *omega, int force_merge, uint8_t *corr, int32_t *stats);
+
 int oracle_lsd(const void *code, const uint8_t *s, const double *llr, int mu, const int64_t *omega,
                int force_merge, uint8_t *corr, int32_t *stats) {
+    return lsd_impl(code, s, llr, mu, 0, omega, force_merge, corr, stats);
+}
+
+/* LSD-mu whose local reprocessing is OSD-CS of order cs_order >= 1 instead of OSD-E (mu = 0:
+ * LSD-0, no reprocessing). */
+int oracle_lsd_cs(const void *code, const uint8_t *s, const double *llr, int mu, int cs_order,
+                  const int64_t *omega, uint8_t *corr, int32_t *stats) {
+    return lsd_impl(code, s, llr, mu, cs_order < 1 ? 1 : cs_order, omega, 0, corr, stats);
+}
+
+static int lsd_impl(const void *code, const uint8_t *s, const double *llr, int mu, int cs_order,
+                    const int64_t *omega, int force_merge, uint8_t *corr, int32_t *stats) {
     const ocode *c = (const ocode *)code;
     uint32_t status = 0;
     memset(corr, 0, c->n);
@@ -560,7 +611,8 @@ int oracle_lsd(const void *code, const uint8_t *s, const double *llr, int mu, co
             if (cl[a].ncols > maxc) maxc = cl[a].ncols;
             if (cl[a].nrows > maxr) maxr = cl[a].nrows;
             if (cl[a].frozen) continue;
-            cluster_solve(c, &cl[a], s, llr, force_merge ? 0 : mu, omega, rowpos, corr);
+            cluster_solve(c, &cl[a], s, llr, force_merge ? 0 : mu, (force_merge || mu == 0) ? 0 : cs_order, omega,
+                          rowpos, corr);
         }
         if (stats) {
             stats[0] = nalive; stats[1] = maxc; stats[2] = rounds; stats[3] = tot;

@@ -36,7 +36,10 @@ assert INFO_DTYPE.itemsize == 12
 class QlsdParams(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("ms_scaling", ctypes.c_float),
                 ("lsd_order", ctypes.c_int32), ("osd_method", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("osd_order", ctypes.c_int32)]
+
+
+OSD_E, OSD_CS = 0, 1
 
 
 class QlsdError(RuntimeError):
@@ -142,13 +145,15 @@ class Decoder:
     """qlsd_decoder: params + priors + device workspace for up to max_batch shots."""
 
     def __init__(self, code: Code, priors: np.ndarray, max_batch: int, max_iter: int = 30,
-                 ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0):
+                 ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0, osd_method: int = OSD_E,
+                 osd_order: int = 0):
         self.code = code
         self.max_batch = int(max_batch)
         pri = np.ascontiguousarray(priors, dtype=np.float64)
         if pri.shape != (code.n,):
             raise ValueError("priors must have shape (n,)")
-        self.params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags))
+        self.params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), int(osd_method), int(flags),
+                                 int(osd_order))
         h = ctypes.c_void_p()
         _check(lib().qlsd_decoder_create(code._h, ctypes.byref(self.params), pri.ctypes.data,
                                          self.max_batch, ctypes.byref(h)))
@@ -273,6 +278,11 @@ class Decoder:
         info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
         self.osd0_into(s, llr.contiguous(), corr, info)
         return corr, info
+
+
+def mu_from_fraction(n: int, fraction: float) -> int:
+    """LSD-mu growth steps as a fraction of the faults (Appendix D's parametrisation): round(f n)."""
+    return int(max(0, round(fraction * n)))
 
 
 def parse_info(info) -> np.ndarray:
@@ -429,7 +439,7 @@ class Server:
     def add_code(self, code: "Code", priors: np.ndarray, batch_shots: int, max_lanes: int = 2,
                  max_iter: int = 30, ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0):
         pri = np.ascontiguousarray(priors, dtype=np.float64)
-        params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags))
+        params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags), 0)
         cid, lanes = ctypes.c_int32(), ctypes.c_int32()
         _check(_serve_lib().qlsd_server_add_code(self._h, code._h, ctypes.byref(params), pri.ctypes.data,
                                                  int(batch_shots), int(max_lanes), ctypes.byref(cid),

@@ -214,9 +214,13 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     if (max_batch < 1) return fail(QLSD_E_BATCH, "max_batch must be >= 1");
     if (params->max_iter < 1 || params->max_iter > 30000) return fail(QLSD_E_INVALID, "max_iter out of range");
     if (!(params->ms_scaling > 0.f && params->ms_scaling <= 1.f)) return fail(QLSD_E_INVALID, "ms_scaling must be in (0,1]");
-    if (params->lsd_order < 0 || params->lsd_order > 12)
-        return fail(QLSD_E_UNSUPPORTED, "lsd_order must be in [0, 12]");
-    if (params->osd_method != 0) return fail(QLSD_E_UNSUPPORTED, "only osd_method 0 (exhaustive)");
+    if (params->osd_method != 0 && params->osd_method != 1)
+        return fail(QLSD_E_UNSUPPORTED, "osd_method must be 0 (exhaustive) or 1 (combination sweep)");
+    if (params->osd_method == 0 && (params->lsd_order < 0 || params->lsd_order > 12))
+        return fail(QLSD_E_UNSUPPORTED, "lsd_order must be in [0, 12] with OSD-E");
+    if (params->osd_method == 1 && (params->lsd_order < 0 || params->lsd_order > 4096 || params->osd_order < 1 ||
+                                    params->osd_order > 12))
+        return fail(QLSD_E_UNSUPPORTED, "OSD-CS needs lsd_order in [0, 4096] and osd_order in [1, 12]");
     const DevGraph &g = code->g;
     if (code->min_rw < 2) return fail(QLSD_E_INVALID, "BP needs every row weight >= 2");
     if (g.max_rw > kMaxRowWeight || g.max_cw > kMaxColWeight)
@@ -413,6 +417,7 @@ static LsdArgs lsd_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, const f
     a.keys_in_lds = d->lsd_keys_in_lds;
     a.graph_in_lds = d->lsd_graph_in_lds;
     a.mu = d->params.lsd_order;
+    a.cs_order = d->params.osd_method == 1 ? d->params.osd_order : 0;
     a.omega = d->d_omega;
     a.wave_bytes = d->lsd_wave_bytes;
     return a;

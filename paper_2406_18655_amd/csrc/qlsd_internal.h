@@ -52,7 +52,8 @@ struct LsdArgs {
                                // (a shot BP leaves unsolved ran all of it), 0 otherwise
     int keys_in_lds;
     int graph_in_lds;          // H staged as u16 CSR/CSC in LDS once per workgroup
-    int mu;                    // LSD order (0 = LSD-0)
+    int mu;                    // LSD order (0 = LSD-0): extra growth rounds, and the OSD-E order
+    int cs_order;              // > 0: local reprocessing is OSD-CS of this order instead of OSD-E
     const int64_t *omega;      // n: integer fault weights for the order-mu search (mu > 0)
     int wave_bytes;            // LDS bytes per wavefront
     int coherent_llr;          // llr rows written during this kernel by other workgroups: read them

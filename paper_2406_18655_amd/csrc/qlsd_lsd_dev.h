@@ -332,12 +332,117 @@ __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (i
 // the pivot combination of column T_k (every T_k lies in the span of the pivots).  The cost is
 // the integer weight of the set columns; the strictly smallest cost wins, the smaller t on ties.
 // Patterns are spread over the lanes.
+// Integer weight of the pivot columns set in x (uniform; every lane computes the same sum).
+template <int W>
+__device__ __forceinline__ int64_t pivot_cost(const LsdLds &S, const uint64_t (&x)[W]) {
+    int64_t cost = 0;
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        uint64_t v = x[s];
+        while (v) {
+            cost += S.wq[s * 64 + __builtin_ctzll(v)];
+            v &= v - 1;
+        }
+    }
+    return cost;
+}
+
+// z: the pivot rows of cluster c (inC) whose combination reproduces column col.
+template <int W, class G, class BB>
+__device__ __forceinline__ void column_combination(const LsdLds &S, const G &g, const BB &B, const uint64_t (&inC)[W],
+                                                   int col, int lane, uint64_t (&z)[W]) {
+    constexpr int K = 64 * W;
+    uint32_t bf = 0;
+    for (int e = g.col_ptr(col); e < g.col_ptr(col + 1); e++) {
+        const int lr = S.loc[g.row_idx(e)];
+        if (lr >= 0 && lr < K && (lr & 63) == lane) bf |= 1u << (lr >> 6);
+    }
+    uint64_t a[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) a[s] = ballot((bf >> s) & 1u) & B.piv[s];
+#pragma unroll
+    for (int s = 0; s < W; s++) z[s] = ballot(((B.piv[s] & inC[s]) >> lane) & 1ull && parity_C<W>(B, s, a));
+}
+
+// Local OSD-CS (combination sweep) of one valid cluster c: candidates in the order zero pattern,
+// every single dependent column of the cluster (T, ascending key), every pair (a, b), a < b < w,
+// of its first w dependent columns (T_w, already selected into tsel/zk/tw); each scored by the
+// integer weight of its solution; the strictly smallest cost wins, ties to the candidate met
+// first.  xc: the cluster's LSD-0 solution over pivot rows.
+template <int W, int KNP, class G, class BB>
+__device__ void osd_cs_cluster(const LsdArgs &A, const LsdLds &S, const G &g, const BB &B, const uint64_t (&xc)[W],
+                               const uint64_t (&inC)[W], int c, int nnp, int w, const float *llr, int lane) {
+    const int64_t cost0 = pivot_cost<W>(S, xc);
+    // singles: every dependent column of the cluster, best (cost, key)
+    int64_t bs_cost = INT64_MAX;
+    uint64_t bs_key = ~0ull;
+    for (int e = 0; e < nnp; e++) {
+        const int col = __builtin_amdgcn_readfirstlane(S.colNP[e]);
+        const int rr = S.loc[g.row_idx(g.col_ptr(col))];
+        if (__builtin_amdgcn_readfirstlane(S.croot[rr]) != c) continue;
+        uint64_t z[W], x[W];
+        column_combination<W>(S, g, B, inC, col, lane, z);
+#pragma unroll
+        for (int s = 0; s < W; s++) x[s] = xc[s] ^ z[s];
+        const int64_t cost = pivot_cost<W>(S, x) + A.omega[col];
+        const uint32_t kj = (G::kInLds || A.keys_in_lds) ? S.keys[col] : ordered_key(llr[col]);
+        const uint64_t key = ((uint64_t)kj << 32) | (uint32_t)col;
+        if (cost < bs_cost || (cost == bs_cost && key < bs_key)) { bs_cost = cost; bs_key = key; }
+    }
+    // pairs among T_w, lexicographic index order
+    const int npair = w * (w - 1) / 2;
+    uint64_t bp = ~0ull;  // (cost + 2^50) << 12 | pair index, the smallest per lane
+    for (int p = lane; p < npair; p += 64) {
+        int a = 0, rem = p;
+        while (rem >= w - 1 - a) { rem -= w - 1 - a; a++; }
+        const int b = a + 1 + rem;
+        uint64_t x[W];
+#pragma unroll
+        for (int s = 0; s < W; s++) x[s] = xc[s] ^ S.zk[a * W + s] ^ S.zk[b * W + s];
+        const int64_t cost = pivot_cost<W>(S, x) + S.tw[a] + S.tw[b];
+        const uint64_t key = ((uint64_t)(cost + (1ll << 50)) << 12) | (uint64_t)p;
+        bp = key < bp ? key : bp;
+    }
+    bp = wave_min_u64(bp);
+    const int64_t bp_cost = bp == ~0ull ? INT64_MAX : (int64_t)(bp >> 12) - (1ll << 50);
+    uint64_t x[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) x[s] = xc[s];
+    if (bs_cost < cost0 && bs_cost <= bp_cost) {
+        const int col = (int)(uint32_t)bs_key;
+        uint64_t z[W];
+        column_combination<W>(S, g, B, inC, col, lane, z);
+#pragma unroll
+        for (int s = 0; s < W; s++) x[s] ^= z[s];
+        if (lane == 0) atomicOr(&S.cbit[col >> 5], 1u << (col & 31));
+    } else if (bp_cost < cost0 && bp_cost < bs_cost) {
+        const int p = (int)(bp & 4095ull);
+        int a = 0, rem = p;
+        while (rem >= w - 1 - a) { rem -= w - 1 - a; a++; }
+        const int b = a + 1 + rem;
+#pragma unroll
+        for (int s = 0; s < W; s++) x[s] ^= S.zk[a * W + s] ^ S.zk[b * W + s];
+        if (lane == 0) {
+            atomicOr(&S.cbit[S.tsel[a] >> 5], 1u << (S.tsel[a] & 31));
+            atomicOr(&S.cbit[S.tsel[b] >> 5], 1u << (S.tsel[b] & 31));
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < W; s++)
+        if ((x[s] >> lane) & 1ull) {
+            const int col = S.colAt[s * 64 + lane];
+            atomicOr(&S.cbit[col >> 5], 1u << (col & 31));
+        }
+    wave_sync();
+}
+
 // KNP: capacity of the dependent-column list colNP (at most 64 * 64 entries).
 template <int W, int KNP, class G, class BB>
 __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, const BB &B,
                                const uint64_t (&x0)[W], int nrows, int npc, const float *llr, int lane) {
     constexpr int K = 64 * W;
-    const int mu = A.mu < kMaxMu ? A.mu : kMaxMu;
+    // OSD-E: T_w = the first min(mu, |T|) columns; OSD-CS: pairs among the first min(w, |T|)
+    const int mu = A.cs_order > 0 ? (A.cs_order < kMaxMu ? A.cs_order : kMaxMu) : (A.mu < kMaxMu ? A.mu : kMaxMu);
 #pragma unroll
     for (int s = 0; s < W; s++) {
         const int r = s * 64 + lane;
@@ -402,10 +507,14 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
                 }
             }
             wave_sync();
-            // search the 2^w patterns
             uint64_t xc[W];
 #pragma unroll
             for (int s = 0; s < W; s++) xc[s] = x0[s] & inC[s];
+            if (A.cs_order > 0) {
+                osd_cs_cluster<W, KNP>(A, S, g, B, xc, inC, c, nnp, w, llr, lane);
+                continue;
+            }
+            // search the 2^w patterns
             const int npat = 1 << w;
             uint64_t best = ~0ull;
             for (int pt = lane; pt < npat; pt += 64) {

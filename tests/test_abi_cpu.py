@@ -65,7 +65,7 @@ def test_null_handles_are_rejected(lib):
 
 def test_info_layout_matches_header():
     assert binding.INFO_DTYPE.itemsize == 12
-    assert ctypes.sizeof(binding.QlsdParams) == 20
+    assert ctypes.sizeof(binding.QlsdParams) == 24  # six 4-byte fields of qlsd_params
     assert binding.COMPLETION_DTYPE.itemsize == 40
     import oracle.learned as ol
     with open(os.path.join(ROOT, "include", "qlsd_net.h")) as f:

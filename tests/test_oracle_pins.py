@@ -347,3 +347,57 @@ def test_lsd_mu_truncated_reprocessing_worked_example(oracle_mod):
         assert st == 0
         assert corr.tolist() == case["correction"], case["mu"]
         assert (stats[0], stats[1], stats[2]) == (case["clusters"], case["max_cluster_cols"], case["rounds"])
+
+
+def test_lsd_cs_worked_example_reaches_past_the_first_columns(oracle_mod):
+    """On the truncation fixture with one extra growth step, T = [f3, f0]: OSD-E of order 1 only
+    flips f3 (cost 15), while OSD-CS of order 1 tries every single of T and finds {f0} (cost 1)
+    (hand-derived from the fixture's derivation; combination sweep order: zero pattern, singles
+    in key order, pairs among the first w)."""
+    g = _gold("lsd_mu_truncation_example.json")
+    code = oracle_mod.Code.from_dense(np.array(g["H"], dtype=np.uint8))
+    s = np.array(g["syndrome"], dtype=np.uint8)
+    llr = np.array(g["llr"], dtype=np.float64)
+    om = np.array(g["omega"], dtype=np.int64)
+    e1, _, _ = oracle_mod.lsd(code, s, llr, mu=1, omega=om)
+    assert e1.tolist() == [0, 0, 1, 1, 0]
+    c1, st, stats = oracle_mod.lsd_cs(code, s, llr, mu=1, cs_order=1, omega=om)
+    assert st == 0 and c1.tolist() == [1, 0, 0, 0, 0] and stats[2] == 2
+    c0, _, _ = oracle_mod.lsd_cs(code, s, llr, mu=0, cs_order=3, omega=om)
+    assert c0.tolist() == [0, 1, 1, 0, 0]  # mu = 0 is LSD-0
+
+
+def test_lsd_cs_with_two_free_columns_is_exhaustive(oracle_mod):
+    """When the grown cluster covers a connected code with n - rank(H) <= 2 dependent columns,
+    zero pattern + singles + the one pair enumerate every solution of H x = s, so OSD-CS returns
+    the minimum-cost solution (brute force over all 2^n vectors)."""
+    rng = np.random.default_rng(12)
+    done = tries = 0
+    while done < 30:
+        tries += 1
+        assert tries < 20000
+        m = int(rng.integers(4, 8))
+        n = m + int(rng.integers(-1, 2))
+        H = _random_ldpc(rng, m, n, 2)  # even columns: rank <= m - 1
+        if n - gf2_rank(H) not in (1, 2) or not H.any(axis=1).all():
+            continue
+        F = (H.T.astype(int) @ H.astype(int)) > 0
+        reach, frontier = {0}, [0]
+        while frontier:
+            j = frontier.pop()
+            for k in np.nonzero(F[j])[0]:
+                if k not in reach:
+                    reach.add(int(k)); frontier.append(int(k))
+        if len(reach) != n:
+            continue
+        e = (rng.random(n) < 0.3).astype(np.uint8)
+        s = ((H.astype(int) @ e) % 2).astype(np.uint8)
+        if not s.any():
+            continue
+        om = rng.integers(1, 50, size=n).astype(np.int64)
+        code = oracle_mod.Code.from_dense(H)
+        corr, st, stats = oracle_mod.lsd_cs(code, s, rng.normal(size=n), mu=n + 2, cs_order=2, omega=om)
+        best = min(int(om @ np.array(b)) for b in itertools.product([0, 1], repeat=n)
+                   if (((H.astype(int) @ np.array(b)) % 2) == s).all())
+        assert stats[3] == n and int(om @ corr) == best
+        done += 1
