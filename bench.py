@@ -61,6 +61,10 @@ def parse():
                     help="[[144,12,12]] over p in {0.01,0.02,0.04,0.05,0.06}: 10^6 shots per point "
                          "(15 launches of 65,536 plus one of 16,960), GPU LER and shots/s, the oracle's "
                          "LER on the first 65,536 shots, and the learned form")
+    ap.add_argument("--cluster-stats", action="store_true",
+                    help="Appendix A's cluster statistics: nu, kappa and kappa_alpha of LSD's final clusters "
+                         "(shots BP 30 does not solve) against the optimal factorization of the same errors, "
+                         "[[144,12,12]] over p and the synthetic DEM, with the Bethe-lattice estimates")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (three launches), the "
                          "reference for scaling HBM byte counters")
@@ -722,6 +726,61 @@ def sweep_main(args):
                           "learned_weights": "bb144_mix_T10.npy"}), flush=True)
 
 
+def cluster_stats_main(args):
+    """Distributions of nu (clusters per shot), kappa (largest cluster) and kappa_alpha (size-
+    weighted mean cluster size) for LSD's final clusters and for the optimal factorization
+    (connected components of the true error in the fault graph), both on the shots BP does not
+    solve, plus the optimal factorization over all shots; Bethe-lattice estimates for the fault-
+    graph degree theta (the two forms the paper prints, Appendices A and B)."""
+    import torch
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, synthetic_dem
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    def dist(x):
+        x = np.asarray(x, dtype=np.float64)
+        if x.size == 0:
+            return None
+        return {"mean": round(float(x.mean()), 4), "p50": float(np.percentile(x, 50)),
+                "p90": float(np.percentile(x, 90)), "p99": float(np.percentile(x, 99)), "max": float(x.max())}
+
+    def summary(st):
+        st = st.astype(np.float64)
+        ka = np.where(st[:, 2] > 0, st[:, 3] / np.maximum(st[:, 2], 1), 0.0)
+        return {"nu": dist(st[:, 0]), "kappa": dist(st[:, 1]), "kappa_alpha": dist(ka)}
+
+    cases = [("bb144", bivariate_bicycle(p=p), p, 0) for p in (0.01, 0.02, 0.04, 0.05, 0.06)]
+    cases.append(("dem936x8800", synthetic_dem(), None, 10))
+    for name, code, p, mu in cases:
+        B = 65536 if name == "dem936x8800" else 262144
+        bc = binding.Code.from_dense(code.H)
+        ds = binding.DeviceSampler(code)
+        e, s = ds.sample(B, args.seed + 4242)
+        dec = binding.Decoder(bc, code.priors, B, max_iter=30, lsd_order=mu)
+        llr, hard, info = dec.bp(s)
+        torch.cuda.synchronize()
+        fail = np.nonzero((binding.parse_info(info)["status"] & 1) == 0)[0]
+        idx = torch.from_numpy(fail).cuda()
+        _, _, st = dec.lsd_stats(s[idx].contiguous(), llr[idx].contiguous())
+        opt = binding.error_clusters(bc, e)
+        torch.cuda.synchronize()
+        st, opt = st.cpu().numpy(), opt.cpu().numpy()
+        F = (code.H.T.astype(np.int64) @ code.H.astype(np.int64)) > 0
+        np.fill_diagonal(F, False)
+        deg = F.sum(1)
+        theta = float(deg.max())
+        pbar = float(code.priors.mean())
+        bethe = {"theta": theta, "theta_mean": round(float(deg.mean()), 2), "p": pbar,
+                 "appendix_A": round(pbar / (1 - pbar * (theta - 1)), 5) if pbar * (theta - 1) < 1 else None,
+                 "appendix_B": round((1 + pbar) / (1 - (theta - 1) * pbar), 5) if pbar * (theta - 1) < 1 else None}
+        print(json.dumps({"workload": name, "p": p, "shots": B, "bp_max_iter": 30, "lsd_order": mu,
+                          "bp_failures": int(len(fail)),
+                          "lsd": summary(st), "optimal_on_bp_failures": summary(opt[fail]),
+                          "optimal_all_shots": summary(opt[opt[:, 2] > 0]), "bethe": bethe}), flush=True)
+
+
 def copy_calibration(nbytes):
     """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the factor that turns
     the decoder kernels' counter readings into bytes."""
@@ -738,6 +797,8 @@ if __name__ == "__main__":
     _a = parse()
     if _a.record_counters:
         record_counters(_a.record_counters[0], _a.record_counters[1], _a.counters_json)
+    elif _a.cluster_stats:
+        cluster_stats_main(_a)
     elif _a.copy_calibration:
         copy_calibration(_a.copy_calibration)
     elif _a.sweep:

@@ -86,6 +86,16 @@ typedef struct {
     int32_t max_cluster_cols; /* LSD: largest cluster, in columns */
 } qlsd_shot_info;             /* 12 bytes */
 
+/* Cluster statistics of one shot (Appendix A): nu clusters, the largest of kappa faults, and the
+ * size-weighted mean cluster size kappa_alpha = sumsq_cols / total_cols (the expected size of
+ * the cluster a random member fault belongs to).  16 bytes. */
+typedef struct {
+    int32_t n_clusters; /* nu */
+    int32_t max_cols;   /* kappa */
+    int32_t total_cols; /* faults in all clusters */
+    int32_t sumsq_cols; /* sum over clusters of the squared fault count */
+} qlsd_cluster_stats;
+
 /* H as CSR (host): row_ptr[m+1], col_idx[nnz] with columns sorted and unique per row.
  * 1 <= m, n; nnz = row_ptr[m].  Copies to the current HIP device. */
 qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *row_ptr,
@@ -130,6 +140,18 @@ qlsd_status qlsd_bp(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, float
  * in error; ties broken by the smaller fault index) -> corrections device u8[B*n]. */
 qlsd_status qlsd_lsd(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
                      uint8_t *corrections, qlsd_shot_info *info, void *stream);
+
+/* qlsd_lsd, and stats device qlsd_cluster_stats[B] receives the statistics of the clusters LSD
+ * ended with (their columns: every fault a cluster took in, pivot or not; zeros for a shot
+ * with no flipped detector, NaN input or overflow). */
+qlsd_status qlsd_lsd_stats(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
+                           uint8_t *corrections, qlsd_shot_info *info, qlsd_cluster_stats *stats, void *stream);
+
+/* The optimal factorization of Appendix A for errors device u8[B*n]: the connected components
+ * of each error's faults in the fault graph (faults adjacent iff they share a detector) ->
+ * stats device qlsd_cluster_stats[B]. */
+qlsd_status qlsd_error_clusters(qlsd_code code, const uint8_t *errors, int32_t B, qlsd_cluster_stats *stats,
+                                void *stream);
 
 /* Global OSD-0 only (Sec. 2.2, inversion decoding): on soft information llr device float[B*n]
  * (lower = more likely in error, ties broken by the smaller fault index) every column of H is

@@ -55,6 +55,7 @@ def lib():
             L.oracle_lsd.argtypes = [P, P, P, I, P, I, P, P]
             L.oracle_lsd_cs.argtypes = [P, P, P, I, I, P, P, P]
             L.oracle_osd0.argtypes = [P, P, P, P]
+            L.oracle_error_clusters.argtypes = [P, P, P]
             L.oracle_decode_batch.argtypes = [P, P, P, I, I, D, I, P, P, P, P, P, I]
             L.oracle_max_threads.restype = I
             _lib = L
@@ -132,13 +133,13 @@ def bp_min_magnitude(code: Code, lam: np.ndarray, s: np.ndarray, iters: int, alp
 
 def lsd(code: Code, s: np.ndarray, llr: np.ndarray, mu: int = 0, omega: np.ndarray | None = None,
         force_merge: bool = False):
-    """One shot of LSD-mu on soft information llr -> (corr uint8[n], status, stats[6]):
+    """One shot of LSD-mu on soft information llr -> (corr uint8[n], status, stats[7]):
     stats = clusters, largest cluster's columns, rounds, clustered columns, clustered checks,
-    largest cluster's checks."""
+    largest cluster's checks, sum of squared cluster column counts."""
     s = np.ascontiguousarray(s, dtype=np.uint8)
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     corr = np.empty(code.n, dtype=np.uint8)
-    stats = np.zeros(6, dtype=np.int32)
+    stats = np.zeros(7, dtype=np.int32)
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.int64)
     st = lib().oracle_lsd(code._h, _p(s), _p(llr), int(mu), None if om is None else _p(om),
                           int(force_merge), _p(corr), _p(stats))
@@ -147,14 +148,32 @@ def lsd(code: Code, s: np.ndarray, llr: np.ndarray, mu: int = 0, omega: np.ndarr
 
 def lsd_cs(code: Code, s: np.ndarray, llr: np.ndarray, mu: int, cs_order: int, omega: np.ndarray):
     """One shot of LSD-mu (mu extra growth rounds) with local OSD-CS of order cs_order
-    -> (corr uint8[n], status, stats[6]) as lsd()."""
+    -> (corr uint8[n], status, stats[7]) as lsd()."""
     s = np.ascontiguousarray(s, dtype=np.uint8)
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     corr = np.empty(code.n, dtype=np.uint8)
-    stats = np.zeros(6, dtype=np.int32)
+    stats = np.zeros(7, dtype=np.int32)
     om = np.ascontiguousarray(omega, dtype=np.int64)
     st = lib().oracle_lsd_cs(code._h, _p(s), _p(llr), int(mu), int(cs_order), _p(om), _p(corr), _p(stats))
     return corr, int(st), stats
+
+
+def error_clusters(code: Code, e: np.ndarray):
+    """Optimal factorization of one error (Appendix A): (nu, kappa, total faults, sum of squared
+    cluster sizes) of the connected components of its faults in the fault graph."""
+    e = np.ascontiguousarray(e, dtype=np.uint8)
+    out = np.zeros(4, dtype=np.int64)
+    lib().oracle_error_clusters(code._h, _p(e), _p(out))
+    return tuple(int(x) for x in out)
+
+
+def cluster_summary(nu, kappa, total, sumsq):
+    """Per-shot nu, kappa and kappa_alpha = sum |C|^2 / sum |C| (the expected size of the
+    cluster a random member fault belongs to, Appendix A) as float arrays; shots with no
+    cluster get kappa_alpha 0."""
+    total = np.asarray(total, dtype=np.float64)
+    return (np.asarray(nu, np.float64), np.asarray(kappa, np.float64),
+            np.where(total > 0, np.asarray(sumsq, np.float64) / np.maximum(total, 1), 0.0))
 
 
 def osd0(code: Code, s: np.ndarray, llr: np.ndarray):

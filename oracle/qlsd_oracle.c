@@ -522,9 +522,9 @@ static int lsd_round(const ocode *c, cluster_t *cl, int ncl, int *owner, int *in
 
 /*
  * LSD (order mu) on soft information llr.  corr (n bytes) receives e_hat.
- * stats (nullable, 6 ints): final cluster count, largest cluster column count,
+ * stats (nullable, 7 ints): final cluster count, largest cluster column count,
  * growth rounds, total clustered columns, total clustered checks, largest cluster
- * check count.  Returns status bits.
+ * check count, sum over clusters of the squared column count.  Returns status bits.
  * force_merge != 0 puts every check into one cluster that may grow by any column:
  * the result is then global OSD-0.
  */
@@ -548,7 +548,7 @@ static int lsd_impl(const void *code, const uint8_t *s, const double *llr, int m
     const ocode *c = (const ocode *)code;
     uint32_t status = 0;
     memset(corr, 0, c->n);
-    if (stats) memset(stats, 0, sizeof(int32_t) * 6);
+    if (stats) memset(stats, 0, sizeof(int32_t) * 7);
     for (int j = 0; j < c->n; j++)
         if (isnan(llr[j])) return (int)ST_BAD_LLR;
 
@@ -602,11 +602,12 @@ static int lsd_impl(const void *code, const uint8_t *s, const double *llr, int m
             rounds++;
         }
         /* step 6: local solutions, united into one correction */
-        int nalive = 0, maxc = 0, tot = 0, totr = 0, maxr = 0;
+        int nalive = 0, maxc = 0, tot = 0, totr = 0, maxr = 0, sumsq = 0;
         for (int a = 0; a < ncl; a++) {
             if (!cl[a].alive) continue;
             nalive++;
             tot += cl[a].ncols;
+            sumsq += cl[a].ncols * cl[a].ncols;
             totr += cl[a].nrows;
             if (cl[a].ncols > maxc) maxc = cl[a].ncols;
             if (cl[a].nrows > maxr) maxr = cl[a].nrows;
@@ -616,7 +617,7 @@ static int lsd_impl(const void *code, const uint8_t *s, const double *llr, int m
         }
         if (stats) {
             stats[0] = nalive; stats[1] = maxc; stats[2] = rounds; stats[3] = tot;
-            stats[4] = totr; stats[5] = maxr;
+            stats[4] = totr; stats[5] = maxr; stats[6] = sumsq;
         }
         free(sel); free(dsu);
     }
@@ -654,6 +655,45 @@ int oracle_osd0(const void *code, const uint8_t *s, const double *llr, uint8_t *
         for (int t = 0; t < n; t++) if (bit_get(x, t)) corr[order[t]] = 1;
     free(rhs); free(x); elim_free(&el); free(rowpos); free(order);
     return ok ? 0 : (int)ST_UNSAT;
+}
+
+/* ------------------------------------------------------ cluster statistics */
+
+/*
+ * The optimal factorization of Appendix A: the clusters of an error are the connected
+ * components of its faults in the fault graph (two faults adjacent iff they share a
+ * detector).  out (4 values): number of clusters nu, largest cluster kappa (faults), total
+ * faults, sum over clusters of the squared size (kappa_alpha = that / total).  Breadth-first
+ * search from every unvisited faulty node.
+ */
+void oracle_error_clusters(const void *code, const uint8_t *e, int64_t *out) {
+    const ocode *c = (const ocode *)code;
+    int n = c->n;
+    int *seen = (int *)calloc(n > 0 ? n : 1, sizeof(int));
+    int *queue = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int64_t nu = 0, kappa = 0, tot = 0, sq = 0;
+    for (int j0 = 0; j0 < n; j0++) {
+        if (!(e[j0] & 1) || seen[j0]) continue;
+        int head = 0, tail = 0;
+        queue[tail++] = j0;
+        seen[j0] = 1;
+        while (head < tail) {
+            int j = queue[head++];
+            for (int k = c->col_ptr[j]; k < c->col_ptr[j + 1]; k++) {
+                int i = c->row_idx[k];
+                for (int q = c->row_ptr[i]; q < c->row_ptr[i + 1]; q++) {
+                    int j2 = c->col_idx[q];
+                    if ((e[j2] & 1) && !seen[j2]) { seen[j2] = 1; queue[tail++] = j2; }
+                }
+            }
+        }
+        nu++;
+        tot += tail;
+        sq += (int64_t)tail * tail;
+        if (tail > kappa) kappa = tail;
+    }
+    out[0] = nu; out[1] = kappa; out[2] = tot; out[3] = sq;
+    free(seen); free(queue);
 }
 
 /* ---------------------------------------------------------------- BP+LSD */

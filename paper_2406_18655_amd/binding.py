@@ -24,7 +24,7 @@ FLAG_OSD0_POST = 8
 
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
-           "qlsd_osd0",
+           "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
            "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
 
@@ -66,6 +66,8 @@ def lib():
         L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
         L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
         L.qlsd_osd0.argtypes = [P, P, P, I32, P, P, P]
+        L.qlsd_lsd_stats.argtypes = [P, P, P, I32, P, P, P, P]
+        L.qlsd_error_clusters.argtypes = [P, P, I32, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
         L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
         L.qlsd_sync.argtypes = [P]
@@ -73,7 +75,7 @@ def lib():
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
-                   "qlsd_osd0",
+                   "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
                    "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
@@ -268,6 +270,20 @@ class Decoder:
         self.lsd_into(s, llr.contiguous(), corr, info)
         return corr, info
 
+    def lsd_stats(self, syndromes, llr):
+        """LSD on llr -> (corrections, info, cluster stats int32 [B, 4]: nu, kappa, total, sum of squares)."""
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        if llr.dtype != torch.float32 or tuple(llr.shape) != (B, self.code.n) or not llr.is_cuda:
+            raise ValueError("llr must be a float32 CUDA tensor [B, n]")
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device)
+        stats = torch.empty((B, 4), dtype=torch.int32, device=s.device)
+        _check(lib().qlsd_lsd_stats(self._h, _ptr(s), _ptr(llr.contiguous()), B, _ptr(corr), _ptr(info), _ptr(stats),
+                                    _stream()))
+        return corr, info, stats
+
     def osd0(self, syndromes, llr, want_info: bool = True):
         import torch
         s = self._prep(syndromes)
@@ -278,6 +294,17 @@ class Decoder:
         info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
         self.osd0_into(s, llr.contiguous(), corr, info)
         return corr, info
+
+
+def error_clusters(code: Code, errors):
+    """Optimal factorization of each error (qlsd_error_clusters) -> int32 [B, 4] device tensor:
+    nu, kappa, total faults, sum of squared cluster sizes."""
+    import torch
+    B = errors.shape[0]
+    _need(errors, (B, code.n), "uint8", "errors")
+    out = torch.empty((B, 4), dtype=torch.int32, device=errors.device)
+    _check(lib().qlsd_error_clusters(code._h, _ptr(errors), B, _ptr(out), _stream()))
+    return out
 
 
 def mu_from_fraction(n: int, fraction: float) -> int:

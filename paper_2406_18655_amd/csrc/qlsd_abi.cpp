@@ -626,6 +626,43 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     return QLSD_OK;
 }
 
+qlsd_status qlsd_lsd_stats(qlsd_decoder d, const uint8_t *syndromes, const float *llr, int32_t B,
+                           uint8_t *corrections, qlsd_shot_info *info, qlsd_cluster_stats *stats, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK || B == 0) return st;
+    if (!llr || !stats) return fail(QLSD_E_INVALID, "llr or stats is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
+    const Ws w = decoder_ws(d);
+    LsdArgs l = lsd_args(d, w, syndromes, llr, corrections, info);
+    l.count = B;
+    l.cstats = stats;
+    with_overflow_list(d, w, l);
+    HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
+    if (d->wide) {
+        LsdArgs x = lsd_args(d, w, syndromes, llr, corrections, info);
+        x.list = w.ovf_list;
+        x.list_count = w.ctl + kCtlOvf;
+        x.next_item = w.ctl + kCtlItemW;
+        x.keys_in_lds = d->wide_keys_in_lds;
+        x.graph_in_lds = 0;
+        x.cstats = stats;
+        HIP_OK(launch_lsd_wide(x, w.wide_ws, w.wide_grid, s));
+    }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_error_clusters(qlsd_code code, const uint8_t *errors, int32_t B, qlsd_cluster_stats *stats,
+                                void *stream) {
+    g_err[0] = 0;
+    if (!code || B < 0 || (B > 0 && (!errors || !stats))) return fail(QLSD_E_INVALID, "bad error-cluster call");
+    if (B == 0) return QLSD_OK;
+    if (sizeof(int32_t) * (2 * (size_t)code->g.n + code->g.m) > kLdsPerCu - 1024)
+        return fail(QLSD_E_UNSUPPORTED, "graph too large for the error-cluster kernel");
+    HIP_OK(launch_error_clusters(code->g, errors, B, stats, (hipStream_t)stream));
+    return QLSD_OK;
+}
+
 qlsd_status qlsd_osd0(qlsd_decoder d, const uint8_t *syndromes, const float *llr, int32_t B,
                       uint8_t *corrections, qlsd_shot_info *info, void *stream) {
     qlsd_status st = check_call(d, syndromes, B, corrections);

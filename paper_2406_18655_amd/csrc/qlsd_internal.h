@@ -62,6 +62,7 @@ struct LsdArgs {
     int *done_count;           // with skip_done: how many were (nullable); all done -> no work
     int *ovf_list;             // nullable: shots whose clusters outgrew the kernel's capacity are
     int *ovf_count;            //   appended here for the wide kernel (max_batch entries)
+    qlsd_cluster_stats *cstats;  // B (nullable): per-shot statistics of the final clusters
 };
 
 // BP with LSD folded in (plain decode with slot BP): a workgroup whose slots have drained turns
@@ -104,6 +105,8 @@ size_t lsd_wide_ws_words();                 // per workgroup
 size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
 hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
+
+hipError_t launch_error_clusters(const DevGraph &g, const uint8_t *e, int B, qlsd_cluster_stats *out, hipStream_t st);
 
 // Global OSD-0 (one wavefront per shot; qlsd_osd.hip).
 struct OsdArgs {

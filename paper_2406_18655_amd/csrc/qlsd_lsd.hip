@@ -112,6 +112,55 @@ __global__ __launch_bounds__(64) void lsd_wide_kernel(LsdArgs A, uint64_t *ws) {
     }
 }
 
+// Optimal factorization (Appendix A) of each error: connected components of its faults in the
+// fault graph.  One wavefront per shot (grid-stride): every detector of a faulty column remembers
+// the first faulty column that reached it and unites later ones with it (lock-free hooking of
+// the larger root under the smaller, as in LSD); then each component's size is counted at its root.
+__global__ __launch_bounds__(64) void error_cluster_kernel(DevGraph g, const uint8_t *e, int B,
+                                                           qlsd_cluster_stats *out) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    const int m = g.m, n = g.n;
+    int32_t *par = (int32_t *)smem;   // n
+    int32_t *cnt = par + n;           // n
+    int32_t *owner = cnt + n;         // m
+    for (int b = blockIdx.x; b < B; b += gridDim.x) {
+        const uint8_t *er = e + (size_t)b * n;
+        for (int j = lane; j < n; j += 64) { par[j] = j; cnt[j] = 0; }
+        for (int i = lane; i < m; i += 64) owner[i] = -1;
+        wave_sync();
+        for (int j = lane; j < n; j += 64) {
+            if (!(er[j] & 1)) continue;
+            for (int k = g.col_ptr[j]; k < g.col_ptr[j + 1]; k++) {
+                const int prev = atomicCAS(&owner[g.row_idx[k]], -1, j);
+                if (prev >= 0) unite(par, prev, j);
+            }
+        }
+        wave_sync();
+        for (int j = lane; j < n; j += 64)
+            if (er[j] & 1) atomicAdd(&cnt[find_root(par, j)], 1);
+        wave_sync();
+        uint32_t nu = 0u, mx = 0u, tot = 0u, sq = 0u;
+        for (int j = lane; j < n; j += 64) {
+            const uint32_t v = (uint32_t)cnt[j];
+            nu += v ? 1u : 0u;
+            mx = v > mx ? v : mx;
+            tot += v;
+            sq += v * v;
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            nu += (uint32_t)__shfl_xor((int)nu, off, 64);
+            const uint32_t o = (uint32_t)__shfl_xor((int)mx, off, 64);
+            mx = o > mx ? o : mx;
+            tot += (uint32_t)__shfl_xor((int)tot, off, 64);
+            sq += (uint32_t)__shfl_xor((int)sq, off, 64);
+        }
+        if (lane == 0) out[b] = qlsd_cluster_stats{(int)nu, (int)mx, (int)tot, (int)sq};
+        wave_sync();
+    }
+}
+
 // Shots flagged by BP -> a dense list (one 64-shot ballot and one atomic per wavefront).
 __global__ void compact_kernel(const uint8_t *flag, int B, int *list, int *count) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,6 +188,16 @@ size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu) 
 size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds, bool with_mu) {
     return (graph_in_lds ? lsd_graph_bytes(g.m, g.n, g.nnz) : 0) +
            lsd_wave_bytes(g, W, keys_in_lds, with_mu) * (kLsdThreads / 64);
+}
+
+hipError_t launch_error_clusters(const DevGraph &g, const uint8_t *e, int B, qlsd_cluster_stats *out, hipStream_t st) {
+    const size_t lds = sizeof(int32_t) * (2 * (size_t)g.n + g.m);
+    hipError_t err = hipFuncSetAttribute((const void *)error_cluster_kernel,
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (err != hipSuccess) return err;
+    const int grid = B < 4096 ? B : 4096;
+    hipLaunchKernelGGL(error_cluster_kernel, dim3(grid), dim3(64), lds, st, g, e, B, out);
+    return hipGetLastError();
 }
 
 size_t lsd_wide_ws_words() { return (size_t)2 * kWideW * kWideW * 64; }

@@ -617,6 +617,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     uint8_t status = QLSD_ST_LSD_RUN;
     int rounds = 0;
     auto finish = [&](uint8_t st, int ncl, int maxc) {
+        if (A.cstats && ncl == 0 && lane == 0) A.cstats[shot] = qlsd_cluster_stats{0, 0, 0, 0};
         if (A.info && lane == 0) {
             qlsd_shot_info inf;
             inf.status = st;
@@ -981,21 +982,30 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     // Largest cluster in columns (only when the caller asked for the info record): every
     // clustered fault counts once at the final root of its first detector's local row.  The
     // selection array is free after the last round (osd_e_clusters does not use it).
-    auto max_cluster_cols = [&]() -> int {
-        if (!A.info) return 0;
+    // With A.cstats the same counts also give the shot's cluster statistics.
+    auto max_cluster_cols = [&](int ncl) -> int {
+        if (!A.info && !A.cstats) return 0;
         uint32_t *cnt = (uint32_t *)S.sel;
         for (int r = lane; r < K; r += 64) cnt[r] = 0u;
         wave_sync();
         for (int j = lane; j < n; j += 64)
             if (in_col(S.incol, j)) atomicAdd(&cnt[find_root(S.croot, S.loc[g.row_idx(g.col_ptr(j))])], 1u);
         wave_sync();
-        uint32_t mx = 0u;
-        for (int r = lane; r < K; r += 64) mx = cnt[r] > mx ? cnt[r] : mx;
+        uint32_t mx = 0u, tot = 0u, sq = 0u;
+        for (int r = lane; r < K; r += 64) {
+            const uint32_t v = cnt[r];
+            mx = v > mx ? v : mx;
+            tot += v;
+            sq += v * v;
+        }
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             const uint32_t o = (uint32_t)__shfl_xor((int)mx, off, 64);
             mx = o > mx ? o : mx;
+            tot += (uint32_t)__shfl_xor((int)tot, off, 64);
+            sq += (uint32_t)__shfl_xor((int)sq, off, 64);
         }
+        if (A.cstats && lane == 0) A.cstats[shot] = qlsd_cluster_stats{ncl, (int)mx, (int)tot, (int)sq};
         return (int)mx;
     };
 
@@ -1026,12 +1036,12 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         }
         // faults of frozen clusters stay zero: their pivot rows never enter `as`
         write_row();
-        finish(status, ncl, max_cluster_cols());
+        finish(status, ncl, max_cluster_cols(ncl));
         return;
     }
     if constexpr (MU) osd_e_clusters<W, KNP>(A, S, g, B, x0, nrows, npc, llr, lane);
     write_row();
-    finish(status, ncl, max_cluster_cols());
+    finish(status, ncl, max_cluster_cols(ncl));
 }
 
 // Per-wavefront LDS block of decode_shot (lsd_layout order) at `base`.

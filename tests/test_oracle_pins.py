@@ -401,3 +401,28 @@ def test_lsd_cs_with_two_free_columns_is_exhaustive(oracle_mod):
                    if (((H.astype(int) @ np.array(b)) % 2) == s).all())
         assert stats[3] == n and int(om @ corr) == best
         done += 1
+
+
+def test_cluster_statistics_hand_worked(oracle_mod):
+    """Appendix A's statistics on the length-5 repetition code, whose fault graph is the path
+    0-1-2-3-4 (consecutive faults share a check).  Optimal factorization: error {0,1,3} has
+    clusters {0,1} and {3} (nu 2, kappa 2, kappa_alpha = (4+1)/3); error {0,2,4} has three
+    singletons (kappa_alpha 1); an empty error has none.  LSD's final clusters on the two
+    worked examples: one cluster of columns {1,2} (sum of squares 4) and one of {0,1,2,3} (16)."""
+    g = _gold("lsd_repetition_examples.json")
+    H = np.array(g["H"], dtype=np.uint8)
+    code = oracle_mod.Code.from_dense(H)
+    assert oracle_mod.error_clusters(code, np.array([1, 1, 0, 1, 0])) == (2, 2, 3, 5)
+    assert oracle_mod.error_clusters(code, np.array([1, 0, 1, 0, 1])) == (3, 1, 3, 3)
+    assert oracle_mod.error_clusters(code, np.zeros(5)) == (0, 0, 0, 0)
+    nu, kappa, ka = oracle_mod.cluster_summary([2, 3, 0], [2, 1, 0], [3, 3, 0], [5, 3, 0])
+    np.testing.assert_allclose(ka, [5 / 3, 1.0, 0.0])
+    want = {"merge": (1, 2, 4), "index_tiebreak_failure": (1, 4, 16)}
+    for case in g["cases"]:
+        _, _, stats = oracle_mod.lsd(code, np.array(case["syndrome"], dtype=np.uint8), np.full(5, 2.0))
+        assert (stats[0], stats[1], stats[6]) == want[case["name"]], case["name"]
+    # the fault graph of a (r, c)-regular H has degree theta = c (r - 1) (Appendix A): BB 15
+    bb = bivariate_bicycle()
+    F = (bb.H.T.astype(int) @ bb.H.astype(int)) > 0
+    np.fill_diagonal(F, False)
+    assert set(F.sum(1)) == {15}
