@@ -65,6 +65,10 @@ def parse():
                     help="Appendix A's cluster statistics: nu, kappa and kappa_alpha of LSD's final clusters "
                          "(shots BP 30 does not solve) against the optimal factorization of the same errors, "
                          "[[144,12,12]] over p and the synthetic DEM, with the Bethe-lattice estimates")
+    ap.add_argument("--window", action="store_true",
+                    help="(3,1) overlapping-window BP + LSD over a 12-round memory experiment on [[144,12,12]] "
+                         "(phenomenological noise): per-cycle logical error rate and shots/s against decoding "
+                         "the whole 12-round history at once")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (three launches), the "
                          "reference for scaling HBM byte counters")
@@ -726,6 +730,50 @@ def sweep_main(args):
                           "learned_weights": "bb144_mix_T10.npy"}), flush=True)
 
 
+def window_main(args):
+    """Multi-round decoding: the 12-round memory DEM of the headline code (936 detectors, 2736
+    faults) decoded by the (w=3, c=1) overlapping-window scheme and, for comparison, as one
+    12-round history; shots drawn by the library's sampler, inputs in HBM while timed."""
+    import torch
+    from paper_2406_18655_amd import binding
+    from paper_2406_18655_amd.workloads import bivariate_bicycle, round_dem
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    cycles, B, reps = 12, 16384, 8
+    for p in (0.01, 0.02, 0.025, 0.03):
+        dem = round_dem(bivariate_bicycle(p=p), cycles, p, p)
+        bc = binding.Code.from_dense(dem.H)
+        ds = binding.DeviceSampler(dem)
+        legs = {"window_3_1": binding.WindowDecoder(bc, dem.priors, dem.det_round, 3, 1, B, max_iter=30),
+                "full_history": binding.Decoder(bc, dem.priors, B, max_iter=30)}
+        res = {}
+        for name, dec in legs.items():
+            fails, ms = 0, 0.0
+            out = torch.empty((B, dem.n), dtype=torch.uint8, device="cuda")
+            for r in range(reps):
+                e, s = ds.sample(B, args.seed + 31 * r)
+                dec.decode_into(s, out)  # warm
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                dec.decode_into(s, out)
+                b.record()
+                torch.cuda.synchronize()
+                ms += a.elapsed_time(b)
+                if not torch.equal(ds.syndromes(out), s):
+                    print(f"{name}: correction does not satisfy its syndrome", file=sys.stderr)
+                    sys.exit(3)
+                fails += int(ds.failures(e, out).sum().item())
+            n = reps * B
+            q = fails / n
+            res[name] = {"ler_total": q, "sigma": float(np.sqrt(max(q, 1 / n) * (1 - q) / n)),
+                         "per_cycle": 1.0 - (1.0 - q) ** (1.0 / cycles),
+                         "shots_per_s": round(n / (ms * 1e-3), 1)}
+        print(json.dumps({"workload": f"bb144_memory_{cycles}rounds_phenomenological", "p": p,
+                          "H": f"{dem.m}x{dem.n}", "shots": reps * B, "bp_max_iter": 30, "lsd_order": 0,
+                          "windows": legs["window_3_1"].windows, **res}), flush=True)
+
+
 def cluster_stats_main(args):
     """Distributions of nu (clusters per shot), kappa (largest cluster) and kappa_alpha (size-
     weighted mean cluster size) for LSD's final clusters and for the optimal factorization
@@ -799,6 +847,8 @@ if __name__ == "__main__":
         record_counters(_a.record_counters[0], _a.record_counters[1], _a.counters_json)
     elif _a.cluster_stats:
         cluster_stats_main(_a)
+    elif _a.window:
+        window_main(_a)
     elif _a.copy_calibration:
         copy_calibration(_a.copy_calibration)
     elif _a.sweep:

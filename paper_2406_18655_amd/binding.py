@@ -417,6 +417,65 @@ class DeviceSampler:
         return out
 
 
+# --------------------------------------------------------------------------- windows
+WINDOW_EXPORTS = ["qlsd_window_create", "qlsd_window_decode", "qlsd_window_count", "qlsd_window_destroy"]
+
+
+def _window_lib():
+    L = lib()
+    if not getattr(L, "_window_ready", False):
+        P, I32 = ctypes.c_void_p, ctypes.c_int32
+        L.qlsd_window_create.argtypes = [P, P, P, I32, I32, ctypes.POINTER(QlsdParams), I32, ctypes.POINTER(P)]
+        L.qlsd_window_create.restype = ctypes.c_int
+        L.qlsd_window_decode.argtypes = [P, P, I32, P, P]
+        L.qlsd_window_decode.restype = ctypes.c_int
+        L.qlsd_window_count.argtypes = [P]
+        L.qlsd_window_count.restype = ctypes.c_int32
+        L.qlsd_window_destroy.argtypes = [P]
+        L._window_ready = True
+    return L
+
+
+class WindowDecoder:
+    """qlsd_window: (w, c) overlapping-window BP + LSD over a multi-round DEM (include/qlsd_window.h)."""
+
+    def __init__(self, code: Code, priors: np.ndarray, det_round: np.ndarray, w: int, c: int, max_batch: int,
+                 max_iter: int = 30, ms_scaling: float = 0.625, lsd_order: int = 0, flags: int = 0):
+        self.code = code
+        self.max_batch = int(max_batch)
+        pri = np.ascontiguousarray(priors, dtype=np.float64)
+        dr = np.ascontiguousarray(det_round, dtype=np.int32)
+        if pri.shape != (code.n,) or dr.shape != (code.m,):
+            raise ValueError("priors must have shape (n,) and det_round shape (m,)")
+        self.params = QlsdParams(int(max_iter), float(ms_scaling), int(lsd_order), 0, int(flags), 0)
+        h = ctypes.c_void_p()
+        _check(_window_lib().qlsd_window_create(code._h, pri.ctypes.data, dr.ctypes.data, int(w), int(c),
+                                                ctypes.byref(self.params), self.max_batch, ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.qlsd_window_destroy(self._h)
+            self._h = None
+
+    @property
+    def windows(self) -> int:
+        return int(_window_lib().qlsd_window_count(self._h))
+
+    def decode_into(self, syndromes, corrections, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        _need(syndromes, (B, self.code.m), "uint8", "syndromes")
+        _need(corrections, (B, self.code.n), "uint8", "corrections")
+        _check(_window_lib().qlsd_window_decode(self._h, _ptr(syndromes), B, _ptr(corrections),
+                                                _stream() if stream is None else stream))
+
+    def decode(self, syndromes):
+        import torch
+        corr = torch.empty((syndromes.shape[0], self.code.n), dtype=torch.uint8, device=syndromes.device)
+        self.decode_into(syndromes.contiguous(), corr)
+        return corr
+
+
 # --------------------------------------------------------------------------- serving
 SERVE_EXPORTS = ["qlsd_server_create", "qlsd_server_add_code", "qlsd_server_set_net", "qlsd_server_submit_many",
                  "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions",

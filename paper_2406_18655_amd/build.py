@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqlsd.so")
-SOURCES = ["qlsd_bp.hip", "qlsd_lsd.hip", "qlsd_osd.hip", "qlsd_sample.hip", "qlsd_net.hip", "qlsd_abi.cpp", "qlsd_serve.cpp"]
+SOURCES = ["qlsd_bp.hip", "qlsd_lsd.hip", "qlsd_osd.hip", "qlsd_sample.hip", "qlsd_window.hip", "qlsd_net.hip", "qlsd_abi.cpp", "qlsd_serve.cpp"]
 ARCH = os.environ.get("QLSD_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -19,6 +19,11 @@ Sec. 2.1; the code families are the ones its numerical results use):
   row rank.
 * ``synthetic_dem(...)`` -- a band-diagonal sparse detector matrix shaped like a
   12-round circuit-level detector error model, with log-uniform fault priors.
+* ``round_dem(code, rounds, p_data, p_meas)`` -- the detector error model of a memory
+  experiment with noisy syndrome rounds (phenomenological noise: data flips before every
+  round, flipped measurements) followed by one perfect round, with detectors per round and
+  the code's logicals carried over to the data faults; the multi-round workload of the
+  overlapping-window decoder.
 """
 from __future__ import annotations
 
@@ -37,6 +42,7 @@ class CheckMatrix:
     priors: np.ndarray                # float64 [n], 0 < p_j < 1
     Hz: Optional[np.ndarray] = None   # conjugate checks (CSS), used only to score failures
     logicals: Optional[np.ndarray] = None  # uint8 [k, n]: residual r fails iff logicals @ r != 0
+    det_round: Optional[np.ndarray] = None  # int32 [m]: syndrome round of each detector (multi-round DEMs)
 
     @property
     def m(self) -> int:
@@ -286,3 +292,34 @@ def synthetic_dem(n_det: int = 936, n_fault: int = 8800, rounds: int = 12, max_r
                 load[i] += 1
     priors = np.exp(rng.uniform(np.log(p_lo), np.log(p_hi), size=n_fault))
     return CheckMatrix(name=f"dem_{n_det}x{n_fault}_s{seed}", H=H, priors=priors)
+
+
+def round_dem(code: CheckMatrix, rounds: int = 12, p_data: float = 0.01, p_meas: float = 0.01) -> CheckMatrix:
+    """Memory experiment over `rounds` noisy syndrome rounds plus one perfect final round.
+
+    Detector (r, i) = s_i(r) xor s_i(r-1), r = 0..rounds (s(-1) = 0).  A data flip on fault j
+    before round r flips s_i(r'), r' >= r, for every check i of j, i.e. detectors (r, i) only;
+    a flipped measurement of check i in round r < rounds flips detectors (r, i) and (r+1, i).
+    Columns: data faults (r, j) at column r*n + j, then measurement faults (r, i) at
+    (rounds+1)*n + r*m + i.  The logical class of a residual is that of its summed data part,
+    so each data fault carries its code column of the logicals; measurement faults carry none.
+    det_round[(r, i)] = r.
+    """
+    H0 = code.H.astype(np.uint8)
+    m, n = H0.shape
+    R = rounds
+    nd, nm = (R + 1) * n, R * m
+    H = np.zeros(((R + 1) * m, nd + nm), dtype=np.uint8)
+    for r in range(R + 1):
+        H[r * m:(r + 1) * m, r * n:(r + 1) * n] = H0
+    for r in range(R):
+        for i in range(m):
+            H[r * m + i, nd + r * m + i] = 1
+            H[(r + 1) * m + i, nd + r * m + i] = 1
+    priors = np.concatenate([np.full(nd, p_data), np.full(nm, p_meas)])
+    logicals = None
+    if code.logicals is not None:
+        logicals = np.concatenate([np.tile(code.logicals, (1, R + 1)),
+                                   np.zeros((code.logicals.shape[0], nm), dtype=np.uint8)], axis=1)
+    det_round = np.repeat(np.arange(R + 1, dtype=np.int32), m)
+    return CheckMatrix(name=f"rounds{R}_{code.name}", H=H, priors=priors, logicals=logicals, det_round=det_round)

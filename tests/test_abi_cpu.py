@@ -35,7 +35,9 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(net) == set(binding.NET_EXPORTS)
     smp = [x for x in _declared_symbols("qlsd_sample.h") if x != "qlsd_last_error"]
     assert set(smp) == set(binding.SAMPLE_EXPORTS)
-    for name in decl + serve + net + smp:
+    win = _declared_symbols("qlsd_window.h")
+    assert set(win) == set(binding.WINDOW_EXPORTS)
+    for name in decl + serve + net + smp + win:
         assert hasattr(lib, name), name
 
 

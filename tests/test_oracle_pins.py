@@ -426,3 +426,30 @@ def test_cluster_statistics_hand_worked(oracle_mod):
     F = (bb.H.T.astype(int) @ bb.H.astype(int)) > 0
     np.fill_diagonal(F, False)
     assert set(F.sum(1)) == {15}
+
+
+def test_round_dem_structure_and_window_oracle(oracle_mod):
+    """The multi-round detector error model: summing each check's detectors over all rounds gives
+    the code syndrome of the summed data error (measurement flips cancel in pairs), so a residual
+    that satisfies every detector has a data part in ker(H); detectors per round equal m.  The
+    window oracle: one window covering every round is plain BP + LSD; with w = 3, c = 1 every
+    correction satisfies the full syndrome (each round's detectors are settled when its faults
+    are committed); the per-cycle rate inverts the compounding of independent cycles."""
+    from oracle import window as ow
+    from paper_2406_18655_amd.workloads import round_dem, repetition_code, CheckMatrix
+    base = surface_hgp(3, p=0.05)
+    dem = round_dem(base, rounds=4, p_data=0.03, p_meas=0.03)
+    m, n, R = base.m, base.n, 4
+    assert dem.H.shape == ((R + 1) * m, (R + 1) * n + R * m) and (np.bincount(dem.det_round) == m).all()
+    e, S = sample(dem, 300, seed=4)
+    D = S.reshape(300, R + 1, m).sum(axis=1) & 1
+    data = e[:, :(R + 1) * n].reshape(300, R + 1, n).sum(axis=1) & 1
+    np.testing.assert_array_equal(D, (data.astype(int) @ base.H.T.astype(int)) & 1)
+    full = ow.window_decode(dem.H, dem.priors, dem.det_round, S, w=R + 1, c=1, max_iter=20)
+    code = oracle_mod.Code.from_dense(dem.H)
+    ref, _, _, _ = oracle_mod.decode_batch(code, oracle_mod.llr_from_priors(dem.priors), S, 20)
+    np.testing.assert_array_equal(full, ref)
+    win = ow.window_decode(dem.H, dem.priors, dem.det_round, S, w=3, c=1, max_iter=20)
+    assert (((win.astype(int) @ dem.H.T.astype(int)) & 1) == S).all()
+    assert ow.windows(dem.det_round, 3, 1) == [(0, 3, 1), (1, 4, 2), (2, 5, 5)]
+    assert abs(ow.per_cycle(1 - (1 - 0.01) ** 12, 12) - 0.01) < 1e-15
