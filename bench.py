@@ -80,6 +80,10 @@ def parse():
     ap.add_argument("--record-counters", nargs=2, metavar=("PASS1_CSV", "PASS2_CSV"), default=None,
                     help="write --counters-json from two rocprofv3 counter_collection.csv files of a "
                          "bench run (SQ_INSTS_VALU SQ_ACTIVE_INST_VALU ... / SQ_ACTIVE_INST_LDS ...)")
+    ap.add_argument("--record-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    default=None,
+                    help="write --traffic-json from rocprofv3 FETCH_SIZE / WRITE_SIZE counter_collection.csv files "
+                         "of a bench run and of a --copy-calibration run")
     ap.add_argument("--latency-launches", type=int, default=200,
                     help="isolated launches timed for the per-launch latency percentiles")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming (per-request latency) leg")
@@ -365,8 +369,10 @@ def isolated_latencies(dec, batches, corr, n):
     return np.array(out)
 
 
-# VALU issue peak: 256 CUs x 4 SIMDs, one 64-lane VALU instruction per SIMD per clock at 2.4 GHz
-VALU_PEAK_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9
+# VALU issue peak: each of a CU's 4 SIMDs finishes one 64-lane VALU instruction every 4 clocks (16
+# lanes per clock), i.e. one wave-instruction per CU per clock: 256 x 2.4 GHz (the 157.3 TFLOP/s fp32
+# vector figure is this rate x 64 lanes x 2 (packed) x 2 (FMA))
+VALU_PEAK_WAVE_INSTR_PER_S = 256 * 2.4e9
 CLOCK_HZ = 2.4e9
 
 
@@ -432,6 +438,37 @@ def osd0_leg(code, bcode, batches, args, f_plain, plain_rate):
             "mcnemar_vs_bp_lsd": {"only_osd_fails": int(np.sum(f & ~f_plain)),
                                   "only_lsd_fails": int(np.sum(~f & f_plain))},
             "bp_lsd_speedup": round(plain_rate / rate, 3), "shots_scored": int(n)}
+
+
+def record_traffic(fetch, write, cfetch, cwrite, path):
+    """HBM bytes per launch of the fused BP + LSD kernel: the median FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) over its dispatches, each scaled by what the same counter reads for a
+    plain device copy of known size (mean over the calibration copies)."""
+    import csv
+
+    def per_dispatch(fn, needle):
+        v = [float(r["Counter_Value"]) for r in csv.DictReader(open(fn)) if needle in r.get("Kernel_Name", "")]
+        return v
+
+    f_k = float(np.median(per_dispatch(fetch, "bp_lds_kernel<6, 3, true, 2>")))
+    w_k = float(np.median(per_dispatch(write, "bp_lds_kernel<6, 3, true, 2>")))
+    # the 1 GiB copies (the calibration run's last, tiny copy returns a flag to the host)
+    cf = [v for v in per_dispatch(cfetch, "copyBuffer") if v > 1024.0]
+    cw = [v for v in per_dispatch(cwrite, "copyBuffer") if v > 1024.0]
+    nbytes = 1 << 30
+    f_fac = nbytes / 1024.0 / float(np.mean(cf))
+    w_fac = nbytes / 1024.0 / float(np.mean(cw))
+    rec = {"kernel": "bp_lds_kernel<6,3,true,2> (BP + LSD-0 in one kernel)",
+           "workload": "bb144_codecap_p0.05_bp50_lsd0, 65536 shots per launch",
+           "kernel_source_hash": _kernel_hash(),
+           "bytes_per_launch": round(1024.0 * (f_k * f_fac + w_k * w_fac)),
+           "fetch_kib_per_launch_raw": round(f_k, 2), "write_kib_per_launch_raw": round(w_k, 2),
+           "copy_calibration": {"bytes": nbytes, "fetch_kib_raw": round(float(np.mean(cf)), 1),
+                                "write_kib_raw": round(float(np.mean(cw)), 1),
+                                "fetch_factor": round(f_fac, 4), "write_factor": round(w_fac, 4)}}
+    with open(path, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec))
 
 
 def stream_leg(code, bcode, args):
@@ -845,6 +882,8 @@ if __name__ == "__main__":
     _a = parse()
     if _a.record_counters:
         record_counters(_a.record_counters[0], _a.record_counters[1], _a.counters_json)
+    elif _a.record_traffic:
+        record_traffic(*_a.record_traffic, _a.traffic_json)
     elif _a.cluster_stats:
         cluster_stats_main(_a)
     elif _a.window:
