@@ -480,11 +480,18 @@ def stream_leg(code, bcode, args):
     N = args.stream_requests
     e, S = sample(code, 2 * N, seed=args.seed + 777)
 
-    def run(arrivals, pool):
+    import torch
+
+    def run(arrivals, pool, device=False):
         srv = binding.Server(16 << 30)
         cid, lanes = srv.add_code(bcode, code.priors, batch_shots=16384, max_lanes=3, max_iter=args.max_iter)
-        out = np.zeros((pool.shape[0], code.n), dtype=np.uint8)
-        srv.submit_many(cid, pool, out, np.arange(pool.shape[0], dtype=np.uint64), arrivals)
+        if device:
+            pd = torch.from_numpy(np.ascontiguousarray(pool)).cuda()
+            out = torch.empty((pool.shape[0], code.n), dtype=torch.uint8, device="cuda")
+            srv.submit_many_device(cid, pd, out, np.arange(pool.shape[0], dtype=np.uint64), arrivals)
+        else:
+            out = np.zeros((pool.shape[0], code.n), dtype=np.uint8)
+            srv.submit_many(cid, pool, out, np.arange(pool.shape[0], dtype=np.uint64), arrivals)
         srv.start()
         srv.wait(pool.shape[0], timeout_s=300)
         comp = srv.completions()
@@ -507,6 +514,19 @@ def stream_leg(code, bcode, args):
                               "p99_us": round(float(np.percentile(lat, 99)), 1),
                               "mean_batch": round(float(mb), 1)})
     res["latency_includes"] = "host staging, PCIe copies both ways, scheduler polling"
+    # device-resident requests (syndromes and corrections stay in HBM): no staging, no PCIe
+    _, max_dev, _ = run(np.zeros(2 * N), S, device=True)
+    dev = {"max_throughput_shots_per_s": round(max_dev, 1), "points": []}
+    for frac in (0.5, 0.9):
+        rate = frac * max_dev
+        arr = np.cumsum(rng.exponential(1e6 / rate, size=N))
+        lat, thr, mb = run(arr, S[:N], device=True)
+        dev["points"].append({"offered_frac_of_max": frac, "offered_shots_per_s": round(rate, 1),
+                              "served_shots_per_s": round(thr, 1),
+                              "p50_us": round(float(np.percentile(lat, 50)), 1),
+                              "p99_us": round(float(np.percentile(lat, 99)), 1),
+                              "mean_batch": round(float(mb), 1)})
+    res["device_resident"] = dev
     return res
 
 
@@ -666,18 +686,19 @@ def serve_main(args):
         del e, S
     torch.cuda.synchronize()
     print(f"[serve] {per_code} requests per code sampled", file=sys.stderr, flush=True)
-    weights = os.path.join(HERE, "paper_2406_18655_amd", "weights", "bb144_mix_T10.npy")
+    wdir = os.path.join(HERE, "paper_2406_18655_amd", "weights")
+    learned_lanes = {"bb144": (10, "bb144_mix_T10.npy"), "dem936x8800": (30, "dem_T30.npy")}
     for ordering, rate in [(o, float(x)) for o in args.serve_ordering.split(",") for x in args.serve_rates.split(",")]:
         rng = np.random.default_rng(args.seed)
         srv = binding.Server(64 << 30)
         outs, cids = [], []
         for k, (name, code, T, mu, bs) in enumerate(mix):
             bc = binding.Code.from_dense(code.H)
-            learned = ordering == "learned" and name == "bb144"
+            learned = ordering == "learned" and name in learned_lanes
             cid, lanes = srv.add_code(bc, code.priors, batch_shots=bs, max_lanes=3,
-                                      max_iter=10 if learned else T, lsd_order=mu)
+                                      max_iter=learned_lanes[name][0] if learned else T, lsd_order=mu)
             if learned:
-                srv.set_net(cid, binding.Net(bc, code.priors, np.load(weights)))
+                srv.set_net(cid, binding.Net(bc, code.priors, np.load(os.path.join(wdir, learned_lanes[name][1]))))
             arr = np.cumsum(rng.exponential(1e6 / (rate / len(mix)), size=per_code))
             out = np.zeros((per_code, code.n), dtype=np.uint8)
             srv.submit_many(cid, pools[k], out, np.arange(per_code, dtype=np.uint64), arr)
@@ -703,7 +724,8 @@ def serve_main(args):
                           "p99_us": round(float(np.percentile(lat, 99)), 1),
                           "per_code": codes,
                           "ordering": "plain BP+LSD" if ordering == "plain" else
-                                      "[[144,12,12]]: BP 10 + learned refinement + LSD; others plain",
+                                      "[[144,12,12]]: BP 10 + learned refinement + LSD; DEM: BP 30 + learned "
+                                      "refinement + LSD-10; others plain",
                           "latency_includes": "host staging, PCIe copies, scheduler polling"}), flush=True)
 
 

@@ -1,16 +1,23 @@
 /*
  * qlsd_serve.h -- continuous-batching decode service over several codes (part of libqlsd.so).
  *
- * A server owns, per registered code, a few "lanes": each lane is a decoder (qlsd_decoder with
+ * A server owns, per registered code, "lanes": each lane is a decoder (qlsd_decoder with
  * max_batch = batch_shots), its own HIP stream, pinned host staging and device buffers for one
- * batch.  Lanes are the unit of admission: a code gets as many lanes as fit in the server's
- * device-memory budget (at least one, else registration fails with QLSD_E_NOMEM).  A scheduler
- * thread forms a batch for a lane as soon as the lane is free, from whatever requests of that
- * code have arrived (FIFO, up to batch_shots) -- requests that arrive while other batches run
- * wait in host memory and are admitted as lanes free up; nothing is dropped.  Batches of
- * different codes (and of different lanes of one code) overlap on the device.  Every decode is
- * the BP + LSD of qlsd_decode (include/qlsd.h), so a request's correction does not depend on
- * which other requests shared its batch.
+ * batch.  Lanes are the unit of admission by device memory, decided while the server runs: a
+ * code gets one lane at registration (else registration fails with QLSD_E_NOMEM); whenever all
+ * of its lanes are busy and at least half a batch of its requests has arrived, the scheduler
+ * adds a lane (up to max_lanes) if the decoder workspace and batch buffers fit in what is left
+ * of the server's device-memory budget; an extra lane that has been idle for the retire time
+ * (20 ms by default) is freed, returning its memory to the budget for the other codes.  A
+ * scheduler thread forms a batch for a lane as soon as the lane is free, from whatever requests
+ * of that code have arrived (FIFO, up to batch_shots) -- requests that arrive while other
+ * batches run wait and are admitted as lanes free up; nothing is dropped.  Batches of different
+ * codes (and of different lanes of one code) overlap on the device.  Every decode is the BP +
+ * LSD of qlsd_decode (include/qlsd.h), so a request's correction does not depend on which other
+ * requests shared its batch.  Requests are either host-staged (qlsd_server_submit_many: copied
+ * through pinned memory both ways) or device-resident (qlsd_server_submit_many_device: syndromes
+ * and corrections stay in device memory; a batch whose requests sit in consecutive rows is
+ * decoded in place, otherwise gathered with device-to-device copies).
  *
  * Arrival times make open-loop load tests possible without a host thread per request: a
  * submitted request becomes visible to the scheduler only once the server clock (microseconds
@@ -51,15 +58,17 @@ typedef struct {
  * one batch of buffers per lane). */
 qlsd_status qlsd_server_create(size_t device_budget_bytes, qlsd_server *out);
 
-/* Registers a code with decoder parameters and priors (host, n doubles).  Creates up to
- * max_lanes lanes, each decoding batches of at most batch_shots shots, as far as the budget
- * allows.  *code_id receives the code's id; *lanes_out (nullable) the lanes created. */
+/* Registers a code with decoder parameters and priors (host, n doubles; copied).  Creates its
+ * first lane now; the scheduler adds lanes up to max_lanes while the budget allows (see above).
+ * Each lane decodes batches of at most batch_shots shots.  *code_id receives the code's id;
+ * *lanes_out (nullable) the lanes created now (1). */
 qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_params *params,
                                  const double *priors, int32_t batch_shots, int32_t max_lanes,
                                  int32_t *code_id, int32_t *lanes_out);
 
 /* Attaches a learned LLR refinement (include/qlsd_net.h, built for the same code) to every lane
- * of code_id, or detaches it with net = NULL; only before qlsd_server_start.  The net is shared
+ * of code_id (and to the lanes it gets later), or detaches it with net = NULL; only before
+ * qlsd_server_start.  The net is shared
  * read-only by the lanes and must outlive the server.  On large graphs each lane's decoder gets a
  * feature workspace, charged to the device budget (QLSD_E_NOMEM if it does not fit). */
 qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net);
@@ -70,6 +79,19 @@ qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net);
 qlsd_status qlsd_server_submit_many(qlsd_server s, int32_t code_id, int32_t count,
                                     const uint8_t *syndromes, uint8_t *corrections_out,
                                     const uint64_t *tags, const double *arrival_us);
+
+/* As qlsd_server_submit_many with device-resident requests: syndromes device u8[count*m] and
+ * corrections_out device u8[count*n] (caller-owned, valid until the completions are reported);
+ * no host staging or PCIe copies.  A batch holds requests of one kind only. */
+qlsd_status qlsd_server_submit_many_device(qlsd_server s, int32_t code_id, int32_t count,
+                                           const uint8_t *syndromes, uint8_t *corrections_out,
+                                           const uint64_t *tags, const double *arrival_us);
+
+/* Lanes of a code: *now currently held, *created and *retired so far (each nullable). */
+qlsd_status qlsd_server_lanes(qlsd_server s, int32_t code_id, int32_t *now, int32_t *created, int32_t *retired);
+
+/* Idle time (microseconds) after which an extra lane is freed; only before qlsd_server_start. */
+qlsd_status qlsd_server_set_retire_us(qlsd_server s, double retire_us);
 
 /* Starts the scheduler thread; the server clock starts at 0 here. */
 qlsd_status qlsd_server_start(qlsd_server s);

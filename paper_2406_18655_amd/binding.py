@@ -478,6 +478,7 @@ class WindowDecoder:
 
 # --------------------------------------------------------------------------- serving
 SERVE_EXPORTS = ["qlsd_server_create", "qlsd_server_add_code", "qlsd_server_set_net", "qlsd_server_submit_many",
+                 "qlsd_server_submit_many_device", "qlsd_server_lanes", "qlsd_server_set_retire_us",
                  "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions",
                  "qlsd_server_now_us", "qlsd_server_destroy"]
 
@@ -495,6 +496,9 @@ def _serve_lib():
         L.qlsd_server_add_code.argtypes = [P, P, ctypes.POINTER(QlsdParams), P, I32, I32,
                                            ctypes.POINTER(I32), ctypes.POINTER(I32)]
         L.qlsd_server_submit_many.argtypes = [P, I32, I32, P, P, P, P]
+        L.qlsd_server_submit_many_device.argtypes = [P, I32, I32, P, P, P, P]
+        L.qlsd_server_lanes.argtypes = [P, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)]
+        L.qlsd_server_set_retire_us.argtypes = [P, D]
         L.qlsd_server_set_net.argtypes = [P, I32, P]
         L.qlsd_server_start.argtypes = [P]
         L.qlsd_server_wait.argtypes = [P, I64, D]
@@ -503,6 +507,7 @@ def _serve_lib():
         L.qlsd_server_now_us.restype = D
         L.qlsd_server_destroy.argtypes = [P]
         for fn in ("qlsd_server_create", "qlsd_server_add_code", "qlsd_server_set_net", "qlsd_server_submit_many",
+                   "qlsd_server_submit_many_device", "qlsd_server_lanes", "qlsd_server_set_retire_us",
                    "qlsd_server_start", "qlsd_server_wait", "qlsd_server_completions"):
             getattr(L, fn).restype = ctypes.c_int
         L._serve_ready = True
@@ -554,6 +559,28 @@ class Server:
         _check(_serve_lib().qlsd_server_submit_many(self._h, int(code_id), S.shape[0], S.ctypes.data,
                                                     outputs.ctypes.data, tg.ctypes.data,
                                                     None if ar is None else ar.ctypes.data))
+
+    def submit_many_device(self, code_id: int, syndromes, outputs, tags: np.ndarray,
+                           arrival_us: Optional[np.ndarray] = None):
+        """Device-resident requests: syndromes uint8 CUDA [N, m], outputs uint8 CUDA [N, n]."""
+        m, n = self.codes[code_id]
+        N = syndromes.shape[0]
+        _need(syndromes, (N, m), "uint8", "syndromes")
+        _need(outputs, (N, n), "uint8", "outputs")
+        tg = np.ascontiguousarray(tags, dtype=np.uint64)
+        ar = None if arrival_us is None else np.ascontiguousarray(arrival_us, dtype=np.float64)
+        self._keep += [syndromes, outputs, tg, ar]
+        _check(_serve_lib().qlsd_server_submit_many_device(self._h, int(code_id), N, _ptr(syndromes), _ptr(outputs),
+                                                           tg.ctypes.data, None if ar is None else ar.ctypes.data))
+
+    def lanes(self, code_id: int):
+        """(lanes held now, created so far, retired so far) of a code."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_serve_lib().qlsd_server_lanes(self._h, int(code_id), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    def set_retire_us(self, us: float):
+        _check(_serve_lib().qlsd_server_set_retire_us(self._h, float(us)))
 
     def start(self):
         _check(_serve_lib().qlsd_server_start(self._h))

@@ -10,6 +10,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -25,6 +26,7 @@ struct Request {
     uint8_t *out;
     uint64_t tag;
     double arrival_us;
+    bool dev;  // syn and out are device memory (no host staging)
 };
 
 struct Lane {
@@ -34,19 +36,28 @@ struct Lane {
     uint8_t *d_syn = nullptr, *d_corr = nullptr, *d_info = nullptr;
     uint8_t *h_syn = nullptr, *h_corr = nullptr, *h_info = nullptr;
     bool busy = false;
+    bool dev_batch = false;   // the batch in flight holds device requests
+    double idle_since = 0.0;  // server clock when the lane last finished a batch
+    size_t bytes = 0;         // device memory charged to the budget
     std::vector<Request> batch;
 };
 
 struct Code {
-    int m = 0, n = 0, batch_shots = 0;
-    std::vector<Lane> lanes;
+    int m = 0, n = 0, batch_shots = 0, max_lanes = 1;
+    qlsd_code code = nullptr;
+    qlsd_params params{};
+    std::vector<double> priors;
+    qlsd_net net = nullptr;
+    std::vector<std::unique_ptr<Lane>> lanes;
     std::deque<Request> pending;  // arrival order
+    std::atomic<int> n_lanes{0}, created{0}, retired{0};  // read by qlsd_server_lanes
 };
 
 }  // namespace
 
 struct qlsd_server_s {
     size_t budget = 0, used = 0;
+    double retire_us = 20000.0;  // an extra lane idle this long is freed
     std::vector<Code *> codes;
     std::mutex mu;                      // pending queues and completions
     std::condition_variable cv;
@@ -91,32 +102,125 @@ void free_lane(Lane &l) {
     l = Lane();
 }
 
+// A new lane of code c if its device memory fits the remaining budget (decoder workspace, the
+// refinement workspace of an attached net, one batch of buffers); nullptr otherwise.  Runs at
+// registration and in the scheduler thread, which admits lanes as memory frees.
+std::unique_ptr<Lane> make_lane(qlsd_server_s *s, Code &c, qlsd_status *st_out) {
+    auto l = std::unique_ptr<Lane>(new (std::nothrow) Lane());
+    *st_out = QLSD_E_NOMEM;
+    if (!l) return nullptr;
+    qlsd_status st = qlsd_decoder_create(c.code, &c.params, c.priors.data(), c.batch_shots, &l->dec);
+    if (st == QLSD_OK && c.net) st = qlsd_decoder_set_net(l->dec, c.net);
+    if (st != QLSD_OK) {
+        if (l->dec) qlsd_decoder_destroy(l->dec);
+        *st_out = st;
+        return nullptr;
+    }
+    const size_t bufs = (size_t)c.batch_shots * (c.m + c.n + sizeof(qlsd_shot_info));
+    l->bytes = qlsd::decoder_device_bytes(l->dec) + bufs;
+    if (s->used + l->bytes > s->budget) {
+        qlsd_decoder_destroy(l->dec);
+        qlsd::set_last_error("device budget too small for another lane of this code");
+        return nullptr;
+    }
+    const int bs = c.batch_shots;
+    const bool ok = hipStreamCreateWithFlags(&l->stream, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&l->done, hipEventDisableTiming) == hipSuccess &&
+                    hipMalloc((void **)&l->d_syn, (size_t)bs * c.m) == hipSuccess &&
+                    hipMalloc((void **)&l->d_corr, (size_t)bs * c.n) == hipSuccess &&
+                    hipMalloc((void **)&l->d_info, (size_t)bs * sizeof(qlsd_shot_info)) == hipSuccess &&
+                    hipHostMalloc((void **)&l->h_syn, (size_t)bs * c.m, 0) == hipSuccess &&
+                    hipHostMalloc((void **)&l->h_corr, (size_t)bs * c.n, 0) == hipSuccess &&
+                    hipHostMalloc((void **)&l->h_info, (size_t)bs * sizeof(qlsd_shot_info), 0) == hipSuccess;
+    if (!ok) {
+        free_lane(*l);
+        qlsd::set_last_error("lane allocation failed");
+        return nullptr;
+    }
+    l->batch.reserve(bs);
+    l->idle_since = now_us(s);
+    s->used += l->bytes;
+    c.created++;
+    *st_out = QLSD_OK;
+    return l;
+}
+
 // Launches one batch on a free lane from the requests of code c that have arrived.  A lane
 // starts while another lane of the same code is still running only if at least half a batch has
 // arrived: at light load one batch per code is in flight (fewer small decodes contending for
 // the device), under backlog every lane works.
+// Requests arrived by time t (the pending queue is in arrival order).
+size_t arrived(const Code &c, double t) {
+    const auto end = std::upper_bound(c.pending.begin(), c.pending.end(), t,
+                                      [](double v, const Request &r) { return v < r.arrival_us; });
+    return (size_t)(end - c.pending.begin());
+}
+
+// Device requests: consecutive requests whose rows follow each other in the caller's arrays
+// form one run, moved with one device-to-device copy (a batch that is a single run is decoded
+// in place, with no copy at all).
+template <class F>
+void for_runs(const std::vector<Request> &batch, size_t row_in, size_t row_out, F &&f) {
+    size_t b = 0;
+    while (b < batch.size()) {
+        size_t e = b + 1;
+        while (e < batch.size() && batch[e].syn == batch[b].syn + (e - b) * row_in &&
+               batch[e].out == batch[b].out + (e - b) * row_out)
+            e++;
+        f(b, e);
+        b = e;
+    }
+}
+
 bool launch_batch(qlsd_server_s *s, Code &c, Lane &l, double t, int busy_lanes) {
     {
         std::lock_guard<std::mutex> g(s->mu);
-        if (busy_lanes > 0) {
-            const auto end = std::upper_bound(c.pending.begin(), c.pending.end(), t,
-                                              [](double v, const Request &r) { return v < r.arrival_us; });
-            if ((end - c.pending.begin()) * 2 < c.batch_shots) return false;
-        }
-        while (!c.pending.empty() && (int)l.batch.size() < c.batch_shots && c.pending.front().arrival_us <= t) {
+        if (busy_lanes > 0 && arrived(c, t) * 2 < (size_t)c.batch_shots) return false;
+        // one batch carries requests of one kind (host-staged or device-resident)
+        const bool dev = !c.pending.empty() && c.pending.front().dev;
+        while (!c.pending.empty() && (int)l.batch.size() < c.batch_shots && c.pending.front().arrival_us <= t &&
+               c.pending.front().dev == dev) {
             l.batch.push_back(c.pending.front());
             c.pending.pop_front();
         }
+        l.dev_batch = dev;
     }
     const int B = (int)l.batch.size();
     if (B == 0) return false;
-    for (int b = 0; b < B; b++) memcpy(l.h_syn + (size_t)b * c.m, l.batch[b].syn, c.m);
-    bool ok = hipMemcpyAsync(l.d_syn, l.h_syn, (size_t)B * c.m, hipMemcpyHostToDevice, l.stream) == hipSuccess;
-    if (ok && qlsd_decode(l.dec, l.d_syn, B, l.d_corr, (qlsd_shot_info *)l.d_info, l.stream) != QLSD_OK) {
-        fail_server(s, "decode failed: %s", qlsd_last_error());
-        return false;  // the batch's requests are not completed; waiters see the error
+    bool ok = true;
+    if (l.dev_batch) {
+        int runs = 0;
+        for_runs(l.batch, c.m, c.n, [&](size_t, size_t) { runs++; });
+        const uint8_t *syn = l.d_syn;
+        uint8_t *out = l.d_corr;
+        if (runs == 1) {
+            syn = l.batch[0].syn;
+            out = l.batch[0].out;
+        } else {
+            for_runs(l.batch, c.m, c.n, [&](size_t b, size_t e) {
+                ok = ok && hipMemcpyAsync(l.d_syn + b * c.m, l.batch[b].syn, (e - b) * c.m, hipMemcpyDeviceToDevice,
+                                          l.stream) == hipSuccess;
+            });
+        }
+        if (ok && qlsd_decode(l.dec, syn, B, out, (qlsd_shot_info *)l.d_info, l.stream) != QLSD_OK) {
+            fail_server(s, "decode failed: %s", qlsd_last_error());
+            return false;
+        }
+        if (runs > 1)
+            for_runs(l.batch, c.m, c.n, [&](size_t b, size_t e) {
+                ok = ok && hipMemcpyAsync(l.batch[b].out, l.d_corr + b * c.n, (e - b) * c.n, hipMemcpyDeviceToDevice,
+                                          l.stream) == hipSuccess;
+            });
+    } else {
+        for (int b = 0; b < B; b++) memcpy(l.h_syn + (size_t)b * c.m, l.batch[b].syn, c.m);
+        ok = hipMemcpyAsync(l.d_syn, l.h_syn, (size_t)B * c.m, hipMemcpyHostToDevice, l.stream) == hipSuccess;
+        if (ok && qlsd_decode(l.dec, l.d_syn, B, l.d_corr, (qlsd_shot_info *)l.d_info, l.stream) != QLSD_OK) {
+            fail_server(s, "decode failed: %s", qlsd_last_error());
+            return false;  // the batch's requests are not completed; waiters see the error
+        }
+        ok = ok && hipMemcpyAsync(l.h_corr, l.d_corr, (size_t)B * c.n, hipMemcpyDeviceToHost, l.stream) == hipSuccess;
     }
-    ok = ok && hipMemcpyAsync(l.h_corr, l.d_corr, (size_t)B * c.n, hipMemcpyDeviceToHost, l.stream) == hipSuccess &&
+    ok = ok &&
          hipMemcpyAsync(l.h_info, l.d_info, (size_t)B * sizeof(qlsd_shot_info), hipMemcpyDeviceToHost, l.stream) ==
              hipSuccess &&
          hipEventRecord(l.done, l.stream) == hipSuccess;
@@ -133,7 +237,7 @@ void finish_batch(qlsd_server_s *s, int code_id, Code &c, Lane &l) {
     const int B = (int)l.batch.size();
     std::vector<qlsd_completion> recs(B);
     for (int b = 0; b < B; b++) {
-        memcpy(l.batch[b].out, l.h_corr + (size_t)b * c.n, c.n);
+        if (!l.dev_batch) memcpy(l.batch[b].out, l.h_corr + (size_t)b * c.n, c.n);
         qlsd_completion &r = recs[b];
         memset(&r, 0, sizeof(r));
         r.tag = l.batch[b].tag;
@@ -145,6 +249,7 @@ void finish_batch(qlsd_server_s *s, int code_id, Code &c, Lane &l) {
     }
     l.batch.clear();
     l.busy = false;
+    l.idle_since = t;
     {
         std::lock_guard<std::mutex> g(s->mu);
         s->done.insert(s->done.end(), recs.begin(), recs.end());
@@ -157,11 +262,27 @@ void scheduler(qlsd_server_s *s) {
     while (true) {
         bool progress = false, any_busy = false;
         const double t = now_us(s);
+        // retire extra lanes that have idled: their memory admits lanes of codes with a backlog
+        for (Code *cp : s->codes) {
+            Code &c = *cp;
+            for (size_t k = c.lanes.size(); k-- > 1;) {
+                Lane &l = *c.lanes[k];
+                if (!l.busy && t - l.idle_since > s->retire_us) {
+                    s->used -= l.bytes;
+                    free_lane(l);
+                    c.lanes.erase(c.lanes.begin() + (long)k);
+                    c.retired++;
+                    c.n_lanes = (int)c.lanes.size();
+                    progress = true;
+                }
+            }
+        }
         for (size_t ci = 0; ci < s->codes.size(); ci++) {
             Code &c = *s->codes[ci];
             int busy = 0;
-            for (Lane &l : c.lanes) busy += l.busy ? 1 : 0;
-            for (Lane &l : c.lanes) {
+            for (auto &lp : c.lanes) busy += lp->busy ? 1 : 0;
+            for (auto &lp : c.lanes) {
+                Lane &l = *lp;
                 if (l.busy) {
                     const hipError_t q = hipEventQuery(l.done);
                     if (q == hipSuccess) {
@@ -172,8 +293,8 @@ void scheduler(qlsd_server_s *s) {
                         fail_server(s, "device failure: %s", hipGetErrorString(q));
                         // let in-flight work drain before the thread ends
                         for (Code *cc : s->codes)
-                            for (Lane &ll : cc->lanes)
-                                if (ll.busy) hipStreamSynchronize(ll.stream);
+                            for (auto &ll : cc->lanes)
+                                if (ll->busy) hipStreamSynchronize(ll->stream);
                         return;
                     }
                 }
@@ -182,6 +303,24 @@ void scheduler(qlsd_server_s *s) {
                     progress = true;
                 }
                 any_busy |= l.busy;
+            }
+            // every lane busy and a backlog of at least half a batch: admit one more lane if the
+            // budget has room for it now
+            if (!s->failed.load() && busy == (int)c.lanes.size() && (int)c.lanes.size() < c.max_lanes) {
+                size_t backlog;
+                {
+                    std::lock_guard<std::mutex> g(s->mu);
+                    backlog = arrived(c, t);
+                }
+                if (backlog * 2 >= (size_t)c.batch_shots) {
+                    qlsd_status st;
+                    auto nl = make_lane(s, c, &st);
+                    if (nl) {
+                        c.lanes.push_back(std::move(nl));
+                        c.n_lanes = (int)c.lanes.size();
+                        progress = true;
+                    }
+                }
             }
         }
         if (s->stop.load() && !any_busy) return;
@@ -218,40 +357,18 @@ qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_param
     c->m = qlsd::code_rows(code);
     c->n = qlsd::code_cols(code);
     c->batch_shots = batch_shots;
-    for (int k = 0; k < max_lanes; k++) {
-        Lane l;
-        qlsd_status st = qlsd_decoder_create(code, params, priors, batch_shots, &l.dec);
-        if (st != QLSD_OK) {
-            if (k == 0) { delete c; return st; }
-            break;
-        }
-        const size_t bufs = (size_t)batch_shots * (c->m + c->n + sizeof(qlsd_shot_info));
-        const size_t need = qlsd::decoder_device_bytes(l.dec) + bufs;
-        if (s->used + need > s->budget) {
-            qlsd_decoder_destroy(l.dec);
-            if (k == 0) {
-                delete c;
-                return serr(s, QLSD_E_NOMEM, "device budget too small for one lane of this code");
-            }
-            break;
-        }
-        bool ok = hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) == hipSuccess &&
-                  hipEventCreateWithFlags(&l.done, hipEventDisableTiming) == hipSuccess &&
-                  hipMalloc((void **)&l.d_syn, (size_t)batch_shots * c->m) == hipSuccess &&
-                  hipMalloc((void **)&l.d_corr, (size_t)batch_shots * c->n) == hipSuccess &&
-                  hipMalloc((void **)&l.d_info, (size_t)batch_shots * sizeof(qlsd_shot_info)) == hipSuccess &&
-                  hipHostMalloc((void **)&l.h_syn, (size_t)batch_shots * c->m, 0) == hipSuccess &&
-                  hipHostMalloc((void **)&l.h_corr, (size_t)batch_shots * c->n, 0) == hipSuccess &&
-                  hipHostMalloc((void **)&l.h_info, (size_t)batch_shots * sizeof(qlsd_shot_info), 0) == hipSuccess;
-        if (!ok) {
-            free_lane(l);
-            if (k == 0) { delete c; return serr(s, QLSD_E_NOMEM, "lane allocation failed"); }
-            break;
-        }
-        l.batch.reserve(batch_shots);
-        s->used += need;
-        c->lanes.push_back(std::move(l));
+    c->max_lanes = max_lanes;
+    c->code = code;
+    c->params = *params;
+    c->priors.assign(priors, priors + c->n);
+    qlsd_status st;
+    auto l = make_lane(s, *c, &st);
+    if (!l) {
+        delete c;
+        return st == QLSD_OK ? QLSD_E_NOMEM : st;
     }
+    c->lanes.push_back(std::move(l));
+    c->n_lanes = 1;
     *code_id = (int32_t)s->codes.size();
     if (lanes_out) *lanes_out = (int32_t)c->lanes.size();
     s->codes.push_back(c);
@@ -261,8 +378,10 @@ qlsd_status qlsd_server_add_code(qlsd_server s, qlsd_code code, const qlsd_param
 qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net) {
     if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
     if (s->started.load()) return serr(s, QLSD_E_INVALID, "nets must be attached before qlsd_server_start");
+    Code &c = *s->codes[code_id];
     // a net on a large graph gives every lane's decoder a feature workspace: charge it to the budget
-    for (Lane &l : s->codes[code_id]->lanes) {
+    for (auto &lp : c.lanes) {
+        Lane &l = *lp;
         const size_t before = qlsd::decoder_device_bytes(l.dec);
         const qlsd_status st = qlsd_decoder_set_net(l.dec, net);
         if (st != QLSD_OK) return st;
@@ -272,7 +391,9 @@ qlsd_status qlsd_server_set_net(qlsd_server s, int32_t code_id, qlsd_net net) {
             return serr(s, QLSD_E_NOMEM, "device budget too small for the refinement workspace of every lane");
         }
         s->used = s->used + after - before;
+        l.bytes = l.bytes + after - before;
     }
+    c.net = net;  // lanes created later get it too
     return QLSD_OK;
 }
 
@@ -288,8 +409,41 @@ qlsd_status qlsd_server_submit_many(qlsd_server s, int32_t code_id, int32_t coun
         const double a = arrival_us ? arrival_us[k] : 0.0;
         if (a < last) return serr(s, QLSD_E_INVALID, "arrival times of a code must be non-decreasing");
         last = a;
-        c.pending.push_back(Request{syndromes + (size_t)k * c.m, corrections_out + (size_t)k * c.n, tags[k], a});
+        c.pending.push_back(Request{syndromes + (size_t)k * c.m, corrections_out + (size_t)k * c.n, tags[k], a, false});
     }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_submit_many_device(qlsd_server s, int32_t code_id, int32_t count, const uint8_t *syndromes,
+                                           uint8_t *corrections_out, const uint64_t *tags, const double *arrival_us) {
+    if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
+    if (count < 0 || (count > 0 && (!syndromes || !corrections_out || !tags)))
+        return serr(s, QLSD_E_INVALID, "bad request arrays");
+    Code &c = *s->codes[code_id];
+    std::lock_guard<std::mutex> g(s->mu);
+    double last = c.pending.empty() ? -1e300 : c.pending.back().arrival_us;
+    for (int32_t k = 0; k < count; k++) {
+        const double a = arrival_us ? arrival_us[k] : 0.0;
+        if (a < last) return serr(s, QLSD_E_INVALID, "arrival times of a code must be non-decreasing");
+        last = a;
+        c.pending.push_back(Request{syndromes + (size_t)k * c.m, corrections_out + (size_t)k * c.n, tags[k], a, true});
+    }
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_lanes(qlsd_server s, int32_t code_id, int32_t *now, int32_t *created, int32_t *retired) {
+    if (!s || code_id < 0 || code_id >= (int32_t)s->codes.size()) return serr(s, QLSD_E_INVALID, "bad server or code id");
+    const Code &c = *s->codes[code_id];
+    if (now) *now = c.n_lanes.load();
+    if (created) *created = c.created.load();
+    if (retired) *retired = c.retired.load();
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_server_set_retire_us(qlsd_server s, double retire_us) {
+    if (!s || !(retire_us >= 0.0)) return serr(s, QLSD_E_INVALID, "bad server or retire time");
+    if (s->started.load()) return serr(s, QLSD_E_INVALID, "set before qlsd_server_start");
+    s->retire_us = retire_us;
     return QLSD_OK;
 }
 
@@ -332,7 +486,7 @@ void qlsd_server_destroy(qlsd_server s) {
     s->stop = true;
     if (s->worker.joinable()) s->worker.join();
     for (Code *c : s->codes) {
-        for (Lane &l : c->lanes) free_lane(l);
+        for (auto &l : c->lanes) free_lane(*l);
         delete c;
     }
     delete s;

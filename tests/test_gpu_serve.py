@@ -60,7 +60,7 @@ def test_mix_equals_alone():
     assert (comp["done_us"] >= comp["arrival_us"]).all()
     assert comp["batch_size"].max() > 1  # requests really were batched together
     for code, T, mu, S, out, lanes in jobs:
-        assert lanes == 2
+        assert lanes == 1  # one lane at registration; more are admitted at run time
         assert (((out.astype(np.int64) @ code.H.T.astype(np.int64)) % 2) == S).all()
         np.testing.assert_array_equal(out, _alone(code, T, mu, S))
     lat = comp["done_us"] - comp["arrival_us"]
@@ -86,14 +86,17 @@ def test_budget_limits_lanes():
     srv = binding.Server(int(2.5 * _lane_bytes(code, 4096)))
     cid, lanes = srv.add_code(binding.Code.from_dense(code.H), code.priors, batch_shots=4096, max_lanes=4,
                               max_iter=50)
-    assert lanes == 2
-    e, S = sample(code, 3000, seed=3)
-    out = np.zeros((3000, code.n), dtype=np.uint8)
-    srv.submit_many(cid, S, out, np.arange(3000, dtype=np.uint64))
+    e, S = sample(code, 30000, seed=3)
+    out = np.zeros((30000, code.n), dtype=np.uint8)
+    srv.submit_many(cid, S, out, np.arange(30000, dtype=np.uint64))
     srv.start()
-    srv.wait(3000, timeout_s=60)
-    assert len(srv.completions()) == 3000
+    srv.wait(30000, timeout_s=60)
+    assert len(srv.completions()) == 30000
+    now, created, retired = srv.lanes(cid)
     srv.close()
+    # the backlog admitted a second lane (perhaps more than once, after a retirement); a third
+    # never fits: lanes held at once stay at two
+    assert lanes == 1 and created >= 2 and created - retired <= 2
     np.testing.assert_array_equal(out, _alone(code, 50, 0, S))
 
 
@@ -174,3 +177,58 @@ def test_served_results_against_oracle(oracle_mod):
         print(f"{code.name}: served {f_srv.mean():.4f} oracle {f_ref.mean():.4f} (2 sigma {two_sigma:.4f}); "
               f"{int((~conv).sum())} LSD requests bit-exact; BP sample exempt {exempt}")
         assert abs(f_srv.mean() - f_ref.mean()) <= two_sigma
+
+
+def test_lanes_admitted_as_memory_frees():
+    """Two codes share a budget with room for one extra lane in total.  A backlog of code A first
+    takes that room; once A goes idle its extra lane is retired, and a later backlog of code B is
+    admitted into the freed memory.  Every request is served, equal to its decoder alone."""
+    a, b = bivariate_bicycle(p=0.05), random_34_hgp(16, p=0.03)
+    ba, bb_ = binding.Code.from_dense(a.H), binding.Code.from_dense(b.H)
+    la, lb = _lane_bytes(a, 4096), _lane_bytes(b, 4096)
+    srv = binding.Server(int(la + lb + 1.05 * max(la, lb)))
+    srv.set_retire_us(10000.0)
+    ca, _ = srv.add_code(ba, a.priors, batch_shots=4096, max_lanes=3, max_iter=50)
+    cb, _ = srv.add_code(bb_, b.priors, batch_shots=4096, max_lanes=3, max_iter=30)
+    ea, Sa = sample(a, 20000, seed=81)
+    eb, Sb = sample(b, 20000, seed=82)
+    oa, ob = np.zeros((20000, a.n), np.uint8), np.zeros((20000, b.n), np.uint8)
+    srv.submit_many(ca, Sa, oa, np.arange(20000, dtype=np.uint64), np.zeros(20000))
+    srv.submit_many(cb, Sb, ob, np.arange(20000, dtype=np.uint64), np.full(20000, 200000.0))  # 200 ms later
+    srv.start()
+    srv.wait(40000, timeout_s=120)
+    assert len(srv.completions()) == 40000
+    na, cra, rea = srv.lanes(ca)
+    nb, crb, reb = srv.lanes(cb)
+    srv.close()
+    print(f"A: created {cra} retired {rea}; B: created {crb} retired {reb}")
+    # B's second lane only fits once A's extra lane has been retired
+    assert cra >= 2 and rea >= 1 and crb == 2
+    np.testing.assert_array_equal(oa, _alone(a, 50, 0, Sa))
+    np.testing.assert_array_equal(ob, _alone(b, 30, 0, Sb))
+
+
+def test_device_resident_requests():
+    """Requests whose syndromes and corrections stay in device memory (no host staging), mixed
+    with host-staged requests of the same code; both equal the decoder alone."""
+    code = bivariate_bicycle(p=0.05)
+    bc = binding.Code.from_dense(code.H)
+    srv = binding.Server(8 << 30)
+    cid, _ = srv.add_code(bc, code.priors, batch_shots=2048, max_lanes=2, max_iter=50)
+    e, S = sample(code, 9000, seed=83)
+    sd = torch.from_numpy(S[:6000]).cuda()
+    od = torch.zeros((6000, code.n), dtype=torch.uint8, device="cuda")
+    oh = np.zeros((3000, code.n), dtype=np.uint8)
+    rng = np.random.default_rng(2)
+    arr = np.cumsum(rng.exponential(2.0, size=9000))
+    srv.submit_many_device(cid, sd[:4000], od[:4000], np.arange(4000, dtype=np.uint64), arr[:4000])
+    srv.submit_many(cid, S[6000:], oh, np.arange(3000, dtype=np.uint64) + 10000, arr[4000:7000])
+    srv.submit_many_device(cid, sd[4000:], od[4000:], np.arange(2000, dtype=np.uint64) + 20000, arr[7000:])
+    srv.start()
+    srv.wait(9000, timeout_s=60)
+    comp = srv.completions()
+    srv.close()
+    assert len(comp) == 9000
+    ref = _alone(code, 50, 0, S)
+    np.testing.assert_array_equal(od.cpu().numpy(), ref[:6000])
+    np.testing.assert_array_equal(oh, ref[6000:])
