@@ -174,11 +174,26 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms)
  * B <= max_batch, typically one full batch of the workload) and keeps the fastest -- for BP
  * with shot slots, the slots per workgroup and workgroups per compute unit (timed on the whole
  * qlsd_decode when no refinement net is attached, since the shape decides whether BP and LSD
- * can share one kernel); for LSD, the number of workgroups.  Outputs never depend on these shapes.  Synchronous on `stream`;
+ * can share one kernel); for LSD, the number of workgroups, then the LSD capacity tier (as
+ * qlsd_decoder_set_lsd_capacity, every tier up to the decoder's default, timed on the whole
+ * decode).  Outputs never depend on these shapes.  Synchronous on `stream`;
  * allocates and frees scratch output buffers; must not overlap other calls on this decoder.
  * `report` (host char[report_len], nullable) receives one line per candidate and the choice. */
 qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, int32_t reps,
                               void *stream, char *report, int32_t report_len);
+
+/* LSD capacity tier, a schedule for uneven cluster sizes (Sec. 4.2 grows clusters of unbounded
+ * size; most shots need few local rows, a few need many).  The LSD kernel holds a shot's
+ * Gauss-Jordan basis in registers with room for local_rows (64, 128 or 256) clustered checks per
+ * wavefront; a shot whose clusters outgrow it is handed whole to the wide LSD kernel (1024 local
+ * rows, basis in device memory).  Smaller tiers run more wavefronts per compute unit and, at 64
+ * or 128, let BP and LSD share one kernel; outputs never depend on the tier.  The decoder's
+ * default is the smallest tier that holds every check of the code (256 when m > 128); LSD-mu
+ * decoders accept 256 only (QLSD_E_UNSUPPORTED otherwise).  May allocate the wide kernel's
+ * workspace (device memory, freed with the decoder); QLSD_E_UNSUPPORTED when the wide kernel does
+ * not fit the code or that allocation fails, leaving the decoder unchanged.  Host-side; must not
+ * overlap other calls on this decoder. */
+qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder dec, int32_t local_rows);
 
 /* Waits for the decoder's last work and reports a device failure, if any. */
 qlsd_status qlsd_sync(qlsd_decoder dec);

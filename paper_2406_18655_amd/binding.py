@@ -25,8 +25,8 @@ FLAG_OSD0_POST = 8
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
            "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
-           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
-           "qlsd_code_destroy"]
+           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity", "qlsd_sync",
+           "qlsd_last_error", "qlsd_decoder_destroy", "qlsd_code_destroy"]
 
 INFO_DTYPE = np.dtype([("status", np.uint8), ("reserved", np.uint8), ("bp_iters", np.int16),
                        ("n_clusters", np.int16), ("rounds", np.int16), ("max_cluster_cols", np.int32)])
@@ -70,13 +70,14 @@ def lib():
         L.qlsd_error_clusters.argtypes = [P, P, I32, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
         L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
+        L.qlsd_decoder_set_lsd_capacity.argtypes = [P, I32]
         L.qlsd_sync.argtypes = [P]
         L.qlsd_last_error.restype = ctypes.c_char_p
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
                    "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
-                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_sync"):
+                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -216,6 +217,11 @@ class Decoder:
         _check(lib().qlsd_decoder_tune(self._h, _ptr(syndromes), syndromes.shape[0], int(reps),
                                        _stream() if stream is None else stream, buf, len(buf)))
         return buf.value.decode()
+
+    def set_lsd_capacity(self, local_rows: int):
+        """LSD capacity tier: 64, 128 or 256 local rows per wavefront, shots beyond it finished by
+        the wide kernel (include/qlsd.h); outputs do not depend on it."""
+        _check(lib().qlsd_decoder_set_lsd_capacity(self._h, int(local_rows)))
 
     def stage_ms(self):
         """(bp_ms, lsd_ms) of the last decode call (needs FLAG_STAGE_TIMING)."""

@@ -118,7 +118,7 @@ size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
     return n * (sizeof(float) + sizeof(int64_t)) + kCtlWords * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
            d->netws_bytes +
-           (d->wide ? B * sizeof(int) + (size_t)d->wide_grid * lsd_wide_ws_words() * sizeof(uint64_t) : 0);
+           (d->d_wide_ws ? B * sizeof(int) + (size_t)d->wide_grid * lsd_wide_ws_words() * sizeof(uint64_t) : 0);
 }
 }  // namespace qlsd
 
@@ -492,6 +492,7 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
         f.lsd.list_count = w.ctl + kCtlList;
         f.lsd.bp_iters = d->params.max_iter;
         f.lsd.coherent_llr = 1;
+        with_overflow_list(d, w, f.lsd);
         f.list_w = w.list;
         f.tail = w.ctl + kCtlList;
         f.bp_done = w.ctl + kCtlBpDone;
@@ -507,7 +508,9 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
         rest.skip_done = 1;
         rest.done_count = w.ctl + kCtlLsdDone;
         rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
+        with_overflow_list(d, w, rest);
         HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
+        HIP_OK(run_wide(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
         if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
         return QLSD_OK;
     }
@@ -677,6 +680,51 @@ qlsd_status qlsd_osd0(qlsd_decoder d, const uint8_t *syndromes, const float *llr
     return QLSD_OK;
 }
 
+// Sets the LSD kernel's local-row capacity to 64 * W (W in {1, 2, 4}); shots that outgrow it go
+// to the wide kernel, whose workspace is allocated here when first needed.  Returns false (and
+// leaves the decoder as it was) when W does not fit the LDS budget or cannot be allocated.
+static bool set_lsd_capacity(qlsd_decoder d, int W) {
+    const DevGraph &g = d->code->g;
+    const bool with_mu = d->params.lsd_order > 0;
+    if (with_mu && W != 4) return false;  // LSD-mu kernels are built for W = 4 only
+    if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0, with_mu) > kLdsPerCu - 1024) return false;
+    const bool need_wide = g.m > 64 * W || (with_mu && g.n > 64 * W);
+    if (need_wide && !d->d_wide_ws) {
+        const bool keys = lsd_wide_lds(g, true, with_mu) <= kLdsPerCu - 1024;
+        if (!keys && lsd_wide_lds(g, false, with_mu) > kLdsPerCu - 1024) return false;
+        int *ovf = nullptr;
+        uint64_t *ws = nullptr;
+        const int grid = std::min(d->num_cus, 64);
+        if (hipMalloc((void **)&ovf, sizeof(int) * (size_t)d->max_batch) != hipSuccess) return false;
+        if (hipMalloc((void **)&ws, sizeof(uint64_t) * (size_t)grid * lsd_wide_ws_words()) != hipSuccess) {
+            hipFree(ovf);
+            return false;
+        }
+        d->d_ovf_list = ovf;
+        d->d_wide_ws = ws;
+        d->wide_grid = grid;
+        d->wide_keys_in_lds = keys;
+    }
+    d->lsd_W = W;
+    d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0, with_mu);
+    d->wide = need_wide;
+    return true;
+}
+
+qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder d, int32_t local_rows) {
+    if (!d) return fail(QLSD_E_INVALID, "null decoder");
+    if (local_rows != 64 && local_rows != 128 && local_rows != 256)
+        return fail(QLSD_E_INVALID, "LSD capacity must be 64, 128 or 256 local rows (got %d)", local_rows);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != d->code->device)
+        return fail(QLSD_E_INVALID, "decoder lives on device %d, current is %d", d->code->device, dev);
+    if (!set_lsd_capacity(d, local_rows / 64))
+        return fail(QLSD_E_UNSUPPORTED, "LSD capacity %d: %s", local_rows,
+                    d->params.lsd_order > 0 ? "LSD-mu decoders run with 256 local rows"
+                                            : "the wide kernel does not fit this code, or its workspace could not be allocated");
+    return QLSD_OK;
+}
+
 qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t B, int32_t reps, void *stream,
                               char *report, int32_t report_len) {
     qlsd_status st = check_call(d, syndromes, B, syndromes);
@@ -776,6 +824,24 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
     d->lsd_grid = best_lsd;
     snprintf(line, sizeof(line), "lsd chosen: %d workgroups\n", best_lsd);
     rep += line;
+    // LSD capacity per wavefront (the schedule for uneven cluster sizes): every tier up to the
+    // one that can never overflow, shots beyond a smaller tier's capacity finished by the wide
+    // kernel; timed on the whole decode (the tier also decides whether BP and LSD share a kernel)
+    {
+        const int W0 = d->lsd_W;
+        int best_W = W0;
+        float best_ms = 1e30f;
+        for (int W : {1, 2, 4}) {
+            if (W > W0 || !set_lsd_capacity(d, W)) continue;
+            const float ms = timeit(decode_run);
+            snprintf(line, sizeof(line), "lsd capacity %d local rows per wavefront: decode %.4f ms\n", 64 * W, ms);
+            rep += line;
+            if (ms > 0.f && ms < best_ms) { best_ms = ms; best_W = W; }
+        }
+        set_lsd_capacity(d, best_W);
+        snprintf(line, sizeof(line), "lsd capacity chosen: %d local rows\n", 64 * best_W);
+        rep += line;
+    }
     const hipError_t e = hipStreamSynchronize(s);
     cleanup();
     if (e != hipSuccess) return fail(QLSD_E_DEVICE, "tuning failed: %s", hipGetErrorString(e));

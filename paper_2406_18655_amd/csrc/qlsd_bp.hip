@@ -313,9 +313,11 @@ __device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, 
     }
 }
 
-// LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots.  At most
-// 128 VGPRs (4 wavefronts per SIMD), so that four BP workgroups fit on a CU.
-template <int MAXRW, int MAXCW, bool REG, int LSDW>
+// LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots; OVF: the
+// code has more checks than the 64 W local rows, and a shot whose clusters outgrow them is listed
+// for the wide kernel (compiled in only where it can happen: it costs registers).  At most 128
+// VGPRs (4 wavefronts per SIMD), so that four BP workgroups fit on a CU.
+template <int MAXRW, int MAXCW, bool REG, int LSDW, bool OVF = false>
 __global__ __launch_bounds__(kBpThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void bp_lds_kernel(BpArgs args, FuseArgs f) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -704,7 +706,7 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
             const int h = __builtin_amdgcn_readfirstlane(r.y);
             if (shot < 0) break;  // no entry h, or it is left to the stand-alone launch (the call
                                   // that returned it has marked the previous shot done)
-            decode_shot<LSDW, false>(f.lsd, S2, gv, shot, lane);  // LSD-0 only
+            decode_shot<LSDW, false, decltype(gv), false, OVF>(f.lsd, S2, gv, shot, lane);  // LSD-0 only
             wave_sync();
             done_h = h;
             done_shot = shot;
@@ -877,12 +879,12 @@ size_t bp_lds_bytes(const DevGraph &g, int S) {
     return align16(b);
 }
 
-template <int RW, int CW, bool REG, int LSDW>
+template <int RW, int CW, bool REG, int LSDW, bool OVF>
 static hipError_t launch_bp_t(const BpArgs &a, const FuseArgs &f, int grid, size_t lds, hipStream_t st) {
-    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW, REG, LSDW>,
+    hipError_t e = hipFuncSetAttribute((const void *)bp_lds_kernel<RW, CW, REG, LSDW, OVF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG, LSDW>), dim3(grid), dim3(kBpThreads), lds, st, a, f);
+    hipLaunchKernelGGL((bp_lds_kernel<RW, CW, REG, LSDW, OVF>), dim3(grid), dim3(kBpThreads), lds, st, a, f);
     return hipGetLastError();
 }
 
@@ -1093,13 +1095,13 @@ hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
     return launch_bp_graph_t<kMaxRowWeight, kMaxColWeight>(a, grid, lds, st);
 }
 
-template <int LSDW>
+template <int LSDW, bool OVF = false>
 static hipError_t launch_bp_w(const BpArgs &a, const FuseArgs &f, int grid, size_t lds, hipStream_t st) {
     const DevGraph &g = a.g;
-    if (bp_regular63(g)) return launch_bp_t<6, 3, true, LSDW>(a, f, grid, lds, st);
-    if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false, LSDW>(a, f, grid, lds, st);
-    if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false, LSDW>(a, f, grid, lds, st);
-    return launch_bp_t<kMaxRowWeight, kMaxColWeight, false, LSDW>(a, f, grid, lds, st);
+    if (bp_regular63(g)) return launch_bp_t<6, 3, true, LSDW, OVF>(a, f, grid, lds, st);
+    if (g.max_rw <= 8 && g.max_cw <= 4) return launch_bp_t<8, 4, false, LSDW, OVF>(a, f, grid, lds, st);
+    if (g.max_rw <= 16 && g.max_cw <= 8) return launch_bp_t<16, 8, false, LSDW, OVF>(a, f, grid, lds, st);
+    return launch_bp_t<kMaxRowWeight, kMaxColWeight, false, LSDW, OVF>(a, f, grid, lds, st);
 }
 
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
@@ -1110,6 +1112,13 @@ hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
 
 hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st) {
     const size_t lds = std::max(bp_lds_bytes(a.g, a.S), (size_t)f.lsd_bytes);
+    if (f.lsd.ovf_list && a.g.m > 64 * W) {
+        switch (W) {
+            case 1: return launch_bp_w<1, true>(a, f, grid, lds, st);
+            case 2: return launch_bp_w<2, true>(a, f, grid, lds, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (W) {
         case 1: return launch_bp_w<1>(a, f, grid, lds, st);
         case 2: return launch_bp_w<2>(a, f, grid, lds, st);

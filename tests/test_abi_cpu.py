@@ -60,6 +60,7 @@ def test_code_create_rejects_bad_csr(lib):
 def test_null_handles_are_rejected(lib):
     assert lib.qlsd_decode(None, None, 0, None, None, None) == -1
     assert lib.qlsd_sync(None) == -1
+    assert lib.qlsd_decoder_set_lsd_capacity(None, 64) == -1
     assert lib.qlsd_last_error() != b""
     lib.qlsd_decoder_destroy(None)
     lib.qlsd_code_destroy(None)

@@ -35,3 +35,56 @@ def test_tuned_decoder_matches_untuned(which):
     tuned.decode_into(s, c1, i1)
     torch.cuda.synchronize()
     assert torch.equal(c0, c1) and torch.equal(i0, i1)
+
+
+def _with_heavy_shots(code, B, heavy, p_heavy, seed):
+    """B sampled shots plus `heavy` shots of dense errors (density p_heavy), whose clusters
+    outgrow the small LSD capacity tiers; every syndrome is H e, so in the image of H."""
+    e, S = sample(code, B, seed=seed)
+    rng = np.random.default_rng(seed + 1)
+    E = (rng.random((heavy, code.n)) < p_heavy).astype(np.int64)
+    Sh = ((E @ code.H.T.astype(np.int64)) & 1).astype(np.uint8)
+    return np.ascontiguousarray(np.concatenate([S, Sh]))
+
+
+@pytest.mark.parametrize("which", ["bb144", "hgp16", "dem"])
+@pytest.mark.parametrize("separate", [False, True])
+def test_capacity_tiers_decode_alike(which, separate):
+    """Every LSD capacity tier (64, 128, 256 local rows per wavefront) returns the default tier's
+    corrections and shot info: shots beyond a small tier go whole to the wide kernel, on the
+    fused BP+LSD path as on the separate one."""
+    from paper_2406_18655_amd.workloads import synthetic_dem
+    code = {"bb144": lambda: bivariate_bicycle(p=0.05), "hgp16": lambda: random_34_hgp(16, p=0.04),
+            "dem": synthetic_dem}[which]()
+    S = _with_heavy_shots(code, 4000, 96, 0.01 if which == "dem" else 0.12, seed=85)
+    B = S.shape[0]
+    s = torch.from_numpy(S).cuda()
+    bc = binding.Code.from_dense(code.H)
+    flags = binding.FLAG_SEPARATE_LSD if separate else 0
+    T = 30
+    ref = binding.Decoder(bc, code.priors, B, max_iter=T, flags=flags)
+    c0 = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+    i0 = torch.empty((B, 12), dtype=torch.uint8, device="cuda")
+    ref.decode_into(s, c0, i0)
+    torch.cuda.synchronize()
+    inf = binding.parse_info(i0.cpu().numpy())
+    big = int((inf["max_cluster_cols"] > 64).sum())
+    print(f"case {which} separate={separate}: {B} shots, {big} with a cluster beyond 64 columns", flush=True)
+    assert not (inf["status"] & binding.ST_OVERFLOW).any()
+    for rows in (64, 128, 256):
+        d = binding.Decoder(bc, code.priors, B, max_iter=T, flags=flags)
+        d.set_lsd_capacity(rows)
+        c1, i1 = torch.empty_like(c0), torch.empty_like(i0)
+        for _ in range(2):  # a second call reuses the overflow list and the wide workspace
+            c1.fill_(7)
+            d.decode_into(s, c1, i1)
+            torch.cuda.synchronize()
+            assert torch.equal(c0, c1), rows
+            assert torch.equal(i0, i1), rows
+        del d
+    with pytest.raises(binding.QlsdError):
+        ref.set_lsd_capacity(96)
+    mu = binding.Decoder(bc, code.priors, 64, max_iter=T, lsd_order=4)
+    with pytest.raises(binding.QlsdError):
+        mu.set_lsd_capacity(128)
+    mu.set_lsd_capacity(256)
