@@ -316,31 +316,30 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     binding.attach_net(dec2, net)
     out["two_streams_value"] = round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1)
     del dec2
-    if True:
-        # plain BP + LSD over its own knobs (BP budget, LSD order mu of Sec. 4.3), on the same
-        # shots: the fastest setting whose logical error rate is not above the learned form's
-        # (differences within 2 sigma count as equal) is the plain decoder at matched error rate
-        q, n = float(f.mean()), f.size
-        grid, best = [], None
-        Ts, mus = ((10, 30, 50, 100), (0, 4, 10)) if args.workload == "dem" else ((10, 20, 50), (0, 2, 4, 8, 12))
-        for T in Ts:
-            for mu in mus:
-                # every grid point gets the autotuner and the timing of the learned leg
-                d = binding.Decoder(bcode, code.priors, B, max_iter=T, lsd_order=mu)
-                chosen = [l for l in d.tune(batches[0][1], reps=3).splitlines() if "chosen" in l]
-                fm, rate_m, ms_m, _ = _score_and_time(code, d, batches, args.steps, args.warmup,
-                                                      f"plain BP {T} LSD-{mu}")
-                qm = float(fm.mean())
-                two_sigma = 2 * float(np.sqrt(max(q, 1 / n) * (1 - q) / n + max(qm, 1 / n) * (1 - qm) / n))
-                grid.append([T, mu, round(qm, 6), round(rate_m / 1e6, 2)])
-                if qm <= q + two_sigma and (best is None or rate_m > best["value"]):
-                    best = {"bp_max_iter": T, "lsd_order": mu, "ler": round(qm, 6), "value": round(rate_m, 1),
-                            "ler_difference_two_sigma": round(two_sigma, 6), "tuning": chosen,
-                            "mcnemar": _mcnemar(f, fm)}
-        out["plain_at_matched_ler"] = {
-            "best": best, "speedup_of_learned": None if best is None else round(rate / best["value"], 3),
-            "timing": f"every leg autotuned, {args.steps} timed steps after {args.warmup} warm-up",
-            "grid": {"columns": ["bp_max_iter", "lsd_order", "ler", "M_shots_per_s"], "rows": grid}}
+    # plain BP + LSD over its own knobs (BP budget, LSD order mu of Sec. 4.3), on the same
+    # shots: the fastest setting whose logical error rate is not above the learned form's
+    # (differences within 2 sigma count as equal) is the plain decoder at matched error rate
+    q, n = float(f.mean()), f.size
+    grid, best = [], None
+    Ts, mus = ((10, 30, 50, 100), (0, 4, 10)) if args.workload == "dem" else ((10, 20, 50), (0, 2, 4, 8, 12))
+    for T in Ts:
+        for mu in mus:
+            # every grid point gets the autotuner and the timing of the learned leg
+            d = binding.Decoder(bcode, code.priors, B, max_iter=T, lsd_order=mu)
+            chosen = [l for l in d.tune(batches[0][1], reps=3).splitlines() if "chosen" in l]
+            fm, rate_m, ms_m, _ = _score_and_time(code, d, batches, args.steps, args.warmup,
+                                                  f"plain BP {T} LSD-{mu}")
+            qm = float(fm.mean())
+            two_sigma = 2 * float(np.sqrt(max(q, 1 / n) * (1 - q) / n + max(qm, 1 / n) * (1 - qm) / n))
+            grid.append([T, mu, round(qm, 6), round(rate_m / 1e6, 2)])
+            if qm <= q + two_sigma and (best is None or rate_m > best["value"]):
+                best = {"bp_max_iter": T, "lsd_order": mu, "ler": round(qm, 6), "value": round(rate_m, 1),
+                        "ler_difference_two_sigma": round(two_sigma, 6), "tuning": chosen,
+                        "mcnemar": _mcnemar(f, fm)}
+    out["plain_at_matched_ler"] = {
+        "best": best, "speedup_of_learned": None if best is None else round(rate / best["value"], 3),
+        "timing": f"every leg autotuned, {args.steps} timed steps after {args.warmup} warm-up",
+        "grid": {"columns": ["bp_max_iter", "lsd_order", "ler", "M_shots_per_s"], "rows": grid}}
     return out
 
 

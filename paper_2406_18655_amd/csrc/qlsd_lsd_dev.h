@@ -175,19 +175,23 @@ struct Basis<W, false> {
     uint64_t CT[W][W];
     uint64_t piv[W];  // uniform: pivot local rows
     uint64_t sp[W];   // uniform: reduced syndrome over local rows
+    int ns;           // uniform: slices 0..ns-1 of local rows are in use (the rest stays zero)
+    static constexpr bool kInMem = false;
     __device__ __forceinline__ uint64_t &M(int s, int w) { return Mrow[s][w]; }
     __device__ __forceinline__ uint64_t &C(int s, int w) { return CT[s][w]; }
     __device__ __forceinline__ uint64_t M(int s, int w) const { return Mrow[s][w]; }
     __device__ __forceinline__ uint64_t C(int s, int w) const { return CT[s][w]; }
-    // slice s of local rows (or of pivot rows) may be non-zero
+    // slice s of local rows (or of pivot rows) may be non-zero; the register code bounds its
+    // loops at compile time instead (insert_column picks a tier from ns)
     __device__ __forceinline__ bool active(int) const { return true; }
-    // word w of Mrow at lane row (64 rs + rl); rs is wave-uniform but not a compile-time index,
-    // so it is selected by unrolled compares (a runtime array index would put the basis in
+    // word w of Mrow at lane row (64 rs + rl), rs < NS; rs is wave-uniform but not a compile-time
+    // index, so it is selected by unrolled compares (a runtime array index would put the basis in
     // scratch memory)
+    template <int NS = W>
     __device__ __forceinline__ uint64_t row_word(int rs, int w, int rl) const {
         uint64_t v = 0;
 #pragma unroll
-        for (int s = 0; s < W; s++)
+        for (int s = 0; s < NS; s++)
             if (s == rs) v = readlane64(Mrow[s][w], rl);
         return v;
     }
@@ -199,11 +203,13 @@ struct Basis<W, true> {
     int ns;         // uniform: slices 0..ns-1 of local rows are in use
     uint64_t piv[W];
     uint64_t sp[W];
+    static constexpr bool kInMem = true;
     __device__ __forceinline__ uint64_t &M(int s, int w) { return mem[(s * W + w) * 64]; }
     __device__ __forceinline__ uint64_t &C(int s, int w) { return mem[((W + s) * W + w) * 64]; }
     __device__ __forceinline__ uint64_t M(int s, int w) const { return mem[(s * W + w) * 64]; }
     __device__ __forceinline__ uint64_t C(int s, int w) const { return mem[((W + s) * W + w) * 64]; }
     __device__ __forceinline__ bool active(int s) const { return s < ns; }
+    template <int NS = W>
     __device__ __forceinline__ uint64_t row_word(int rs, int w, int rl) const {
         return readlane64(mem[(rs * W + w) * 64], rl);
     }
@@ -217,20 +223,20 @@ __device__ __forceinline__ int parity_and(const uint64_t (&a)[W], const uint64_t
     return c & 1;
 }
 
-// parity of (row s of Mrow, or of CT) AND b over the slices in use
-template <int W, class BB>
+// parity of (row s of Mrow, or of CT) AND b over the slices in use (the first NS)
+template <int W, class BB, int NS = W>
 __device__ __forceinline__ int parity_M(const BB &B, int s, const uint64_t (&b)[W]) {
     int c = 0;
 #pragma unroll
-    for (int w = 0; w < W; w++)
+    for (int w = 0; w < NS; w++)
         if (B.active(w)) c += __popcll(B.M(s, w) & b[w]);
     return c & 1;
 }
-template <int W, class BB>
+template <int W, class BB, int NS = W>
 __device__ __forceinline__ int parity_C(const BB &B, int s, const uint64_t (&b)[W]) {
     int c = 0;
 #pragma unroll
-    for (int w = 0; w < W; w++)
+    for (int w = 0; w < NS; w++)
         if (B.active(w)) c += __popcll(B.C(s, w) & b[w]);
     return c & 1;
 }
@@ -238,74 +244,77 @@ __device__ __forceinline__ int parity_C(const BB &B, int s, const uint64_t (&b)[
 // Adds column col (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
 // The column's local rows are held by lanes base .. base + cw - 1 of lr_src (-1: no entry).
-template <int W, class BB>
-__device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
+// NS: only local-row slices 0..NS-1 can be non-zero (the shot's rows all lie below 64 NS), so
+// the column, the reduced rows and every new pivot lie there too and the loops stop at NS.
+template <int W, int NS, class BB>
+__device__ __forceinline__ bool insert_column_ns(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base,
+                                                 int cw) {
     // the column's support over local rows, as W wave-uniform masks
     uint64_t cm[W];
 #pragma unroll
     for (int s = 0; s < W; s++) cm[s] = 0;
     for (int u = 0; u < cw; u++) {
         const int lr = __builtin_amdgcn_readlane(lr_src, base + u);
-        if (lr >= 0 && lr < 64 * W) {
+        if (lr >= 0 && lr < 64 * NS) {
 #pragma unroll
-            for (int s = 0; s < W; s++)
+            for (int s = 0; s < NS; s++)
                 if ((lr >> 6) == s) cm[s] |= 1ull << (lr & 63);
         }
     }
     uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
 #pragma unroll
-    for (int s = 0; s < W; s++) bf |= (uint32_t)((cm[s] >> lane) & 1ull) << s;
+    for (int s = 0; s < NS; s++) bf |= (uint32_t)((cm[s] >> lane) & 1ull) << s;
     uint64_t a[W];
 #pragma unroll
-    for (int s = 0; s < W; s++) a[s] = cm[s] & B.piv[s];
+    for (int s = 0; s < W; s++) a[s] = s < NS ? cm[s] & B.piv[s] : 0ull;
     uint32_t bpf = 0;
 #pragma unroll
-    for (int s = 0; s < W; s++)
-        if (B.active(s)) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W>(B, s, a)) << s;
+    for (int s = 0; s < NS; s++)
+        if (B.active(s)) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W, BB, NS>(B, s, a)) << s;
     uint64_t bp[W];
     int rs = -1;
 #pragma unroll
-    for (int s = 0; s < W; s++) {
+    for (int s = 0; s < NS; s++) {
         bp[s] = ballot((bpf >> s) & 1u);
         if (rs < 0 && bp[s]) rs = s;
     }
     if (rs < 0) return false;
     uint64_t bprs = 0;
 #pragma unroll
-    for (int s = 0; s < W; s++)
+    for (int s = 0; s < NS; s++)
         if (s == rs) bprs = bp[s];
     const int rl = __builtin_ctzll(bprs);
     uint64_t R[W];
 #pragma unroll
-    for (int w = 0; w < W; w++) R[w] = B.active(w) ? B.row_word(rs, w, rl) : 0ull;
+    for (int w = 0; w < NS; w++) R[w] = B.active(w) ? B.template row_word<NS>(rs, w, rl) : 0ull;
     // rows in the reduced column's support: eliminate the new pivot row from the old pivots
 #pragma unroll
-    for (int s = 0; s < W; s++) {
+    for (int s = 0; s < NS; s++) {
         if ((bpf >> s) & 1u) {
 #pragma unroll
-            for (int w = 0; w < W; w++)
+            for (int w = 0; w < NS; w++)
                 if (B.active(w)) B.M(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
     // combination tracking
 #pragma unroll
-    for (int s = 0; s < W; s++) {
+    for (int s = 0; s < NS; s++) {
         if (!B.active(s)) continue;
         const bool is_piv = (B.piv[s] >> lane) & 1ull;
-        if (is_piv && parity_C<W>(B, s, a)) {
+        if (is_piv && parity_C<W, BB, NS>(B, s, a)) {
 #pragma unroll
-            for (int w = 0; w < W; w++)
+            for (int w = 0; w < NS; w++)
                 if (B.active(w)) B.C(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
         }
         if (s == rs && lane == rl) {
 #pragma unroll
-            for (int w = 0; w < W; w++)
+            for (int w = 0; w < NS; w++)
                 if (B.active(w)) B.C(s, w) = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
     bool sp_hit = false;
 #pragma unroll
-    for (int s = 0; s < W; s++)
+    for (int s = 0; s < NS; s++)
         if (s == rs) {
             B.piv[s] |= 1ull << rl;
             sp_hit = (B.sp[s] >> rl) & 1ull;
@@ -313,14 +322,30 @@ __device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_
     if (lane == 0) S.colAt[rs * 64 + rl] = col;
     if (sp_hit) {
 #pragma unroll
-        for (int s = 0; s < W; s++) B.sp[s] ^= bp[s];
+        for (int s = 0; s < NS; s++) B.sp[s] ^= bp[s];
     }
 #pragma unroll
-    for (int s = 0; s < W; s++) {
+    for (int s = 0; s < NS; s++) {
         B.piv[s] = uniform64(B.piv[s]);
         B.sp[s] = uniform64(B.sp[s]);
     }
     return true;
+}
+
+
+// Adds column col to the basis (see insert_column_ns).  The register basis runs the tier of the
+// slices in use (a shot whose clusters hold at most 64 rows costs a W = 1 elimination); the
+// device-memory basis tests each slice at run time.
+template <int W, class BB>
+__device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
+    if constexpr (BB::kInMem || W == 1) {
+        return insert_column_ns<W, W>(B, S, col, lane, lr_src, base, cw);
+    } else {
+        if constexpr (W == 2) {
+            if (B.ns <= 1) return insert_column_ns<W, 1>(B, S, col, lane, lr_src, base, cw);
+        }
+        return insert_column_ns<W, W>(B, S, col, lane, lr_src, base, cw);
+    }
 }
 
 __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
@@ -592,7 +617,10 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     }
     for (int w = lane; w < (n + 31) / 32; w += 64) { S.incol[w] = 0u; S.cbit[w] = 0u; }
     for (int i = lane; i < m; i += 64) { S.loc[i] = -1; S.claimer[i] = kFree; }
-    for (int r = lane; r < K; r += 64) S.lroot[r] = -1;  // validity stamps of an earlier shot
+    for (int r = lane; r < K; r += 64) {
+        S.lroot[r] = -1;    // validity stamps of an earlier shot
+        S.sel[r] = ~0ull;   // per-root selection (cleared again as each round reads it)
+    }
     wave_sync();
 
     // the correction row from the bit vector, written once on every exit
@@ -684,8 +712,8 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         const int msl = (m + 63) >> 6;
         for (int s = 0; s < msl; s++)
             for (int w = 0; w < msl; w++) { B.M(s, w) = 0; B.C(s, w) = 0; }
-        B.ns = (nrows + 63) >> 6;
     }
+    B.ns = (nrows + 63) >> 6;
 #pragma unroll
     for (int s = 0; s < W; s++) {
         if constexpr (!WIDE) {
@@ -704,10 +732,8 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     int mu_left = 0;
     int npc = 0;  // dependent columns recorded in colNP
     for (;;) {
-        // (1) selection: per growing root, the candidate of smallest key (round-start state)
-#pragma unroll
-        for (int s = 0; s < W; s++) S.sel[s * 64 + lane] = ~0ull;
-        wave_sync();
+        // (1) selection: per growing root, the candidate of smallest key (round-start state);
+        // every entry of sel is ~0 here
         // Branch-light: a row's root and cached candidate are read together, then the root's
         // state and the candidate's taken bit (reads of rows past nrows are in bounds and unused).
 #pragma unroll
@@ -766,6 +792,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const int cr = S.croot[r];
             const uint8_t st = S.state[r];
             const uint64_t key = S.sel[r];
+            if (key != ~0ull) S.sel[r] = ~0ull;  // ready for the next round
             const bool growing = r < nrows && cr == r && ((MU && grow_all) ? st != kFrozen : st == kInvalid);
             const bool take = growing && key != ~0ull;
             if (growing && key == ~0ull && st == kInvalid) {
@@ -836,14 +863,40 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 merged |= unite(S.croot, c, S.croot[S.loc[d]]);
             }
         };
-        if (has0) join(d0, c0p);
-        for (int id = lane + 64; id < npairs; id += 64) {
-            int d, c;
-            if (pair_of(id, d, c)) join(d, c);
+        int nrows_new;
+        if (npairs <= 64) {
+            // one pair per lane: the claimed detectors become local rows nrows, nrows + 1, ... in
+            // lane order (any numbering of the new rows gives the same pivot columns and solution)
+            const int cl = has0 ? S.claimer[d0] : kFree;
+            const bool add = has0 && cl != kFree && cl == c0p;
+            const uint64_t bal = ballot(add);
+            if (add) {
+                const int idx = nrows + __popcll(bal & ((1ull << lane) - 1ull));
+                if (idx < K) {
+                    S.rowOf[idx] = d0;
+                    S.croot[idx] = c0p;
+                    S.state[idx] = kValid;
+                    S.cand[idx] = kStale;
+                    S.loc[d0] = idx;
+                }
+            } else if (has0) {
+                // claimed by a smaller root, or clustered before the round (then never claimed)
+                int other = cl;
+                if (cl == kFree) other = S.croot[S.loc[d0]];
+                merged |= unite(S.croot, c0p, other);
+            }
+            nrows_new = nrows + __popcll(bal);
+            if (lane == 0) S.ctl[0] = nrows_new;
+        } else {
+            if (has0) join(d0, c0p);
+            for (int id = lane + 64; id < npairs; id += 64) {
+                int d, c;
+                if (pair_of(id, d, c)) join(d, c);
+            }
         }
         const bool any_merge = ballot(merged) != 0ull;
         wave_sync();
-        const int nrows_new = __builtin_amdgcn_readfirstlane(S.ctl[0]);
+        if (npairs > 64) nrows_new = __builtin_amdgcn_readfirstlane(S.ctl[0]);
         if (nrows_new > K) { overflow(status); return; }
         // flatten the forest (only after a merge: otherwise every row already points at a root,
         // new rows at the round-start root that claimed them); release this round's claims
@@ -862,7 +915,7 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             for (int r = nrows + lane; r < nrows_new; r += 64) S.claimer[S.rowOf[r]] = kFree;
         }
         nrows = nrows_new;
-        if constexpr (WIDE) B.ns = (nrows + 63) >> 6;
+        B.ns = (nrows + 63) >> 6;
         wave_sync();
 
         // (4) the round's distinct new columns, ascending key, each reduced on the fly.  Order:
@@ -927,13 +980,17 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                 col = __builtin_amdgcn_readfirstlane(col);
                 base = __builtin_amdgcn_readfirstlane(base);
                 cwc = __builtin_amdgcn_readfirstlane(cwc);
-                if (lane == 0) S.incol[col >> 5] |= 1u << (col & 31);
+                // no read of incol before the next sync: the update need not return
+                if (lane == 0) atomicOr(&S.incol[col >> 5], 1u << (col & 31));
                 const bool pivot = insert_column<W>(B, S, col, lane, lr_src, base, cwc);
                 if (MU && !pivot && A.mu > 0) {
                     if (lane == 0 && npc < KNP) S.colNP[npc] = col;
                     npc++;
                 }
             }
+            // the order array lives in the selection array, which the next round needs cleared
+            if (!fast)
+                for (int p = lane; p < (nsel + 1) / 2; p += 64) S.sel[p] = ~0ull;
         }
         wave_sync();
 

@@ -82,6 +82,8 @@ __device__ void osd0_shot(const OsdArgs &A, uint64_t *keys, uint32_t *cbit, int3
         for (int s = 0; s < msl; s++)
             for (int w = 0; w < msl; w++) { B.M(s, w) = 0; B.C(s, w) = 0; }
         B.ns = msl;
+    } else {
+        B.ns = W;
     }
     bool any = false;
 #pragma unroll
