@@ -244,12 +244,23 @@ __device__ __forceinline__ int parity_C(const BB &B, int s, const uint64_t (&b)[
 // Adds column col (its detectors are all clustered) to the Gauss-Jordan basis.  Returns true iff
 // it became a pivot.  On-the-fly elimination (Sec. 4.2): only the new column is reduced.
 // The column's local rows are held by lanes base .. base + cw - 1 of lr_src (-1: no entry).
+// Two steps: the reduction of the column against the basis (insert_plan, which only reads the
+// basis) and the update of the basis with the new pivot (insert_apply).
+template <int W>
+struct InsertPlan {
+    uint32_t bpf;    // this lane: bit s = local row 64 s + lane lies in the reduced column
+    uint32_t cflag;  // this lane: bit s = pivot row 64 s + lane's combination uses the column
+    uint64_t bp[W];  // uniform: the reduced column over local rows
+    uint64_t R[W];   // uniform: the new pivot row's Mrow words
+    int rs, rl;      // uniform: the new pivot's local row, 64 rs + rl
+};
+
 // NS: only local-row slices 0..NS-1 can be non-zero (the shot's rows all lie below 64 NS), so
-// the column, the reduced rows and every new pivot lie there too and the loops stop at NS.
+// the column, the reduced rows and the new pivot lie there too and the loops stop at NS; the
+// entries of P for slices NS..W-1 are zero.  Returns false iff the column is dependent.
 template <int W, int NS, class BB>
-__device__ __forceinline__ bool insert_column_ns(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base,
-                                                 int cw) {
-    // the column's support over local rows, as W wave-uniform masks
+__device__ __forceinline__ bool insert_plan(const BB &B, int lane, int lr_src, int base, int cw, InsertPlan<W> &P) {
+    // the column's support over local rows, as NS wave-uniform masks
     uint64_t cm[W];
 #pragma unroll
     for (int s = 0; s < W; s++) cm[s] = 0;
@@ -264,57 +275,66 @@ __device__ __forceinline__ bool insert_column_ns(BB &B, const LsdLds &S, int col
     uint32_t bf = 0;  // bit s: this lane's local row s*64+lane is in the column's support
 #pragma unroll
     for (int s = 0; s < NS; s++) bf |= (uint32_t)((cm[s] >> lane) & 1ull) << s;
-    uint64_t a[W];
+    uint64_t a[W];    // the column's support on pivot rows
 #pragma unroll
     for (int s = 0; s < W; s++) a[s] = s < NS ? cm[s] & B.piv[s] : 0ull;
-    uint32_t bpf = 0;
+    P.bpf = 0;
 #pragma unroll
     for (int s = 0; s < NS; s++)
-        if (B.active(s)) bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W, BB, NS>(B, s, a)) << s;
-    uint64_t bp[W];
-    int rs = -1;
+        if (B.active(s)) P.bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W, BB, NS>(B, s, a)) << s;
+    P.rs = -1;
 #pragma unroll
-    for (int s = 0; s < NS; s++) {
-        bp[s] = ballot((bpf >> s) & 1u);
-        if (rs < 0 && bp[s]) rs = s;
+    for (int s = 0; s < W; s++) {
+        P.bp[s] = s < NS ? ballot((P.bpf >> s) & 1u) : 0ull;
+        if (P.rs < 0 && P.bp[s]) P.rs = s;
     }
-    if (rs < 0) return false;
+    if (P.rs < 0) return false;
     uint64_t bprs = 0;
 #pragma unroll
     for (int s = 0; s < NS; s++)
-        if (s == rs) bprs = bp[s];
-    const int rl = __builtin_ctzll(bprs);
-    uint64_t R[W];
+        if (s == P.rs) bprs = P.bp[s];
+    P.rl = __builtin_ctzll(bprs);
 #pragma unroll
-    for (int w = 0; w < NS; w++) R[w] = B.active(w) ? B.template row_word<NS>(rs, w, rl) : 0ull;
-    // rows in the reduced column's support: eliminate the new pivot row from the old pivots
-#pragma unroll
-    for (int s = 0; s < NS; s++) {
-        if ((bpf >> s) & 1u) {
-#pragma unroll
-            for (int w = 0; w < NS; w++)
-                if (B.active(w)) B.M(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
-        }
-    }
-    // combination tracking
+    for (int w = 0; w < W; w++) P.R[w] = (w < NS && B.active(w)) ? B.template row_word<NS>(P.rs, w, P.rl) : 0ull;
+    P.cflag = 0;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         if (!B.active(s)) continue;
         const bool is_piv = (B.piv[s] >> lane) & 1ull;
-        if (is_piv && parity_C<W, BB, NS>(B, s, a)) {
+        if (is_piv && parity_C<W, BB, NS>(B, s, a)) P.cflag |= 1u << s;
+    }
+    return true;
+}
+
+template <int W, class BB>
+__device__ __forceinline__ void insert_apply(BB &B, const LsdLds &S, int col, int lane, const InsertPlan<W> &P) {
+    const int rs = P.rs, rl = P.rl;
+    // rows in the reduced column's support: eliminate the new pivot row from the old pivots
 #pragma unroll
-            for (int w = 0; w < NS; w++)
-                if (B.active(w)) B.C(s, w) ^= R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+    for (int s = 0; s < W; s++) {
+        if ((P.bpf >> s) & 1u) {
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.M(s, w) ^= P.R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
+        }
+    }
+    // combination tracking
+#pragma unroll
+    for (int s = 0; s < W; s++) {
+        if ((P.cflag >> s) & 1u) {
+#pragma unroll
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.C(s, w) ^= P.R[w] ^ ((w == rs) ? (1ull << rl) : 0ull);
         }
         if (s == rs && lane == rl) {
 #pragma unroll
-            for (int w = 0; w < NS; w++)
-                if (B.active(w)) B.C(s, w) = R[w] | ((w == rs) ? (1ull << rl) : 0ull);
+            for (int w = 0; w < W; w++)
+                if (B.active(w)) B.C(s, w) = P.R[w] | ((w == rs) ? (1ull << rl) : 0ull);
         }
     }
     bool sp_hit = false;
 #pragma unroll
-    for (int s = 0; s < NS; s++)
+    for (int s = 0; s < W; s++)
         if (s == rs) {
             B.piv[s] |= 1ull << rl;
             sp_hit = (B.sp[s] >> rl) & 1ull;
@@ -322,30 +342,30 @@ __device__ __forceinline__ bool insert_column_ns(BB &B, const LsdLds &S, int col
     if (lane == 0) S.colAt[rs * 64 + rl] = col;
     if (sp_hit) {
 #pragma unroll
-        for (int s = 0; s < NS; s++) B.sp[s] ^= bp[s];
+        for (int s = 0; s < W; s++) B.sp[s] ^= P.bp[s];
     }
 #pragma unroll
-    for (int s = 0; s < NS; s++) {
+    for (int s = 0; s < W; s++) {
         B.piv[s] = uniform64(B.piv[s]);
         B.sp[s] = uniform64(B.sp[s]);
     }
-    return true;
 }
 
-
-// Adds column col to the basis (see insert_column_ns).  The register basis runs the tier of the
-// slices in use (a shot whose clusters hold at most 64 rows costs a W = 1 elimination); the
-// device-memory basis tests each slice at run time.
+// The register basis reduces the column in the tier of the slices in use (a shot whose clusters
+// hold at most 64 rows costs a one-slice reduction); the device-memory basis tests each slice at
+// run time.
 template <int W, class BB>
 __device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
-    if constexpr (BB::kInMem || W == 1) {
-        return insert_column_ns<W, W>(B, S, col, lane, lr_src, base, cw);
+    InsertPlan<W> P;
+    bool piv;
+    if constexpr (!BB::kInMem && W == 2) {
+        piv = B.ns <= 1 ? insert_plan<W, 1>(B, lane, lr_src, base, cw, P) : insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     } else {
-        if constexpr (W == 2) {
-            if (B.ns <= 1) return insert_column_ns<W, 1>(B, S, col, lane, lr_src, base, cw);
-        }
-        return insert_column_ns<W, W>(B, S, col, lane, lr_src, base, cw);
+        piv = insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     }
+    if (!piv) return false;
+    insert_apply<W>(B, S, col, lane, P);
+    return true;
 }
 
 __device__ __forceinline__ bool in_col(const uint32_t *incol, int j) { return (incol[j >> 5] >> (j & 31)) & 1u; }
@@ -743,6 +763,15 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             const bool valid = r < nrows;
             const int cr = S.croot[r];
             uint64_t best = S.cand[r];
+            // a graph in LDS: the row's edge range is read alongside (rows past nrows hold a stale
+            // detector of an earlier shot, or nothing yet: clamped to a valid index)
+            int e0 = 0, e1 = 0;
+            if constexpr (G::kInLds) {
+                const int d = S.rowOf[r];
+                const int dd = (unsigned)d < (unsigned)m ? d : 0;
+                e0 = g.row_ptr(dd);
+                e1 = g.row_ptr(dd + 1);
+            }
             const int c = valid ? cr : 0;
             const uint32_t bc = (uint32_t)best;
             const uint32_t inc = S.incol[(bc < (uint32_t)n ? bc : 0u) >> 5];
@@ -751,9 +780,12 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             {
                 {
                     if (grow && (best == kStale || (best != ~0ull && ((inc >> (bc & 31)) & 1u)))) {
-                        const int d = S.rowOf[r];
                         best = ~0ull;
-                        const int e0 = g.row_ptr(d), e1 = g.row_ptr(d + 1);
+                        if constexpr (!G::kInLds) {
+                            const int d = S.rowOf[r];
+                            e0 = g.row_ptr(d);
+                            e1 = g.row_ptr(d + 1);
+                        }
                         // kScan entries per pass, every load issued before any is used (entries
                         // past the row's end re-read its last one and are masked out), so a row of
                         // weight <= kScan costs two dependent rounds of loads (6 fits the small
@@ -835,9 +867,12 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
             return ok;
         };
         // this lane's first pair is decoded once and kept for the unions
-        int d0 = 0, c0p = 0;
+        int d0 = 0, c0p = 0, loc0 = -1;
         const bool has0 = lane < npairs && pair_of(lane, d0, c0p);
-        if (has0 && S.loc[d0] < 0) atomicMin(&S.claimer[d0], c0p);
+        if (has0) {
+            loc0 = S.loc[d0];
+            if (loc0 < 0) atomicMin(&S.claimer[d0], c0p);
+        }
         for (int id = lane + 64; id < npairs; id += 64) {
             int d, c;
             if (pair_of(id, d, c) && S.loc[d] < 0) atomicMin(&S.claimer[d], c);
@@ -867,7 +902,8 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
         if (npairs <= 64) {
             // one pair per lane: the claimed detectors become local rows nrows, nrows + 1, ... in
             // lane order (any numbering of the new rows gives the same pivot columns and solution)
-            const int cl = has0 ? S.claimer[d0] : kFree;
+            // detectors clustered before the round were never claimed
+            const int cl = has0 && loc0 < 0 ? S.claimer[d0] : kFree;
             const bool add = has0 && cl != kFree && cl == c0p;
             const uint64_t bal = ballot(add);
             if (add) {
@@ -880,10 +916,11 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
                     S.loc[d0] = idx;
                 }
             } else if (has0) {
-                // claimed by a smaller root, or clustered before the round (then never claimed)
+                // claimed by a smaller root, or clustered before the round: in the common case the
+                // detector is the picking cluster's own (its row points at that round-start root)
                 int other = cl;
-                if (cl == kFree) other = S.croot[S.loc[d0]];
-                merged |= unite(S.croot, c0p, other);
+                if (cl == kFree) other = S.croot[loc0];
+                if (other != c0p) merged |= unite(S.croot, c0p, other);
             }
             nrows_new = nrows + __popcll(bal);
             if (lane == 0) S.ctl[0] = nrows_new;
