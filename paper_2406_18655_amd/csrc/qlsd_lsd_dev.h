@@ -360,6 +360,10 @@ __device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_
     bool piv;
     if constexpr (!BB::kInMem && W == 2) {
         piv = B.ns <= 1 ? insert_plan<W, 1>(B, lane, lr_src, base, cw, P) : insert_plan<W, W>(B, lane, lr_src, base, cw, P);
+    } else if constexpr (!BB::kInMem && W == 4) {
+        piv = B.ns <= 1   ? insert_plan<W, 1>(B, lane, lr_src, base, cw, P)
+              : B.ns <= 2 ? insert_plan<W, 2>(B, lane, lr_src, base, cw, P)
+                          : insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     } else {
         piv = insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     }
