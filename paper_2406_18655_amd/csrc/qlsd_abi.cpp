@@ -89,11 +89,15 @@ struct qlsd_decoder_s {
     unsigned char *d_netws;  // feature workspace of the refinement on large graphs (else nullptr)
     size_t netws_bytes;
     // shots whose clusters can outgrow the LSD kernel's 64 * lsd_W local rows (or, with LSD-mu,
-    // its dependent-column list) go on to the wide LSD kernel
-    bool wide;
-    int wide_grid, wide_keys_in_lds;
+    // its dependent-column list) are listed (ovf) and go on to the mid LSD kernel (512 local rows,
+    // basis in LDS), and those that outgrow it to the wide LSD kernel (1024 rows, basis in device
+    // memory); either tier is left out when it cannot be needed or does not fit in LDS
+    bool ovf, mid, wide;
+    int mid_grid, mid_keys_in_lds, wide_grid, wide_keys_in_lds;
     int *d_ovf_list;     // max_batch: shots the LSD kernel could not hold
-    uint64_t *d_wide_ws; // wide_grid * lsd_wide_ws_words(): the wide kernel's Gauss-Jordan bases
+    int *d_ovf2_list;    // max_batch (mid and wide): shots the mid kernel could not hold
+    uint64_t *d_wide_ws; // wide_grid * lsd_wide_ws_words(): the wide kernel's Gauss-Jordan bases (also
+                         // the global OSD-0 basis when m > 256)
     // global OSD-0 (qlsd_osd0, QLSD_FLAG_OSD0_POST): basis words per lane row, sort length
     int osd_W, osd_P, osd_wave_bytes;
     bool osd_ok;
@@ -103,8 +107,8 @@ namespace qlsd {
 // Decoder counters, each on its own 128-byte line: the one-kernel path polls the list counters
 // while BP workgroups hit the queue counter, and atomics on a shared line would serialise.
 constexpr int kCtlQueue = 0, kCtlList = 32, kCtlItem = 64, kCtlBpDone = 96, kCtlItem2 = 128, kCtlLsdDone = 160,
-              kCtlOvf = 192, kCtlItemW = 224;
-constexpr int kCtlWords = 256;
+              kCtlOvf = 192, kCtlItemW = 224, kCtlOvf2 = 256, kCtlItemM = 288;
+constexpr int kCtlWords = 320;
 void set_last_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -117,12 +121,61 @@ int code_cols(qlsd_code c) { return c->g.n; }
 size_t decoder_device_bytes(qlsd_decoder d) {
     const size_t n = (size_t)d->code->g.n, B = (size_t)d->max_batch;
     return n * (sizeof(float) + sizeof(int64_t)) + kCtlWords * sizeof(int) + B * (1 + sizeof(int) + n * sizeof(float)) +
-           d->netws_bytes +
-           (d->d_wide_ws ? B * sizeof(int) + (size_t)d->wide_grid * lsd_wide_ws_words() * sizeof(uint64_t) : 0);
+           d->netws_bytes + (d->d_ovf_list ? B * sizeof(int) : 0) + (d->d_ovf2_list ? B * sizeof(int) : 0) +
+           (d->d_wide_ws ? (size_t)d->wide_grid * lsd_wide_ws_words() * sizeof(uint64_t) : 0);
 }
 }  // namespace qlsd
 
 extern "C" {
+
+// Overflow tiers of an LSD kernel with 64 W local rows (see the decoder fields) and their buffers,
+// allocated when first needed; the wide kernel's workspace also serves global OSD-0 when m > 256.
+// require: refuse (return false) when shots can overflow and no overflow kernel fits.  On false
+// the decoder is left as it was.
+static bool configure_overflow(qlsd_decoder d, int W, bool require) {
+    const DevGraph &g = d->code->g;
+    const bool with_mu = d->params.lsd_order > 0;
+    const size_t lim = kLdsPerCu - 1024;
+    const bool need = g.m > 64 * W || (with_mu && g.n > 64 * W);
+    bool mid = false, mid_keys = false, wide = false, wide_keys = false;
+    if (need) {
+        // keys in LDS when they fit, else read from the LLR rows
+        mid_keys = lsd_mid_lds(g, true, with_mu) <= lim;
+        mid = mid_keys || lsd_mid_lds(g, false, with_mu) <= lim;
+        if (!mid || g.m > kMidRows) {
+            wide_keys = lsd_wide_lds(g, true, with_mu) <= lim;
+            wide = wide_keys || lsd_wide_lds(g, false, with_mu) <= lim;
+        }
+    }
+    const bool ovf = mid || wide;
+    if (require && need && !ovf) return false;
+    const bool wws = wide || d->osd_W == kWideW;
+    const int wgrid = std::min(d->num_cus, 64);
+    const size_t B = (size_t)d->max_batch;
+    int *l1 = d->d_ovf_list, *l2 = d->d_ovf2_list;
+    uint64_t *ws = d->d_wide_ws;
+    bool ok = true;
+    if (ok && ovf && !l1) ok = hipMalloc((void **)&l1, sizeof(int) * B) == hipSuccess;
+    if (ok && mid && wide && !l2) ok = hipMalloc((void **)&l2, sizeof(int) * B) == hipSuccess;
+    if (ok && wws && !ws) ok = hipMalloc((void **)&ws, sizeof(uint64_t) * (size_t)wgrid * lsd_wide_ws_words()) == hipSuccess;
+    if (!ok) {
+        if (l1 != d->d_ovf_list) hipFree(l1);
+        if (l2 != d->d_ovf2_list) hipFree(l2);
+        if (ws != d->d_wide_ws) hipFree(ws);
+        return false;
+    }
+    if (ws != d->d_wide_ws) d->wide_grid = wgrid;
+    d->d_ovf_list = l1;
+    d->d_ovf2_list = l2;
+    d->d_wide_ws = ws;
+    d->ovf = ovf;
+    d->mid = mid;
+    d->mid_keys_in_lds = mid_keys;
+    d->mid_grid = d->num_cus;
+    d->wide = wide;
+    d->wide_keys_in_lds = wide_keys;
+    return true;
+}
 
 const char *qlsd_last_error(void) { return g_err; }
 
@@ -287,28 +340,22 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         return fail(QLSD_E_UNSUPPORTED, "LSD workspace per wavefront too large");
     }
     d->lsd_grid = 8 * d->num_cus;
-    // capacity of lsd_kernel: 64 W local rows (one per clustered detector, so never more than m)
-    // and, with LSD-mu, 64 W dependent columns (never more than n)
-    d->wide = g.m > 64 * W || (with_mu && g.n > 64 * W);
-    if (d->wide) {
-        // keys in LDS when they fit, else read from the LLR rows; a graph too large for either
-        // keeps the OVERFLOW status on such shots
-        d->wide_keys_in_lds = lsd_wide_lds(g, true, with_mu) <= kLdsPerCu - 1024;
-        d->wide = d->wide_keys_in_lds || lsd_wide_lds(g, false, with_mu) <= kLdsPerCu - 1024;
-        d->wide_grid = std::min(d->num_cus, 64);
-    }
     // OSD-0: register basis for m <= 256, the wide (device-memory) basis up to 1024 rows, which
-    // reuses the wide LSD kernel's workspace (a decoder with m > 256 always has one)
+    // uses the wide LSD kernel's workspace (allocated below for every decoder with m > 256)
     d->osd_W = g.m <= 64 ? 1 : g.m <= 128 ? 2 : g.m <= 256 ? 4 : kWideW;
     d->osd_P = 1;
     while (d->osd_P < g.n) d->osd_P <<= 1;
     d->osd_wave_bytes = (int)osd0_wave_bytes(g, d->osd_W, d->osd_P);
-    d->osd_ok = d->osd_P <= kOsdMaxSort && g.m <= kWideRows && (d->osd_W != kWideW || d->wide) &&
+    d->osd_ok = d->osd_P <= kOsdMaxSort && g.m <= kWideRows &&
                 (size_t)d->osd_wave_bytes * (d->osd_W == kWideW ? 1 : 4) <= kLdsPerCu - 1024;
     if ((params->flags & QLSD_FLAG_OSD0_POST) && !d->osd_ok) {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "OSD-0 supports n <= %d and m <= %d (n=%d, m=%d)", kOsdMaxSort, kWideRows, g.n, g.m);
     }
+    d->ovf = d->mid = d->wide = false;
+    d->d_ovf_list = d->d_ovf2_list = nullptr;
+    d->d_wide_ws = nullptr;
+    d->wide_grid = d->mid_grid = 0;
     d->timing = (params->flags & QLSD_FLAG_STAGE_TIMING) != 0;
     for (int k = 0; k < 3; k++) d->ev[k] = nullptr;
     if (d->timing)
@@ -325,11 +372,10 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     hipError_t e3 = hipMalloc((void **)&d->d_flag, (size_t)max_batch);
     if (e3 == hipSuccess) e3 = hipMalloc((void **)&d->d_list, sizeof(int) * (size_t)max_batch);
     hipError_t e4 = hipMalloc((void **)&d->d_llr, sizeof(float) * (size_t)max_batch * g.n);
-    if (e4 == hipSuccess && d->wide) {
-        e4 = hipMalloc((void **)&d->d_ovf_list, sizeof(int) * (size_t)max_batch);
-        if (e4 == hipSuccess)
-            e4 = hipMalloc((void **)&d->d_wide_ws, sizeof(uint64_t) * (size_t)d->wide_grid * lsd_wide_ws_words());
-    }
+    // capacity of lsd_kernel: 64 W local rows (one per clustered detector, so never more than m)
+    // and, with LSD-mu, 64 W dependent columns (never more than n); a graph too large for every
+    // overflow kernel keeps the OVERFLOW status on such shots
+    if (e4 == hipSuccess && !configure_overflow(d, W, false)) e4 = hipErrorOutOfMemory;
     if (e1 || e2 || e3 || e4) {
         qlsd_decoder_destroy(d);
         return fail(QLSD_E_NOMEM, "device workspace allocation failed (max_batch=%d)", max_batch);
@@ -348,6 +394,7 @@ void qlsd_decoder_destroy(qlsd_decoder d) {
     hipFree(d->d_llr);
     hipFree(d->d_netws);
     hipFree(d->d_ovf_list);
+    hipFree(d->d_ovf2_list);
     hipFree(d->d_wide_ws);
     for (int k = 0; k < 3; k++)
         if (d->ev[k]) hipEventDestroy(d->ev[k]);
@@ -361,13 +408,14 @@ struct Ws {
     uint8_t *flag;      // B: shot goes from BP to LSD
     int *list;          // B: shots for LSD
     float *llr;         // B x n: posteriors handed from BP to LSD
-    int *ovf_list;      // B (decoders that can overflow): shots for the wide LSD kernel
+    int *ovf_list;      // B (decoders that can overflow): shots for the mid (else the wide) LSD kernel
+    int *ovf2_list;     // B (mid and wide): shots for the wide LSD kernel
     uint64_t *wide_ws;  // wide_grid * lsd_wide_ws_words()
     int wide_grid;
 };
 
 static Ws decoder_ws(qlsd_decoder d) {
-    return Ws{d->d_ctl, d->d_flag, d->d_list, d->d_llr, d->d_ovf_list, d->d_wide_ws, d->wide_grid};
+    return Ws{d->d_ctl, d->d_flag, d->d_list, d->d_llr, d->d_ovf_list, d->d_ovf2_list, d->d_wide_ws, d->wide_grid};
 }
 
 static BpArgs bp_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, int B) {
@@ -423,24 +471,43 @@ static LsdArgs lsd_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, const f
     return a;
 }
 
-// LSD kernel arguments list overflowing shots for the wide kernel (decoders that can overflow)
+// LSD kernel arguments list overflowing shots for the overflow kernels (decoders that can overflow)
 static void with_overflow_list(qlsd_decoder d, const Ws &w, LsdArgs &l) {
-    if (!d->wide) return;
+    if (!d->ovf) return;
     l.ovf_list = w.ovf_list;
     l.ovf_count = w.ctl + kCtlOvf;
 }
 
-// The wide LSD kernel over the shots the LSD kernel listed (it exits at once when none was).
-static hipError_t run_wide(qlsd_decoder d, const Ws &ws, const uint8_t *syn, const float *llr, uint8_t *corr,
-                           qlsd_shot_info *info, int bp_iters, hipStream_t s) {
-    if (!d->wide) return hipSuccess;
+// The overflow kernels over the shots the LSD kernel listed: the mid kernel, then the wide kernel
+// over the shots the mid kernel listed (each exits at once when nothing was listed).
+static hipError_t run_overflow(qlsd_decoder d, const Ws &ws, const uint8_t *syn, const float *llr, uint8_t *corr,
+                               qlsd_shot_info *info, int bp_iters, hipStream_t s,
+                               qlsd_cluster_stats *cstats = nullptr) {
+    if (!d->ovf) return hipSuccess;
+    if (d->mid) {
+        LsdArgs x = lsd_args(d, ws, syn, llr, corr, info);
+        x.list = ws.ovf_list;
+        x.list_count = ws.ctl + kCtlOvf;
+        x.next_item = ws.ctl + kCtlItemM;
+        x.bp_iters = bp_iters;
+        x.keys_in_lds = d->mid_keys_in_lds;
+        x.graph_in_lds = 0;
+        x.cstats = cstats;
+        if (d->wide) {
+            x.ovf_list = ws.ovf2_list;
+            x.ovf_count = ws.ctl + kCtlOvf2;
+        }
+        const hipError_t e = launch_lsd_mid(x, d->mid_grid, s);
+        if (e != hipSuccess || !d->wide) return e;
+    }
     LsdArgs w = lsd_args(d, ws, syn, llr, corr, info);
-    w.list = ws.ovf_list;
-    w.list_count = ws.ctl + kCtlOvf;
+    w.list = d->mid ? ws.ovf2_list : ws.ovf_list;
+    w.list_count = ws.ctl + (d->mid ? kCtlOvf2 : kCtlOvf);
     w.next_item = ws.ctl + kCtlItemW;
     w.bp_iters = bp_iters;
     w.keys_in_lds = d->wide_keys_in_lds;
     w.graph_in_lds = 0;
+    w.cstats = cstats;
     return launch_lsd_wide(w, ws.wide_ws, ws.wide_grid, s);
 }
 
@@ -510,7 +577,7 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
         rest.coherent_llr = 0;  // after the kernel boundary plain loads see every row
         with_overflow_list(d, w, rest);
         HIP_OK(launch_lsd(rest, d->lsd_W, std::min(d->lsd_grid, d->num_cus), s));
-        HIP_OK(run_wide(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
+        HIP_OK(run_overflow(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
         if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
         return QLSD_OK;
     }
@@ -536,7 +603,7 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
     l.bp_iters = d->params.max_iter;
     with_overflow_list(d, w, l);
     HIP_OK(launch_lsd(l, d->lsd_W, d->lsd_grid, s));
-    HIP_OK(run_wide(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
+    HIP_OK(run_overflow(d, w, syndromes, w.llr, corrections, info, d->params.max_iter, s));
     if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
     return QLSD_OK;
 }
@@ -580,8 +647,11 @@ qlsd_status qlsd_decode_static(qlsd_decoder d, const uint8_t *syndromes, int32_t
     };
     const size_t o_ctl = take(sizeof(int) * kCtlWords), o_flag = take((size_t)B), o_list = take(sizeof(int) * (size_t)B),
                  o_llr = take(sizeof(float) * (size_t)B * n);
-    const size_t o_ovf = d->wide ? take(sizeof(int) * (size_t)B) : 0;
-    const size_t o_wide = d->wide ? take(sizeof(uint64_t) * lsd_wide_ws_words() * kStaticWideGrid) : 0;
+    const bool two = d->mid && d->wide;
+    const bool wws = d->wide || ((d->params.flags & QLSD_FLAG_OSD0_POST) && d->osd_W == kWideW);
+    const size_t o_ovf = d->ovf ? take(sizeof(int) * (size_t)B) : 0;
+    const size_t o_ovf2 = two ? take(sizeof(int) * (size_t)B) : 0;
+    const size_t o_wide = wws ? take(sizeof(uint64_t) * lsd_wide_ws_words() * kStaticWideGrid) : 0;
     if (off > kStaticScratchBytes)
         return fail(QLSD_E_BATCH, "qlsd_decode_static: B=%d needs %zu bytes of scratch, the library holds %zu",
                     B, off, kStaticScratchBytes);
@@ -593,8 +663,9 @@ qlsd_status qlsd_decode_static(qlsd_decoder d, const uint8_t *syndromes, int32_t
     w.flag = base + o_flag;
     w.list = (int *)(base + o_list);
     w.llr = (float *)(base + o_llr);
-    w.ovf_list = d->wide ? (int *)(base + o_ovf) : nullptr;
-    w.wide_ws = d->wide ? (uint64_t *)(base + o_wide) : nullptr;
+    w.ovf_list = d->ovf ? (int *)(base + o_ovf) : nullptr;
+    w.ovf2_list = two ? (int *)(base + o_ovf2) : nullptr;
+    w.wide_ws = wws ? (uint64_t *)(base + o_wide) : nullptr;
     w.wide_grid = kStaticWideGrid;
     return decode_with(d, w, syndromes, B, corrections, info, (hipStream_t)stream, false);
 }
@@ -625,7 +696,7 @@ qlsd_status qlsd_lsd(qlsd_decoder d, const uint8_t *syndromes, const float *llr,
     l.count = B;
     with_overflow_list(d, w, l);
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
-    HIP_OK(run_wide(d, w, syndromes, llr, corrections, info, 0, s));
+    HIP_OK(run_overflow(d, w, syndromes, llr, corrections, info, 0, s));
     return QLSD_OK;
 }
 
@@ -642,16 +713,7 @@ qlsd_status qlsd_lsd_stats(qlsd_decoder d, const uint8_t *syndromes, const float
     l.cstats = stats;
     with_overflow_list(d, w, l);
     HIP_OK(launch_lsd(l, d->lsd_W, std::min(d->lsd_grid, (B + 3) / 4), s));
-    if (d->wide) {
-        LsdArgs x = lsd_args(d, w, syndromes, llr, corrections, info);
-        x.list = w.ovf_list;
-        x.list_count = w.ctl + kCtlOvf;
-        x.next_item = w.ctl + kCtlItemW;
-        x.keys_in_lds = d->wide_keys_in_lds;
-        x.graph_in_lds = 0;
-        x.cstats = stats;
-        HIP_OK(launch_lsd_wide(x, w.wide_ws, w.wide_grid, s));
-    }
+    HIP_OK(run_overflow(d, w, syndromes, llr, corrections, info, 0, s, stats));
     return QLSD_OK;
 }
 
@@ -681,33 +743,17 @@ qlsd_status qlsd_osd0(qlsd_decoder d, const uint8_t *syndromes, const float *llr
 }
 
 // Sets the LSD kernel's local-row capacity to 64 * W (W in {1, 2, 4}); shots that outgrow it go
-// to the wide kernel, whose workspace is allocated here when first needed.  Returns false (and
-// leaves the decoder as it was) when W does not fit the LDS budget or cannot be allocated.
+// to the overflow kernels, whose buffers are allocated here when first needed.  Returns false (and
+// leaves the decoder as it was) when W does not fit the LDS budget, no overflow kernel fits the
+// code, or an allocation fails.
 static bool set_lsd_capacity(qlsd_decoder d, int W) {
     const DevGraph &g = d->code->g;
     const bool with_mu = d->params.lsd_order > 0;
     if (with_mu && W != 4) return false;  // LSD-mu kernels are built for W = 4 only
     if (lsd_total_lds(g, W, d->lsd_keys_in_lds != 0, d->lsd_graph_in_lds != 0, with_mu) > kLdsPerCu - 1024) return false;
-    const bool need_wide = g.m > 64 * W || (with_mu && g.n > 64 * W);
-    if (need_wide && !d->d_wide_ws) {
-        const bool keys = lsd_wide_lds(g, true, with_mu) <= kLdsPerCu - 1024;
-        if (!keys && lsd_wide_lds(g, false, with_mu) > kLdsPerCu - 1024) return false;
-        int *ovf = nullptr;
-        uint64_t *ws = nullptr;
-        const int grid = std::min(d->num_cus, 64);
-        if (hipMalloc((void **)&ovf, sizeof(int) * (size_t)d->max_batch) != hipSuccess) return false;
-        if (hipMalloc((void **)&ws, sizeof(uint64_t) * (size_t)grid * lsd_wide_ws_words()) != hipSuccess) {
-            hipFree(ovf);
-            return false;
-        }
-        d->d_ovf_list = ovf;
-        d->d_wide_ws = ws;
-        d->wide_grid = grid;
-        d->wide_keys_in_lds = keys;
-    }
+    if (!configure_overflow(d, W, true)) return false;
     d->lsd_W = W;
     d->lsd_wave_bytes = (int)lsd_wave_bytes(g, W, d->lsd_keys_in_lds != 0, with_mu);
-    d->wide = need_wide;
     return true;
 }
 

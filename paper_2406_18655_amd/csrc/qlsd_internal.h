@@ -104,6 +104,12 @@ constexpr int kWideDependent = 4096;  // LSD-mu: dependent clustered columns the
 size_t lsd_wide_ws_words();                 // per workgroup
 size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
 hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st);
+// Mid LSD: as the wide kernel with kMidRows local rows and the basis in LDS (no workspace); shots
+// that outgrow it are appended to a.ovf_list / a.ovf_count (when set) for the wide kernel.
+constexpr int kMidW = 8;
+constexpr int kMidRows = 64 * kMidW;
+size_t lsd_mid_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
+hipError_t launch_lsd_mid(const LsdArgs &a, int grid, hipStream_t st);
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st);
 
 hipError_t launch_error_clusters(const DevGraph &g, const uint8_t *e, int B, qlsd_cluster_stats *out, hipStream_t st);

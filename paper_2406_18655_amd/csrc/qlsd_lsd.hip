@@ -92,22 +92,30 @@ hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
 // one wavefront per workgroup runs the same per-shot code with 64 * kWideW local rows, its
 // Gauss-Jordan basis in this workgroup's slice of device memory and only the slices of local
 // rows in use visited.  Shots beyond even this capacity keep the OVERFLOW status.
-template <bool MU>
+// Shots whose clusters outgrow a register basis, one wavefront per workgroup, 64 WW local rows.
+// BLDS (WW = kMidW): the basis sits in LDS after the wavefront's arrays, and a shot that outgrows
+// it is listed for the device-memory kernel (A.ovf_list); otherwise (WW = kWideW) the basis is the
+// workgroup's block of ws.
+template <bool MU, int WW, bool BLDS>
 __global__ __launch_bounds__(64) void lsd_wide_kernel(LsdArgs A, uint64_t *ws) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
+    const int total = *A.list_count;
+    if (total == 0) return;
     GView<false> g;
     g.max_cw = A.g.max_cw;
     g.rp = A.g.row_ptr; g.ci = A.g.col_idx; g.cp = A.g.col_ptr; g.ri = A.g.row_idx;
-    const LsdLds S = carve_lsd(smem, A.g.m, A.g.n, kWideRows, A.keys_in_lds != 0, A.mu > 0, kWideDependent);
-    uint64_t *mem = ws + (size_t)blockIdx.x * (2 * kWideW * kWideW * 64);
-    const int total = *A.list_count;
+    size_t offs[kLsdLayoutEntries];
+    const size_t arrays = lsd_layout(A.g.m, A.g.n, 64 * WW, A.keys_in_lds != 0, A.mu > 0, offs, kWideDependent);
+    const LsdLds S = carve_lsd(smem, A.g.m, A.g.n, 64 * WW, A.keys_in_lds != 0, A.mu > 0, kWideDependent);
+    uint64_t *mem = BLDS ? (uint64_t *)(smem + ((arrays + 15) & ~(size_t)15))
+                         : ws + (size_t)blockIdx.x * (2 * WW * WW * 64);
     for (;;) {
         int item = 0;
         if (lane == 0) item = atomicAdd(A.next_item, 1);
         item = __builtin_amdgcn_readfirstlane(item);
         if (item >= total) break;
-        decode_shot<kWideW, MU, GView<false>, true>(A, S, g, A.list[item], lane, mem);
+        decode_shot<WW, MU, GView<false>, true, BLDS, BLDS>(A, S, g, A.list[item], lane, mem);
         wave_sync();
     }
 }
@@ -207,17 +215,31 @@ size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu) {
     return lsd_layout(g.m, g.n, kWideRows, keys_in_lds, with_mu, offs, kWideDependent);
 }
 
-hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st) {
+size_t lsd_mid_lds(const DevGraph &g, bool keys_in_lds, bool with_mu) {
     size_t offs[kLsdLayoutEntries];
-    const size_t lds = lsd_layout(a.g.m, a.g.n, kWideRows, a.keys_in_lds != 0, a.mu > 0, offs, kWideDependent);
-    const void *fn = a.mu > 0 ? (const void *)lsd_wide_kernel<true> : (const void *)lsd_wide_kernel<false>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const size_t arrays = lsd_layout(g.m, g.n, kMidRows, keys_in_lds, with_mu, offs, kWideDependent);
+    return ((arrays + 15) & ~(size_t)15) + sizeof(uint64_t) * 2 * kMidW * kMidW * 64;
+}
+
+template <bool MU, int WW, bool BLDS>
+static hipError_t launch_wide_t(const LsdArgs &a, uint64_t *ws, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)lsd_wide_kernel<MU, WW, BLDS>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (a.mu > 0)
-        hipLaunchKernelGGL((lsd_wide_kernel<true>), dim3(grid), dim3(64), lds, st, a, ws);
-    else
-        hipLaunchKernelGGL((lsd_wide_kernel<false>), dim3(grid), dim3(64), lds, st, a, ws);
+    hipLaunchKernelGGL((lsd_wide_kernel<MU, WW, BLDS>), dim3(grid), dim3(64), lds, st, a, ws);
     return hipGetLastError();
+}
+
+hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st) {
+    const size_t lds = lsd_wide_lds(a.g, a.keys_in_lds != 0, a.mu > 0);
+    return a.mu > 0 ? launch_wide_t<true, kWideW, false>(a, ws, grid, lds, st)
+                    : launch_wide_t<false, kWideW, false>(a, ws, grid, lds, st);
+}
+
+hipError_t launch_lsd_mid(const LsdArgs &a, int grid, hipStream_t st) {
+    const size_t lds = lsd_mid_lds(a.g, a.keys_in_lds != 0, a.mu > 0);
+    return a.mu > 0 ? launch_wide_t<true, kMidW, true>(a, nullptr, grid, lds, st)
+                    : launch_wide_t<false, kMidW, true>(a, nullptr, grid, lds, st);
 }
 
 // LSD-mu decoders always use W = 4 (their extra growth rounds need the room), so LSD-mu code is

@@ -164,13 +164,16 @@ __device__ bool unite(int32_t *par, int x, int y) {
 // The shot's Gauss-Jordan basis.  Mrow(s, w): lane row s's bits over pivot local rows 64w..64w+63
 // (rows of the reduced pivot vectors); CT(s, w): for a pivot row, the pivots whose combination uses
 // the column that created it.  InMem = false keeps both in registers (the LSD kernels, W <= 4);
-// InMem = true keeps them in a per-wavefront slice of device memory ([2][W][W][64] words, lane
-// fastest) for the wide kernel that takes the shots whose clusters outgrow the register basis.
-template <int W, bool InMem>
+// InMem = true keeps them in a per-wavefront block of memory ([2][W][W][64] words, lane fastest)
+// for the kernels that take the shots whose clusters outgrow the register basis: in LDS (InLds,
+// the 512-row kernel) or in device memory (the 1024-row kernel).
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+template <int W, bool InMem, bool InLds = false>
 struct Basis;
 
 template <int W>
-struct Basis<W, false> {
+struct Basis<W, false, false> {
     uint64_t Mrow[W][W];
     uint64_t CT[W][W];
     uint64_t piv[W];  // uniform: pivot local rows
@@ -197,15 +200,17 @@ struct Basis<W, false> {
     }
 };
 
-template <int W>
-struct Basis<W, true> {
-    uint64_t *mem;  // this wavefront's slice, offset by its lane
+template <int W, bool InLds>
+struct Basis<W, true, InLds> {
+    // an LDS-qualified pointer keeps the accesses ds_ instructions
+    using Ptr = typename std::conditional<InLds, lds_u64 *, uint64_t *>::type;
+    Ptr mem;        // this wavefront's block, offset by its lane
     int ns;         // uniform: slices 0..ns-1 of local rows are in use
     uint64_t piv[W];
     uint64_t sp[W];
     static constexpr bool kInMem = true;
-    __device__ __forceinline__ uint64_t &M(int s, int w) { return mem[(s * W + w) * 64]; }
-    __device__ __forceinline__ uint64_t &C(int s, int w) { return mem[((W + s) * W + w) * 64]; }
+    __device__ __forceinline__ auto &M(int s, int w) { return mem[(s * W + w) * 64]; }
+    __device__ __forceinline__ auto &C(int s, int w) { return mem[((W + s) * W + w) * 64]; }
     __device__ __forceinline__ uint64_t M(int s, int w) const { return mem[(s * W + w) * 64]; }
     __device__ __forceinline__ uint64_t C(int s, int w) const { return mem[((W + s) * W + w) * 64]; }
     __device__ __forceinline__ bool active(int s) const { return s < ns; }
@@ -355,7 +360,7 @@ __device__ __forceinline__ void insert_apply(BB &B, const LsdLds &S, int col, in
 // hold at most 64 rows costs a one-slice reduction); the device-memory basis tests each slice at
 // run time.
 template <int W, class BB>
-__device__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
+__device__ __forceinline__ bool insert_column(BB &B, const LsdLds &S, int col, int lane, int lr_src, int base, int cw) {
     InsertPlan<W> P;
     bool piv;
     if constexpr (!BB::kInMem && W == 2) {
@@ -613,11 +618,12 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
 
 // MU: the decoder runs LSD-mu (A.mu > 0); decoders without it get no LSD-mu code at all, which
 // leaves the register allocator more room in the LSD-0 rounds.
-// WIDE: the basis lives in device memory at basis_mem (this wavefront's [2][W][W][64] words) and
+// WIDE: the basis lives in memory at basis_mem (this wavefront's [2][W][W][64] words: in LDS when
+// BLDS, else in device memory) and
 // only the slices of local rows in use are visited; the other kernels keep it in registers.
 // OVF: a shot that outgrows the capacity is appended to A.ovf_list (when set) for the wide kernel.
-template <int W, bool MU, class G, bool WIDE = false, bool OVF = false>
-__device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane,
+template <int W, bool MU, class G, bool WIDE = false, bool OVF = false, bool BLDS = false>
+__device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane,
                             uint64_t *basis_mem = nullptr) {
     constexpr int K = 64 * W;
     constexpr int KNP = WIDE ? kWideDependent : K;  // capacity of the dependent-column list
@@ -729,11 +735,12 @@ __device__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int s
     const int nseed = nrows;
     if (lane == 0) S.ctl[0] = nrows;
 
-    Basis<W, WIDE> B;
+    Basis<W, WIDE, BLDS> B;
     if constexpr (WIDE) {
-        // rows and pivots only ever occupy the first ceil(m/64) slices; the rest stays untouched
-        B.mem = basis_mem + lane;
-        const int msl = (m + 63) >> 6;
+        // rows and pivots only ever occupy the first min(ceil(m/64), W) slices (a shot with more
+        // rows has overflowed); the rest stays untouched
+        B.mem = (typename Basis<W, true, BLDS>::Ptr)basis_mem + lane;
+        const int msl = min((m + 63) >> 6, W);
         for (int s = 0; s < msl; s++)
             for (int w = 0; w < msl; w++) { B.M(s, w) = 0; B.C(s, w) = 0; }
     }
