@@ -369,6 +369,11 @@ __device__ __forceinline__ bool insert_column(BB &B, const LsdLds &S, int col, i
         piv = B.ns <= 1   ? insert_plan<W, 1>(B, lane, lr_src, base, cw, P)
               : B.ns <= 2 ? insert_plan<W, 2>(B, lane, lr_src, base, cw, P)
                           : insert_plan<W, W>(B, lane, lr_src, base, cw, P);
+    } else if constexpr (BB::kInMem && W >= 8) {
+        // memory bases: tiers of four slices (the loops still test each slice at run time)
+        if (B.ns <= 4) piv = insert_plan<W, 4>(B, lane, lr_src, base, cw, P);
+        else if (W > 8 && B.ns <= 8) piv = insert_plan<W, (W > 8 ? 8 : W)>(B, lane, lr_src, base, cw, P);
+        else piv = insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     } else {
         piv = insert_plan<W, W>(B, lane, lr_src, base, cw, P);
     }
