@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-ordering leg")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="skip the learned leg's grid of plain BP budgets and LSD orders (the comparison at "
+                         "matched error rate), e.g. for short profiled runs")
     ap.add_argument("--tune", action="store_true",
                     help="run qlsd_decoder_tune on batch 0 before the timed steps (on the headline batch it "
                          "lands on the default shapes within noise)")
@@ -316,6 +319,8 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
     binding.attach_net(dec2, net)
     out["two_streams_value"] = round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1)
     del dec2
+    if args.no_grid:
+        return out
     # plain BP + LSD over its own knobs (BP budget, LSD order mu of Sec. 4.3), on the same
     # shots: the fastest setting whose logical error rate is not above the learned form's
     # (differences within 2 sigma count as equal) is the plain decoder at matched error rate
@@ -408,13 +413,13 @@ def record_counters(pass1, pass2, path):
         rows = list(csv.DictReader(open(fn)))
         by = {}
         for r in rows:
-            if "bp_lds_kernel<6, 3, true, 2>" not in r.get("Kernel_Name", ""):
+            if "bp_lds_kernel<6, 3, true, 2, false>" not in r.get("Kernel_Name", ""):
                 continue
             by.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
         for k, v in by.items():
             vals[k] = float(np.median(v))
     vals["kernel_source_hash"] = _kernel_hash()
-    vals["kernel"] = "bp_lds_kernel<6, 3, true, 2> (BP 50 + LSD-0 in one kernel)"
+    vals["kernel"] = "bp_lds_kernel<6, 3, true, 2, false> (BP 50 + LSD-0 in one kernel)"
     with open(path, "w") as f:
         json.dump(vals, f, indent=1)
     print(json.dumps(vals))
@@ -447,15 +452,15 @@ def record_traffic(fetch, write, cfetch, cwrite, path):
         v = [float(r["Counter_Value"]) for r in csv.DictReader(open(fn)) if needle in r.get("Kernel_Name", "")]
         return v
 
-    f_k = float(np.median(per_dispatch(fetch, "bp_lds_kernel<6, 3, true, 2>")))
-    w_k = float(np.median(per_dispatch(write, "bp_lds_kernel<6, 3, true, 2>")))
+    f_k = float(np.median(per_dispatch(fetch, "bp_lds_kernel<6, 3, true, 2, false>")))
+    w_k = float(np.median(per_dispatch(write, "bp_lds_kernel<6, 3, true, 2, false>")))
     # the 1 GiB copies (the calibration run's last, tiny copy returns a flag to the host)
     cf = [v for v in per_dispatch(cfetch, "copyBuffer") if v > 1024.0]
     cw = [v for v in per_dispatch(cwrite, "copyBuffer") if v > 1024.0]
     nbytes = 1 << 30
     f_fac = nbytes / 1024.0 / float(np.mean(cf))
     w_fac = nbytes / 1024.0 / float(np.mean(cw))
-    rec = {"kernel": "bp_lds_kernel<6,3,true,2> (BP + LSD-0 in one kernel)",
+    rec = {"kernel": "bp_lds_kernel<6,3,true,2,false> (BP + LSD-0 in one kernel)",
            "workload": "bb144_codecap_p0.05_bp50_lsd0, 65536 shots per launch",
            "kernel_source_hash": _kernel_hash(),
            "bytes_per_launch": round(1024.0 * (f_k * f_fac + w_k * w_fac)),

@@ -176,7 +176,8 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms)
  * qlsd_decode when no refinement net is attached, since the shape decides whether BP and LSD
  * can share one kernel); for LSD, the number of workgroups, then the LSD capacity tier (as
  * qlsd_decoder_set_lsd_capacity, every tier up to the decoder's default, timed on the whole
- * decode).  Outputs never depend on these shapes.  Synchronous on `stream`;
+ * decode; a smaller tier is kept only when it is at least 10 % faster on the sample, since other
+ * batches may hold more shots that outgrow it).  Outputs never depend on these shapes.  Synchronous on `stream`;
  * allocates and frees scratch output buffers; must not overlap other calls on this decoder.
  * `report` (host char[report_len], nullable) receives one line per candidate and the choice. */
 qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, int32_t reps,

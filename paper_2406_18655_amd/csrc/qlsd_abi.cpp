@@ -871,19 +871,30 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
     snprintf(line, sizeof(line), "lsd chosen: %d workgroups\n", best_lsd);
     rep += line;
     // LSD capacity per wavefront (the schedule for uneven cluster sizes): every tier up to the
-    // one that can never overflow, shots beyond a smaller tier's capacity finished by the wide
-    // kernel; timed on the whole decode (the tier also decides whether BP and LSD share a kernel)
+    // default, shots beyond a smaller tier's capacity decoded again by the overflow kernels; timed
+    // on the whole decode (the tier also decides whether BP and LSD share a kernel)
     {
         const int W0 = d->lsd_W;
         int best_W = W0;
-        float best_ms = 1e30f;
-        for (int W : {1, 2, 4}) {
+        // A tier below the default re-decodes the shots that outgrow it after the LSD kernel; one
+        // sample batch may hold fewer of them than other batches will, so such a tier must beat
+        // the default by kCapacityMargin to be kept
+        constexpr float kCapacityMargin = 0.9f;
+        float ms_w[3] = {0.f, 0.f, 0.f};
+        for (int k = 2; k >= 0; k--) {
+            const int W = 1 << k;
             if (W > W0 || !set_lsd_capacity(d, W)) continue;
-            const float ms = timeit(decode_run);
-            snprintf(line, sizeof(line), "lsd capacity %d local rows per wavefront: decode %.4f ms\n", 64 * W, ms);
+            ms_w[k] = timeit(decode_run);
+            snprintf(line, sizeof(line), "lsd capacity %d local rows per wavefront: decode %.4f ms\n", 64 * W, ms_w[k]);
             rep += line;
-            if (ms > 0.f && ms < best_ms) { best_ms = ms; best_W = W; }
         }
+        const int k0 = W0 == 4 ? 2 : W0 == 2 ? 1 : 0;
+        float best_ms = ms_w[k0] > 0.f ? ms_w[k0] : 1e30f;
+        for (int k = 0; k < k0; k++)
+            if (ms_w[k] > 0.f && ms_w[k] < kCapacityMargin * ms_w[k0] && ms_w[k] < best_ms) {
+                best_ms = ms_w[k];
+                best_W = 1 << k;
+            }
         set_lsd_capacity(d, best_W);
         snprintf(line, sizeof(line), "lsd capacity chosen: %d local rows\n", 64 * best_W);
         rep += line;
