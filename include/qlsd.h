@@ -121,11 +121,12 @@ qlsd_status qlsd_decode(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, u
 
 /* qlsd_decode without the decoder's own device workspace, for callers that cannot allocate
  * (work under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * per-call scratch (counters, shot lists, the BP-to-LSD posterior rows, the wide-LSD bases) is
- * carved from one static device array of the library, 48 MiB per GPU, held until the process
- * ends.  Same arguments, kernels and outputs as qlsd_decode; no allocation, memset or host
- * synchronisation.  QLSD_E_BATCH if B's scratch (about B * (4n + 9) bytes plus 2 MiB when
- * clusters can outgrow the LSD kernel) exceeds 48 MiB; QLSD_E_UNSUPPORTED for a decoder whose
+ * per-call scratch (counters, shot lists, the BP-to-LSD posterior rows, the overflow lists and
+ * the 1024-row LSD bases) is carved from one static device array of the library, 48 MiB per GPU,
+ * held until the process ends.  Same arguments, kernels and outputs as qlsd_decode; no
+ * allocation, memset or host synchronisation.  QLSD_E_BATCH if B's scratch (at most about
+ * B * (4n + 13) bytes, plus 2 MiB of bases when m > 512, or with QLSD_FLAG_OSD0_POST when
+ * m > 256) exceeds 48 MiB; QLSD_E_UNSUPPORTED for a decoder whose
  * attached refinement net needs its own workspace (large graphs).  Every call on one GPU shares
  * that GPU's array: calls that overlap on one GPU (any decoder, any stream) race. */
 qlsd_status qlsd_decode_static(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,

@@ -1,7 +1,9 @@
 """qlsd_decode_static: the decode of qlsd_decode with its per-call scratch carved from the
 library's static device array instead of the decoder's workspace.  Through the C ABI, against
 qlsd_decode on the same decoder and shots, two calls in a row, the second with a smaller batch;
-the one-kernel BP + LSD path, the separate-kernel path with LSD-mu and the wide LSD kernel."""
+the one-kernel BP + LSD path, the separate-kernel path with LSD-mu and both overflow tiers (the
+512-row LDS kernel and the 1024-row device-memory kernel, whose lists and bases also come from the
+static array)."""
 import numpy as np
 import pytest
 
@@ -25,7 +27,7 @@ def _cases(which):
         return code, dict(max_iter=50), (65536, 1000), None
     if which == "dem":
         code = synthetic_dem()
-        return code, dict(max_iter=100, lsd_order=10), (1024, 100), 0.4
+        return code, dict(max_iter=100, lsd_order=10), (1024, 100), (0.12, 0.4)
     code = random_34_hgp(32, p=0.1)
     return code, dict(max_iter=30), (256, 37), None
 
@@ -39,9 +41,10 @@ def test_static_scratch_decode_equals_decode(which):
     rng = np.random.default_rng(17)
     for k, B in enumerate(sizes):
         e, S = sample(code, B, seed=6100 + k)
-        if heavy is not None and k == 0:  # a syndrome whose clusters reach the wide LSD kernel
+        if heavy is not None and k == 0:  # syndromes whose clusters reach the overflow kernels
             S = S.copy()
-            S[3] = (rng.random(code.m) < heavy).astype(np.uint8)
+            for i, f in enumerate(heavy):
+                S[3 + i] = (rng.random(code.m) < f).astype(np.uint8)
         s = torch.from_numpy(np.ascontiguousarray(S)).cuda()
         want, winfo = dec.decode(s, want_info=True)
         got, ginfo = dec.decode_static(s, want_info=True)
