@@ -73,9 +73,9 @@ typedef struct {
 #define QLSD_ST_LSD_RUN 2u      /* LSD produced the correction                          */
 #define QLSD_ST_UNSAT 4u        /* some cluster could not be made valid (s not in image) */
 #define QLSD_ST_BAD_LLR 8u      /* NaN soft information; correction left at zero        */
-#define QLSD_ST_OVERFLOW 16u    /* clusters outgrew even the wide LSD kernel (more than 1024
-                                   clustered detectors, or more than 4096 dependent columns
-                                   with LSD-mu); correction zero */
+#define QLSD_ST_OVERFLOW 16u    /* clusters outgrew even the 1024-row overflow kernel (more
+                                   than 1024 clustered detectors, or more than 4096 dependent
+                                   columns with LSD-mu); correction zero */
 
 typedef struct {
     uint8_t status;           /* QLSD_ST_* bits */
@@ -114,8 +114,10 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
  * workgroups' BP left unsolved; a stand-alone LSD launch then finishes any shot not yet
  * taken.  Outputs are identical either way (every shot's LSD is the same function of its
  * syndrome and BP posterior).  Shots whose clusters outgrow the LSD kernel's register basis
- * (64 W local rows, W = 1, 2 or 4 chosen from m; 4 with LSD-mu) are finished by a wide LSD
- * kernel with up to 1024 local rows (same results, slower per shot). */
+ * (64 W local rows, W = 1, 2 or 4 chosen from m; 4 with LSD-mu; see
+ * qlsd_decoder_set_lsd_capacity) are decoded again by an overflow kernel with 512 local rows
+ * (basis in LDS) and, beyond that, one with 1024 (basis in device memory): same results, slower
+ * per shot. */
 qlsd_status qlsd_decode(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, uint8_t *corrections,
                         qlsd_shot_info *info, void *stream);
 
@@ -187,13 +189,13 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_
 /* LSD capacity tier, a schedule for uneven cluster sizes (Sec. 4.2 grows clusters of unbounded
  * size; most shots need few local rows, a few need many).  The LSD kernel holds a shot's
  * Gauss-Jordan basis in registers with room for local_rows (64, 128 or 256) clustered checks per
- * wavefront; a shot whose clusters outgrow it is handed whole to the wide LSD kernel (1024 local
- * rows, basis in device memory).  Smaller tiers run more wavefronts per compute unit and, at 64
+ * wavefront; a shot whose clusters outgrow it is handed whole to the overflow kernels (512 local
+ * rows with the basis in LDS, then 1024 in device memory).  Smaller tiers run more wavefronts per compute unit and, at 64
  * or 128, let BP and LSD share one kernel; outputs never depend on the tier.  The decoder's
  * default is the smallest tier that holds every check of the code (256 when m > 128); LSD-mu
- * decoders accept 256 only (QLSD_E_UNSUPPORTED otherwise).  May allocate the wide kernel's
- * workspace (device memory, freed with the decoder); QLSD_E_UNSUPPORTED when the wide kernel does
- * not fit the code or that allocation fails, leaving the decoder unchanged.  Host-side; must not
+ * decoders accept 256 only (QLSD_E_UNSUPPORTED otherwise).  May allocate the overflow lists and
+ * the 1024-row kernel's workspace (device memory, freed with the decoder); QLSD_E_UNSUPPORTED when
+ * no overflow kernel fits the code or an allocation fails, leaving the decoder unchanged.  Host-side; must not
  * overlap other calls on this decoder. */
 qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder dec, int32_t local_rows);
 

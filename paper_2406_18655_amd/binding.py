@@ -220,7 +220,7 @@ class Decoder:
 
     def set_lsd_capacity(self, local_rows: int):
         """LSD capacity tier: 64, 128 or 256 local rows per wavefront, shots beyond it finished by
-        the wide kernel (include/qlsd.h); outputs do not depend on it."""
+        the overflow kernels (include/qlsd.h); outputs do not depend on it."""
         _check(lib().qlsd_decoder_set_lsd_capacity(self._h, int(local_rows)))
 
     def stage_ms(self):

@@ -767,7 +767,7 @@ qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder d, int32_t local_rows) {
     if (!set_lsd_capacity(d, local_rows / 64))
         return fail(QLSD_E_UNSUPPORTED, "LSD capacity %d: %s", local_rows,
                     d->params.lsd_order > 0 ? "LSD-mu decoders run with 256 local rows"
-                                            : "the wide kernel does not fit this code, or its workspace could not be allocated");
+                                            : "no overflow kernel fits this code, or an allocation failed");
     return QLSD_OK;
 }
 

@@ -315,7 +315,7 @@ __device__ __noinline__ int2 fuse_step(int *list, int *next_item, int *bp_done, 
 
 // LSDW = 0: BP only.  LSDW = W > 0: BP, then LSD (decode_shot<W>) on published shots; OVF: the
 // code has more checks than the 64 W local rows, and a shot whose clusters outgrow them is listed
-// for the wide kernel (compiled in only where it can happen: it costs registers).  At most 128
+// for the overflow kernels (compiled in only where it can happen: it costs registers).  At most 128
 // VGPRs (4 wavefronts per SIMD), so that four BP workgroups fit on a CU.
 template <int MAXRW, int MAXCW, bool REG, int LSDW, bool OVF = false>
 __global__ __launch_bounds__(kBpThreads) __attribute__((amdgpu_waves_per_eu(4)))

@@ -61,7 +61,7 @@ struct LsdArgs {
     int skip_done;             // list entries < 0 were decoded already (after the fused kernel)
     int *done_count;           // with skip_done: how many were (nullable); all done -> no work
     int *ovf_list;             // nullable: shots whose clusters outgrew the kernel's capacity are
-    int *ovf_count;            //   appended here for the wide kernel (max_batch entries)
+    int *ovf_count;            //   appended here for the next overflow kernel (max_batch entries)
     qlsd_cluster_stats *cstats;  // B (nullable): per-shot statistics of the final clusters
 };
 
@@ -100,7 +100,7 @@ hipError_t launch_lsd(const LsdArgs &a, int W, int grid, hipStream_t st);
 // ws (grid * lsd_wide_ws_words() words); decodes the shots listed in a.list / *a.list_count.
 constexpr int kWideW = 16;
 constexpr int kWideRows = 64 * kWideW;
-constexpr int kWideDependent = 4096;  // LSD-mu: dependent clustered columns the wide kernel can list
+constexpr int kWideDependent = 4096;  // LSD-mu: dependent clustered columns the overflow kernels can list
 size_t lsd_wide_ws_words();                 // per workgroup
 size_t lsd_wide_lds(const DevGraph &g, bool keys_in_lds, bool with_mu);
 hipError_t launch_lsd_wide(const LsdArgs &a, uint64_t *ws, int grid, hipStream_t st);

@@ -88,11 +88,9 @@ hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
     return hipGetLastError();
 }
 
-// Wide LSD for the shots whose clusters outgrew the register basis of lsd_kernel (listed by it):
-// one wavefront per workgroup runs the same per-shot code with 64 * kWideW local rows, its
-// Gauss-Jordan basis in this workgroup's slice of device memory and only the slices of local
-// rows in use visited.  Shots beyond even this capacity keep the OVERFLOW status.
-// Shots whose clusters outgrow a register basis, one wavefront per workgroup, 64 WW local rows.
+// Overflow LSD for the shots whose clusters outgrew the register basis of lsd_kernel (listed by
+// it): one wavefront per workgroup runs the same per-shot code with 64 WW local rows, visiting
+// only the slices of local rows in use.  Shots beyond the last tier keep the OVERFLOW status.
 // BLDS (WW = kMidW): the basis sits in LDS after the wavefront's arrays, and a shot that outgrows
 // it is listed for the device-memory kernel (A.ovf_list); otherwise (WW = kWideW) the basis is the
 // workgroup's block of ws.

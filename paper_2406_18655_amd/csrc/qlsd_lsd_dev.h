@@ -626,7 +626,8 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
 // WIDE: the basis lives in memory at basis_mem (this wavefront's [2][W][W][64] words: in LDS when
 // BLDS, else in device memory) and
 // only the slices of local rows in use are visited; the other kernels keep it in registers.
-// OVF: a shot that outgrows the capacity is appended to A.ovf_list (when set) for the wide kernel.
+// OVF: a shot that outgrows the capacity is appended to A.ovf_list (when set) for the next
+// overflow kernel.
 template <int W, bool MU, class G, bool WIDE = false, bool OVF = false, bool BLDS = false>
 __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane,
                             uint64_t *basis_mem = nullptr) {
@@ -702,7 +703,7 @@ __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, c
     auto overflow = [&](uint8_t st) {
         write_row();
         finish(st | QLSD_ST_OVERFLOW, 0, 0);
-        // hand the shot to the wide kernel (launched after this one), which rewrites both
+        // hand the shot to the next overflow kernel (launched after this one), which rewrites both
         if constexpr (OVF) {
             if (A.ovf_list && lane == 0) A.ovf_list[atomicAdd(A.ovf_count, 1)] = shot;
         }

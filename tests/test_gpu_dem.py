@@ -109,7 +109,7 @@ def test_bb_lsd_mu_bit_exact(oracle_mod):
 
 def test_dem_overflowing_shot_decoded_in_batch(oracle_mod, dem):
     """A syndrome with more flipped detectors than the LSD kernel's capacity (256 local rows with
-    LSD order 10) goes on to the wide LSD kernel: it comes back decoded (H e_hat = s, equal to the
+    LSD order 10) goes on to the overflow kernels: it comes back decoded (H e_hat = s, equal to the
     oracle on the same posteriors, no OVERFLOW flag), and its neighbours in the batch are
     unaffected."""
     code = dem

@@ -51,7 +51,7 @@ def _with_heavy_shots(code, B, heavy, p_heavy, seed):
 @pytest.mark.parametrize("separate", [False, True])
 def test_capacity_tiers_decode_alike(which, separate):
     """Every LSD capacity tier (64, 128, 256 local rows per wavefront) returns the default tier's
-    corrections and shot info: shots beyond a small tier go whole to the wide kernel, on the
+    corrections and shot info: shots beyond a small tier go whole to the overflow kernels, on the
     fused BP+LSD path as on the separate one."""
     from paper_2406_18655_amd.workloads import synthetic_dem
     code = {"bb144": lambda: bivariate_bicycle(p=0.05), "hgp16": lambda: random_34_hgp(16, p=0.04),

@@ -1,7 +1,8 @@
 """Shots whose clusters outgrow the LSD kernel's register basis (more than 64 W local rows, or,
-with LSD-mu, more than 64 W dependent columns) are finished by the wide LSD kernel, whose basis
-lives in device memory: they must come back bit-exact against the oracle like every other shot
-(Sec. 4.1 / Alg. 1 with Appendix B's rounds; Appendix D for LSD-mu), never as a zero correction."""
+with LSD-mu, more than 64 W dependent columns) are decoded again by the overflow kernels (512
+local rows with the basis in LDS, then 1024 with the basis in device memory): they must come back
+bit-exact against the oracle like every other shot (Sec. 4.1 / Alg. 1 with Appendix B's rounds;
+Appendix D for LSD-mu), never as a zero correction."""
 import numpy as np
 import pytest
 
