@@ -30,6 +30,7 @@ constexpr int SV_W0 = 0, SV_B0 = 64, SV_A = 96, SV_BL = 192, SV_W = 288, SV_BO =
 
 typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8v __attribute__((ext_vector_type(8)));
 
 // float -> bf16, round to nearest even (gfx950 converts in hardware: v_cvt_pk_bf16_f32)
 __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
@@ -438,7 +439,9 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
 
 // ------------------------------------------------------------------------------------------
 // Inference: one wavefront per shot, no workgroup barriers.  The A/B/C weight fragments of all
-// three layers sit in registers (9 matrices x 2 k-steps x 2 output tiles of 4 bf16 per lane).
+// three layers sit in registers (9 matrices x 2 output tiles of 8 bf16 per lane), and each
+// product covers the whole hidden width in one v_mfma_f32_16x16x32_bf16 (gfx950's double-K form,
+// twice the rate of the 16x16x16 form per issued instruction).
 // Products are formed transposed, D = W X^T, so that after an MFMA a lane holds 4 consecutive
 // output features of one node -- the same fragment the next product reads -- and results
 // leave as packed 8-byte words.  The neighbour means enter by linearity,
@@ -479,6 +482,18 @@ __device__ __forceinline__ int pair_off(int node, int q2, bool &swap) {
     const int p = (2 * q2) ^ ((node >> 1) & 7);
     swap = (p & 1) != 0;
     return node * 64 + ((p & ~1) << 3);
+}
+// Features 8q .. 8q+7 of the node whose row starts at byte row_off, in order: one 16-byte read of
+// the chunk pair (2q, 2q+1), halves exchanged where the swizzle stored them swapped.  This is the
+// operand a lane of group q supplies to v_mfma_f32_16x16x32_bf16 (lane l: column l & 15,
+// k = 8 (l >> 4) .. +7).
+__device__ __forceinline__ bf16x8v lds_pair(const unsigned char *base, int row_off, int q) {
+    const int p = (2 * q) ^ ((row_off >> 7) & 7);
+    const uint4 v = *(const uint4 *)(base + row_off + ((p & ~1) << 3));
+    return __builtin_bit_cast(bf16x8v, (p & 1) ? make_uint4(v.z, v.w, v.x, v.y) : v);
+}
+__device__ __forceinline__ float4v mfma32(bf16x8v a, bf16x8v b, float4v c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 template <int DR, int DC>
@@ -545,21 +560,20 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
     }
     __syncthreads();
 
-    // A-operand fragments: wf[mat][ks][ot] = W[ot*16 + (lane&15)][ks*16 + 4(lane>>4) .. +3]
-    const int r16 = lane & 15, kq = (lane >> 4) * 4;
-    short4v wf[9][2][2];
+    // A-operand fragments of v_mfma_f32_16x16x32_bf16 (the whole hidden width in one product):
+    // wf[mat][ot] = W[ot*16 + (lane&15)][8(lane>>4) .. +7]
+    const int r16 = lane & 15, kq = (lane >> 4) * 4, q8 = lane >> 4;
+    bf16x8v wf[9][2];
 #pragma unroll
     for (int mat = 0; mat < 9; mat++) {
         const int layer = mat / 3, which = mat % 3;
         const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
 #pragma unroll
-        for (int ks = 0; ks < 2; ks++)
-#pragma unroll
-            for (int ot = 0; ot < 2; ot++) {
-                const float *w = W + (ot * 16 + r16) * HID + ks * 16 + kq;
-                const uint32_t lo = pack_bf16x2(w[0], w[1]), hi = pack_bf16x2(w[2], w[3]);
-                wf[mat][ks][ot] = __builtin_bit_cast(short4v, make_uint2(lo, hi));
-            }
+        for (int ot = 0; ot < 2; ot++) {
+            const float *w = W + (ot * 16 + r16) * HID + 8 * q8;
+            wf[mat][ot] = __builtin_bit_cast(bf16x8v, make_uint4(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3]),
+                                                                pack_bf16x2(w[4], w[5]), pack_bf16x2(w[6], w[7])));
+        }
     }
 
     const int total = A.list ? *A.list_count : A.count;
@@ -601,13 +615,9 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
                 const uint16_t *nb = nbc + i * dr;
 #pragma unroll
                 for (int k = 0; k < (DR ? DR : dr); k++) {
-                    const int off = nb[k];
-                    const short4v x0 = lds_frag(Hb, off, kq >> 2), x1 = lds_frag(Hb, off, 4 + (kq >> 2));
+                    const bf16x8v x = lds_pair(Hb, nb[k], q8);
 #pragma unroll
-                    for (int ot = 0; ot < 2; ot++) {
-                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][0][ot], x0, acc[ot], 0, 0, 0);
-                        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 0][1][ot], x1, acc[ot], 0, 0, 0);
-                    }
+                    for (int ot = 0; ot < 2; ot++) acc[ot] = mfma32(wf[l * 3 + 0][ot], x, acc[ot]);
                 }
                 const float rd = rdc[i], sgn = i < m ? (float)sg[i] : 0.f;
 #pragma unroll
@@ -626,24 +636,17 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
             // writes only its own node's words)
             for (int rt = 0; rt < NP / 16; rt++) {
                 const int j = rt * 16 + r16;
-                const short4v h0 = lds_frag(Hb, j * 64, kq >> 2), h1 = lds_frag(Hb, j * 64, 4 + (kq >> 2));
+                const bf16x8v h = lds_pair(Hb, j * 64, q8);
                 float4v as[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
                 float4v an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int ot = 0; ot < 2; ot++) {
-                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][0][ot], h0, as[ot], 0, 0, 0);
-                    as[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 1][1][ot], h1, as[ot], 0, 0, 0);
-                }
+                for (int ot = 0; ot < 2; ot++) as[ot] = mfma32(wf[l * 3 + 1][ot], h, as[ot]);
                 const uint16_t *nb = nbf + j * dc;
 #pragma unroll
                 for (int k = 0; k < (DC ? DC : dc); k++) {
-                    const int off = nb[k];
-                    const short4v y0 = lds_frag(Cb, off, kq >> 2), y1 = lds_frag(Cb, off, 4 + (kq >> 2));
+                    const bf16x8v y = lds_pair(Cb, nb[k], q8);
 #pragma unroll
-                    for (int ot = 0; ot < 2; ot++) {
-                        an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][0][ot], y0, an[ot], 0, 0, 0);
-                        an[ot] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wf[l * 3 + 2][1][ot], y1, an[ot], 0, 0, 0);
-                    }
+                    for (int ot = 0; ot < 2; ot++) an[ot] = mfma32(wf[l * 3 + 2][ot], y, an[ot]);
                 }
                 const float rd = rdf[j];
                 const bool live = j < n;
