@@ -180,7 +180,8 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms)
  * can share one kernel); for LSD, the number of workgroups, then the LSD capacity tier (as
  * qlsd_decoder_set_lsd_capacity, every tier up to the decoder's default, timed on the whole
  * decode; a smaller tier is kept only when it is at least 10 % faster on the sample, since other
- * batches may hold more shots that outgrow it).  Outputs never depend on these shapes.  Synchronous on `stream`;
+ * batches may hold more shots that outgrow it), and at 256 rows the LSD schedule (as
+ * qlsd_decoder_set_lsd_schedule; the batched one kept when 2 % faster).  Outputs never depend on these shapes.  Synchronous on `stream`;
  * allocates and frees scratch output buffers; must not overlap other calls on this decoder.
  * `report` (host char[report_len], nullable) receives one line per candidate and the choice. */
 qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_t B, int32_t reps,
@@ -198,6 +199,17 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder dec, const uint8_t *syndromes, int32_
  * no overflow kernel fits the code or an allocation fails, leaving the decoder unchanged.  Host-side; must not
  * overlap other calls on this decoder. */
 qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder dec, int32_t local_rows);
+
+/* LSD schedule of the 256-row kernel (Sec. 4.1 and Appendix B grow every invalid cluster in a
+ * round; the paper parallelises over clusters).  QLSD_LSD_PER_COLUMN (the default) reduces the
+ * round's new columns one at a time in key order; QLSD_LSD_CLUSTER_BATCHED groups them so that a
+ * batch holds one column per cluster and reduces a batch in one pass over the shot's local rows
+ * (clusters own disjoint rows), in rounds with 4 to 64 selections.  Outputs never depend on the
+ * schedule.  QLSD_E_UNSUPPORTED for the batched schedule when the capacity is below 256 local
+ * rows.  Host-side; must not overlap other calls on this decoder.  qlsd_decoder_tune times both. */
+#define QLSD_LSD_PER_COLUMN 0
+#define QLSD_LSD_CLUSTER_BATCHED 1
+qlsd_status qlsd_decoder_set_lsd_schedule(qlsd_decoder dec, int32_t schedule);
 
 /* Waits for the decoder's last work and reports a device failure, if any. */
 qlsd_status qlsd_sync(qlsd_decoder dec);

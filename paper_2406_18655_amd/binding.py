@@ -25,8 +25,9 @@ FLAG_OSD0_POST = 8
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
            "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
-           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity", "qlsd_sync",
-           "qlsd_last_error", "qlsd_decoder_destroy", "qlsd_code_destroy"]
+           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
+           "qlsd_decoder_set_lsd_schedule", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
+           "qlsd_code_destroy"]
 
 INFO_DTYPE = np.dtype([("status", np.uint8), ("reserved", np.uint8), ("bp_iters", np.int16),
                        ("n_clusters", np.int16), ("rounds", np.int16), ("max_cluster_cols", np.int32)])
@@ -40,6 +41,7 @@ class QlsdParams(ctypes.Structure):
 
 
 OSD_E, OSD_CS = 0, 1
+LSD_PER_COLUMN, LSD_CLUSTER_BATCHED = 0, 1
 
 
 class QlsdError(RuntimeError):
@@ -71,13 +73,15 @@ def lib():
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
         L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
         L.qlsd_decoder_set_lsd_capacity.argtypes = [P, I32]
+        L.qlsd_decoder_set_lsd_schedule.argtypes = [P, I32]
         L.qlsd_sync.argtypes = [P]
         L.qlsd_last_error.restype = ctypes.c_char_p
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
                    "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
-                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity", "qlsd_sync"):
+                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
+                   "qlsd_decoder_set_lsd_schedule", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -222,6 +226,11 @@ class Decoder:
         """LSD capacity tier: 64, 128 or 256 local rows per wavefront, shots beyond it finished by
         the overflow kernels (include/qlsd.h); outputs do not depend on it."""
         _check(lib().qlsd_decoder_set_lsd_capacity(self._h, int(local_rows)))
+
+    def set_lsd_schedule(self, schedule: int):
+        """LSD_PER_COLUMN or LSD_CLUSTER_BATCHED (256-row kernel only; include/qlsd.h); outputs
+        do not depend on it."""
+        _check(lib().qlsd_decoder_set_lsd_schedule(self._h, int(schedule)))
 
     def stage_ms(self):
         """(bp_ms, lsd_ms) of the last decode call (needs FLAG_STAGE_TIMING)."""

@@ -82,6 +82,7 @@ struct qlsd_decoder_s {
     int bp_slots, bp_grid;
     bool bp_graph;       // one workgroup per shot (large graphs) instead of S slots per workgroup
     int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds, lsd_graph_in_lds;
+    bool lsd_cb;         // cluster-batched column insertion (W = 4; qlsd_decoder_set_lsd_schedule)
     int num_cus;
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
     bool timing;
@@ -352,6 +353,7 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "OSD-0 supports n <= %d and m <= %d (n=%d, m=%d)", kOsdMaxSort, kWideRows, g.n, g.m);
     }
+    d->lsd_cb = false;
     d->ovf = d->mid = d->wide = false;
     d->d_ovf_list = d->d_ovf2_list = nullptr;
     d->d_wide_ws = nullptr;
@@ -468,6 +470,7 @@ static LsdArgs lsd_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, const f
     a.cs_order = d->params.osd_method == 1 ? d->params.osd_order : 0;
     a.omega = d->d_omega;
     a.wave_bytes = d->lsd_wave_bytes;
+    a.cluster_batched = d->lsd_cb && d->lsd_W == 4;
     return a;
 }
 
@@ -771,6 +774,17 @@ qlsd_status qlsd_decoder_set_lsd_capacity(qlsd_decoder d, int32_t local_rows) {
     return QLSD_OK;
 }
 
+qlsd_status qlsd_decoder_set_lsd_schedule(qlsd_decoder d, int32_t schedule) {
+    if (!d) return fail(QLSD_E_INVALID, "null decoder");
+    if (schedule != QLSD_LSD_PER_COLUMN && schedule != QLSD_LSD_CLUSTER_BATCHED)
+        return fail(QLSD_E_INVALID, "unknown LSD schedule %d", schedule);
+    if (schedule == QLSD_LSD_CLUSTER_BATCHED && d->lsd_W != 4)
+        return fail(QLSD_E_UNSUPPORTED, "the cluster-batched schedule runs in the 256-row LSD kernel (capacity is %d)",
+                    64 * d->lsd_W);
+    d->lsd_cb = schedule == QLSD_LSD_CLUSTER_BATCHED;
+    return QLSD_OK;
+}
+
 qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t B, int32_t reps, void *stream,
                               char *report, int32_t report_len) {
     qlsd_status st = check_call(d, syndromes, B, syndromes);
@@ -897,6 +911,19 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
             }
         set_lsd_capacity(d, best_W);
         snprintf(line, sizeof(line), "lsd capacity chosen: %d local rows\n", 64 * best_W);
+        rep += line;
+    }
+    // LSD schedule of the 256-row kernel: columns one at a time, or batched across the clusters
+    // that grow in the same round (kept only when 2 % faster: it costs registers)
+    if (d->lsd_W == 4) {
+        d->lsd_cb = false;
+        const float ms0 = timeit(decode_run);
+        d->lsd_cb = true;
+        const float ms1 = timeit(decode_run);
+        d->lsd_cb = ms1 > 0.f && ms0 > 0.f && ms1 < 0.98f * ms0;
+        snprintf(line, sizeof(line), "lsd schedule per column: decode %.4f ms; batched across clusters: %.4f ms\n", ms0, ms1);
+        rep += line;
+        snprintf(line, sizeof(line), "lsd schedule chosen: %s\n", d->lsd_cb ? "batched across clusters" : "per column");
         rep += line;
     }
     const hipError_t e = hipStreamSynchronize(s);

@@ -63,6 +63,7 @@ struct LsdArgs {
     int *ovf_list;             // nullable: shots whose clusters outgrew the kernel's capacity are
     int *ovf_count;            //   appended here for the next overflow kernel (max_batch entries)
     qlsd_cluster_stats *cstats;  // B (nullable): per-shot statistics of the final clusters
+    int cluster_batched;       // W = 4 kernel: reduce the round's columns batched across clusters
 };
 
 // BP with LSD folded in (plain decode with slot BP): a workgroup whose slots have drained turns

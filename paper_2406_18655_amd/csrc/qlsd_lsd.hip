@@ -28,8 +28,9 @@ namespace qlsd {
 
 namespace {
 
-// At most 128 VGPRs (4 wavefronts per SIMD) for W <= 2, 256 (2 per SIMD) for W = 4.
-template <int W, bool GL, bool MU>
+// At most 128 VGPRs (4 wavefronts per SIMD) for W <= 2, 256 (2 per SIMD) for W = 4.  CB: the
+// cluster-batched schedule of the column insertion (W = 4 only; chosen by the autotuner).
+template <int W, bool GL, bool MU, bool CB = false>
 __global__ __launch_bounds__(kLsdThreads) __attribute__((amdgpu_waves_per_eu(W <= 2 ? 4 : 2)))
 void lsd_kernel(LsdArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -65,27 +66,31 @@ void lsd_kernel(LsdArgs A) {
         if (item >= total) break;
         const int shot = A.list ? A.list[item] : item;
         if (A.skip_done && shot < 0) continue;
-        decode_shot<W, MU, GView<GL>, false, true>(A, S, g, shot, lane);
+        decode_shot<W, MU, GView<GL>, false, true, false, CB>(A, S, g, shot, lane);
         wave_sync();
     }
+}
+
+template <int W, bool GL, bool MU, bool CB>
+hipError_t launch_lsd_k(const LsdArgs &a, int grid, size_t lds, hipStream_t st) {
+    hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, GL, MU, CB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((lsd_kernel<W, GL, MU, CB>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+    return hipGetLastError();
 }
 
 template <int W, bool MU>
 hipError_t launch_lsd_w(const LsdArgs &a, int grid, hipStream_t st) {
     const size_t lds = (a.graph_in_lds ? lsd_graph_bytes(a.g.m, a.g.n, a.g.nnz) : 0) +
                        (size_t)a.wave_bytes * (kLsdThreads / 64);
-    if (a.graph_in_lds) {
-        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, true, MU>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((lsd_kernel<W, true, MU>), dim3(grid), dim3(kLsdThreads), lds, st, a);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void *)lsd_kernel<W, false, MU>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((lsd_kernel<W, false, MU>), dim3(grid), dim3(kLsdThreads), lds, st, a);
+    if constexpr (W == 4) {
+        if (a.cluster_batched)
+            return a.graph_in_lds ? launch_lsd_k<W, true, MU, true>(a, grid, lds, st)
+                                  : launch_lsd_k<W, false, MU, true>(a, grid, lds, st);
     }
-    return hipGetLastError();
+    return a.graph_in_lds ? launch_lsd_k<W, true, MU, false>(a, grid, lds, st)
+                          : launch_lsd_k<W, false, MU, false>(a, grid, lds, st);
 }
 
 // Overflow LSD for the shots whose clusters outgrew the register basis of lsd_kernel (listed by

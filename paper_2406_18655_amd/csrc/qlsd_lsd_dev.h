@@ -68,6 +68,7 @@ struct GView {
 constexpr int kFree = 0x7fffffff;
 constexpr int kMaxMu = 12;  // largest supported order mu (2^mu patterns per cluster)
 constexpr uint8_t kValid = 0, kInvalid = 1, kFrozen = 2;
+constexpr int kBatchMin = 4;  // cluster-batched schedule: selections in a round from which it batches
 
 struct LsdLds {
     uint32_t *keys;    // n (when keys_in_lds)
@@ -621,6 +622,169 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
     }
 }
 
+// One batch of the round's new columns reduced together (insert_round_batched): `mark` tags the
+// local rows of the batch's columns in lroot, the cluster slots are in selu (per root: its pivot
+// row, then the lane of its batch column), and `stage` receives the new pivot rows' Mrow words.
+// NS as for insert_plan.  dep: this lane's column (inb) turned out dependent.
+template <int W, int NS, class BB>
+__device__ __forceinline__ void reduce_batch(BB &B, const LsdLds &S, int lane, int mark, bool inb, int root, int col,
+                                             const int (&crv)[W], bool &dep) {
+    uint32_t *selu = (uint32_t *)S.sel;
+    uint64_t *stage = S.lkey;
+    uint32_t bf = 0;  // bit s: local row 64 s + lane lies in its cluster's batch column
+#pragma unroll
+    for (int s = 0; s < NS; s++) bf |= (uint32_t)(S.lroot[s * 64 + lane] == mark) << s;
+    uint64_t a[W];    // the batch columns' support on pivot rows
+#pragma unroll
+    for (int s = 0; s < W; s++) a[s] = s < NS ? ballot((bf >> s) & 1u) & B.piv[s] : 0ull;
+    // a row's Mrow (and a pivot's CT) has bits only at its own cluster's pivots, so one parity
+    // pass reduces every cluster's column on that cluster's rows
+    uint32_t bpf = 0, cfl = 0;
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        if (!B.active(s)) continue;
+        bpf |= (uint32_t)(((bf >> s) & 1u) ^ parity_M<W, BB, NS>(B, s, a)) << s;
+        if (((B.piv[s] >> lane) & 1ull) && parity_C<W, BB, NS>(B, s, a)) cfl |= 1u << s;
+    }
+    // each cluster's pivot: its smallest local row in the reduced column (as a one-column
+    // insertion picks it)
+#pragma unroll
+    for (int s = 0; s < NS; s++)
+        if ((bpf >> s) & 1u) atomicMin(&selu[2 * crv[s]], (uint32_t)(s * 64 + lane));
+    wave_sync();
+    int pr[W], slot[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) { pr[s] = -1; slot[s] = 0; }
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        if (((bpf | cfl) >> s) & 1u) {
+            // a cluster whose column turned out dependent has no pivot (all ones): pr stays -1
+            const uint32_t prv = selu[2 * crv[s]];
+            pr[s] = prv < (uint32_t)(64 * W) ? (int)prv : -1;
+            slot[s] = (int)(selu[2 * crv[s] + 1] & 63u);
+            if (pr[s] == s * 64 + lane) {
+#pragma unroll
+                for (int w = 0; w < NS; w++) stage[slot[s] * W + w] = B.M(s, w);
+            }
+        }
+    }
+    dep = inb && selu[2 * root] == 0xffffffffu;  // no row of the cluster in the reduced column
+    wave_sync();
+    uint64_t newp[W], flip[W];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        // rows of a cluster without a new pivot are left alone (a dependent column changes nothing)
+        const bool rowb = ((bpf >> s) & 1u) && pr[s] >= 0, rowc = ((cfl >> s) & 1u) && pr[s] >= 0;
+        const bool is_new = pr[s] == s * 64 + lane;
+        bool sp_hit = false;
+        if (rowb || rowc) {
+            const int ps = pr[s] >> 6, pl = pr[s] & 63;
+            uint64_t R[W];
+#pragma unroll
+            for (int w = 0; w < NS; w++) R[w] = stage[slot[s] * W + w];
+            if (rowb) {
+#pragma unroll
+                for (int w = 0; w < NS; w++)
+                    if (B.active(w)) B.M(s, w) ^= R[w] ^ ((w == ps) ? (1ull << pl) : 0ull);
+            }
+            if (rowc) {
+#pragma unroll
+                for (int w = 0; w < NS; w++)
+                    if (B.active(w)) B.C(s, w) ^= R[w] ^ ((w == ps) ? (1ull << pl) : 0ull);
+            }
+            if (is_new) {
+#pragma unroll
+                for (int w = 0; w < NS; w++)
+                    if (B.active(w)) B.C(s, w) = R[w] | ((w == ps) ? (1ull << pl) : 0ull);
+            }
+#pragma unroll
+            for (int t = 0; t < NS; t++)
+                if (t == ps) sp_hit = (B.sp[t] >> pl) & 1ull;
+        }
+        newp[s] = ballot(is_new);
+        // the reduced syndrome changes by the reduced column wherever the cluster's pivot row
+        // carries a syndrome bit
+        flip[s] = ballot(rowb && sp_hit);
+    }
+    // the new pivots' columns: the pivot lane takes its cluster's batch column
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        const int c = __shfl(col, slot[s], 64);
+        if (pr[s] == s * 64 + lane) S.colAt[s * 64 + lane] = c;
+    }
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        B.piv[s] = uniform64(B.piv[s] | newp[s]);
+        B.sp[s] = uniform64(B.sp[s] ^ flip[s]);
+    }
+}
+
+// Phase (4) with the cluster-batched schedule (rounds of kBatchMin to 64 selections): the round's
+// distinct columns are grouped by the cluster they end up in after this round's merges, batch b
+// holding every cluster's b-th column in ascending key, so a batch has at most one column per
+// cluster.  Clusters own disjoint local rows, so a batch is reduced in one pass (reduce_batch) with
+// the same pivots and the same dependent columns as inserting its columns one by one in key order
+// -- the paper's parallelism across clusters, spread over the lanes of the shot's wavefront.
+// lkey is read into registers first (it then serves as the staging area); the cluster slots in
+// the selection array are all ones again on return, and the marks in lroot are never read back.
+template <int W, bool MU, int KNP, class G, class BB>
+__device__ __forceinline__ void insert_round_batched(const LsdArgs &A, const LsdLds &S, const G &g, BB &B, int nsel,
+                                                     int rounds, int &npc, int lane) {
+    const bool selp = lane < nsel;
+    const uint64_t kp = selp ? S.lkey[lane] : ~0ull;
+    const int col = (int)(uint32_t)kp;
+    int root = 0;
+    if (selp) root = S.croot[S.loc[g.row_idx(g.col_ptr(col))]];  // every row points at its root here
+    int crv[W];
+#pragma unroll
+    for (int s = 0; s < W; s++) crv[s] = S.croot[s * 64 + lane];
+    bool dup = !selp;
+    for (int q = 0; q < nsel; q++) dup |= readlane64(kp, q) == kp && q < lane;
+    int bidx = 0;  // distinct columns of the same cluster with a smaller key
+    for (int q = 0; q < nsel; q++) {
+        const bool dq = __builtin_amdgcn_readlane((int)dup, q) != 0;
+        bidx += (!dq && __builtin_amdgcn_readlane(root, q) == root && readlane64(kp, q) < kp) ? 1 : 0;
+    }
+    uint32_t *selu = (uint32_t *)S.sel;
+    wave_sync();  // every lane has read lkey before it becomes the staging area
+    for (int b = 0;; b++) {
+        const bool inb = !dup && bidx == b;
+        if (!ballot(inb)) break;
+        const int mark = -2 - b - 64 * rounds;  // below -1: no root, stamp or earlier mark of the shot
+        if (inb) {
+            const int c0 = g.col_ptr(col), c1 = g.col_ptr(col + 1);
+            for (int e = c0; e < c1; e++) S.lroot[S.loc[g.row_idx(e)]] = mark;
+            atomicOr(&S.incol[col >> 5], 1u << (col & 31));
+            selu[2 * root + 1] = (uint32_t)lane;
+        }
+        wave_sync();
+        bool dep = false;
+        if constexpr (BB::kInMem) {
+            reduce_batch<W, W>(B, S, lane, mark, inb, root, col, crv, dep);
+        } else {
+            if (B.ns <= 1) reduce_batch<W, 1>(B, S, lane, mark, inb, root, col, crv, dep);
+            else if (B.ns <= 2) reduce_batch<W, (W < 2 ? W : 2)>(B, S, lane, mark, inb, root, col, crv, dep);
+            else reduce_batch<W, W>(B, S, lane, mark, inb, root, col, crv, dep);
+        }
+        if constexpr (MU) {
+            if (A.mu > 0) {
+                const uint64_t dball = ballot(dep);
+                if (dep) {
+                    const int at = npc + __popcll(dball & ((1ull << lane) - 1ull));
+                    if (at < KNP) S.colNP[at] = col;
+                }
+                npc += __popcll(dball);
+            }
+        }
+        wave_sync();
+        if (inb) {  // the cluster slots back to all ones for the next batch and the next round
+            selu[2 * root] = 0xffffffffu;
+            selu[2 * root + 1] = 0xffffffffu;
+        }
+        wave_sync();
+    }
+}
+
 // MU: the decoder runs LSD-mu (A.mu > 0); decoders without it get no LSD-mu code at all, which
 // leaves the register allocator more room in the LSD-0 rounds.
 // WIDE: the basis lives in memory at basis_mem (this wavefront's [2][W][W][64] words: in LDS when
@@ -628,7 +792,8 @@ __device__ void osd_e_clusters(const LsdArgs &A, const LsdLds &S, const G &g, co
 // only the slices of local rows in use are visited; the other kernels keep it in registers.
 // OVF: a shot that outgrows the capacity is appended to A.ovf_list (when set) for the next
 // overflow kernel.
-template <int W, bool MU, class G, bool WIDE = false, bool OVF = false, bool BLDS = false>
+// CB: the cluster-batched schedule of phase (4) (insert_round_batched); same results.
+template <int W, bool MU, class G, bool WIDE = false, bool OVF = false, bool BLDS = false, bool CB = false>
 __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, const G &g, int shot, int lane,
                             uint64_t *basis_mem = nullptr) {
     constexpr int K = 64 * W;
@@ -980,7 +1145,16 @@ __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, c
         // (lane p: selection p) and each pair's local row is read once, here, for all columns of the
         // round at the same time (lane id: pair id, as in the claims); otherwise an order array in
         // LDS and per-column lookups.
-        {
+        bool batched = false;
+        if constexpr (CB) {
+            // the cluster-batched schedule: several clusters growing at once have their columns
+            // reduced together
+            if (nsel >= kBatchMin && nsel <= 64) {
+                insert_round_batched<W, MU, KNP>(A, S, g, B, nsel, rounds, npc, lane);
+                batched = true;
+            }
+        }
+        if (!batched) {
             const bool fast = npairs <= 64;
             int32_t *order = (int32_t *)S.sel;
             int rank = 0, colp = 0, lr_pair = -1;

@@ -61,6 +61,7 @@ def test_null_handles_are_rejected(lib):
     assert lib.qlsd_decode(None, None, 0, None, None, None) == -1
     assert lib.qlsd_sync(None) == -1
     assert lib.qlsd_decoder_set_lsd_capacity(None, 64) == -1
+    assert lib.qlsd_decoder_set_lsd_schedule(None, 0) == -1
     assert lib.qlsd_last_error() != b""
     lib.qlsd_decoder_destroy(None)
     lib.qlsd_code_destroy(None)

@@ -88,3 +88,65 @@ def test_capacity_tiers_decode_alike(which, separate):
     with pytest.raises(binding.QlsdError):
         mu.set_lsd_capacity(128)
     mu.set_lsd_capacity(256)
+
+
+@pytest.mark.parametrize("which,mu", [("dem", 0), ("dem", 10), ("hgp24", 0), ("hgp16", 4)])
+def test_cluster_batched_schedule_decodes_alike(which, mu):
+    """The cluster-batched LSD schedule (one column per cluster per batch, reduced together)
+    returns the per-column schedule's corrections and shot info, with and without LSD-mu."""
+    from paper_2406_18655_amd.workloads import synthetic_dem
+    code = {"dem": synthetic_dem, "hgp24": lambda: random_34_hgp(24, p=0.04),
+            "hgp16": lambda: random_34_hgp(16, p=0.05)}[which]()
+    S = _with_heavy_shots(code, 3000, 64, 0.004 if which == "dem" else 0.06, seed=87)
+    B = S.shape[0]
+    s = torch.from_numpy(S).cuda()
+    bc = binding.Code.from_dense(code.H)
+    T = 30
+    out = []
+    for sched in (binding.LSD_PER_COLUMN, binding.LSD_CLUSTER_BATCHED):
+        d = binding.Decoder(bc, code.priors, B, max_iter=T, lsd_order=mu)
+        d.set_lsd_schedule(sched)
+        c = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+        i = torch.empty((B, 12), dtype=torch.uint8, device="cuda")
+        d.decode_into(s, c, i)
+        torch.cuda.synchronize()
+        out.append((c, i))
+    inf = binding.parse_info(out[0][1].cpu().numpy())
+    many = int((inf["n_clusters"] >= 4).sum())
+    print(f"case {which} mu={mu}: {B} shots, {many} ending with 4 or more clusters", flush=True)
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+def test_cluster_batched_schedule_bit_exact_against_oracle(oracle_mod):
+    """LSD alone on identical float32 posteriors: the cluster-batched schedule against the oracle,
+    shot by shot, on DEM shots BP leaves unsolved plus denser syndromes with many clusters."""
+    from paper_2406_18655_amd.workloads import synthetic_dem
+    code = synthetic_dem()
+    S = _with_heavy_shots(code, 1500, 40, 0.003, seed=89)
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, S.shape[0], max_iter=20)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    keep = np.nonzero((binding.parse_info(info)["status"] & 1) == 0)[0][:150]
+    S, L = np.ascontiguousarray(S[keep]), np.ascontiguousarray(llr.cpu().numpy()[keep])
+    d = binding.Decoder(bc, code.priors, S.shape[0], max_iter=20)
+    d.set_lsd_schedule(binding.LSD_CLUSTER_BATCHED)
+    corr, info = d.lsd(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda())
+    torch.cuda.synchronize()
+    corr, inf = corr.cpu().numpy(), binding.parse_info(info)
+    oc = oracle_mod.Code.from_dense(code.H)
+    for b in range(S.shape[0]):
+        want, st, stats = oracle_mod.lsd(oc, S[b], L[b].astype(np.float64))
+        assert (corr[b] == want).all(), b
+        assert (inf["n_clusters"][b], inf["rounds"][b], inf["max_cluster_cols"][b]) == (stats[0], stats[2], stats[1]), b
+    print(f"{S.shape[0]} shots bit-exact, max clusters {int(inf['n_clusters'].max())}")
+
+
+def test_cluster_batched_schedule_needs_the_256_row_kernel():
+    code = bivariate_bicycle(p=0.05)
+    d = binding.Decoder(binding.Code.from_dense(code.H), code.priors, 64, max_iter=10)
+    with pytest.raises(binding.QlsdError):
+        d.set_lsd_schedule(binding.LSD_CLUSTER_BATCHED)
+    with pytest.raises(binding.QlsdError):
+        d.set_lsd_schedule(7)
+    d.set_lsd_schedule(binding.LSD_PER_COLUMN)
