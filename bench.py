@@ -60,6 +60,10 @@ def parse():
                     help="plain: BP+LSD for every code; learned: the [[144,12,12]] lanes run BP 10 + "
                          "the trained refinement + LSD")
     ap.add_argument("--serve-requests", type=int, default=1000000, help="requests per rate (all codes together)")
+    ap.add_argument("--serve-hw-queues", type=int, default=8,
+                    help="HIP hardware queues for the service (GPU_MAX_HW_QUEUES, set before HIP starts; HIP's "
+                         "default of 4 makes lanes beyond the fourth share a queue and wait behind each other's "
+                         "batches); 0 leaves the environment as it is")
     ap.add_argument("--sweep", action="store_true",
                     help="[[144,12,12]] over p in {0.01,0.02,0.04,0.05,0.06}: 10^6 shots per point "
                          "(15 launches of 65,536 plus one of 16,960), GPU LER and shots/s, the oracle's "
@@ -668,6 +672,8 @@ def host_cpu():
 def serve_main(args):
     """Continuous-batching service over HGP(3,4) n=16/24/32, the BB code and the synthetic DEM
     (uniform mix), Poisson arrivals at each rate; latency = completion - arrival per request."""
+    if args.serve_hw_queues > 0:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_hw_queues)  # read when HIP initialises below
     import torch
     from paper_2406_18655_amd import binding
     from paper_2406_18655_amd.workloads import bivariate_bicycle, random_34_hgp, synthetic_dem, sample

@@ -55,7 +55,10 @@ typedef struct {
 } qlsd_completion;       /* 40 bytes */
 
 /* device_budget_bytes: device memory the lanes of all codes may use (decoder workspace plus
- * one batch of buffers per lane). */
+ * one batch of buffers per lane).  Each lane has its own stream; HIP maps streams onto hardware
+ * queues (GPU_MAX_HW_QUEUES per process, 4 by default), and lanes that share a queue wait behind
+ * each other's batches, so a process serving more than four lanes should raise it (e.g. to 8)
+ * before HIP initialises. */
 qlsd_status qlsd_server_create(size_t device_budget_bytes, qlsd_server *out);
 
 /* Registers a code with decoder parameters and priors (host, n doubles; copied).  Creates its
