@@ -442,9 +442,10 @@ __global__ __launch_bounds__(kNetThreads) void net_kernel(NetArgs A) {
 // three layers sit in registers (9 matrices x 2 output tiles of 8 bf16 per lane), and each
 // product covers the whole hidden width in one v_mfma_f32_16x16x32_bf16 (gfx950's double-K form,
 // twice the rate of the 16x16x16 form per issued instruction).
-// Products are formed transposed, D = W X^T, so that after an MFMA a lane holds 4 consecutive
-// output features of one node -- the same fragment the next product reads -- and results
-// leave as packed 8-byte words.  The neighbour means enter by linearity,
+// Products are formed transposed, D = W X^T, with the output rows of W permuted so that after
+// the two products of a layer (two 16-feature output tiles) a lane holds 8 consecutive output
+// features of one node -- the same feature group the next product reads -- and results leave
+// as one packed 16-byte word.  The neighbour means enter by linearity,
 //     A m_i = (1/deg_i) sum_{j in N(i)} A h_j,     C g_j = (1/deg_j) sum_{i in N(j)} C c_i,
 // so each neighbour's bf16 feature words feed the MFMA directly (no unpacking or vector sums)
 // and the 1/deg scaling is applied to the float32 accumulator.  Neighbour lists are padded to
@@ -460,37 +461,30 @@ __host__ __device__ inline size_t infer_shared_bytes(int n, int m, int dr, int d
 // Per wavefront: fault and check feature rows (bf16 x 32 each), plus one zero sentinel row each
 // for the padding of irregular neighbour lists (a code with every row and every column of full
 // weight pads nothing but its 16-row tiles, whose results are discarded), and one signed byte
-// per check for the syndrome sign.
+// per check of the padded tiles for the syndrome sign (0 on padding).
 __host__ __device__ inline bool infer_regular(const DevGraph &g) {
     return g.min_rw == g.max_rw && g.min_cw == g.max_cw;
 }
 __host__ __device__ inline size_t infer_wave_bytes(int n, int m, bool regular) {
-    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + pad16(m) + (regular ? 0 : 2)) * HID) + al16((size_t)m);
+    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + pad16(m) + (regular ? 0 : 2)) * HID) + al16((size_t)pad16(m));
 }
 
-// Feature rows are 64 B (32 bf16 = 8 chunks of 4).  Chunk c of node v is stored at chunk
-// position c ^ ((v >> 1) & 7) of its row: a half-wavefront reads one chunk pair of 16 nodes,
-// and the swizzle spreads those reads over all LDS banks (conflict-free for consecutive nodes).
-__device__ __forceinline__ int frag_off(int row_off, int c) {  // row_off = 64 * node
-    return row_off + ((c ^ ((row_off >> 7) & 7)) << 3);
+// Feature rows are 64 B: 32 bf16 as four 16-byte groups of 8 features.  Group q of node v sits at
+// group position q ^ f(v), f(v) = ((v >> 1) & 3) ^ ((v >> 3) & 1), of its row.  Over 16 consecutive
+// nodes (a tile) and a fixed group, any 8 aligned nodes then cover all 8 16-byte slots of a
+// 128-byte bank window and any 4 nodes equal mod 4 all 4 slots of their 64-byte quarter of a
+// 256-byte window, so the tile's 16-byte reads and writes are free of bank conflicts with either
+// width of LDS bank set.  The swizzled row offset srow(v) = 64 v | (f(v) << 4) carries the
+// swizzle: group q of node v is at srow(v) ^ 16 q, and the neighbour tables hold srow() of each
+// neighbour, so a gather costs one XOR per load.  f depends on bits 1..3 of v only, so the row
+// of node 16 rt + r sits at 1024 rt + srow(r).
+__host__ __device__ __forceinline__ int srow(int node) {
+    return node * 64 | ((((node >> 1) & 3) ^ ((node >> 3) & 1)) << 4);
 }
-__device__ __forceinline__ short4v lds_frag(const unsigned char *base, int row_off, int c) {
-    return *(const short4v *)(base + frag_off(row_off, c));
-}
-// Whole-row access: chunks (2q, 2q+1) stay an aligned 16-byte pair, possibly swapped.
-__device__ __forceinline__ int pair_off(int node, int q2, bool &swap) {
-    const int p = (2 * q2) ^ ((node >> 1) & 7);
-    swap = (p & 1) != 0;
-    return node * 64 + ((p & ~1) << 3);
-}
-// Features 8q .. 8q+7 of the node whose row starts at byte row_off, in order: one 16-byte read of
-// the chunk pair (2q, 2q+1), halves exchanged where the swizzle stored them swapped.  This is the
-// operand a lane of group q supplies to v_mfma_f32_16x16x32_bf16 (lane l: column l & 15,
-// k = 8 (l >> 4) .. +7).
-__device__ __forceinline__ bf16x8v lds_pair(const unsigned char *base, int row_off, int q) {
-    const int p = (2 * q) ^ ((row_off >> 7) & 7);
-    const uint4 v = *(const uint4 *)(base + row_off + ((p & ~1) << 3));
-    return __builtin_bit_cast(bf16x8v, (p & 1) ? make_uint4(v.z, v.w, v.x, v.y) : v);
+// Features 8q .. 8q+7 of the node with swizzled row offset so: the operand a lane of group q
+// supplies to v_mfma_f32_16x16x32_bf16 (lane l: column l & 15, k = 8 (l >> 4) .. +7).
+__device__ __forceinline__ bf16x8v lds_group(const unsigned char *base, int so, int q16) {
+    return *(const bf16x8v *)(base + (so ^ q16));
 }
 __device__ __forceinline__ float4v mfma32(bf16x8v a, bf16x8v b, float4v c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -528,21 +522,21 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
     }
     for (int x = t; x < MP * dr; x += blockDim.x) {
         const int i = x / dr, k = x - i * dr;
-        int off = sent * NP * HID * 2;
+        int v = sent * NP;
         if (i < m) {
             const int e0 = A.g.row_ptr[i], e1 = A.g.row_ptr[i + 1];
-            if (e0 + k < e1) off = A.g.col_idx[e0 + k] * HID * 2;
+            if (e0 + k < e1) v = A.g.col_idx[e0 + k];
         }
-        nbc[x] = (uint16_t)off;
+        nbc[x] = (uint16_t)srow(v);
     }
     for (int x = t; x < NP * dc; x += blockDim.x) {
         const int j = x / dc, k = x - j * dc;
-        int off = sent * MP * HID * 2;
+        int v = sent * MP;
         if (j < n) {
             const int c0 = A.g.col_ptr[j], c1 = A.g.col_ptr[j + 1];
-            if (c0 + k < c1) off = A.g.row_idx[c0 + k] * HID * 2;
+            if (c0 + k < c1) v = A.g.row_idx[c0 + k];
         }
-        nbf[x] = (uint16_t)off;
+        nbf[x] = (uint16_t)srow(v);
     }
     for (int x = t; x < MP; x += blockDim.x) {
         const int d = x < m ? A.g.row_ptr[x + 1] - A.g.row_ptr[x] : 0;
@@ -560,9 +554,11 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
     }
     __syncthreads();
 
-    // A-operand fragments of v_mfma_f32_16x16x32_bf16 (the whole hidden width in one product):
-    // wf[mat][ot] = W[ot*16 + (lane&15)][8(lane>>4) .. +7]
-    const int r16 = lane & 15, kq = (lane >> 4) * 4, q8 = lane >> 4;
+    // A-operand fragments of v_mfma_f32_16x16x32_bf16 (the whole hidden width in one product).
+    // Output tile ot's row r computes feature 8 (r >> 2) + 4 ot + (r & 3), so that the lane
+    // holding rows 4 q8 .. +3 of both tiles holds features 8 q8 .. 8 q8 + 7: one whole feature
+    // group, stored as one 16-byte word.  wf[mat][ot] = W[8 (r16 >> 2) + 4 ot + (r16 & 3)][8 q8 .. +7]
+    const int r16 = lane & 15, q8 = lane >> 4;
     bf16x8v wf[9][2];
 #pragma unroll
     for (int mat = 0; mat < 9; mat++) {
@@ -570,38 +566,38 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
         const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
 #pragma unroll
         for (int ot = 0; ot < 2; ot++) {
-            const float *w = W + (ot * 16 + r16) * HID + 8 * q8;
+            const float *w = W + (8 * (r16 >> 2) + 4 * ot + (r16 & 3)) * HID + 8 * q8;
             wf[mat][ot] = __builtin_bit_cast(bf16x8v, make_uint4(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3]),
                                                                 pack_bf16x2(w[4], w[5]), pack_bf16x2(w[6], w[7])));
         }
     }
 
+    // per lane: the tile row's swizzled offset is 1024 rt + srow(lane & 15), and the lane reads,
+    // and after a product writes, feature group q8 of that row (byte offset go within the tile)
+    const int q16 = q8 << 4, go = srow(r16) ^ q16;
     const int total = A.list ? *A.list_count : A.count;
     for (int item = blockIdx.x * nwav + wave; item < total; item += gridDim.x * nwav) {
         const int shot = A.list ? A.list[item] : item;
         const uint8_t *syn = A.syn + (size_t)shot * m;
         const float *llr = A.llr + (size_t)shot * n;
-        for (int i = lane; i < m; i += 64) sg[i] = (syn[i] & 1) ? -1 : 1;
-        // input layer: lane j computes tanh once and writes its fault's 32 features (4 x 16 B)
+        for (int i = lane; i < MP; i += 64) sg[i] = i < m ? ((syn[i] & 1) ? -1 : 1) : 0;
+        // input layer: lane j computes tanh once and writes its fault's 32 features (4 x 16 B).
+        // Padding nodes (j >= n) get relu(b0): no neighbour list names them and no output reads them.
         for (int j = lane; j < NP; j += 64) {
             float x0 = 0.f, x1 = 0.f;
             if (j < n) { x0 = tanhf(llr[j] * 0.125f); x1 = lam[j] * 0.125f; }
+            const int so = srow(j);
 #pragma unroll
             for (int f8 = 0; f8 < HID; f8 += 8) {
                 uint32_t w[4];
 #pragma unroll
                 for (int h2 = 0; h2 < 4; h2++) {
                     const int f = f8 + 2 * h2;
-                    float v0 = 0.f, v1 = 0.f;
-                    if (j < n) {
-                        v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
-                        v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
-                    }
+                    const float v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
+                    const float v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
                     w[h2] = pack_bf16x2(v0, v1);
                 }
-                bool sw;
-                const int o = pair_off(j, f8 >> 3, sw);
-                *(uint4 *)(Hb + o) = sw ? make_uint4(w[2], w[3], w[0], w[1]) : make_uint4(w[0], w[1], w[2], w[3]);
+                *(uint4 *)(Hb + (so ^ ((f8 >> 3) << 4))) = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -615,61 +611,64 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
                 const uint16_t *nb = nbc + i * dr;
 #pragma unroll
                 for (int k = 0; k < (DR ? DR : dr); k++) {
-                    const bf16x8v x = lds_pair(Hb, nb[k], q8);
+                    const bf16x8v x = lds_group(Hb, nb[k], q16);
 #pragma unroll
                     for (int ot = 0; ot < 2; ot++) acc[ot] = mfma32(wf[l * 3 + 0][ot], x, acc[ot]);
                 }
-                const float rd = rdc[i], sgn = i < m ? (float)sg[i] : 0.f;
+                const float rd = rdc[i], sgn = (float)sg[i];
+                uint32_t w[4];
 #pragma unroll
                 for (int ot = 0; ot < 2; ot++) {
-                    const float4v av = *(const float4v *)(sv + SV_A + l * HID + ot * 16 + kq);
+                    const float4v av = *(const float4v *)(sv + SV_A + l * HID + 8 * q8 + 4 * ot);
                     float v[4];
 #pragma unroll
                     for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc[ot][q] + sgn * av[q], 0.f);
-                    *(uint2 *)(Cb + frag_off(i * 64, ot * 4 + (kq >> 2))) =
-                        make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    w[2 * ot] = pack_bf16x2(v[0], v[1]);
+                    w[2 * ot + 1] = pack_bf16x2(v[2], v[3]);
                 }
+                *(uint4 *)(Cb + rt * 1024 + go) = make_uint4(w[0], w[1], w[2], w[3]);
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b)   (in place: a lane reads and
-            // writes only its own node's words)
+            // faults: h_j = relu(B h_j + b + (1/deg_j) sum_i C c_i), b entering as the accumulator of
+            // B h_j (in place: a lane reads and writes only its own node's words; padding rows
+            // are computed like the rest and never read)
             for (int rt = 0; rt < NP / 16; rt++) {
                 const int j = rt * 16 + r16;
-                const bf16x8v h = lds_pair(Hb, j * 64, q8);
-                float4v as[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-                float4v an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+                const bf16x8v h = *(const bf16x8v *)(Hb + rt * 1024 + go);
+                float4v as[2], an[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
 #pragma unroll
-                for (int ot = 0; ot < 2; ot++) as[ot] = mfma32(wf[l * 3 + 1][ot], h, as[ot]);
+                for (int ot = 0; ot < 2; ot++)
+                    as[ot] = mfma32(wf[l * 3 + 1][ot], h, *(const float4v *)(sv + SV_BL + l * HID + 8 * q8 + 4 * ot));
                 const uint16_t *nb = nbf + j * dc;
 #pragma unroll
                 for (int k = 0; k < (DC ? DC : dc); k++) {
-                    const bf16x8v y = lds_pair(Cb, nb[k], q8);
+                    const bf16x8v y = lds_group(Cb, nb[k], q16);
 #pragma unroll
                     for (int ot = 0; ot < 2; ot++) an[ot] = mfma32(wf[l * 3 + 2][ot], y, an[ot]);
                 }
                 const float rd = rdf[j];
-                const bool live = j < n;
+                uint32_t w[4];
 #pragma unroll
                 for (int ot = 0; ot < 2; ot++) {
-                    const float4v bv = *(const float4v *)(sv + SV_BL + l * HID + ot * 16 + kq);
                     float v[4];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) v[q] = live ? fmaxf(as[ot][q] + rd * an[ot][q] + bv[q], 0.f) : 0.f;
-                    *(uint2 *)(Hb + frag_off(j * 64, ot * 4 + (kq >> 2))) =
-                        make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * an[ot][q] + as[ot][q], 0.f);
+                    w[2 * ot] = pack_bf16x2(v[0], v[1]);
+                    w[2 * ot + 1] = pack_bf16x2(v[2], v[3]);
                 }
+                *(uint4 *)(Hb + rt * 1024 + go) = make_uint4(w[0], w[1], w[2], w[3]);
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
         }
         for (int j = lane; j < n; j += 64) {
             float d = sv[SV_BO];
+            const int so = srow(j);
 #pragma unroll
             for (int f8 = 0; f8 < 4; f8++) {
-                bool sw;
-                const uint4 v = *(const uint4 *)(Hb + pair_off(j, f8, sw));
-                const uint32_t w[4] = {sw ? v.z : v.x, sw ? v.w : v.y, sw ? v.x : v.z, sw ? v.y : v.w};
+                const uint4 v = *(const uint4 *)(Hb + (so ^ (f8 << 4)));
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int h2 = 0; h2 < 4; h2++) {
                     d += sv[SV_W + f8 * 8 + 2 * h2] * __uint_as_float(w[h2] << 16);
