@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/qlsd_net.h"
@@ -65,7 +66,9 @@ struct NetArgs {
     const uint32_t *nbc;    // large-graph inference: [MP][max_rw] byte offsets of fault rows (padded)
     const uint32_t *nbf;    // [NP][max_cw] byte offsets of check rows (padded)
     const float *rdc;       // [MP] 1 / check degree (0 on padding)
-    const float *rdf;       // [NP] 1 / fault degree
+    const float *rdf;       // [NP] 1 / fault degree (of the fault in each row)
+    const int32_t *perm;    // [NP] large-graph inference: fault held by each feature row (-1: padding)
+    const int32_t *tdeg;    // [NP/16] largest fault degree of each 16-row tile
 };
 
 struct NetLds {
@@ -685,31 +688,61 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
 
 // ------------------------------------------------------------------------------------------
 // Large-graph inference (graphs whose features do not fit in LDS, e.g. the 936 x 8800 detector
-// error model): one workgroup per shot, its 8 wavefronts splitting the 16-node tiles of each
-// phase, features in a workgroup-private slice of the device workspace (sized to stay in the
-// last-level cache across the grid).  The arithmetic is that of net_infer_kernel: transposed
-// products with weight fragments in registers, neighbour means by linearity on the float32
-// accumulator, padded neighbour lists with a zero sentinel row (u32 byte offsets built once per
-// net by big_tables_kernel).  Neighbour loads are issued in groups of kGather before their MFMAs.
+// error model): one workgroup per shot, its wavefronts splitting the 16-node tiles of each
+// phase, features in a workgroup-private slice of the device workspace (kept in the last-level
+// cache across the grid).  The arithmetic is that of net_infer_kernel: transposed products on
+// v_mfma_f32_16x16x32_bf16 with the output rows of W permuted so that a lane ends a layer holding
+// one whole 8-feature group (one 16-byte store), neighbour means by linearity on the float32
+// accumulator, zero sentinel rows for padding.  Fault rows are stored sorted by degree (row r
+// holds fault perm[r]), so the 16 faults of a tile have equal or near-equal degree and a tile
+// gathers only up to its own largest degree (tdeg[tile]) instead of the code's; the network
+// treats every node alike and each neighbour sum keeps its order, so the row order changes no
+// result.  The fault phase issues the loads of two tiles before their products; the check
+// phase loads the next group's table entries while the current group's gathers are in flight.
 // ------------------------------------------------------------------------------------------
-constexpr int kBigWaves = 12;
-constexpr int kGather = 6;
-constexpr int kFaultGather = 6;  // neighbours of a fault gathered together (padded; heavier columns loop)
-constexpr int kFaultTiles = 1;   // fault tiles per pass
+constexpr int kBigWaves = 16;
+constexpr int kGather = 10;      // check-phase gathers in flight per tile
+constexpr int kFaultGather = 6;  // fault-phase gathers per tile and pass (heavier tiles loop)
+constexpr int kFaultTiles = 2;   // fault tiles per pass
 
-__global__ void big_tables_kernel(DevGraph g, uint32_t *nbc, uint32_t *nbf, float *rdc, float *rdf) {
+// Fault row order of the large-graph kernel: faults sorted by degree, largest first (stable);
+// rows n .. pad16(n)-1 are padding (-1).
+static void big_fault_order(const std::vector<int32_t> &col_ptr, int n, std::vector<int32_t> &perm,
+                            std::vector<int32_t> &rowof, std::vector<int32_t> &tdeg) {
+    const int NP = pad16(n);
+    int maxd = 0;
+    for (int j = 0; j < n; j++) maxd = std::max(maxd, col_ptr[j + 1] - col_ptr[j]);
+    std::vector<int> start(maxd + 2, 0);
+    for (int j = 0; j < n; j++) start[maxd - (col_ptr[j + 1] - col_ptr[j]) + 1]++;
+    for (int d = 1; d <= maxd + 1; d++) start[d] += start[d - 1];
+    perm.assign(NP, -1);
+    rowof.assign(n, 0);
+    for (int j = 0; j < n; j++) {
+        const int r = start[maxd - (col_ptr[j + 1] - col_ptr[j])]++;
+        perm[r] = j;
+        rowof[j] = r;
+    }
+    tdeg.assign(NP / 16, 0);
+    for (int r = 0; r < n; r++) {
+        const int j = perm[r];
+        tdeg[r >> 4] = std::max(tdeg[r >> 4], col_ptr[j + 1] - col_ptr[j]);
+    }
+}
+
+__global__ void big_tables_kernel(DevGraph g, const int32_t *perm, const int32_t *rowof, uint32_t *nbc, uint32_t *nbf,
+                                  float *rdc, float *rdf) {
     const int NP = pad16(g.n), MP = pad16(g.m), dr = g.max_rw, dc = g.max_cw;
     const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x, stride = (size_t)gridDim.x * blockDim.x;
     for (size_t x = tid; x < (size_t)MP * dr; x += stride) {
         const int i = (int)(x / dr), k = (int)(x % dr);
         uint32_t off = (uint32_t)NP * 64u;
-        if (i < g.m && g.row_ptr[i] + k < g.row_ptr[i + 1]) off = (uint32_t)g.col_idx[g.row_ptr[i] + k] * 64u;
+        if (i < g.m && g.row_ptr[i] + k < g.row_ptr[i + 1]) off = (uint32_t)rowof[g.col_idx[g.row_ptr[i] + k]] * 64u;
         nbc[x] = off;
     }
     for (size_t x = tid; x < (size_t)NP * dc; x += stride) {
-        const int j = (int)(x / dc), k = (int)(x % dc);
+        const int r = (int)(x / dc), k = (int)(x % dc), j = perm[r];
         uint32_t off = (uint32_t)MP * 64u;
-        if (j < g.n && g.col_ptr[j] + k < g.col_ptr[j + 1]) off = (uint32_t)g.row_idx[g.col_ptr[j] + k] * 64u;
+        if (j >= 0 && g.col_ptr[j] + k < g.col_ptr[j + 1]) off = (uint32_t)g.row_idx[g.col_ptr[j] + k] * 64u;
         nbf[x] = off;
     }
     for (size_t x = tid; x < (size_t)MP; x += stride) {
@@ -717,7 +750,8 @@ __global__ void big_tables_kernel(DevGraph g, uint32_t *nbc, uint32_t *nbf, floa
         rdc[x] = d > 0 ? 1.0f / (float)d : 0.f;
     }
     for (size_t x = tid; x < (size_t)NP; x += stride) {
-        const int d = x < (size_t)g.n ? g.col_ptr[x + 1] - g.col_ptr[x] : 0;
+        const int j = perm[x];
+        const int d = j >= 0 ? g.col_ptr[j + 1] - g.col_ptr[j] : 0;
         rdf[x] = d > 0 ? 1.0f / (float)d : 0.f;
     }
 }
@@ -731,15 +765,16 @@ __host__ __device__ inline size_t big_slice_bytes(int n, int m) {
     return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID);
 }
 
-__device__ __forceinline__ short4v gfrag(const unsigned char *base, uint32_t off) {
-    return *(const short4v *)(base + off);
+__device__ __forceinline__ bf16x8v gload(const unsigned char *base, uint32_t off) {
+    return *(const bf16x8v *)(base + off);
 }
 
 __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A) {
     __shared__ float sv[SV_N];
-    __shared__ uint2 wfl[9 * 2 * 2 * 64];  // weight fragments, [mat][ks][ot][lane] (lane-contiguous)
+    __shared__ uint4 wfl[9 * 2 * 64];  // weight fragments [mat][ot][lane], output rows permuted
     extern __shared__ __align__(16) unsigned char smem[];  // sg: m floats; then fault neighbour rows
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, t = threadIdx.x;
+    const int lane = threadIdx.x & 63, t = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int n = A.g.n, m = A.g.m, NP = pad16(n), MP = pad16(m), dr = A.g.max_rw, dc = A.g.max_cw;
     float *sg = (float *)smem;
     // the fault phase's neighbour lists as u16 check rows (MP = the zero row), read from LDS
@@ -747,7 +782,6 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
     for (int x = t; x < NP * dc; x += blockDim.x) nbf16[x] = (uint16_t)(A.nbf[x] >> 6);
     unsigned char *Hb = A.act + (size_t)blockIdx.x * A.act_stride;
     unsigned char *Cb = Hb + (size_t)(NP + 1) * 64;
-    const uint16_t *H16 = (const uint16_t *)Hb;
 
     for (int x = t; x < SV_N; x += blockDim.x) {
         float v;
@@ -759,21 +793,27 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
         else v = A.theta[P_BO];
         sv[x] = v;
     }
-    // A-operand fragment (mat, ks, ot) of lane l: W[ot*16 + (l&15)][ks*16 + 4(l>>4) .. +3]
-    for (int x = t; x < 9 * 2 * 2 * 64; x += blockDim.x) {
-        const int l = x & 63, ot = (x >> 6) & 1, ks = (x >> 7) & 1, mat = x >> 8;
-        const int layer = mat / 3, which = mat % 3;
+    // A-operand fragment (mat, ot) of lane l: W[8 (r >> 2) + 4 ot + (r & 3)][8 q .. 8 q + 7], r = l & 15,
+    // q = l >> 4 (the output-row order of net_infer_kernel)
+    for (int x = t; x < 9 * 2 * 64; x += blockDim.x) {
+        const int l = x & 63, ot = (x >> 6) & 1, mat = x >> 7;
+        const int layer = mat / 3, which = mat % 3, r = l & 15, q = l >> 4;
         const float *W = A.theta + P_LAYER + layer * P_LSTRIDE + (which == 0 ? P_A : which == 1 ? P_B : P_C);
-        const float *w = W + (ot * 16 + (l & 15)) * HID + ks * 16 + (l >> 4) * 4;
-        wfl[x] = make_uint2(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3]));
+        const float *w = W + (8 * (r >> 2) + 4 * ot + (r & 3)) * HID + 8 * q;
+        wfl[x] = make_uint4(pack_bf16x2(w[0], w[1]), pack_bf16x2(w[2], w[3]), pack_bf16x2(w[4], w[5]),
+                            pack_bf16x2(w[6], w[7]));
     }
     if (t < 16) {  // sentinel rows (never written again)
         ((uint32_t *)(Hb + (size_t)NP * 64))[t] = 0u;
         ((uint32_t *)(Cb + (size_t)MP * 64))[t] = 0u;
     }
-    const int r16 = lane & 15, kq = (lane >> 4) * 4;
+    const int r16 = lane & 15, q8 = lane >> 4, q16 = q8 << 4;
     __syncthreads();
-    auto frag = [&](int mat, int ks, int ot) { return __builtin_bit_cast(short4v, wfl[((mat * 2 + ks) * 2 + ot) * 64 + lane]); };
+    auto frag = [&](int mat, int ot) { return __builtin_bit_cast(bf16x8v, wfl[(mat * 2 + ot) * 64 + lane]); };
+    auto store_group = [&](unsigned char *p, const float4v &v0, const float4v &v1) {
+        *(uint4 *)p = make_uint4(pack_bf16x2(v0[0], v0[1]), pack_bf16x2(v0[2], v0[3]), pack_bf16x2(v1[0], v1[1]),
+                                 pack_bf16x2(v1[2], v1[3]));
+    };
 
     const int total = A.list ? *A.list_count : A.count;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
@@ -781,135 +821,144 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
         const uint8_t *syn = A.syn + (size_t)shot * m;
         const float *llr = A.llr + (size_t)shot * n;
         for (int i = t; i < m; i += blockDim.x) sg[i] = (syn[i] & 1) ? -1.f : 1.f;
-        // input layer: thread j writes its fault's 32 features (4 x 16 B)
-        for (int j = t; j < NP; j += blockDim.x) {
+        // input layer: thread r writes the 32 features of fault perm[r] into row r (4 x 16 B);
+        // padding rows get relu(b0) and are never read
+        for (int r = t; r < NP; r += blockDim.x) {
+            // the 96 input-layer parameters are re-read from LDS each row rather than held in
+            // registers across the shot loop
+            asm volatile("" ::: "memory");
+            const int j = A.perm[r];
             float x0 = 0.f, x1 = 0.f;
-            if (j < n) { x0 = tanhf(llr[j] * 0.125f); x1 = A.lam[j] * 0.125f; }
+            if (j >= 0) { x0 = tanhf(llr[j] * 0.125f); x1 = A.lam[j] * 0.125f; }
 #pragma unroll
             for (int f8 = 0; f8 < HID; f8 += 8) {
                 uint32_t w[4];
 #pragma unroll
                 for (int h2 = 0; h2 < 4; h2++) {
                     const int f = f8 + 2 * h2;
-                    float v0 = 0.f, v1 = 0.f;
-                    if (j < n) {
-                        v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
-                        v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
-                    }
+                    const float v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
+                    const float v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
                     w[h2] = pack_bf16x2(v0, v1);
                 }
-                *(uint4 *)(Hb + (size_t)j * 64 + f8 * 2) = make_uint4(w[0], w[1], w[2], w[3]);
+                *(uint4 *)(Hb + (size_t)r * 64 + f8 * 2) = make_uint4(w[0], w[1], w[2], w[3]);
             }
         }
         __syncthreads();
         for (int l = 0; l < NL; l++) {
             // checks: c_i = relu((1/deg_i) sum_j A h_j + sigma_i a)
             {
-                const short4v a00 = frag(l * 3, 0, 0), a01 = frag(l * 3, 0, 1), a10 = frag(l * 3, 1, 0),
-                              a11 = frag(l * 3, 1, 1);
+                const bf16x8v a0 = frag(l * 3, 0), a1 = frag(l * 3, 1);
+                const float4v av0 = *(const float4v *)(sv + SV_A + l * HID + 8 * q8);
+                const float4v av1 = *(const float4v *)(sv + SV_A + l * HID + 8 * q8 + 4);
                 for (int rt = wave; rt < MP / 16; rt += kBigWaves) {
                     const int i = rt * 16 + r16;
                     float4v acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
                     const uint32_t *nb = A.nbc + (size_t)i * dr;
+                    uint32_t off[kGather];
+#pragma unroll
+                    for (int k = 0; k < kGather; k++) off[k] = k < dr ? nb[k] : (uint32_t)NP * 64u;
                     for (int k0 = 0; k0 < dr; k0 += kGather) {
-                        short4v x0[kGather], x1[kGather];
+                        bf16x8v x[kGather];
+#pragma unroll
+                        for (int k = 0; k < kGather; k++) x[k] = gload(Hb, off[k] + q16);
+#pragma unroll
+                        for (int k = 0; k < kGather; k++)
+                            off[k] = k0 + kGather + k < dr ? nb[k0 + kGather + k] : (uint32_t)NP * 64u;
 #pragma unroll
                         for (int k = 0; k < kGather; k++) {
-                            const uint32_t off = k0 + k < dr ? nb[k0 + k] : (uint32_t)NP * 64u;
-                            x0[k] = gfrag(Hb, off + kq * 2);
-                            x1[k] = gfrag(Hb, off + 32 + kq * 2);
-                        }
-#pragma unroll
-                        for (int k = 0; k < kGather; k++) {
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a00, x0[k], acc0, 0, 0, 0);
-                            acc0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a10, x1[k], acc0, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a01, x0[k], acc1, 0, 0, 0);
-                            acc1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a11, x1[k], acc1, 0, 0, 0);
+                            acc0 = mfma32(a0, x[k], acc0);
+                            acc1 = mfma32(a1, x[k], acc1);
                         }
                     }
                     const float rd = A.rdc[i], sgn = i < m ? sg[i] : 0.f;
-                    float v[4];
+                    float4v v0, v1;
 #pragma unroll
-                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc0[q] + sgn * sv[SV_A + l * HID + kq + q], 0.f);
-                    *(uint2 *)(Cb + (size_t)i * 64 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
-#pragma unroll
-                    for (int q = 0; q < 4; q++) v[q] = fmaxf(rd * acc1[q] + sgn * sv[SV_A + l * HID + 16 + kq + q], 0.f);
-                    *(uint2 *)(Cb + (size_t)i * 64 + 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    for (int q = 0; q < 4; q++) {
+                        v0[q] = fmaxf(rd * acc0[q] + sgn * av0[q], 0.f);
+                        v1[q] = fmaxf(rd * acc1[q] + sgn * av1[q], 0.f);
+                    }
+                    store_group(Cb + (size_t)i * 64 + q16, v0, v1);
                 }
             }
             __syncthreads();
-            // faults: h_j = relu(B h_j + (1/deg_j) sum_i C c_i + b), in place (own rows only); every
-            // gather of a pass's tiles in flight together
+            // faults: h_j = relu(B h_j + b + (1/deg_j) sum_i C c_i), b entering as the accumulator
+            // of B h_j; in place (own rows only)
             {
-                const short4v b00 = frag(l * 3 + 1, 0, 0), b01 = frag(l * 3 + 1, 0, 1), b10 = frag(l * 3 + 1, 1, 0),
-                              b11 = frag(l * 3 + 1, 1, 1);
-                const short4v c00 = frag(l * 3 + 2, 0, 0), c01 = frag(l * 3 + 2, 0, 1), c10 = frag(l * 3 + 2, 1, 0),
-                              c11 = frag(l * 3 + 2, 1, 1);
+                const bf16x8v b0 = frag(l * 3 + 1, 0), b1 = frag(l * 3 + 1, 1);
+                const bf16x8v c0 = frag(l * 3 + 2, 0), c1 = frag(l * 3 + 2, 1);
+                const float4v bv0 = *(const float4v *)(sv + SV_BL + l * HID + 8 * q8);
+                const float4v bv1 = *(const float4v *)(sv + SV_BL + l * HID + 8 * q8 + 4);
                 const int ntiles = NP / 16;
-                for (int rt0 = wave; rt0 < ntiles; rt0 += kFaultTiles * kBigWaves) {
-                    short4v h0[kFaultTiles], h1[kFaultTiles], y0[kFaultTiles][kFaultGather], y1[kFaultTiles][kFaultGather];
+                // one pass: kFaultTiles tiles, each gathering D check rows per fault (the pass's
+                // largest tile degree; the tables pad shorter lists with the zero row), every load
+                // issued before the first product
+                auto pass = [&](auto Dc, int rt0) {
+                    constexpr int D = decltype(Dc)::value;
+                    bf16x8v h[kFaultTiles], y[kFaultTiles][D];
 #pragma unroll
                     for (int tt = 0; tt < kFaultTiles; tt++) {
                         const int rt = rt0 + tt * kBigWaves;
-                        const int j = (rt < ntiles ? rt : rt0) * 16 + r16;
-                        h0[tt] = gfrag(Hb, (uint32_t)j * 64u + kq * 2);
-                        h1[tt] = gfrag(Hb, (uint32_t)j * 64u + 32 + kq * 2);
-                        const uint16_t *nb = nbf16 + (size_t)j * dc;
+                        const int r = (rt < ntiles ? rt : rt0) * 16 + r16;
+                        h[tt] = gload(Hb, (uint32_t)r * 64u + q16);
+                        const uint16_t *nb = nbf16 + (size_t)r * dc;
 #pragma unroll
-                        for (int k = 0; k < kFaultGather; k++) {
-                            const uint32_t off = (k < dc ? (uint32_t)nb[k] : (uint32_t)MP) * 64u;
-                            y0[tt][k] = gfrag(Cb, off + kq * 2);
-                            y1[tt][k] = gfrag(Cb, off + 32 + kq * 2);
-                        }
+                        for (int k = 0; k < D; k++) y[tt][k] = gload(Cb, (uint32_t)nb[k] * 64u + q16);
                     }
 #pragma unroll
                     for (int tt = 0; tt < kFaultTiles; tt++) {
                         const int rt = rt0 + tt * kBigWaves;
                         if (rt >= ntiles) continue;
-                        const int j = rt * 16 + r16;
-                        float4v as0 = {0.f, 0.f, 0.f, 0.f}, as1 = {0.f, 0.f, 0.f, 0.f};
+                        const int r = rt * 16 + r16;
                         float4v an0 = {0.f, 0.f, 0.f, 0.f}, an1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                        for (int k = 0; k < kFaultGather; k++) {
-                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c00, y0[tt][k], an0, 0, 0, 0);
-                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c10, y1[tt][k], an0, 0, 0, 0);
-                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c01, y0[tt][k], an1, 0, 0, 0);
-                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c11, y1[tt][k], an1, 0, 0, 0);
+                        for (int k = 0; k < D; k++) {
+                            an0 = mfma32(c0, y[tt][k], an0);
+                            an1 = mfma32(c1, y[tt][k], an1);
                         }
-                        for (int k0 = kFaultGather; k0 < dc; k0++) {  // columns heavier than kFaultGather
-                            const uint32_t off = (uint32_t)nbf16[(size_t)j * dc + k0] * 64u;
-                            const short4v z0 = gfrag(Cb, off + kq * 2), z1 = gfrag(Cb, off + 32 + kq * 2);
-                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c00, z0, an0, 0, 0, 0);
-                            an0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c10, z1, an0, 0, 0, 0);
-                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c01, z0, an1, 0, 0, 0);
-                            an1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(c11, z1, an1, 0, 0, 0);
+                        if (D == kFaultGather) {  // tiles heavier than kFaultGather
+                            const int dt = A.tdeg[rt];
+                            for (int k = kFaultGather; k < dt; k++) {
+                                const bf16x8v z = gload(Cb, (uint32_t)nbf16[(size_t)r * dc + k] * 64u + q16);
+                                an0 = mfma32(c0, z, an0);
+                                an1 = mfma32(c1, z, an1);
+                            }
                         }
-                        as0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b00, h0[tt], as0, 0, 0, 0);
-                        as0 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b10, h1[tt], as0, 0, 0, 0);
-                        as1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b01, h0[tt], as1, 0, 0, 0);
-                        as1 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(b11, h1[tt], as1, 0, 0, 0);
-                        const float rd = A.rdf[j];
-                        const bool live = j < n;
-                        float v[4];
+                        const float4v as0 = mfma32(b0, h[tt], bv0), as1 = mfma32(b1, h[tt], bv1);
+                        const float rd = A.rdf[r];
+                        float4v v0, v1;
 #pragma unroll
-                        for (int q = 0; q < 4; q++)
-                            v[q] = live ? fmaxf(as0[q] + rd * an0[q] + sv[SV_BL + l * HID + kq + q], 0.f) : 0.f;
-                        *(uint2 *)(Hb + (size_t)j * 64 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                        for (int q = 0; q < 4; q++) {
+                            v0[q] = fmaxf(rd * an0[q] + as0[q], 0.f);
+                            v1[q] = fmaxf(rd * an1[q] + as1[q], 0.f);
+                        }
+                        store_group(Hb + (size_t)r * 64 + q16, v0, v1);
+                    }
+                };
+                for (int rt0 = wave; rt0 < ntiles; rt0 += kFaultTiles * kBigWaves) {
+                    int D = 1;
 #pragma unroll
-                        for (int q = 0; q < 4; q++)
-                            v[q] = live ? fmaxf(as1[q] + rd * an1[q] + sv[SV_BL + l * HID + 16 + kq + q], 0.f) : 0.f;
-                        *(uint2 *)(Hb + (size_t)j * 64 + 32 + kq * 2) = make_uint2(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    for (int tt = 0; tt < kFaultTiles; tt++)
+                        if (rt0 + tt * kBigWaves < ntiles) D = max(D, A.tdeg[rt0 + tt * kBigWaves]);
+                    switch (D) {
+                        case 1: pass(std::integral_constant<int, 1>{}, rt0); break;
+                        case 2: pass(std::integral_constant<int, 2>{}, rt0); break;
+                        case 3: pass(std::integral_constant<int, 3>{}, rt0); break;
+                        case 4: pass(std::integral_constant<int, 4>{}, rt0); break;
+                        case 5: pass(std::integral_constant<int, 5>{}, rt0); break;
+                        default: pass(std::integral_constant<int, kFaultGather>{}, rt0); break;
                     }
                 }
             }
             __syncthreads();
         }
-        for (int j = t; j < n; j += blockDim.x) {
+        for (int r = t; r < NP; r += blockDim.x) {
+            const int j = A.perm[r];
+            if (j < 0) continue;
             float d = sv[SV_BO];
-            const uint4 *h = (const uint4 *)(H16 + (size_t)j * HID);
+            const uint4 *hr = (const uint4 *)(Hb + (size_t)r * 64);
 #pragma unroll
             for (int f8 = 0; f8 < 4; f8++) {
-                const uint4 v = h[f8];
+                const uint4 v = hr[f8];
                 const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
                 for (int h2 = 0; h2 < 4; h2++) {
@@ -1000,6 +1049,7 @@ struct qlsd_net_s {
     // workspace for qlsd_net_forward (decoders bring their own, see qlsd_decoder_set_net)
     uint32_t *d_nbc = nullptr, *d_nbf = nullptr;
     float *d_rdc = nullptr, *d_rdf = nullptr;
+    int32_t *d_perm = nullptr, *d_rowof = nullptr, *d_tdeg = nullptr;  // fault rows sorted by degree
     unsigned char *d_iws = nullptr;
 };
 
@@ -1039,6 +1089,8 @@ static hipError_t launch_infer_big(const qlsd_net_s *net, NetArgs a, unsigned ch
     a.nbf = net->d_nbf;
     a.rdc = net->d_rdc;
     a.rdf = net->d_rdf;
+    a.perm = net->d_perm;
+    a.tdeg = net->d_tdeg;
     const int grid = std::max(1, std::min(max_items, big_slices(net)));
     const size_t lds = big_dyn_lds(a.g);
     hipError_t e = hipFuncSetAttribute((const void *)net_infer_big_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -1113,14 +1165,23 @@ qlsd_status qlsd_net_create(qlsd_code code, const double *priors, const float *p
             set_last_error("graph too large for the refinement's inference kernel");
             return QLSD_E_UNSUPPORTED;
         }
+        std::vector<int32_t> col_ptr(g.n + 1), perm, rowof, tdeg;
         ok = (size_t)(NP + 1) * 64 < (1ull << 32) && (size_t)(MP + 1) * 64 < (1ull << 32) &&
-             hipMalloc((void **)&net->d_nbc, sizeof(uint32_t) * (size_t)MP * g.max_rw) == hipSuccess &&
+             hipMemcpy(col_ptr.data(), g.col_ptr, sizeof(int32_t) * (g.n + 1), hipMemcpyDeviceToHost) == hipSuccess;
+        if (ok) big_fault_order(col_ptr, g.n, perm, rowof, tdeg);
+        ok = ok && hipMalloc((void **)&net->d_nbc, sizeof(uint32_t) * (size_t)MP * g.max_rw) == hipSuccess &&
              hipMalloc((void **)&net->d_nbf, sizeof(uint32_t) * (size_t)NP * g.max_cw) == hipSuccess &&
              hipMalloc((void **)&net->d_rdc, sizeof(float) * MP) == hipSuccess &&
-             hipMalloc((void **)&net->d_rdf, sizeof(float) * NP) == hipSuccess;
+             hipMalloc((void **)&net->d_rdf, sizeof(float) * NP) == hipSuccess &&
+             hipMalloc((void **)&net->d_perm, sizeof(int32_t) * NP) == hipSuccess &&
+             hipMalloc((void **)&net->d_rowof, sizeof(int32_t) * g.n) == hipSuccess &&
+             hipMalloc((void **)&net->d_tdeg, sizeof(int32_t) * (NP / 16)) == hipSuccess &&
+             hipMemcpy(net->d_perm, perm.data(), sizeof(int32_t) * NP, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(net->d_rowof, rowof.data(), sizeof(int32_t) * g.n, hipMemcpyHostToDevice) == hipSuccess &&
+             hipMemcpy(net->d_tdeg, tdeg.data(), sizeof(int32_t) * (NP / 16), hipMemcpyHostToDevice) == hipSuccess;
         if (ok) {
-            hipLaunchKernelGGL(big_tables_kernel, dim3(256), dim3(256), 0, 0, g, net->d_nbc, net->d_nbf, net->d_rdc,
-                               net->d_rdf);
+            hipLaunchKernelGGL(big_tables_kernel, dim3(256), dim3(256), 0, 0, g, net->d_perm, net->d_rowof, net->d_nbc,
+                               net->d_nbf, net->d_rdc, net->d_rdf);
             ok = hipGetLastError() == hipSuccess && hipDeviceSynchronize() == hipSuccess;
         }
         if (!ok) {
@@ -1242,6 +1303,9 @@ void qlsd_net_destroy(qlsd_net net) {
     hipFree(net->d_nbf);
     hipFree(net->d_rdc);
     hipFree(net->d_rdf);
+    hipFree(net->d_perm);
+    hipFree(net->d_rowof);
+    hipFree(net->d_tdeg);
     hipFree(net->d_iws);
     delete net;
 }
