@@ -699,6 +699,9 @@ __global__ __launch_bounds__(64 * kInferWavesMax) void net_infer_kernel(NetArgs 
 // treats every node alike and each neighbour sum keeps its order, so the row order changes no
 // result.  The fault phase issues the loads of two tiles before their products; the check
 // phase loads the next group's table entries while the current group's gathers are in flight.
+// The input layer is never stored: layer 0 recomputes a fault's first-layer features from its
+// 8-byte inputs (tanh(L/8), lambda/8) where it needs them, and the last fault phase applies the
+// output layer to its own bf16-rounded features instead of storing them.
 // ------------------------------------------------------------------------------------------
 constexpr int kBigWaves = 16;
 constexpr int kGather = 10;      // check-phase gathers in flight per tile
@@ -761,8 +764,11 @@ __global__ void big_tables_kernel(DevGraph g, const int32_t *perm, const int32_t
 __host__ __device__ inline size_t big_dyn_lds(const DevGraph &g) {
     return al16(sizeof(float) * (size_t)g.m) + al16(sizeof(uint16_t) * (size_t)pad16(g.n) * g.max_cw);
 }
+// per-workgroup slice: fault rows (NP + 1 with the zero row), check rows (MP + 1), and each fault
+// row's inputs (x0, x1) as a float pair (NP + 1: the zero row's entry is read, then discarded)
 __host__ __device__ inline size_t big_slice_bytes(int n, int m) {
-    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID);
+    return al16(sizeof(uint16_t) * ((size_t)pad16(n) + 1 + pad16(m) + 1) * HID) +
+           al16(sizeof(float) * 2 * ((size_t)pad16(n) + 1));
 }
 
 __device__ __forceinline__ bf16x8v gload(const unsigned char *base, uint32_t off) {
@@ -770,7 +776,7 @@ __device__ __forceinline__ bf16x8v gload(const unsigned char *base, uint32_t off
 }
 
 __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A) {
-    __shared__ float sv[SV_N];
+    __shared__ __align__(16) float sv[SV_N];
     __shared__ uint4 wfl[9 * 2 * 64];  // weight fragments [mat][ot][lane], output rows permuted
     extern __shared__ __align__(16) unsigned char smem[];  // sg: m floats; then fault neighbour rows
     const int lane = threadIdx.x & 63, t = threadIdx.x;
@@ -815,36 +821,40 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                                  pack_bf16x2(v1[2], v1[3]));
     };
 
+    // first-layer features 8 q8 .. +7 of a fault from its inputs (x0, x1) = (tanh(L/8), lambda/8)
+    // (the parameters are read from LDS at each use rather than held in registers)
+    auto h0_group = [&](float x0, float x1) {
+        const float4v *w0 = (const float4v *)(sv + SV_W0 + 16 * q8), *b0 = (const float4v *)(sv + SV_B0 + 8 * q8);
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; i++)
+            v[i] = fmaxf(fmaf(w0[i >> 1][2 * (i & 1)], x0, fmaf(w0[i >> 1][2 * (i & 1) + 1], x1, b0[i >> 2][i & 3])), 0.f);
+        return __builtin_bit_cast(bf16x8v, make_uint4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]),
+                                                      pack_bf16x2(v[4], v[5]), pack_bf16x2(v[6], v[7])));
+    };
+    // the slice's per-row inputs: x1 = lambda/8 once per launch, x0 = tanh(L/8) per shot
+    float2 *X = (float2 *)(Cb + (size_t)(MP + 1) * 64);
+    for (int r = t; r <= NP; r += blockDim.x) {
+        const int j = r < NP ? A.perm[r] : -1;
+        X[r] = make_float2(0.f, j >= 0 ? A.lam[j] * 0.125f : 0.f);
+    }
+    const uint32_t sentinel_off = (uint32_t)NP * 64u;
+
     const int total = A.list ? *A.list_count : A.count;
     for (int item = blockIdx.x; item < total; item += gridDim.x) {
         const int shot = A.list ? A.list[item] : item;
         const uint8_t *syn = A.syn + (size_t)shot * m;
         const float *llr = A.llr + (size_t)shot * n;
         for (int i = t; i < m; i += blockDim.x) sg[i] = (syn[i] & 1) ? -1.f : 1.f;
-        // input layer: thread r writes the 32 features of fault perm[r] into row r (4 x 16 B);
-        // padding rows get relu(b0) and are never read
+        // the input layer is not stored: layer 0 recomputes a fault's first-layer features from
+        // its 8-byte inputs wherever it needs them (padding rows get x0 = 0 and are never read)
         for (int r = t; r < NP; r += blockDim.x) {
-            // the 96 input-layer parameters are re-read from LDS each row rather than held in
-            // registers across the shot loop
-            asm volatile("" ::: "memory");
             const int j = A.perm[r];
-            float x0 = 0.f, x1 = 0.f;
-            if (j >= 0) { x0 = tanhf(llr[j] * 0.125f); x1 = A.lam[j] * 0.125f; }
-#pragma unroll
-            for (int f8 = 0; f8 < HID; f8 += 8) {
-                uint32_t w[4];
-#pragma unroll
-                for (int h2 = 0; h2 < 4; h2++) {
-                    const int f = f8 + 2 * h2;
-                    const float v0 = fmaxf(sv[SV_W0 + f * 2] * x0 + sv[SV_W0 + f * 2 + 1] * x1 + sv[SV_B0 + f], 0.f);
-                    const float v1 = fmaxf(sv[SV_W0 + f * 2 + 2] * x0 + sv[SV_W0 + f * 2 + 3] * x1 + sv[SV_B0 + f + 1], 0.f);
-                    w[h2] = pack_bf16x2(v0, v1);
-                }
-                *(uint4 *)(Hb + (size_t)r * 64 + f8 * 2) = make_uint4(w[0], w[1], w[2], w[3]);
-            }
+            X[r].x = j >= 0 ? tanhf(llr[j] * 0.125f) : 0.f;
         }
         __syncthreads();
-        for (int l = 0; l < NL; l++) {
+        auto layer = [&](auto Lc) {
+            constexpr int l = decltype(Lc)::value;
             // checks: c_i = relu((1/deg_i) sum_j A h_j + sigma_i a)
             {
                 const bf16x8v a0 = frag(l * 3, 0), a1 = frag(l * 3, 1);
@@ -856,14 +866,25 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                     const uint32_t *nb = A.nbc + (size_t)i * dr;
                     uint32_t off[kGather];
 #pragma unroll
-                    for (int k = 0; k < kGather; k++) off[k] = k < dr ? nb[k] : (uint32_t)NP * 64u;
+                    for (int k = 0; k < kGather; k++) off[k] = k < dr ? nb[k] : sentinel_off;
                     for (int k0 = 0; k0 < dr; k0 += kGather) {
                         bf16x8v x[kGather];
+                        if constexpr (l == 0) {
+                            float2 xi[kGather];
 #pragma unroll
-                        for (int k = 0; k < kGather; k++) x[k] = gload(Hb, off[k] + q16);
+                            for (int k = 0; k < kGather; k++) xi[k] = X[off[k] >> 6];
+#pragma unroll
+                            for (int k = 0; k < kGather; k++) {
+                                // the zero row of padded lists stays zero
+                                x[k] = off[k] == sentinel_off ? bf16x8v{} : h0_group(xi[k].x, xi[k].y);
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < kGather; k++) x[k] = gload(Hb, off[k] + q16);
+                        }
 #pragma unroll
                         for (int k = 0; k < kGather; k++)
-                            off[k] = k0 + kGather + k < dr ? nb[k0 + kGather + k] : (uint32_t)NP * 64u;
+                            off[k] = k0 + kGather + k < dr ? nb[k0 + kGather + k] : sentinel_off;
 #pragma unroll
                         for (int k = 0; k < kGather; k++) {
                             acc0 = mfma32(a0, x[k], acc0);
@@ -882,7 +903,8 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
             }
             __syncthreads();
             // faults: h_j = relu(B h_j + b + (1/deg_j) sum_i C c_i), b entering as the accumulator
-            // of B h_j; in place (own rows only)
+            // of B h_j; in place (own rows only).  The last layer stores no features: it applies
+            // the output layer to its bf16-rounded features and writes L' for its faults.
             {
                 const bf16x8v b0 = frag(l * 3 + 1, 0), b1 = frag(l * 3 + 1, 1);
                 const bf16x8v c0 = frag(l * 3 + 2, 0), c1 = frag(l * 3 + 2, 1);
@@ -895,11 +917,13 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                 auto pass = [&](auto Dc, int rt0) {
                     constexpr int D = decltype(Dc)::value;
                     bf16x8v h[kFaultTiles], y[kFaultTiles][D];
+                    float2 xo[kFaultTiles];
 #pragma unroll
                     for (int tt = 0; tt < kFaultTiles; tt++) {
                         const int rt = rt0 + tt * kBigWaves;
                         const int r = (rt < ntiles ? rt : rt0) * 16 + r16;
-                        h[tt] = gload(Hb, (uint32_t)r * 64u + q16);
+                        if constexpr (l == 0) xo[tt] = X[r];
+                        else h[tt] = gload(Hb, (uint32_t)r * 64u + q16);
                         const uint16_t *nb = nbf16 + (size_t)r * dc;
 #pragma unroll
                         for (int k = 0; k < D; k++) y[tt][k] = gload(Cb, (uint32_t)nb[k] * 64u + q16);
@@ -909,6 +933,7 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                         const int rt = rt0 + tt * kBigWaves;
                         if (rt >= ntiles) continue;
                         const int r = rt * 16 + r16;
+                        if constexpr (l == 0) h[tt] = h0_group(xo[tt].x, xo[tt].y);
                         float4v an0 = {0.f, 0.f, 0.f, 0.f}, an1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                         for (int k = 0; k < D; k++) {
@@ -931,7 +956,25 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                             v0[q] = fmaxf(rd * an0[q] + as0[q], 0.f);
                             v1[q] = fmaxf(rd * an1[q] + as1[q], 0.f);
                         }
-                        store_group(Hb + (size_t)r * 64 + q16, v0, v1);
+                        if constexpr (l + 1 < NL) {
+                            store_group(Hb + (size_t)r * 64 + q16, v0, v1);
+                        } else {
+                            // output layer: d_j = b_o + w . h_j over the bf16-rounded features,
+                            // 8 per lane, then summed over the 4 lanes of the fault
+                            const uint32_t w[4] = {pack_bf16x2(v0[0], v0[1]), pack_bf16x2(v0[2], v0[3]),
+                                                   pack_bf16x2(v1[0], v1[1]), pack_bf16x2(v1[2], v1[3])};
+                            const float4v *wo = (const float4v *)(sv + SV_W + 8 * q8);
+                            float d = 0.f;
+#pragma unroll
+                            for (int i = 0; i < 4; i++) {
+                                d += wo[i >> 1][2 * (i & 1)] * __uint_as_float(w[i] << 16);
+                                d += wo[i >> 1][2 * (i & 1) + 1] * __uint_as_float(w[i] & 0xffff0000u);
+                            }
+                            d += __shfl_xor(d, 16, 64);
+                            d += __shfl_xor(d, 32, 64);
+                            const int j = A.perm[r];
+                            if (q8 == 0 && j >= 0) A.llr_out[(size_t)shot * n + j] = llr[j] + (sv[SV_BO] + d);
+                        }
                     }
                 };
                 for (int rt0 = wave; rt0 < ntiles; rt0 += kFaultTiles * kBigWaves) {
@@ -950,25 +993,11 @@ __global__ __launch_bounds__(64 * kBigWaves) void net_infer_big_kernel(NetArgs A
                 }
             }
             __syncthreads();
-        }
-        for (int r = t; r < NP; r += blockDim.x) {
-            const int j = A.perm[r];
-            if (j < 0) continue;
-            float d = sv[SV_BO];
-            const uint4 *hr = (const uint4 *)(Hb + (size_t)r * 64);
-#pragma unroll
-            for (int f8 = 0; f8 < 4; f8++) {
-                const uint4 v = hr[f8];
-                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-                for (int h2 = 0; h2 < 4; h2++) {
-                    d += sv[SV_W + f8 * 8 + 2 * h2] * __uint_as_float(w[h2] << 16);
-                    d += sv[SV_W + f8 * 8 + 2 * h2 + 1] * __uint_as_float(w[h2] & 0xffff0000u);
-                }
-            }
-            A.llr_out[(size_t)shot * n + j] = llr[j] + d;
-        }
-        __syncthreads();
+        };
+        static_assert(NL == 3, "layers are instantiated one by one");
+        layer(std::integral_constant<int, 0>{});
+        layer(std::integral_constant<int, 1>{});
+        layer(std::integral_constant<int, 2>{});
     }
 }
 
