@@ -95,6 +95,9 @@ def parse():
                     help="isolated launches timed for the per-launch latency percentiles")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming (per-request latency) leg")
     ap.add_argument("--no-osd", action="store_true", help="skip the BP + OSD-0 comparator leg")
+    ap.add_argument("--no-two-streams", action="store_true",
+                    help="skip the two-stream context runs (for kernel traces whose averages should not mix in "
+                         "launches that overlap another decoder's)")
     ap.add_argument("--stream-requests", type=int, default=100000)
     return ap.parse_args()
 
@@ -264,11 +267,12 @@ def main():
            "tuning": None if tuning is None else [l for l in tuning.splitlines() if "chosen" in l]}
 
     log(f"timed {args.steps} steps: {shots_per_s:.4g} shots/s")
-    dec2 = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=args.lsd_order)
-    out["two_streams"] = {"value": round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1),
-                          "unit": "shots/s", "note": "consecutive batches on two streams, one launch per "
-                                                     "batch each; context, not the headline"}
-    del dec2
+    if not args.no_two_streams:
+        dec2 = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=args.lsd_order)
+        out["two_streams"] = {"value": round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1),
+                              "unit": "shots/s", "note": "consecutive batches on two streams, one launch per "
+                                                         "batch each; context, not the headline"}
+        del dec2
     if not dem and not args.no_stream:
         log("stream leg")
         out["stream"] = stream_leg(code, bcode, args)
@@ -319,10 +323,11 @@ def learned_leg(code, bcode, batches, args, ler_plain, plain_shots_per_s):
            "ler": round(float(f.mean()), 6), "ler_plain": ler_plain,
            "speedup_vs_plain": round(rate / plain_shots_per_s, 3),
            "shots_scored": int(f.size), "tuning": tuning}
-    dec2 = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
-    binding.attach_net(dec2, net)
-    out["two_streams_value"] = round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1)
-    del dec2
+    if not args.no_two_streams:
+        dec2 = binding.Decoder(bcode, code.priors, B, max_iter=args.learned_iter, lsd_order=args.lsd_order)
+        binding.attach_net(dec2, net)
+        out["two_streams_value"] = round(two_stream_rate(code, [dec, dec2], batches, args.steps), 1)
+        del dec2
     if args.no_grid:
         return out
     # plain BP + LSD over its own knobs (BP budget, LSD order mu of Sec. 4.3), on the same

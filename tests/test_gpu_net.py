@@ -237,6 +237,40 @@ def test_large_graph_forward_and_gradient_match_oracle(which):
     print(f"{which}: worst per-value gradient deviation {worst:.2f} of the bound")
 
 
+def test_large_graph_heavy_columns_match_oracle():
+    """Large-graph inference on a graph built to reach the paths the detector error model does not:
+    columns of weight 7, 9 and 10 (tiles heavier than one gather pass), passes whose two tiles
+    differ in weight, rows of mixed weight, and a fault count that pads its last tile (1100
+    faults: more feature rows than the wave-per-shot kernel can address, so the large-graph kernel
+    runs).  Forward on random syndromes and LLRs against the float64 oracle."""
+    rng = np.random.default_rng(31)
+    m, n = 300, 1100
+    H = np.zeros((m, n), dtype=np.uint8)
+    w = rng.choice([2, 3, 7, 9, 10], size=n, p=[0.5, 0.3, 0.1, 0.05, 0.05])
+    for j in range(n):
+        H[rng.choice(m, size=int(w[j]), replace=False), j] = 1
+    for i in np.nonzero(H.sum(1) < 2)[0]:
+        H[i, rng.choice(n, size=2, replace=False)] = 1
+    assert H.sum(0).max() == 10 and (n + 15) // 16 * 16 + 1 > 1023
+    priors = rng.uniform(0.01, 0.1, size=n)
+    lam = np.log((1 - priors) / priors).astype(np.float32).astype(np.float64)
+    nf = 6
+    S = rng.integers(0, 2, size=(nf, m), dtype=np.uint8)
+    L = (lam[None, :] + rng.normal(0.0, 3.0, size=(nf, n))).astype(np.float32)
+    th = _theta(17)
+    net = binding.Net(binding.Code.from_dense(H), priors, th)
+    out = net.forward(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda())
+    torch.cuda.synchronize()
+    d_gpu = out.cpu().numpy().astype(np.float64) - L.astype(np.float64)
+    worst = 0.0
+    for b in range(nf):
+        d_ref = ol.forward(th.astype(np.float64), H, L[b].astype(np.float64), lam, S[b])
+        rel = np.linalg.norm(d_gpu[b] - d_ref) / max(np.linalg.norm(d_ref), 1e-6)
+        assert rel <= 2e-2, (b, rel)
+        worst = max(worst, _assert_delta_close(d_gpu[b], d_ref, ("heavy", b)))
+    print(f"heavy columns: worst per-value deviation {worst:.2f} of the bound")
+
+
 def test_net_rejects_other_code():
     bb, sc = bivariate_bicycle(p=0.05), surface_hgp(5, 0.05)
     net = binding.Net(binding.Code.from_dense(bb.H), bb.priors, _theta(1))
