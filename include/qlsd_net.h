@@ -22,7 +22,7 @@
  * in LDS (inference: one wavefront per shot).  On larger ones training keeps activations in a
  * device workspace the net allocates at its first gradient call (one slice per compute unit,
  * about 6 MB each for the detector model), and inference runs one workgroup per shot over a
- * feature workspace (about 0.6 MB per compute unit for the detector model): the net's own for
+ * feature workspace (about 0.7 MB per compute unit for the detector model): the net's own for
  * qlsd_net_forward, the decoder's for decoding (allocated by qlsd_decoder_set_net).  Calls that
  * use the net's own workspaces (forward, gradient, train_step) must not overlap in time.
  * All device pointers are caller-owned; calls are asynchronous on `stream` unless stated.

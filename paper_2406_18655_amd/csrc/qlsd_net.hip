@@ -1106,7 +1106,7 @@ static hipError_t launch_net(qlsd_net_s *net, NetArgs a, int grid, hipStream_t s
     return hipGetLastError();
 }
 // Slices of the large-graph inference workspace: one per compute unit, so the grid's features
-// (about 0.6 MB per slice for the detector error model) stay in the last-level cache.
+// (about 0.7 MB per slice for the detector error model) stay in the last-level cache.
 static int big_slices(const qlsd_net_s *net) { return net->num_cus; }
 size_t net_infer_workspace_bytes(const qlsd_net_s *net) {
     return net->wave_infer ? 0 : big_slice_bytes(net->g.n, net->g.m) * (size_t)big_slices(net);
