@@ -55,6 +55,7 @@ def lib():
             L.oracle_lsd.argtypes = [P, P, P, I, P, I, P, P]
             L.oracle_lsd_cs.argtypes = [P, P, P, I, I, P, P, P]
             L.oracle_osd0.argtypes = [P, P, P, P]
+            L.oracle_osd_cs.argtypes = [P, P, P, I, P, P]
             L.oracle_error_clusters.argtypes = [P, P, P]
             L.oracle_decode_batch.argtypes = [P, P, P, I, I, D, I, P, P, P, P, P, I]
             L.oracle_max_threads.restype = I
@@ -181,6 +182,17 @@ def osd0(code: Code, s: np.ndarray, llr: np.ndarray):
     llr = np.ascontiguousarray(llr, dtype=np.float64)
     corr = np.empty(code.n, dtype=np.uint8)
     st = lib().oracle_osd0(code._h, _p(s), _p(llr), _p(corr))
+    return corr, int(st)
+
+
+def osd_cs(code: Code, s: np.ndarray, llr: np.ndarray, cs_order: int, omega: np.ndarray):
+    """Global OSD-CS of order cs_order on soft information llr -> (corr uint8[n], status): the
+    combination sweep over all non-pivot columns of OSD-0's reliability-ordered elimination."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    llr = np.ascontiguousarray(llr, dtype=np.float64)
+    corr = np.empty(code.n, dtype=np.uint8)
+    om = np.ascontiguousarray(omega, dtype=np.int64)
+    st = lib().oracle_osd_cs(code._h, _p(s), _p(llr), int(cs_order), _p(om), _p(corr))
     return corr, int(st)
 
 

@@ -22,6 +22,8 @@
  *   - higher-order LSD-mu (mu extra growth steps, then local
  *     exhaustive OSD of order w per cluster) .................. Appendix D
  *   - OSD-0 (global reliability-ordered inversion) ............ Sec. 2.2 "Inversion decoding"
+ *   - global OSD-CS of order w (the comparator of Sec. 2.3 and Appendix C, the global
+ *     counterpart of LSD-mu's local OSD-CS) ................... Sec. 2.2, Sec. 2.3
  *
  * Readings where the paper is silent (the same ones the HIP path implements):
  *   BP   : r_{i->j} = (-1)^{s_i} * alpha * prod_{j'!=j} sgn(q_{j'->i}) * min_{j'!=j} |q_{j'->i}|,
@@ -654,6 +656,52 @@ int oracle_osd0(const void *code, const uint8_t *s, const double *llr, uint8_t *
     if (ok)
         for (int t = 0; t < n; t++) if (bit_get(x, t)) corr[order[t]] = 1;
     free(rhs); free(x); elim_free(&el); free(rowpos); free(order);
+    return ok ? 0 : (int)ST_UNSAT;
+}
+
+/*
+ * Global OSD-CS of order w: OSD-0's reliability order and greedy pivot set over all columns and
+ * all checks, then the combination sweep of the local OSD-CS reading applied to the whole
+ * matrix -- candidates in the order: the zero pattern (OSD-0), every single non-pivot column in
+ * key order, every pair among the first min(w, |T|) non-pivot columns in lexicographic order;
+ * each fixes those columns to one, solves the pivot part, and is scored by the integer weight
+ * sum_{x_j=1} omega_j; the strictly smallest weight wins (ties to the candidate met first).
+ * Returns ST_UNSAT (zero correction) if s is not in the image of H.
+ */
+int oracle_osd_cs(const void *code, const uint8_t *s, const double *llr, int cs_order, const int64_t *omega,
+                  uint8_t *corr) {
+    const ocode *c = (const ocode *)code;
+    int m = c->m, n = c->n;
+    memset(corr, 0, n);
+    int *order = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int *rows = (int *)malloc(sizeof(int) * (m > 0 ? m : 1));
+    for (int j = 0; j < n; j++) order[j] = j;
+    for (int a = 1; a < n; a++) {
+        int v = order[a], b = a - 1;
+        while (b >= 0 && key_less(llr, v, order[b])) { order[b + 1] = order[b]; b--; }
+        order[b + 1] = v;
+    }
+    for (int i = 0; i < m; i++) rows[i] = i;
+    /* solvability first, on the same elimination OSD-0 uses */
+    int *rowpos = (int *)calloc(m > 0 ? m : 1, sizeof(int));
+    for (int i = 0; i < m; i++) rowpos[i] = i;
+    elim_t el;
+    elim_build(&el, c, rowpos, m, order, n);
+    uint64_t *rhs = (uint64_t *)calloc(el.W, sizeof(uint64_t));
+    uint64_t *x = (uint64_t *)calloc(el.Wc, sizeof(uint64_t));
+    for (int i = 0; i < m; i++) if (s[i] & 1) bit_set(rhs, i);
+    int ok = elim_solve(&el, rhs, x);
+    free(rhs); free(x); elim_free(&el);
+    if (ok) {
+        /* the whole matrix as one cluster whose columns are listed in key order */
+        cluster_t all;
+        memset(&all, 0, sizeof(all));
+        all.rows = rows; all.nrows = m; all.cols = order; all.ncols = n;
+        all.alive = 1; all.valid = 1;
+        for (int i = 0; i < m; i++) rowpos[i] = -1;
+        cluster_solve(c, &all, s, llr, 0, cs_order < 1 ? 1 : cs_order, omega, rowpos, corr);
+    }
+    free(rowpos); free(rows); free(order);
     return ok ? 0 : (int)ST_UNSAT;
 }
 

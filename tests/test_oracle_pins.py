@@ -169,6 +169,68 @@ def test_osd0_matches_textbook_and_forced_merge(oracle_mod):
         np.testing.assert_array_equal(fm, want)
 
 
+def _brute_osd_cs(H, s, llr, w, omega):
+    """Global OSD-CS of order w by brute force: every x with H x = s is enumerated; the non-pivot
+    columns T (the columns that do not raise the rank of the key-ordered prefix, found with a
+    rank test) define the candidates -- no column of T set, exactly one, or exactly two among the
+    first min(w, |T|) -- each owning the one solution with that pattern on T; the smallest
+    integer weight wins, ties to the earlier candidate."""
+    m, n = H.shape
+    order = sorted(range(n), key=lambda j: (llr[j], j))
+    T, prev = [], 0
+    for k in range(n):
+        r = gf2_rank(H[:, order[:k + 1]])
+        if r == prev:
+            T.append(order[k])
+        prev = r
+    wp = min(w, len(T))
+    cands = [()] + [(a,) for a in range(len(T))] + [(a, b) for a in range(wp) for b in range(a + 1, wp)]
+    rank_of = {c: i for i, c in enumerate(cands)}
+    best = None
+    for bits in range(1 << n):
+        x = np.array([(bits >> j) & 1 for j in range(n)], dtype=np.uint8)
+        if (((H.astype(int) @ x) % 2) != s).any():
+            continue
+        pat = tuple(a for a, j in enumerate(T) if x[j])
+        if pat not in rank_of:
+            continue
+        key = (int(omega[x == 1].sum()), rank_of[pat])
+        if best is None or key < best[0]:
+            best = (key, x)
+    return None if best is None else best[1]
+
+
+def test_osd_cs_global_brute_force(oracle_mod):
+    """Global OSD-CS against an exhaustive enumeration of the solutions on small random codes
+    (n <= 14), orders 1..4 and ties in the soft information; never heavier than OSD-0."""
+    rng = np.random.default_rng(23)
+    checked = 0
+    for trial in range(40):
+        m, n = int(rng.integers(3, 7)), int(rng.integers(6, 15))
+        H = (rng.random((m, n)) < 0.4).astype(np.uint8)
+        e = (rng.random(n) < 0.3).astype(np.uint8)
+        s = ((H.astype(int) @ e) % 2).astype(np.uint8)
+        llr = rng.normal(size=n)
+        if trial % 4 == 0:
+            llr = np.round(llr)
+        omega = rng.integers(1, 50, size=n).astype(np.int64)
+        w = int(rng.integers(1, 5))
+        code = oracle_mod.Code.from_dense(H)
+        got, st = oracle_mod.osd_cs(code, s, llr, w, omega)
+        want = _brute_osd_cs(H, s, llr, w, omega)
+        assert st == 0 and want is not None
+        np.testing.assert_array_equal(got, want, err_msg=f"trial {trial}")
+        x0, _ = oracle_mod.osd0(code, s, llr)
+        assert int(omega[got == 1].sum()) <= int(omega[x0 == 1].sum())
+        checked += int((got != x0).any())
+    assert checked >= 5  # the sweep changed the OSD-0 answer in several trials
+    # a syndrome outside the image of H: UNSAT, zero correction
+    H = np.array([[1, 1, 0], [1, 1, 0]], dtype=np.uint8)
+    got, st = oracle_mod.osd_cs(oracle_mod.Code.from_dense(H), np.array([1, 0], np.uint8),
+                                np.zeros(3), 3, np.ones(3, np.int64))
+    assert st == oracle_mod.ST_UNSAT and not got.any()
+
+
 def _random_ldpc(rng, m, n, col_w):
     H = np.zeros((m, n), dtype=np.uint8)
     for j in range(n):
