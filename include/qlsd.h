@@ -66,7 +66,9 @@ typedef struct {
 #define QLSD_FLAG_STAGE_TIMING 2u  /* record HIP events around each kernel of qlsd_decode */
 #define QLSD_FLAG_SEPARATE_LSD 4u  /* qlsd_decode: BP and LSD as two kernels, never overlapped */
 #define QLSD_FLAG_OSD0_POST 8u     /* qlsd_decode: global OSD-0 (qlsd_osd0) instead of LSD after
-                                      BP, the comparator of Sec. 2.2; needs n <= 4096, m <= 1024 */
+                                      BP, the comparator of Sec. 2.2; needs n <= 4096, m <= 1024.
+                                      With osd_method 1: global OSD-CS of order osd_order
+                                      (qlsd_osd_cs) instead, needs m <= 256 */
 
 /* Per-shot status bits (qlsd_shot_info.status). */
 #define QLSD_ST_BP_CONVERGED 1u /* BP's hard decision satisfies s; no LSD was needed   */
@@ -165,6 +167,19 @@ qlsd_status qlsd_error_clusters(qlsd_code code, const uint8_t *errors, int32_t B
  * columns reduced before s was spanned.  QLSD_E_UNSUPPORTED beyond n = 4096 or m = 1024. */
 qlsd_status qlsd_osd0(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B,
                       uint8_t *corrections, qlsd_shot_info *info, void *stream);
+
+/* Global OSD-CS of order `order` in [1, 12] (Sec. 2.2 and 2.3: the BP+OSD comparator at higher
+ * order; the combination sweep of LSD-mu's local reprocessing applied to the whole matrix): the
+ * key order and greedy pivot set of qlsd_osd0 over all n columns, T = the non-pivot columns in
+ * ascending key; candidates in this order -- the OSD-0 solution, every single column of T set,
+ * every pair among the first min(order, |T|) columns of T -- each fixing those columns of T to
+ * one and solving the pivot part; the one of smallest integer weight sum_{e_j=1} omega_j
+ * (omega_j = round(2^20 lambda_j) from the decoder's priors) wins, ties to the candidate met
+ * first.  Arguments, layout and info as qlsd_osd0 (rounds and max_cluster_cols = n, every
+ * column reduced).  QLSD_E_INVALID for an order outside [1, 12]; QLSD_E_UNSUPPORTED beyond
+ * n = 4096 or m = 256. */
+qlsd_status qlsd_osd_cs(qlsd_decoder dec, const uint8_t *syndromes, const float *llr, int32_t B, int32_t order,
+                        uint8_t *corrections, qlsd_shot_info *info, void *stream);
 
 /* Device time (ms) of the BP kernel and of the LSD kernel in the decoder's last
  * qlsd_decode call, from HIP events recorded on that call's stream around each kernel

@@ -24,7 +24,7 @@ FLAG_OSD0_POST = 8
 
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
-           "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
+           "qlsd_osd0", "qlsd_osd_cs", "qlsd_lsd_stats", "qlsd_error_clusters",
            "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
            "qlsd_decoder_set_lsd_schedule", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
@@ -68,6 +68,7 @@ def lib():
         L.qlsd_bp.argtypes = [P, P, I32, P, P, P, P]
         L.qlsd_lsd.argtypes = [P, P, P, I32, P, P, P]
         L.qlsd_osd0.argtypes = [P, P, P, I32, P, P, P]
+        L.qlsd_osd_cs.argtypes = [P, P, P, I32, I32, P, P, P]
         L.qlsd_lsd_stats.argtypes = [P, P, P, I32, P, P, P, P]
         L.qlsd_error_clusters.argtypes = [P, P, I32, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
@@ -79,7 +80,7 @@ def lib():
         L.qlsd_decoder_destroy.argtypes = [P]
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
-                   "qlsd_osd0", "qlsd_lsd_stats", "qlsd_error_clusters",
+                   "qlsd_osd0", "qlsd_osd_cs", "qlsd_lsd_stats", "qlsd_error_clusters",
                    "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
                    "qlsd_decoder_set_lsd_schedule", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
@@ -211,6 +212,12 @@ class Decoder:
         _check(lib().qlsd_osd0(self._h, _ptr(syndromes), _ptr(llr), B, _ptr(corrections), _ptr(info),
                                _stream() if stream is None else stream))
 
+    def osd_cs_into(self, syndromes, llr, order: int, corrections, info=None, stream: Optional[int] = None):
+        B = syndromes.shape[0]
+        self._check_io(syndromes, B, llr=llr, corrections=corrections, info=info)
+        _check(lib().qlsd_osd_cs(self._h, _ptr(syndromes), _ptr(llr), B, int(order), _ptr(corrections), _ptr(info),
+                                 _stream() if stream is None else stream))
+
     def sync(self):
         _check(lib().qlsd_sync(self._h))
 
@@ -308,6 +315,18 @@ class Decoder:
         corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
         info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
         self.osd0_into(s, llr.contiguous(), corr, info)
+        return corr, info
+
+    def osd_cs(self, syndromes, llr, order: int, want_info: bool = True):
+        """Global OSD-CS of the given order (qlsd_osd_cs) on float32 [B, n] soft information."""
+        import torch
+        s = self._prep(syndromes)
+        B = s.shape[0]
+        if llr.dtype != torch.float32 or tuple(llr.shape) != (B, self.code.n) or not llr.is_cuda:
+            raise ValueError("llr must be a float32 CUDA tensor [B, n]")
+        corr = torch.empty((B, self.code.n), dtype=torch.uint8, device=s.device)
+        info = torch.empty((B, 12), dtype=torch.uint8, device=s.device) if want_info else None
+        self.osd_cs_into(s, llr.contiguous(), int(order), corr, info)
         return corr, info
 
 

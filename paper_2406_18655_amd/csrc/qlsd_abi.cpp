@@ -102,6 +102,8 @@ struct qlsd_decoder_s {
     // global OSD-0 (qlsd_osd0, QLSD_FLAG_OSD0_POST): basis words per lane row, sort length
     int osd_W, osd_P, osd_wave_bytes;
     bool osd_ok;
+    int osd_cs_wave_bytes;  // global OSD-CS (qlsd_osd_cs; QLSD_FLAG_OSD0_POST with osd_method 1)
+    bool osd_cs_ok;
 };
 
 namespace qlsd {
@@ -346,12 +348,18 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     d->osd_W = g.m <= 64 ? 1 : g.m <= 128 ? 2 : g.m <= 256 ? 4 : kWideW;
     d->osd_P = 1;
     while (d->osd_P < g.n) d->osd_P <<= 1;
-    d->osd_wave_bytes = (int)osd0_wave_bytes(g, d->osd_W, d->osd_P);
+    d->osd_wave_bytes = (int)osd0_wave_bytes(g, d->osd_W, d->osd_P, false);
     d->osd_ok = d->osd_P <= kOsdMaxSort && g.m <= kWideRows &&
                 (size_t)d->osd_wave_bytes * (d->osd_W == kWideW ? 1 : 4) <= kLdsPerCu - 1024;
+    d->osd_cs_wave_bytes = (int)osd0_wave_bytes(g, d->osd_W, d->osd_P, true);
+    d->osd_cs_ok = d->osd_ok && d->osd_W != kWideW && (size_t)d->osd_cs_wave_bytes * 4 <= kLdsPerCu - 1024;
     if ((params->flags & QLSD_FLAG_OSD0_POST) && !d->osd_ok) {
         delete d;
         return fail(QLSD_E_UNSUPPORTED, "OSD-0 supports n <= %d and m <= %d (n=%d, m=%d)", kOsdMaxSort, kWideRows, g.n, g.m);
+    }
+    if ((params->flags & QLSD_FLAG_OSD0_POST) && params->osd_method == 1 && !d->osd_cs_ok) {
+        delete d;
+        return fail(QLSD_E_UNSUPPORTED, "global OSD-CS supports n <= %d and m <= 256 (n=%d, m=%d)", kOsdMaxSort, g.n, g.m);
     }
     d->lsd_cb = false;
     d->ovf = d->mid = d->wide = false;
@@ -514,10 +522,11 @@ static hipError_t run_overflow(qlsd_decoder d, const Ws &ws, const uint8_t *syn,
     return launch_lsd_wide(w, ws.wide_ws, ws.wide_grid, s);
 }
 
-// Global OSD-0 over the listed shots (list != nullptr) or shots 0..count-1.
+// Global OSD-0 (cs_order 0) or OSD-CS of order cs_order over the listed shots (list != nullptr)
+// or shots 0..count-1.
 static hipError_t run_osd0(qlsd_decoder d, const Ws &w, const uint8_t *syn, const float *llr, int count,
                            const int *list, const int *list_count, uint8_t *corr, qlsd_shot_info *info,
-                           int bp_iters, hipStream_t s) {
+                           int bp_iters, hipStream_t s, int cs_order = 0) {
     OsdArgs a;
     memset(&a, 0, sizeof(a));
     a.g = d->code->g;
@@ -531,8 +540,10 @@ static hipError_t run_osd0(qlsd_decoder d, const Ws &w, const uint8_t *syn, cons
     a.info = info;
     a.bp_iters = bp_iters;
     a.P = d->osd_P;
-    a.wave_bytes = d->osd_wave_bytes;
+    a.wave_bytes = cs_order > 0 ? d->osd_cs_wave_bytes : d->osd_wave_bytes;
     a.ws = w.wide_ws;
+    a.cs_order = cs_order;
+    a.omega = d->d_omega;
     const int grid = d->osd_W == kWideW ? w.wide_grid : 8 * d->num_cus;
     return launch_osd0(a, d->osd_W, grid, s);
 }
@@ -596,7 +607,8 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
     HIP_OK(launch_compact(w.flag, B, w.list, w.ctl + kCtlList, s));
     if (d->net) HIP_OK(net_refine_listed(d->net, d->d_lam, syndromes, w.llr, w.list, w.ctl + kCtlList, B, d->d_netws, s));
     if (d->params.flags & QLSD_FLAG_OSD0_POST) {
-        HIP_OK(run_osd0(d, w, syndromes, w.llr, 0, w.list, w.ctl + kCtlList, corrections, info, d->params.max_iter, s));
+        HIP_OK(run_osd0(d, w, syndromes, w.llr, 0, w.list, w.ctl + kCtlList, corrections, info, d->params.max_iter, s,
+                        d->params.osd_method == 1 ? d->params.osd_order : 0));
         if (timing) HIP_OK(hipEventRecord(d->ev[2], s));
         return QLSD_OK;
     }
@@ -742,6 +754,22 @@ qlsd_status qlsd_osd0(qlsd_decoder d, const uint8_t *syndromes, const float *llr
     hipStream_t s = (hipStream_t)stream;
     HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
     HIP_OK(run_osd0(d, decoder_ws(d), syndromes, llr, B, nullptr, nullptr, corrections, info, 0, s));
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_osd_cs(qlsd_decoder d, const uint8_t *syndromes, const float *llr, int32_t B, int32_t order,
+                        uint8_t *corrections, qlsd_shot_info *info, void *stream) {
+    qlsd_status st = check_call(d, syndromes, B, corrections);
+    if (st != QLSD_OK) return st;
+    if (order < 1 || order > kOsdCsMaxOrder) return fail(QLSD_E_INVALID, "OSD-CS order must be in [1, %d]", kOsdCsMaxOrder);
+    if (B == 0) return QLSD_OK;
+    if (!llr) return fail(QLSD_E_INVALID, "llr is NULL");
+    if (!d->osd_cs_ok)
+        return fail(QLSD_E_UNSUPPORTED, "global OSD-CS supports n <= %d and m <= 256 (n=%d, m=%d)", kOsdMaxSort,
+                    d->code->g.n, d->code->g.m);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_OK(launch_zero(d->d_ctl, kCtlWords, s));
+    HIP_OK(run_osd0(d, decoder_ws(d), syndromes, llr, B, nullptr, nullptr, corrections, info, 0, s, order));
     return QLSD_OK;
 }
 

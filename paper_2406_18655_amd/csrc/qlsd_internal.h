@@ -130,9 +130,25 @@ struct OsdArgs {
     int P;                     // sort length: a power of two >= n
     int wave_bytes;            // LDS per wavefront (osd0_wave_bytes)
     uint64_t *ws;              // W = kWideW: grid * 2 * W * W * 64 words of basis
+    int cs_order;              // 0: OSD-0; w in [1, kOsdCsMaxOrder]: global OSD-CS of order w (W <= 4)
+    const int64_t *omega;      // n integer weights (OSD-CS)
 };
 constexpr int kOsdMaxSort = 4096;  // OSD-0 sorts n <= 4096 keys in LDS
-size_t osd0_wave_bytes(const DevGraph &g, int W, int P);
+constexpr int kOsdCsMaxOrder = 12;
+// LDS of global OSD-CS per wavefront, after the OSD-0 block: pivot weights, the pivot-part change
+// and weight of the first w dependent columns, the dependent columns in key order
+struct OsdCsLds {
+    int64_t *wq;      // 64 W
+    uint64_t *zk;     // kOsdCsMaxOrder * W
+    int64_t *tw;      // kOsdCsMaxOrder
+    int32_t *dep;     // n
+};
+__host__ __device__ inline size_t osd0_wave_bytes_w(int n, int W, int P, bool cs) {
+    size_t b = ((size_t)P * 8 + (size_t)64 * W * 4 + (size_t)((n + 31) / 32) * 4 + 15) & ~(size_t)15;
+    if (cs) b += (8 * ((size_t)64 * W + (size_t)kOsdCsMaxOrder * W + kOsdCsMaxOrder) + 4 * (size_t)n + 15) & ~(size_t)15;
+    return b;
+}
+size_t osd0_wave_bytes(const DevGraph &g, int W, int P, bool cs);
 hipError_t launch_osd0(const OsdArgs &a, int W, int grid, hipStream_t st);  // W in {1, 2, 4, kWideW}
 
 // Host helpers shared by the ABI files.

@@ -118,3 +118,113 @@ def test_osd0_refuses_graphs_beyond_its_sort():
     assert ex.value.status == -6
     with pytest.raises(binding.QlsdError):
         binding.Decoder(bc, code.priors, 4, max_iter=10, flags=binding.FLAG_OSD0_POST)
+
+
+# ------------------------------------------------------------------ global OSD-CS of order w
+
+def _osd_cs_parity(oracle_mod, code, S, L, order):
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, S.shape[0], max_iter=30)
+    corr, info = dec.osd_cs(torch.from_numpy(S).cuda(), torch.from_numpy(L).cuda(), order)
+    torch.cuda.synchronize()
+    corr, inf = corr.cpu().numpy(), binding.parse_info(info)
+    oc = oracle_mod.Code.from_dense(code.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(code.priors))
+    changed = 0
+    for b in range(S.shape[0]):
+        want, st = oracle_mod.osd_cs(oc, S[b], L[b].astype(np.float64), order, om)
+        assert (corr[b] == want).all(), (order, b)
+        assert bool(inf["status"][b] & binding.ST_UNSAT) == bool(st & oracle_mod.ST_UNSAT), b
+        if not st:
+            x0, _ = oracle_mod.osd0(oc, S[b], L[b].astype(np.float64))
+            changed += int((x0 != want).any())
+    return corr, inf, changed
+
+
+@pytest.mark.parametrize("which", ["c1", "c2", "hgp16"])
+def test_osd_cs_bit_exact_on_bp_llrs(oracle_mod, which):
+    """qlsd_osd_cs against the oracle's global OSD-CS on BP's float32 posteriors of the shots BP
+    leaves unsolved, orders 1, 4, 7 and 12 (the sweep changes OSD-0's answer on many shots)."""
+    code = CODES[which]()
+    print(f"case osd_cs_bp_llr {which}", flush=True)
+    e, S = sample(code, 800, seed=63)
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, 800, max_iter=30)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    inf = binding.parse_info(info)
+    idx = np.nonzero((inf["status"] & 1) == 0)[0][:200]
+    assert len(idx) > 10
+    S2 = np.ascontiguousarray(S[idx])
+    L2 = np.ascontiguousarray(llr.cpu().numpy()[idx])
+    for order in (1, 4, 7, 12):
+        corr, oinf, changed = _osd_cs_parity(oracle_mod, code, S2, L2, order)
+        assert (((corr.astype(np.int64) @ code.H.T.astype(np.int64)) & 1) == S2).all()
+        assert (oinf["max_cluster_cols"] == code.n).all()
+        print(f"{which} order {order}: {len(idx)} shots, {changed} differ from OSD-0")
+        if order >= 4:
+            assert changed > 0
+
+
+def test_osd_cs_ties_zero_and_unsat(oracle_mod):
+    """Integer LLRs (order mostly decided by the index), zero syndromes and, on the rank-deficient
+    BB code, syndromes outside the image of H."""
+    code = CODES["c2"]()
+    rng = np.random.default_rng(9)
+    e, S = sample(code, 150, seed=64)
+    S = np.concatenate([S, np.zeros((10, code.m), np.uint8), (rng.random((60, code.m)) < 0.2).astype(np.uint8)])
+    L = rng.integers(-2, 4, size=(S.shape[0], code.n)).astype(np.float32)
+    L[:, ::5] = -0.0
+    corr, inf, _ = _osd_cs_parity(oracle_mod, code, np.ascontiguousarray(S), L, 7)
+    assert not corr[150:160].any()
+    unsat = inf["status"][160:] & binding.ST_UNSAT
+    assert unsat.any() and not unsat.all()
+
+
+def test_bp_osd_cs_decode_against_oracle(oracle_mod):
+    """qlsd_decode with QLSD_FLAG_OSD0_POST and osd_method 1: BP, then global OSD-CS-7 on the shots
+    BP leaves unsolved -- converged shots equal BP's hard decision, the others the oracle's OSD-CS
+    on the same float32 posteriors; fewer logical failures than BP + OSD-0 on the same shots."""
+    code = bivariate_bicycle(p=0.05)
+    B = 4000
+    e, S = sample(code, B, seed=2025)
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, B, max_iter=50, flags=binding.FLAG_OSD0_POST,
+                          osd_method=binding.OSD_CS, osd_order=7)
+    dec0 = binding.Decoder(bc, code.priors, B, max_iter=50, flags=binding.FLAG_OSD0_POST)
+    s = torch.from_numpy(S).cuda()
+    corr, info = dec.decode(s, want_info=True)
+    corr0 = dec0.decode(s)
+    llr, hard, binfo = dec.bp(s)
+    torch.cuda.synchronize()
+    corr, corr0, L, H = corr.cpu().numpy(), corr0.cpu().numpy(), llr.cpu().numpy(), hard.cpu().numpy()
+    conv = (binding.parse_info(binfo)["status"] & 1) == 1
+    np.testing.assert_array_equal(corr[conv], H[conv])
+    oc = oracle_mod.Code.from_dense(code.H)
+    om = oracle_mod.omega_from_llr(oracle_mod.llr_from_priors(code.priors))
+    for b in np.nonzero(~conv)[0]:
+        want, _ = oracle_mod.osd_cs(oc, S[b], L[b].astype(np.float64), 7, om)
+        assert (corr[b] == want).all(), b
+    f_cs, f_0 = logical_failures(code, e, corr).sum(), logical_failures(code, e, corr0).sum()
+    print(f"BP50 + OSD-CS-7 failures {f_cs}, BP50 + OSD-0 {f_0} of {B}")
+    assert f_cs < f_0
+
+
+def test_osd_cs_refusals():
+    code = synthetic_dem()
+    bc = binding.Code.from_dense(code.H)
+    dec = binding.Decoder(bc, code.priors, 4, max_iter=10)
+    s = torch.zeros((4, code.m), dtype=torch.uint8, device="cuda")
+    with pytest.raises(binding.QlsdError) as ex:
+        dec.osd_cs(s, torch.zeros((4, code.n), dtype=torch.float32, device="cuda"), 7)
+    assert ex.value.status == -6
+    with pytest.raises(binding.QlsdError):
+        binding.Decoder(bc, code.priors, 4, max_iter=10, flags=binding.FLAG_OSD0_POST, osd_method=binding.OSD_CS,
+                        osd_order=7)
+    c2 = bivariate_bicycle()
+    d2 = binding.Decoder(binding.Code.from_dense(c2.H), c2.priors, 4, max_iter=10)
+    s2 = torch.zeros((4, c2.m), dtype=torch.uint8, device="cuda")
+    for bad in (0, 13):
+        with pytest.raises(binding.QlsdError) as ex:
+            d2.osd_cs(s2, torch.zeros((4, c2.n), dtype=torch.float32, device="cuda"), bad)
+        assert ex.value.status == -1  # QLSD_E_INVALID
