@@ -279,6 +279,8 @@ def main():
     if not dem and not args.no_osd:
         log("BP + OSD-0 leg")
         out["osd0"] = osd0_leg(code, bcode, batches, args, np.concatenate(ler_gpu), shots_per_s)
+        log("BP + OSD-CS legs")
+        out["osd_cs"] = osd_cs_leg(code, bcode, batches, args, shots_per_s)
     if not args.no_learned:
         log("learned leg")
         out["learned"] = learned_leg(code, bcode, batches, args, out["ler"]["gpu"], shots_per_s)
@@ -449,6 +451,34 @@ def osd0_leg(code, bcode, batches, args, f_plain, plain_rate):
             "mcnemar_vs_bp_lsd": {"only_osd_fails": int(np.sum(f & ~f_plain)),
                                   "only_lsd_fails": int(np.sum(~f & f_plain))},
             "bp_lsd_speedup": round(plain_rate / rate, 3), "shots_scored": int(n)}
+
+
+def osd_cs_leg(code, bcode, batches, args, plain_rate, order=7, mu=16):
+    """Higher-order post-processing on the same batches: BP followed by global OSD-CS of order
+    `order` (the BP+OSD-CS comparator of Sec. 2.3 and Appendix C) against BP followed by LSD-mu
+    whose local reprocessing is OSD-CS of the same order (Appendix D), both timed like the
+    headline; the paired counts compare the two forms shot by shot."""
+    from paper_2406_18655_amd import binding
+    B = batches[0][1].shape[0]
+    g = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, flags=binding.FLAG_OSD0_POST,
+                        osd_method=binding.OSD_CS, osd_order=order)
+    f_g, rate_g, ms_g, _ = _score_and_time(code, g, batches, args.steps, args.warmup, f"BP + OSD-CS-{order}")
+    del g
+    loc = binding.Decoder(bcode, code.priors, B, max_iter=args.max_iter, lsd_order=mu, osd_method=binding.OSD_CS,
+                          osd_order=order)
+    f_l, rate_l, ms_l, _ = _score_and_time(code, loc, batches, args.steps, args.warmup, f"BP + LSD-{mu} CS-{order}")
+    del loc
+    n = f_g.size
+    q_g, q_l = float(f_g.mean()), float(f_l.mean())
+    two_sigma = 2 * float(np.sqrt(max(q_g, 1 / n) * (1 - q_g) / n + max(q_l, 1 / n) * (1 - q_l) / n))
+    return {"order": order, "bp_max_iter": args.max_iter, "shots_scored": int(n),
+            "global": {"value": round(rate_g, 1), "unit": "shots/s", "ms_per_step": round(ms_g, 4),
+                       "ler": round(q_g, 6), "bp_lsd0_speedup": round(plain_rate / rate_g, 3)},
+            "lsd_mu_local": {"lsd_order": mu, "value": round(rate_l, 1), "unit": "shots/s",
+                             "ms_per_step": round(ms_l, 4), "ler": round(q_l, 6)},
+            "ler_difference_two_sigma": round(two_sigma, 6),
+            "mcnemar_local_vs_global": {"only_global_fails": int(np.sum(f_g & ~f_l)),
+                                        "only_local_fails": int(np.sum(~f_g & f_l))}}
 
 
 def record_traffic(fetch, write, cfetch, cwrite, path):
