@@ -64,6 +64,7 @@ struct qlsd_code_s {
     int device;
     DevGraph g;
     int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge, *d_row_edge;
+    int32_t *d_fault_order, *d_check_order;
     int min_rw;
 };
 
@@ -219,6 +220,19 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
             col_edge[k] = e;
             row_edge[e] = k;
         }
+    // faults by decreasing column weight and checks by decreasing row weight, ties by index
+    // (stable counting sorts): kernels that give consecutive lanes consecutive entries then see
+    // one weight in almost every wavefront
+    auto order_by_weight = [](const int32_t *ptr, int count, int maxw) {
+        std::vector<int32_t> ord(count);
+        std::vector<int64_t> start((size_t)maxw + 2, 0);
+        for (int x = 0; x < count; x++) start[(size_t)(maxw - (ptr[x + 1] - ptr[x])) + 1]++;
+        for (int w = 1; w <= maxw + 1; w++) start[w] += start[w - 1];
+        for (int x = 0; x < count; x++) ord[start[maxw - (ptr[x + 1] - ptr[x])]++] = x;
+        return ord;
+    };
+    const std::vector<int32_t> fault_order = order_by_weight(col_ptr.data(), n, max_cw);
+    const std::vector<int32_t> check_order = order_by_weight(row_ptr, m, max_rw);
     qlsd_code c = new (std::nothrow) qlsd_code_s();
     if (!c) return fail(QLSD_E_NOMEM, "host allocation failed");
     HIP_OK(hipGetDevice(&c->device));
@@ -228,6 +242,8 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     hipError_t e4 = dev_copy(&c->d_row_idx, row_idx.data(), (size_t)nnz);
     hipError_t e5 = dev_copy(&c->d_col_edge, col_edge.data(), (size_t)nnz);
     if (e5 == hipSuccess) e5 = dev_copy(&c->d_row_edge, row_edge.data(), (size_t)nnz);
+    if (e5 == hipSuccess) e5 = dev_copy(&c->d_fault_order, fault_order.data(), (size_t)n);
+    if (e5 == hipSuccess) e5 = dev_copy(&c->d_check_order, check_order.data(), (size_t)m);
     if (e1 || e2 || e3 || e4 || e5) {
         qlsd_code_destroy(c);
         return fail(QLSD_E_NOMEM, "device allocation/copy of H failed");
@@ -245,6 +261,8 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     c->g.row_idx = c->d_row_idx;
     c->g.col_edge = c->d_col_edge;
     c->g.row_edge = c->d_row_edge;
+    c->g.fault_order = c->d_fault_order;
+    c->g.check_order = c->d_check_order;
     c->min_rw = min_rw;
     *out = c;
     return QLSD_OK;
@@ -258,6 +276,8 @@ void qlsd_code_destroy(qlsd_code c) {
     hipFree(c->d_row_idx);
     hipFree(c->d_row_edge);
     hipFree(c->d_col_edge);
+    hipFree(c->d_fault_order);
+    hipFree(c->d_check_order);
     delete c;
 }
 

@@ -15,6 +15,7 @@
 // in, the correction out, and the posterior LLRs of shots that go on to LSD.
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "qlsd_internal.h"
 #include "qlsd_lsd_dev.h"
@@ -890,10 +891,15 @@ static hipError_t launch_bp_t(const BpArgs &a, const FuseArgs &f, int grid, size
 
 // Large graphs, fault-major message order.  The messages of fault j sit contiguously at its CSC
 // positions col_ptr[j] .. col_ptr[j+1]; each thread keeps the graph structure it touches in
-// registers for the kernel's lifetime -- for each of its FPT faults (j = t + k*NT) the CSC start,
-// degree and prior, and for its check row (i = t; needs m <= NT) the CSC positions of the row's
-// edges -- so the iteration loop reads no graph tables (only the row indices of faults whose hard
-// decision is 1, for the parity words).  Same arithmetic, in the same order, as bp_graph_kernel.
+// registers for the kernel's lifetime -- for each of its FPT faults the index, CSC start, degree
+// and prior, and for its check row (needs m <= NT) the CSC positions of the row's edges -- so the
+// iteration loop reads no graph tables (only the row indices of faults whose hard decision is 1,
+// for the parity words).  Thread t takes the faults at positions t + k*NT of the code's fault
+// order and the check at position t of its check order (both by decreasing weight), so almost
+// every wavefront's 64 faults, or checks, have one weight: such a wavefront runs its loops over
+// the messages to that weight with scalar branches only, the few mixed ones with a per-lane test
+// on each message.  Same arithmetic, in the same order, as bp_graph_kernel; which thread computes
+// a fault or a check changes no result.
 template <int MAXRW, int MAXCW, int FPT>
 __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -910,26 +916,30 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args)
     const int T = args.max_iter;
     const int lane = t & 63, wave = t >> 6;
 
-    uint32_t fmeta[FPT];  // CSC start | degree << 24
+    // fault record: CSC start (15 bits) | fault (14 bits) << 15 | degree (3 bits) << 29; a record
+    // of degree 0 is no fault
+    uint32_t fmeta[FPT];
     float flam[FPT];
 #pragma unroll
     for (int k = 0; k < FPT; k++) {
-        const int j = t + k * NT;
+        const int p = t + k * NT;
         uint32_t v = 0;
         float l = 0.f;
-        if (j < n) {
+        if (p < n) {
+            const int j = args.g.fault_order[p];
             const int c0 = args.g.col_ptr[j];
-            v = (uint32_t)c0 | ((uint32_t)(args.g.col_ptr[j + 1] - c0) << 24);
+            v = (uint32_t)c0 | ((uint32_t)j << 15) | ((uint32_t)(args.g.col_ptr[j + 1] - c0) << 29);
             l = args.lam[j];
         }
         fmeta[k] = v;
         flam[k] = l;
     }
     uint32_t rpos2[MAXRW / 2];  // CSC positions of the row's edges, two u16 per word (nnz < 65536)
+    const int ci = t < m ? args.g.check_order[t] : m;  // this thread's check (m: none)
     int rw = 0;
-    if (t < m) {
-        const int e0 = args.g.row_ptr[t];
-        rw = args.g.row_ptr[t + 1] - e0;
+    if (ci < m) {
+        const int e0 = args.g.row_ptr[ci];
+        rw = args.g.row_ptr[ci + 1] - e0;
 #pragma unroll
         for (int u = 0; u < MAXRW; u += 2) {
             const uint32_t lo = u < rw ? (uint32_t)args.g.row_edge[e0 + u] : 0u;
@@ -959,27 +969,41 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args)
         bool conv = false;
         for (;;) {
             // fault phase
+            // one fault's update; CWU: the wavefront's common degree (a run-time but wave-uniform
+            // bound, scalar branches only) or, for a mixed wavefront, the lane's own degree
+            auto fault_update = [&](int k, auto Uni) -> float {
+                constexpr bool UNI = decltype(Uni)::value;
+                const int c0 = (int)(fmeta[k] & 0x7fffu), cw = (int)(fmeta[k] >> 29);
+                const int cwb = UNI ? __builtin_amdgcn_readfirstlane(cw) : cw;
+                float r[MAXCW];
+#pragma unroll
+                for (int u = 0; u < MAXCW; u++) r[u] = u < cwb ? msg[c0 + u] : 0.f;
+                float pre[MAXCW + 1];
+                pre[0] = flam[k];
+#pragma unroll
+                for (int u = 0; u < MAXCW; u++) pre[u + 1] = pre[u] + r[u];
+                float suf = 0.f;
+#pragma unroll
+                for (int u = MAXCW - 1; u >= 0; u--) {
+                    if (u < cwb) {
+                        msg[c0 + u] = clampf(pre[u] + suf);
+                        suf += r[u];
+                    }
+                }
+                return clampf(pre[MAXCW]);
+            };
 #pragma unroll
             for (int k = 0; k < FPT; k++) {
-                const int j = t + k * NT;
-                if (j < n) {
-                    const int c0 = (int)(fmeta[k] & 0xffffffu), cw = (int)(fmeta[k] >> 24);
-                    float r[MAXCW];
-#pragma unroll
-                    for (int u = 0; u < MAXCW; u++) r[u] = u < cw ? msg[c0 + u] : 0.f;
-                    float pre[MAXCW + 1];
-                    pre[0] = flam[k];
-#pragma unroll
-                    for (int u = 0; u < MAXCW; u++) pre[u + 1] = pre[u] + r[u];
-                    float suf = 0.f;
-#pragma unroll
-                    for (int u = MAXCW - 1; u >= 0; u--) {
-                        if (u < cw) {
-                            msg[c0 + u] = clampf(pre[u] + suf);
-                            suf += r[u];
-                        }
-                    }
-                    const float Lt = clampf(pre[MAXCW]);
+                const int cw = (int)(fmeta[k] >> 29);
+                const bool uni = __ballot(cw != __builtin_amdgcn_readfirstlane(cw)) == 0;
+                float Lt = 0.f;
+                if (uni) {
+                    if (__builtin_amdgcn_readfirstlane(cw) > 0) Lt = fault_update(k, std::true_type{});
+                } else if (cw > 0) {
+                    Lt = fault_update(k, std::false_type{});
+                }
+                if (cw > 0) {
+                    const int j = (int)((fmeta[k] >> 15) & 0x3fffu), c0 = (int)(fmeta[k] & 0x7fffu);
                     Lv[j] = Lt;
                     if (Lt < 0.f) {
                         for (int u = 0; u < cw; u++) {
@@ -1007,13 +1031,15 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args)
             it++;
             // check phase: thread t owns check t; two passes over the row's messages (minima and
             // sign, then the updates) instead of holding them in registers
-            if (t < m) {
-                const uint32_t sb = (synw[t >> 5] >> (t & 31)) & 1u;
+            auto check_update = [&](auto Uni) {
+                constexpr bool UNI = decltype(Uni)::value;
+                const int rwb = UNI ? __builtin_amdgcn_readfirstlane(rw) : rw;
+                const uint32_t sb = (synw[ci >> 5] >> (ci & 31)) & 1u;
                 uint32_t sg = sb << 31;
                 float mn1 = INFINITY, mn2 = INFINITY;
 #pragma unroll
                 for (int u = 0; u < MAXRW; u++) {
-                    if (u < rw) {
+                    if (u < rwb) {
                         const float q = msg[(rpos2[u / 2] >> (16 * (u & 1))) & 0xffffu];
                         sg ^= __float_as_uint(q);
                         const float a = fabsf(q);
@@ -1024,13 +1050,21 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args)
                 const float m1 = alpha * mn1, m2 = alpha * mn2;
 #pragma unroll
                 for (int u = 0; u < MAXRW; u++) {
-                    if (u < rw) {
+                    if (u < rwb) {
                         const int p = (rpos2[u / 2] >> (16 * (u & 1))) & 0xffffu;
                         const float q = msg[p];
                         const float mag = (fabsf(q) == mn1) ? m2 : m1;
                         const uint32_t sgn = (sg ^ __float_as_uint(q)) & 0x80000000u;
                         msg[p] = __uint_as_float(__float_as_uint(mag) | sgn);
                     }
+                }
+            };
+            {
+                const bool uni = __ballot(rw != __builtin_amdgcn_readfirstlane(rw)) == 0;
+                if (uni) {
+                    if (__builtin_amdgcn_readfirstlane(rw) > 0) check_update(std::true_type{});
+                } else if (rw > 0) {
+                    check_update(std::false_type{});
                 }
             }
             __syncthreads();
@@ -1088,7 +1122,9 @@ hipError_t launch_bp_graph(const BpArgs &a, int grid, hipStream_t st) {
     // register-resident structure: checks <= threads, row weight <= 32, column weight <= 8, u16
     // CSC positions, at most 9 faults per thread (the 936 x 8800 detector error model)
     const DevGraph &g = a.g;
-    if (g.m <= kBpGraphThreads && g.max_rw <= 32 && g.max_cw <= 8 && g.nnz < 65536 && g.n <= 9 * kBpGraphThreads)
+    // the packed fault record needs nnz < 2^15, n < 2^14, column weight <= 7
+    if (g.m <= kBpGraphThreads && g.max_rw <= 32 && g.max_cw <= 7 && g.nnz < 32768 && g.n <= 9 * kBpGraphThreads &&
+        g.n < 16384 && g.fault_order && g.check_order)
         return launch_bp_graph2_t<32, 8, 9>(a, grid, lds, st);
     if (a.g.max_rw <= 8 && a.g.max_cw <= 4) return launch_bp_graph_t<8, 4>(a, grid, lds, st);
     if (a.g.max_rw <= 16 && a.g.max_cw <= 8) return launch_bp_graph_t<16, 8>(a, grid, lds, st);

@@ -17,6 +17,8 @@ struct DevGraph {
     const int32_t *col_ptr, *row_idx;   // n+1, nnz
     const int32_t *col_edge;            // nnz: CSR edge id of each CSC entry
     const int32_t *row_edge;            // nnz: CSC position of each CSR edge (inverse of col_edge)
+    const int32_t *fault_order;         // n: faults by decreasing column weight, ties by index
+    const int32_t *check_order;         // m: checks by decreasing row weight, ties by index
 };
 
 // Arguments of the BP kernel (messages resident in LDS, persistent slots).
