@@ -992,13 +992,44 @@ __global__ __launch_bounds__(kBpGraphThreads) void bp_graph2_kernel(BpArgs args)
                 }
                 return clampf(pre[MAXCW]);
             };
+            // a uniform wavefront's degree as a compile-time constant: no branches in the loops
+            auto fault_fixed = [&](int k, auto Dc) -> float {
+                constexpr int D = decltype(Dc)::value;
+                const int c0 = (int)(fmeta[k] & 0x7fffu);
+                float r[D];
+#pragma unroll
+                for (int u = 0; u < D; u++) r[u] = msg[c0 + u];
+                float pre[D + 1];
+                pre[0] = flam[k];
+#pragma unroll
+                for (int u = 0; u < D; u++) pre[u + 1] = pre[u] + r[u];
+                float suf = 0.f;
+#pragma unroll
+                for (int u = D - 1; u >= 0; u--) {
+                    msg[c0 + u] = clampf(pre[u] + suf);
+                    suf += r[u];
+                }
+                // the remaining MAXCW - D terms of the general form add +0 to pre[D]
+                float last = pre[D];
+#pragma unroll
+                for (int u = D; u < MAXCW; u++) last = last + 0.f;
+                return clampf(last);
+            };
 #pragma unroll
             for (int k = 0; k < FPT; k++) {
                 const int cw = (int)(fmeta[k] >> 29);
-                const bool uni = __ballot(cw != __builtin_amdgcn_readfirstlane(cw)) == 0;
+                const int cwk = __builtin_amdgcn_readfirstlane(cw);
+                const bool uni = __ballot(cw != cwk) == 0;
                 float Lt = 0.f;
                 if (uni) {
-                    if (__builtin_amdgcn_readfirstlane(cw) > 0) Lt = fault_update(k, std::true_type{});
+                    switch (cwk) {
+                        case 0: break;
+                        case 1: Lt = fault_fixed(k, std::integral_constant<int, 1>{}); break;
+                        case 2: Lt = fault_fixed(k, std::integral_constant<int, 2>{}); break;
+                        case 3: Lt = fault_fixed(k, std::integral_constant<int, 3>{}); break;
+                        case 4: Lt = fault_fixed(k, std::integral_constant<int, 4>{}); break;
+                        default: Lt = fault_update(k, std::true_type{}); break;
+                    }
                 } else if (cw > 0) {
                     Lt = fault_update(k, std::false_type{});
                 }
