@@ -218,7 +218,10 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "avg_launch_ms": round(bp_avg_ms, 4),
                 "algorithmic_bytes_per_launch": bytes_per_launch,
-                "lsd_avg_launch_ms": round(float(np.mean(lsd_ms)), 4)}
+                "lsd_avg_launch_ms": round(float(np.mean(lsd_ms)), 4),
+                "note": "algorithmic bytes count every message read and write of an HBM-resident formulation; "
+                        "the messages stay in LDS, so frac compares against that formulation, not the HBM peak "
+                        "(actual DRAM traffic: traffic)"}
     if not dem:
         roofline["binding"] = issue_roofline(args.counters_json, bp_avg_ms)
     if not dem:
