@@ -177,3 +177,40 @@ def test_dem_lsd10_bit_exact_on_every_failed_shot(oracle_mod, dem):
         assert inf["max_cluster_cols"][b] == stats[1], b
         biggest = max(biggest, int(stats[5]))
     print(f"{len(idx)} LSD-10 shots bit-exact; largest cluster {biggest} detectors")
+
+
+def test_large_graph_bp_mixed_weights(oracle_mod):
+    """The one-workgroup-per-shot BP on a graph built to reach its paths the DEM does not: columns
+    of weight 1 to 7 (every degree-specialised body of the fault update, and the wave-uniform
+    general one), rows of weight 2 to 32 in one weight-ordered sweep (wavefronts of one row weight
+    and mixed ones), more faults than the slot BP holds.  Posteriors after 20 iterations without
+    early exit against the float64 oracle."""
+    rng = np.random.default_rng(77)
+    m, n = 800, 6000
+    H = np.zeros((m, n), dtype=np.uint8)
+    rw = np.zeros(m, dtype=np.int64)
+    w = rng.choice(np.arange(1, 8), size=n, p=[0.1, 0.3, 0.3, 0.15, 0.08, 0.05, 0.02])
+    for j in range(n):
+        ok = np.nonzero(rw < 32)[0]
+        rows = rng.choice(ok, size=int(w[j]), replace=False)
+        H[rows, j] = 1
+        rw[rows] += 1
+    for i in np.nonzero(rw < 2)[0]:
+        j = rng.choice(np.nonzero(H.sum(0) < 7)[0], size=2 - int(rw[i]), replace=False)
+        H[i, j] = 1
+    assert H.sum(1).max() <= 32 and H.sum(1).min() >= 2 and set(H.sum(0)) >= {1, 2, 3, 4, 5, 6, 7}
+    priors = rng.uniform(0.001, 0.05, size=n)
+    e = (rng.random((6, n)) < priors).astype(np.uint8)
+    S = ((e.astype(np.int64) @ H.T.astype(np.int64)) & 1).astype(np.uint8)
+    bc = binding.Code.from_dense(H)
+    dec = binding.Decoder(bc, priors, 6, max_iter=20, flags=binding.FLAG_NO_EARLY_EXIT)
+    llr, hard, info = dec.bp(torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    L32 = llr.cpu().numpy().astype(np.float64)
+    oc = oracle_mod.Code.from_dense(H)
+    lam = oracle_mod.llr_from_priors(priors)
+    floor = np.abs(lam).min()
+    for b in range(6):
+        conv, it, L64, h64 = oracle_mod.bp(oc, lam, S[b], 20, early_exit=False)
+        err = np.abs(L32[b] - L64) / np.maximum(np.abs(L64), floor)
+        assert err.max() <= 1e-4, (b, float(err.max()))
