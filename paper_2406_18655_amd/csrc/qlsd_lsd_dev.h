@@ -93,7 +93,9 @@ struct LsdLds {
 };
 
 // A row's cached candidate stays exact while its column is not taken: the taken set only grows,
-// so the minimum over the row's remaining faults can change only when that column is taken.
+// so the minimum over the row's remaining faults can change only when that column is taken.  The
+// rows that may cache a column are its own detectors, all local rows by the time it is taken, so
+// taking a column marks exactly those rows kStale and the selection never tests the cached column.
 constexpr uint64_t kStale = ~0ull - 1ull;
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
@@ -753,7 +755,11 @@ __device__ __forceinline__ void insert_round_batched(const LsdArgs &A, const Lsd
         const int mark = -2 - b - 64 * rounds;  // below -1: no root, stamp or earlier mark of the shot
         if (inb) {
             const int c0 = g.col_ptr(col), c1 = g.col_ptr(col + 1);
-            for (int e = c0; e < c1; e++) S.lroot[S.loc[g.row_idx(e)]] = mark;
+            for (int e = c0; e < c1; e++) {
+                const int lr = S.loc[g.row_idx(e)];
+                S.lroot[lr] = mark;
+                S.cand[lr] = kStale;
+            }
             atomicOr(&S.incol[col >> 5], 1u << (col & 31));
             selu[2 * root + 1] = (uint32_t)lane;
         }
@@ -937,7 +943,8 @@ __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, c
         // (1) selection: per growing root, the candidate of smallest key (round-start state);
         // every entry of sel is ~0 here
         // Branch-light: a row's root and cached candidate are read together, then the root's
-        // state and the candidate's taken bit (reads of rows past nrows are in bounds and unused).
+        // state (reads of rows past nrows are in bounds and unused); a row rescans only when
+        // marked kStale.
 #pragma unroll
         for (int s = 0; s < W; s++) {
             if (s * 64 >= nrows) break;
@@ -955,13 +962,11 @@ __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, c
                 e1 = g.row_ptr(dd + 1);
             }
             const int c = valid ? cr : 0;
-            const uint32_t bc = (uint32_t)best;
-            const uint32_t inc = S.incol[(bc < (uint32_t)n ? bc : 0u) >> 5];
             const uint8_t st = S.state[c];
             const bool grow = valid && ((MU && grow_all) ? st != kFrozen : st == kInvalid);
             {
                 {
-                    if (grow && (best == kStale || (best != ~0ull && ((inc >> (bc & 31)) & 1u)))) {
+                    if (grow && best == kStale) {
                         best = ~0ull;
                         if constexpr (!G::kInLds) {
                             const int d = S.rowOf[r];
@@ -1208,8 +1213,9 @@ __device__ __forceinline__ void decode_shot(const LsdArgs &A, const LsdLds &S, c
                 col = __builtin_amdgcn_readfirstlane(col);
                 base = __builtin_amdgcn_readfirstlane(base);
                 cwc = __builtin_amdgcn_readfirstlane(cwc);
-                // no read of incol before the next sync: the update need not return
+                // no read of incol or cand before the next sync: the updates need not return
                 if (lane == 0) atomicOr(&S.incol[col >> 5], 1u << (col & 31));
+                if (lane >= base && lane < base + cwc && lr_src >= 0) S.cand[lr_src] = kStale;
                 const bool pivot = insert_column<W>(B, S, col, lane, lr_src, base, cwc);
                 if (MU && !pivot && A.mu > 0) {
                     if (lane == 0 && npc < KNP) S.colNP[npc] = col;
