@@ -66,6 +66,12 @@ struct qlsd_code_s {
     int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge, *d_row_edge;
     int32_t *d_fault_order, *d_check_order;
     int min_rw;
+    // host copies of the CSR row pointers and the CSC layout, for launch planning
+    std::vector<int32_t> h_row_ptr, h_col_ptr, h_col_edge;
+    // message strides already chosen for (slots, LDS budget): decoders of one code (serving
+    // lanes) reuse them instead of re-running the model
+    std::mutex stride_mu;
+    std::vector<std::pair<std::pair<int, size_t>, int>> strides;
 };
 
 struct qlsd_decoder_s {
@@ -81,6 +87,7 @@ struct qlsd_decoder_s {
     int *d_list;         // max_batch: flagged shots, compacted
     float *d_llr;        // max_batch x n (LLRs handed from BP to LSD)
     int bp_slots, bp_grid;
+    int bp_se;           // message stride per slot (bp_msg_stride)
     bool bp_graph;       // one workgroup per shot (large graphs) instead of S slots per workgroup
     int lsd_W, lsd_grid, lsd_wave_bytes, lsd_keys_in_lds, lsd_graph_in_lds;
     bool lsd_cb;         // cluster-batched column insertion (W = 4; qlsd_decoder_set_lsd_schedule)
@@ -264,6 +271,14 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     c->g.fault_order = c->d_fault_order;
     c->g.check_order = c->d_check_order;
     c->min_rw = min_rw;
+    try {
+        c->h_row_ptr.assign(row_ptr, row_ptr + m + 1);
+        c->h_col_ptr = col_ptr;
+        c->h_col_edge = col_edge;
+    } catch (...) {
+        qlsd_code_destroy(c);
+        return fail(QLSD_E_NOMEM, "host allocation failed");
+    }
     *out = c;
     return QLSD_OK;
 }
@@ -279,6 +294,19 @@ void qlsd_code_destroy(qlsd_code c) {
     hipFree(c->d_fault_order);
     hipFree(c->d_check_order);
     delete c;
+}
+
+// The slot kernel's message stride for S slots within budget bytes of LDS per workgroup.
+static int bp_stride_for(qlsd_code c, int S, size_t budget) {
+    std::lock_guard<std::mutex> lk(c->stride_mu);
+    for (const auto &e : c->strides)
+        if (e.first.first == S && e.first.second == budget) return e.second;
+    const int se = bp_msg_stride(c->g, c->h_row_ptr.data(), c->h_col_ptr.data(), c->h_col_edge.data(), S, budget);
+    try {
+        c->strides.push_back({{S, budget}, se});
+    } catch (...) {
+    }
+    return se;
 }
 
 qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const double *priors,
@@ -330,13 +358,15 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     for (wg_per_cu = 4; wg_per_cu >= 1; wg_per_cu /= 2) {
         const size_t budget = kBpLdsBudget * (4 / wg_per_cu) - (wg_per_cu == 1 ? 1024 : 0);
         S = kMaxSlots;
-        while (S > 0 && bp_lds_bytes(g, S) > budget) S--;
+        while (S > 0 && bp_lds_bytes(g, S, bp_min_stride(g)) > budget) S--;
         if (S >= 12 || (wg_per_cu == 1 && S >= 4)) break;
     }
     if (S >= 4 && g.n < 65535 && g.nnz < 65535) {
         d->bp_graph = false;
         d->bp_slots = S;
         d->bp_grid = std::max(1, wg_per_cu) * d->num_cus;
+        const int tier = std::max(1, wg_per_cu);
+        d->bp_se = bp_stride_for(code, S, kBpLdsBudget * (4 / tier) - (tier == 1 ? 1024 : 0));
     } else if (bp_graph_lds_bytes(g) <= kLdsPerCu - 1024) {
         // one workgroup per shot with the shot's messages in LDS
         d->bp_graph = true;
@@ -459,6 +489,7 @@ static BpArgs bp_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, int B) {
     a.alpha = d->params.ms_scaling;
     a.early_exit = (d->params.flags & QLSD_FLAG_NO_EARLY_EXIT) ? 0 : 1;
     a.S = d->bp_slots;
+    a.SE = d->bp_se;
     a.next_shot = w.ctl + kCtlQueue;
     return a;
 }
@@ -469,7 +500,7 @@ static BpArgs bp_args(qlsd_decoder d, const Ws &w, const uint8_t *syn, int B) {
 static int fuse_waves(qlsd_decoder d) {
     if (d->bp_graph || d->net || (d->params.flags & (QLSD_FLAG_SEPARATE_LSD | QLSD_FLAG_OSD0_POST))) return 0;
     if (d->lsd_W > 2 || d->params.lsd_order > 0 || !d->lsd_keys_in_lds || d->bp_grid > 4 * d->num_cus) return 0;
-    const size_t avail = bp_lds_bytes(d->code->g, d->bp_slots) - bp_tables_bytes(d->code->g);
+    const size_t avail = bp_lds_bytes(d->code->g, d->bp_slots, d->bp_se) - bp_tables_bytes(d->code->g);
     return (int)std::min<size_t>(4, avail / (size_t)d->lsd_wave_bytes);
 }
 
@@ -599,7 +630,7 @@ static qlsd_status decode_with(qlsd_decoder d, const Ws &w, const uint8_t *syndr
         f.bp_done = w.ctl + kCtlBpDone;
         f.lsd_done = w.ctl + kCtlLsdDone;
         f.lsd_waves = fw;
-        f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots);
+        f.lsd_bytes = (int)bp_lds_bytes(d->code->g, d->bp_slots, d->bp_se);
         if (timing) HIP_OK(hipEventRecord(d->ev[0], s));
         HIP_OK(launch_bp_fused(a, f, d->lsd_W, bp_grid(d, B), s));
         if (timing) HIP_OK(hipEventRecord(d->ev[1], s));
@@ -884,25 +915,27 @@ qlsd_status qlsd_decoder_tune(qlsd_decoder d, const uint8_t *syndromes, int32_t 
     };
     // BP with shot slots: the largest slot count that fits each workgroups-per-CU tier
     if (!d->bp_graph) {
-        int best_S = d->bp_slots, best_grid = d->bp_grid;
+        int best_S = d->bp_slots, best_grid = d->bp_grid, best_se = d->bp_se;
         float best = 1e30f;
         for (int wg : {1, 2, 3, 4, 5, 6, 8}) {
             const size_t budget = kLdsPerCu / wg - 512;
             int S = kMaxSlots;
-            while (S > 0 && bp_lds_bytes(g, S) > budget) S--;
+            while (S > 0 && bp_lds_bytes(g, S, bp_min_stride(g)) > budget) S--;
             if (S < 4) continue;
             d->bp_slots = S;
             d->bp_grid = wg * d->num_cus;
+            d->bp_se = bp_stride_for(d->code, S, budget);
             const bool whole = d->net == nullptr;
             const float ms = whole ? timeit(decode_run) : timeit(bp_run);
             snprintf(line, sizeof(line), "%s slots %d x %d workgroups/CU: %.4f ms\n",
                      whole ? (fuse_waves(d) > 0 ? "decode (BP + LSD one kernel)," : "decode (BP, LSD),") : "bp",
                      S, wg, ms);
             rep += line;
-            if (ms > 0.f && ms < best) { best = ms; best_S = S; best_grid = d->bp_grid; }
+            if (ms > 0.f && ms < best) { best = ms; best_S = S; best_grid = d->bp_grid; best_se = d->bp_se; }
         }
         d->bp_slots = best_S;
         d->bp_grid = best_grid;
+        d->bp_se = best_se;
         snprintf(line, sizeof(line), "bp chosen: slots %d, grid %d\n", best_S, best_grid);
         rep += line;
     }

@@ -6,9 +6,10 @@
 //   hard decision  : e_j = [L_j < 0]; a shot has converged once H e = s (tested after every iteration).
 // Magnitudes of q and L are clamped to 2^64 so that 100 iterations cannot overflow float32.
 //
-// Design (MI355X): a workgroup owns S shot "slots" whose messages live entirely in LDS in an
-// [edge][slot] layout, so lanes that work on the same check or fault for consecutive slots hit
-// consecutive LDS banks.  Each loop iteration runs one check phase and one fault phase over the
+// Design (MI355X): a workgroup owns S shot "slots" whose messages live entirely in LDS, slot after
+// slot at a stride the host picks with a model of the LDS banks (bp_msg_stride), so the lanes that
+// work on a few consecutive checks or faults across the slots spread over the banks.  Each loop
+// iteration runs one check phase and one fault phase over the
 // active slots only.  A slot whose shot converged (or ran out of iterations) is retired and
 // immediately refilled from a global queue, so early-exiting shots never leave lanes idle; the
 // number of work items shrinks only once the queue is empty.  HBM traffic is only the syndrome
@@ -29,8 +30,8 @@ constexpr float kClamp = 18446744073709551616.0f;  // 2^64
 __device__ __forceinline__ float clampf(float x) { return __builtin_amdgcn_fmed3f(x, -kClamp, kClamp); }
 
 struct BpLds {
-    int SE, SN, PW;  // message and posterior strides per slot (odd: consecutive slots hit distinct
-                     // banks); 32-bit words per slot of the syndrome / parity bit vectors
+    int SE, SN, PW;  // message stride per slot (chosen on the host, bp_msg_stride), posterior
+                     // stride (odd); 32-bit words per slot of the syndrome / parity bit vectors
     int C;           // shots per queue chunk
     float *msg, *Lv, *lam;
     uint32_t *synw, *parw;
@@ -55,9 +56,9 @@ constexpr int kSlotArrays = 7;   // int arrays of S entries in the slot-state bl
 constexpr int kCtl = 16;         // control words
 
 template <bool REG>
-__device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S) {
+__device__ inline BpLds carve_bp(unsigned char *base, int m, int n, int E, int S, int SE) {
     BpLds L;
-    L.SE = odd_stride(E);
+    L.SE = SE;
     L.SN = odd_stride(n);
     L.PW = (m + 31) / 32;
     L.C = S;
@@ -325,7 +326,7 @@ void bp_lds_kernel(BpArgs args, FuseArgs f) {
     const int t = threadIdx.x, NT = blockDim.x;
     const int lane = t & 63, wave = t >> 6;
     const int m = args.g.m, n = args.g.n, E = args.g.nnz, S = args.S;
-    BpLds L = carve_bp<REG>(smem, m, n, E, S);
+    BpLds L = carve_bp<REG>(smem, m, n, E, S, args.SE);
     const int C = L.C;
 
     for (int x = t; x <= m; x += NT) L.rp[x] = (uint16_t)args.g.row_ptr[x];
@@ -869,15 +870,74 @@ static bool bp_regular63(const DevGraph &g) {
 
 size_t bp_tables_bytes(const DevGraph &g) { return tables_bytes(g.m, g.n, g.nnz, bp_regular63(g)); }
 
-size_t bp_lds_bytes(const DevGraph &g, int S) {
+size_t bp_lds_bytes(const DevGraph &g, int S, int SE) {
     // carve_bp's order: graph tables, messages, posteriors, priors, bit vectors, slot state, staging
     const size_t PW = ((size_t)g.m + 31) / 32;
     size_t b = bp_tables_bytes(g);
-    b += sizeof(float) * ((size_t)odd_stride(g.nnz) * S + (size_t)odd_stride(g.n) * S + g.n);
+    b += sizeof(float) * ((size_t)SE * S + (size_t)odd_stride(g.n) * S + g.n);
     b += sizeof(uint32_t) * 2 * PW * S;
     b += sizeof(int) * ((size_t)kSlotArrays * S + kCtl);
     b += (size_t)2 * S * g.m;  // two staging buffers of S syndromes
     return align16(b);
+}
+
+int bp_min_stride(const DevGraph &g) { return odd_stride(g.nnz); }
+
+// LDS cycles of one pass of the slot kernel over every check and every fault with all S slots
+// active, in a model of the LDS as 32 banks of 4 bytes serving a wavefront in two halves of 32
+// lanes: a message access costs, per half, the largest number of its lanes whose words fall in one
+// bank.  Lane t of a phase serves slot t mod S of check (or fault) t div S, so the lanes of a
+// wavefront read edge u of a few consecutive checks (faults) in every slot, at slot * SE + edge.
+static long long bp_bank_cycles(const int32_t *row_ptr, const int32_t *col_ptr, const int32_t *col_edge, int m,
+                                int n, int max_rw, int max_cw, int S, int SE) {
+    long long cyc = 0;
+    int bank[32];
+    auto pass = [&](int items, int first_thread, int max_w, auto addr) {
+        const int NT = kBpThreads - first_thread;  // threads of the phase
+        const int R = NT / S;                      // items per step
+        for (int it = 0; it < items; it += R)
+            for (int w0 = 0; w0 < NT; w0 += 64)
+                for (int u = 0; u < max_w; u++)
+                    for (int h = 0; h < 64; h += 32) {
+                        std::fill(bank, bank + 32, 0);
+                        int mx = 0;
+                        for (int l = h; l < h + 32; l++) {
+                            const int t = w0 + l, r = t / S, a = t % S, x = it + r;
+                            if (r >= R || x >= items) continue;
+                            const long long ad = addr(x, u);
+                            if (ad < 0) continue;
+                            mx = std::max(mx, ++bank[(a * (long long)SE + ad) & 31]);
+                        }
+                        cyc += mx;
+                    }
+    };
+    // check phase (wavefronts 1..): edge u of check i is CSR edge row_ptr[i] + u
+    pass(m, 64, max_rw, [&](int i, int u) -> long long {
+        return u < row_ptr[i + 1] - row_ptr[i] ? (long long)row_ptr[i] + u : -1;
+    });
+    // fault phase (every wavefront): edge u of fault j is the CSR edge col_edge[col_ptr[j] + u]
+    pass(n, 0, max_cw, [&](int j, int u) -> long long {
+        return u < col_ptr[j + 1] - col_ptr[j] ? (long long)col_edge[col_ptr[j] + u] : -1;
+    });
+    return cyc;
+}
+
+// The message stride (floats per slot) of S slots within `budget` bytes of LDS: the fewest modelled
+// bank cycles among E .. E + 63 (the smallest stride on ties).  On the [[144,12,12]] code (432
+// edges, 14 slots) the odd stride 433 models 2.8 and 2.6 cycles per half-wavefront access in the
+// check and fault phases, the chosen 437 models 1.0 and 1.5, and BP ran 6 % faster; the stride a
+// 64-bank model prefers ran slower than 437, which is why the model counts 32 banks.
+int bp_msg_stride(const DevGraph &g, const int32_t *row_ptr, const int32_t *col_ptr, const int32_t *col_edge, int S,
+                  size_t budget) {
+    int best = bp_min_stride(g);
+    if (S < 1) return best;
+    long long best_cyc = -1;
+    for (int SE = g.nnz; SE < g.nnz + 64; SE++) {
+        if (bp_lds_bytes(g, S, SE) > budget) break;
+        const long long c = bp_bank_cycles(row_ptr, col_ptr, col_edge, g.m, g.n, g.max_rw, g.max_cw, S, SE);
+        if (best_cyc < 0 || c < best_cyc) { best_cyc = c; best = SE; }
+    }
+    return best;
 }
 
 template <int RW, int CW, bool REG, int LSDW, bool OVF>
@@ -1174,11 +1234,11 @@ static hipError_t launch_bp_w(const BpArgs &a, const FuseArgs &f, int grid, size
 hipError_t launch_bp(const BpArgs &a, int grid, hipStream_t st) {
     FuseArgs f;
     memset(&f, 0, sizeof(f));
-    return launch_bp_w<0>(a, f, grid, bp_lds_bytes(a.g, a.S), st);
+    return launch_bp_w<0>(a, f, grid, bp_lds_bytes(a.g, a.S, a.SE), st);
 }
 
 hipError_t launch_bp_fused(const BpArgs &a, const FuseArgs &f, int W, int grid, hipStream_t st) {
-    const size_t lds = std::max(bp_lds_bytes(a.g, a.S), (size_t)f.lsd_bytes);
+    const size_t lds = std::max(bp_lds_bytes(a.g, a.S, a.SE), (size_t)f.lsd_bytes);
     if (f.lsd.ovf_list && a.g.m > 64 * W) {
         switch (W) {
             case 1: return launch_bp_w<1, true>(a, f, grid, lds, st);

@@ -31,6 +31,7 @@ struct BpArgs {
     float alpha;
     int early_exit;
     int S;                     // shot slots per workgroup
+    int SE;                    // message stride per slot (floats, >= nnz; bp_msg_stride)
     int *next_shot;            // queue head (zeroed before launch)
     uint8_t *corr;             // B x n: hard decision of the last iteration (nullable)
     float *llr_out;            // B x n: posterior LLRs of every shot (nullable)
@@ -85,7 +86,12 @@ struct FuseArgs {
 };
 
 // LDS carve sizes (bytes) shared by host (launch config) and device.
-size_t bp_lds_bytes(const DevGraph &g, int S);
+size_t bp_lds_bytes(const DevGraph &g, int S, int SE);
+// the slot kernel's message stride: the smallest (odd) one, and the one a model of the LDS banks
+// picks for S slots within budget bytes (host copies of the CSR row pointers and the CSC layout)
+int bp_min_stride(const DevGraph &g);
+int bp_msg_stride(const DevGraph &g, const int32_t *row_ptr, const int32_t *col_ptr, const int32_t *col_edge, int S,
+                  size_t budget);
 size_t bp_graph_lds_bytes(const DevGraph &g);
 // with_mu: the decoder runs LSD-mu (order > 0) and needs the LSD-mu arrays
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu);
