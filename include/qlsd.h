@@ -188,6 +188,13 @@ qlsd_status qlsd_osd_cs(qlsd_decoder dec, const uint8_t *syndromes, const float 
  * waits for those events.  Either output pointer (host float) may be NULL. */
 qlsd_status qlsd_decoder_stage_ms(qlsd_decoder dec, float *bp_ms, float *lsd_ms);
 
+/* Switches the stage events of later qlsd_decode calls on (enable != 0) or off, so that a caller
+ * can time a sample of its calls without recording three events on every one (each costs a few
+ * microseconds of device time).  A decoder created with QLSD_FLAG_STAGE_TIMING starts with them
+ * on; QLSD_E_INVALID for one created without it.  qlsd_decoder_stage_ms then reports the last
+ * call made with them on.  Not synchronised with calls in flight on other host threads. */
+qlsd_status qlsd_decoder_set_stage_timing(qlsd_decoder dec, int32_t enable);
+
 /* Autotuner: times candidate launch shapes on a sample batch (syndromes device u8[B*m],
  * B <= max_batch, typically one full batch of the workload) and keeps the fastest -- for BP
  * with shot slots, the slots per workgroup and workgroups per compute unit (timed on the whole

@@ -25,8 +25,9 @@ FLAG_OSD0_POST = 8
 # every symbol include/qlsd.h declares
 EXPORTS = ["qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
            "qlsd_osd0", "qlsd_osd_cs", "qlsd_lsd_stats", "qlsd_error_clusters",
-           "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
-           "qlsd_decoder_set_lsd_schedule", "qlsd_sync", "qlsd_last_error", "qlsd_decoder_destroy",
+           "qlsd_decoder_stage_ms", "qlsd_decoder_set_stage_timing", "qlsd_decoder_tune",
+           "qlsd_decoder_set_lsd_capacity", "qlsd_decoder_set_lsd_schedule", "qlsd_sync", "qlsd_last_error",
+           "qlsd_decoder_destroy",
            "qlsd_code_destroy"]
 
 INFO_DTYPE = np.dtype([("status", np.uint8), ("reserved", np.uint8), ("bp_iters", np.int16),
@@ -72,6 +73,7 @@ def lib():
         L.qlsd_lsd_stats.argtypes = [P, P, P, I32, P, P, P, P]
         L.qlsd_error_clusters.argtypes = [P, P, I32, P, P]
         L.qlsd_decoder_stage_ms.argtypes = [P, P, P]
+        L.qlsd_decoder_set_stage_timing.argtypes = [P, I32]
         L.qlsd_decoder_tune.argtypes = [P, P, I32, I32, P, P, I32]
         L.qlsd_decoder_set_lsd_capacity.argtypes = [P, I32]
         L.qlsd_decoder_set_lsd_schedule.argtypes = [P, I32]
@@ -81,8 +83,8 @@ def lib():
         L.qlsd_code_destroy.argtypes = [P]
         for fn in ("qlsd_code_create", "qlsd_decoder_create", "qlsd_decode", "qlsd_decode_static", "qlsd_bp", "qlsd_lsd",
                    "qlsd_osd0", "qlsd_osd_cs", "qlsd_lsd_stats", "qlsd_error_clusters",
-                   "qlsd_decoder_stage_ms", "qlsd_decoder_tune", "qlsd_decoder_set_lsd_capacity",
-                   "qlsd_decoder_set_lsd_schedule", "qlsd_sync"):
+                   "qlsd_decoder_stage_ms", "qlsd_decoder_set_stage_timing", "qlsd_decoder_tune",
+                   "qlsd_decoder_set_lsd_capacity", "qlsd_decoder_set_lsd_schedule", "qlsd_sync"):
             getattr(L, fn).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -240,10 +242,14 @@ class Decoder:
         _check(lib().qlsd_decoder_set_lsd_schedule(self._h, int(schedule)))
 
     def stage_ms(self):
-        """(bp_ms, lsd_ms) of the last decode call (needs FLAG_STAGE_TIMING)."""
+        """(bp_ms, lsd_ms) of the last decode call made with stage events on (needs FLAG_STAGE_TIMING)."""
         a, b = ctypes.c_float(), ctypes.c_float()
         _check(lib().qlsd_decoder_stage_ms(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
+
+    def set_stage_timing(self, enable: bool):
+        """Stage events on or off for later decode calls (a FLAG_STAGE_TIMING decoder starts with them on)."""
+        _check(lib().qlsd_decoder_set_stage_timing(self._h, 1 if enable else 0))
 
     # -- torch conveniences ----------------------------------------------------------
     def _prep(self, syndromes):

@@ -93,7 +93,8 @@ struct qlsd_decoder_s {
     bool lsd_cb;         // cluster-batched column insertion (W = 4; qlsd_decoder_set_lsd_schedule)
     int num_cus;
     hipEvent_t ev[3];   // stage timing: before BP, between BP and LSD, after LSD
-    bool timing;
+    bool timing;        // the events exist (QLSD_FLAG_STAGE_TIMING)
+    bool timing_on;     // qlsd_decode records them (qlsd_decoder_set_stage_timing)
     qlsd_net net;       // optional refinement between BP and LSD
     unsigned char *d_netws;  // feature workspace of the refinement on large graphs (else nullptr)
     size_t netws_bytes;
@@ -417,6 +418,7 @@ qlsd_status qlsd_decoder_create(qlsd_code code, const qlsd_params *params, const
     d->d_wide_ws = nullptr;
     d->wide_grid = d->mid_grid = 0;
     d->timing = (params->flags & QLSD_FLAG_STAGE_TIMING) != 0;
+    d->timing_on = d->timing;
     for (int k = 0; k < 3; k++) d->ev[k] = nullptr;
     if (d->timing)
         for (int k = 0; k < 3; k++)
@@ -678,7 +680,8 @@ qlsd_status qlsd_decode(qlsd_decoder d, const uint8_t *syndromes, int32_t B, uin
                         qlsd_shot_info *info, void *stream) {
     qlsd_status st = check_call(d, syndromes, B, corrections);
     if (st != QLSD_OK || B == 0) return st;
-    return decode_with(d, decoder_ws(d), syndromes, B, corrections, info, (hipStream_t)stream, d->timing);
+    return decode_with(d, decoder_ws(d), syndromes, B, corrections, info, (hipStream_t)stream,
+                       d->timing && d->timing_on);
 }
 
 // Device address of this device's `scratch` (looked up once per device, with it current).
@@ -1028,6 +1031,14 @@ qlsd_status qlsd_decoder_stage_ms(qlsd_decoder d, float *bp_ms, float *lsd_ms) {
     HIP_OK(hipEventElapsedTime(&b, d->ev[1], d->ev[2]));
     if (bp_ms) *bp_ms = a;
     if (lsd_ms) *lsd_ms = b;
+    return QLSD_OK;
+}
+
+qlsd_status qlsd_decoder_set_stage_timing(qlsd_decoder d, int32_t enable) {
+    g_err[0] = 0;
+    if (!d) return fail(QLSD_E_INVALID, "decoder is NULL");
+    if (!d->timing) return fail(QLSD_E_INVALID, "decoder was created without QLSD_FLAG_STAGE_TIMING");
+    d->timing_on = enable != 0;
     return QLSD_OK;
 }
 

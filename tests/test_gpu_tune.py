@@ -150,3 +150,34 @@ def test_cluster_batched_schedule_needs_the_256_row_kernel():
     with pytest.raises(binding.QlsdError):
         d.set_lsd_schedule(7)
     d.set_lsd_schedule(binding.LSD_PER_COLUMN)
+
+
+def test_stage_timing_switch():
+    """qlsd_decoder_set_stage_timing: with the events off a decode leaves the last timed call's
+    stage times in place and its outputs unchanged; on again, the next call is timed; a decoder
+    created without QLSD_FLAG_STAGE_TIMING refuses the switch."""
+    code = bivariate_bicycle(p=0.05)
+    B = 16384
+    bc = binding.Code.from_dense(code.H)
+    _, S0 = sample(code, B, seed=91)
+    _, S1 = sample(code, B, seed=92)
+    s0, s1 = torch.from_numpy(S0).cuda(), torch.from_numpy(S1).cuda()
+    d = binding.Decoder(bc, code.priors, B, max_iter=50, flags=binding.FLAG_STAGE_TIMING)
+    plain = binding.Decoder(bc, code.priors, B, max_iter=50)
+    c_on = torch.empty((B, code.n), dtype=torch.uint8, device="cuda")
+    c_off, c_ref = torch.empty_like(c_on), torch.empty_like(c_on)
+    d.decode_into(s0, c_on, None)
+    first = d.stage_ms()
+    assert first[0] > 0.0
+    d.set_stage_timing(False)
+    d.decode_into(s1, c_off, None)
+    plain.decode_into(s1, c_ref, None)
+    torch.cuda.synchronize()
+    assert d.stage_ms() == first, "a call with the events off must not re-record them"
+    assert torch.equal(c_off, c_ref)
+    d.set_stage_timing(True)
+    d.decode_into(s1, c_on, None)
+    second = d.stage_ms()
+    assert second[0] > 0.0 and torch.equal(c_on, c_ref)
+    with pytest.raises(binding.QlsdError):
+        plain.set_stage_timing(True)
