@@ -65,6 +65,8 @@ struct qlsd_code_s {
     DevGraph g;
     int32_t *d_row_ptr, *d_col_idx, *d_col_ptr, *d_row_idx, *d_col_edge, *d_row_edge;
     int32_t *d_fault_order, *d_check_order;
+    int32_t *d_fault_msg;  // message layout of the large-graph BP kernel (null when not built)
+    uint16_t *d_row_msg;
     int min_rw;
     // host copies of the CSR row pointers and the CSC layout, for launch planning
     std::vector<int32_t> h_row_ptr, h_col_ptr, h_col_edge;
@@ -241,6 +243,15 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     };
     const std::vector<int32_t> fault_order = order_by_weight(col_ptr.data(), n, max_cw);
     const std::vector<int32_t> check_order = order_by_weight(row_ptr, m, max_rw);
+    std::vector<int32_t> fault_msg;
+    std::vector<uint16_t> row_msg;
+    int msg_words = -1;
+    try {
+        msg_words = bp_graph2_layout(m, n, (int)nnz, row_ptr, col_ptr.data(), row_edge.data(), fault_order.data(),
+                                     check_order.data(), fault_msg, row_msg);
+    } catch (...) {
+        return fail(QLSD_E_NOMEM, "host allocation failed");
+    }
     qlsd_code c = new (std::nothrow) qlsd_code_s();
     if (!c) return fail(QLSD_E_NOMEM, "host allocation failed");
     HIP_OK(hipGetDevice(&c->device));
@@ -252,6 +263,8 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     if (e5 == hipSuccess) e5 = dev_copy(&c->d_row_edge, row_edge.data(), (size_t)nnz);
     if (e5 == hipSuccess) e5 = dev_copy(&c->d_fault_order, fault_order.data(), (size_t)n);
     if (e5 == hipSuccess) e5 = dev_copy(&c->d_check_order, check_order.data(), (size_t)m);
+    if (e5 == hipSuccess && msg_words > 0) e5 = dev_copy(&c->d_fault_msg, fault_msg.data(), (size_t)n);
+    if (e5 == hipSuccess && msg_words > 0) e5 = dev_copy(&c->d_row_msg, row_msg.data(), (size_t)nnz);
     if (e1 || e2 || e3 || e4 || e5) {
         qlsd_code_destroy(c);
         return fail(QLSD_E_NOMEM, "device allocation/copy of H failed");
@@ -271,6 +284,9 @@ qlsd_status qlsd_code_create(int32_t m, int32_t n, int64_t nnz, const int32_t *r
     c->g.row_edge = c->d_row_edge;
     c->g.fault_order = c->d_fault_order;
     c->g.check_order = c->d_check_order;
+    c->g.fault_msg = msg_words > 0 ? c->d_fault_msg : nullptr;
+    c->g.row_msg = msg_words > 0 ? c->d_row_msg : nullptr;
+    c->g.msg_words = std::max(msg_words, 0);
     c->min_rw = min_rw;
     try {
         c->h_row_ptr.assign(row_ptr, row_ptr + m + 1);
@@ -294,6 +310,8 @@ void qlsd_code_destroy(qlsd_code c) {
     hipFree(c->d_col_edge);
     hipFree(c->d_fault_order);
     hipFree(c->d_check_order);
+    hipFree(c->d_fault_msg);
+    hipFree(c->d_row_msg);
     delete c;
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/qlsd.h"
 
 namespace qlsd {
@@ -19,6 +21,11 @@ struct DevGraph {
     const int32_t *row_edge;            // nnz: CSC position of each CSR edge (inverse of col_edge)
     const int32_t *fault_order;         // n: faults by decreasing column weight, ties by index
     const int32_t *check_order;         // m: checks by decreasing row weight, ties by index
+    // message layout of the large-graph BP kernel (bp_graph2_layout; null / 0 when not built):
+    const int32_t *fault_msg;           // n: LDS word of each fault's first message (entry u: + 64 u)
+    const uint16_t *row_msg;            // nnz: per check, in CSR slots, the LDS words of its messages
+                                        // in the order the check phase visits them
+    int msg_words;                      // LDS words the layout spans
 };
 
 // Arguments of the BP kernel (messages resident in LDS, persistent slots).
@@ -93,6 +100,11 @@ int bp_min_stride(const DevGraph &g);
 int bp_msg_stride(const DevGraph &g, const int32_t *row_ptr, const int32_t *col_ptr, const int32_t *col_edge, int S,
                   size_t budget);
 size_t bp_graph_lds_bytes(const DevGraph &g);
+// Builds the large-graph kernel's message layout on the host (see qlsd_bp.hip); returns the
+// LDS words it spans, or -1 when the kernel's limits rule it out.
+int bp_graph2_layout(int m, int n, int nnz, const int32_t *row_ptr, const int32_t *col_ptr, const int32_t *row_edge,
+                     const int32_t *fault_order, const int32_t *check_order, std::vector<int32_t> &fault_msg,
+                     std::vector<uint16_t> &row_msg);
 // with_mu: the decoder runs LSD-mu (order > 0) and needs the LSD-mu arrays
 size_t lsd_wave_bytes(const DevGraph &g, int W, bool keys_in_lds, bool with_mu);
 size_t lsd_total_lds(const DevGraph &g, int W, bool keys_in_lds, bool graph_in_lds, bool with_mu);
