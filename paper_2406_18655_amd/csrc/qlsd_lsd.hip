@@ -173,21 +173,55 @@ __global__ __launch_bounds__(64) void error_cluster_kernel(DevGraph g, const uin
 }
 
 // Shots flagged by BP -> a dense list (one 64-shot ballot and one atomic per wavefront).
-__global__ void compact_kernel(const uint8_t *flag, int B, int *list, int *count) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x & 63;
-    const bool f = b < B && flag[b];
-    const uint64_t bal = __ballot(f);
-    int base = 0;
-    if (lane == 0 && bal) base = atomicAdd(count, (int)__popcll(bal));
-    base = __shfl(base, 0, 64);
-    if (f) list[base + __popcll(bal & ((1ull << lane) - 1ull))] = b;
+// Lists the flagged shots.  A 256-thread workgroup takes 1024 consecutive flags, four per thread
+// (one 32-bit read when the flags are 4-byte aligned), counts them with a wavefront scan, reserves
+// its whole share of the list with a single atomic and writes its entries in shot order: one
+// atomic per 1024 shots instead of one per 64 (the per-wavefront form spent most of its 13 us per
+// 65,536-shot batch queued on that counter).  The order of entries across workgroups is the order
+// of their atomics; every consumer decodes the listed shots independently.
+constexpr int kCompactPerThread = 4;
+constexpr int kCompactPerBlock = 256 * kCompactPerThread;
+__global__ __launch_bounds__(256) void compact_kernel(const uint8_t *flag, int B, int *list, int *count) {
+    __shared__ int wsum[4];
+    __shared__ int wgbase;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int b0 = blockIdx.x * kCompactPerBlock + t * kCompactPerThread;
+    uint32_t bits = 0;  // bit k: shot b0 + k is flagged
+    if (b0 + kCompactPerThread <= B && (((uintptr_t)flag) & 3) == 0) {
+        const uint32_t w = *(const uint32_t *)(flag + b0);
+#pragma unroll
+        for (int k = 0; k < kCompactPerThread; k++) bits |= (((w >> (8 * k)) & 0xffu) != 0u ? 1u : 0u) << k;
+    } else {
+#pragma unroll
+        for (int k = 0; k < kCompactPerThread; k++) bits |= (b0 + k < B && flag[b0 + k] ? 1u : 0u) << k;
+    }
+    const int c = __popc(bits);
+    int incl = c;  // inclusive scan over the wavefront
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int v = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    if (t == 0) {
+        const int total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        wgbase = total > 0 ? atomicAdd(count, total) : 0;
+    }
+    __syncthreads();
+    int pos = wgbase + incl - c;
+    for (int w = 0; w < wave; w++) pos += wsum[w];
+#pragma unroll
+    for (int k = 0; k < kCompactPerThread; k++)
+        if ((bits >> k) & 1u) list[pos++] = b0 + k;
 }
 
 }  // namespace
 
 hipError_t launch_compact(const uint8_t *flag, int B, int *list, int *count, hipStream_t st) {
-    hipLaunchKernelGGL(compact_kernel, dim3((B + 255) / 256), dim3(256), 0, st, flag, B, list, count);
+    if (B <= 0) return hipSuccess;
+    hipLaunchKernelGGL(compact_kernel, dim3((B + kCompactPerBlock - 1) / kCompactPerBlock), dim3(256), 0, st, flag, B,
+                       list, count);
     return hipGetLastError();
 }
 
